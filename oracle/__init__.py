@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the kernel-free boundary integral (KFBI) bidomain hot path.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, deliberately
+unoptimised restatement of the method in NumPy/SciPy double precision.  It is
+used by the test-suite, by the smoke check and by the CPU-baseline leg of the
+benchmark, and by nothing else: the product path (the HIP library and its
+Python binding) never imports, links or calls it, and it shares no code with
+that path.  Inputs come from plain descriptors (see
+``paper_2104_05024_amd.workloads``), passed in by the caller.
+
+Module map (each function cites the passage of the paper it restates):
+
+* ``geometry``  -- level sets, normals, shape operators, interface nodes,
+  grid-node classification and grid-line intersections (Sec. 6, implementation
+  paragraph; Sec. 5.3).
+* ``boxsolve``  -- the 5/7-point operator on the box and its DST-I solver
+  (Sec. 5.2, eq. FDE; end of Sec. 5.3).
+* ``kfbi``      -- density transfer, jump relations, right-hand-side
+  correction (Sec. 5.3, eq. correct), quadratic extrapolation of limit values
+  (Sec. 5.4, eqs. taylor-*, ji, je), the BIE operator and right-hand side
+  (Sec. 4, eq. bie; Algorithm 1), the Neumann solve.
+* ``gmres``     -- restarted GMRES with Givens rotations and the simple
+  (Richardson) iteration (Sec. 4, eq. simple iteration).
+* ``bidomain``  -- FitzHugh-Nagumo reaction steps, Strang splitting and the
+  implicit-midpoint diffusion step (Secs. 2-3, Sec. 7 model paragraph).
+* ``mlp``       -- the warm-start network's forward/backward pass.
+
+Parity pins for every module live in ``tests/test_oracle_*.py``.
+"""

@@ -1,0 +1,200 @@
+"""Seeded synthetic workloads: interface, grid and coefficient descriptors.
+
+This module only *describes* problems (shapes as coefficient lists, grid sizes,
+physical constants, seeded random numbers).  It holds none of the method's
+arithmetic, so both the HIP path and the FP64 CPU checker take their inputs
+from here without sharing any computation.
+
+Every interface is a union of star-shaped closed surfaces (curves in 2D)
+given in polar form  r = R(u),  u = x/|x|,
+
+    R(u) = E(u) * (1 + sum_t c_t * prod_i u_i**e_ti),
+    E(u) = (sum_i u_i**2 / a_i**2) ** (-1/2)          (ellipse / ellipsoid)
+
+``orient = +1`` puts the tissue (the "+" side) inside the surface, ``-1``
+outside it (the inner wall of a shell).  The tissue region is the
+intersection of the per-surface regions.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Surface:
+    axes: Tuple[float, ...]
+    orient: int
+    n_nodes: int
+    terms: List[Tuple[float, Tuple[int, ...]]] = field(default_factory=list)
+
+
+@dataclass
+class Interface:
+    dim: int
+    surfaces: List[Surface]
+
+    @property
+    def n_nodes(self) -> int:
+        return sum(s.n_nodes for s in self.surfaces)
+
+
+@dataclass
+class Grid:
+    dim: int
+    lo: float
+    hi: float
+    cells: int          # I intervals per axis; unknowns are the (I-1)^dim interior nodes
+
+    @property
+    def n(self) -> int:
+        return self.cells - 1
+
+    @property
+    def h(self) -> float:
+        return (self.hi - self.lo) / self.cells
+
+
+@dataclass
+class Coeffs:
+    ncomp: int
+    D: List[List[float]]      # D[c][axis]
+    kappa: float
+
+
+@dataclass
+class BidomainParams:
+    Cm: float = 1.0
+    beta: float = 1.0
+    H: float = 100.0          # FitzHugh-Nagumo: I_ion = H (q - V (V - theta)(1 - V))
+    theta: float = 0.13
+    alpha: float = 0.25       # M(V, q) = alpha V - zeta q
+    zeta: float = 1.0
+    sigma_i: float = 1.0
+    sigma_e: float = 2.0
+    newton_tol: float = 1e-10
+    newton_maxit: int = 50
+
+
+# ----------------------------------------------------------------------------- shapes
+
+def _star_terms(R0: float, A: float, L: int):
+    """Terms of (A/R0) * Re((u_x + i u_y)^L): the polar curve R0 + A cos(L t)."""
+    terms = []
+    for k in range(0, L + 1, 2):
+        c = math.comb(L, k) * (-1) ** (k // 2) * A / R0
+        terms.append((float(c), (L - k, k)))
+    return terms
+
+
+def star2d(R0=0.7, A=0.15, L=5, n_nodes=256) -> Interface:
+    return Interface(2, [Surface((R0, R0), +1, n_nodes, _star_terms(R0, A, L))])
+
+
+def circle2d(R=0.5, n_nodes=256) -> Interface:
+    return Interface(2, [Surface((R, R), +1, n_nodes, [])])
+
+
+def ellipsoid(a=0.9, b=0.7, c=0.5, n_nodes=8192) -> Interface:
+    return Interface(3, [Surface((a, b, c), +1, n_nodes, [])])
+
+
+def sphere(R=0.5, n_nodes=2048) -> Interface:
+    return Interface(3, [Surface((R, R, R), +1, n_nodes, [])])
+
+
+def perturbed_sphere(R=0.8, eps=0.1, n_nodes=32768) -> Interface:
+    """r = R (1 + eps cos(3 theta) sin(2 phi) sin^2(phi))  (theta azimuth, phi polar).
+
+    cos(3 theta) sin^3(phi) = x^3 - 3 x y^2 and sin(2 phi) = 2 sin(phi) z on the
+    unit sphere, so the perturbation is the polynomial 2 eps z (x^3 - 3 x y^2).
+    """
+    terms = [(2 * eps, (3, 0, 1)), (-6 * eps, (1, 2, 1))]
+    return Interface(3, [Surface((R, R, R), +1, n_nodes, terms)])
+
+
+def shell_noise_terms(seed=1, n_terms=8, max_degree=4, amplitude=0.08):
+    """Seeded smooth radial noise: a random polynomial in the unit vector.
+
+    ``n_terms`` monomials of total degree 1..max_degree with random signs and
+    weights, scaled so that sum |c| = amplitude (hence |noise| <= amplitude).
+    """
+    rng = np.random.default_rng(seed)
+    terms = []
+    for _ in range(n_terms):
+        deg = int(rng.integers(1, max_degree + 1))
+        cut = np.sort(rng.integers(0, deg + 1, size=2))
+        e = (int(cut[0]), int(cut[1] - cut[0]), int(deg - cut[1]))
+        terms.append([float(rng.uniform(0.3, 1.0) * rng.choice([-1.0, 1.0])), e])
+    s = sum(abs(t[0]) for t in terms)
+    return [(t[0] * amplitude / s, tuple(t[1])) for t in terms]
+
+
+def thick_shell(outer=(0.9, 0.7, 0.6), inner_scale=0.6, n_nodes=40960, seed=1) -> Interface:
+    """Closed thick shell: tissue between an outer ellipsoid and a noisy inner wall.
+
+    Nodes are split in proportion to the (noise-free) areas, i.e. 1 : inner_scale^2.
+    """
+    frac = inner_scale ** 2 / (1.0 + inner_scale ** 2)
+    n_in = int(round(n_nodes * frac))
+    n_out = n_nodes - n_in
+    inner_axes = tuple(inner_scale * a for a in outer)
+    return Interface(3, [Surface(tuple(outer), +1, n_out, []),
+                         Surface(inner_axes, -1, n_in, shell_noise_terms(seed))])
+
+
+def _radius(surface: Surface, u):
+    """Plain polar radius of a surface in direction u (workload placement only)."""
+    u = np.asarray(u, dtype=np.float64)
+    E = 1.0 / math.sqrt(sum(u[i] ** 2 / surface.axes[i] ** 2 for i in range(len(u))))
+    P = sum(c * np.prod([u[i] ** e[i] for i in range(len(u))]) for c, e in surface.terms)
+    return E * (1.0 + P)
+
+
+def stimulus_center(iface: Interface, seed=0):
+    """Seeded centre of the initial V=1 ball: inside the tissue, mid-wall for a shell."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=iface.dim)
+    u = v / np.linalg.norm(v)
+    if len(iface.surfaces) == 1:
+        r = 0.5 * _radius(iface.surfaces[0], u)
+    else:
+        r = 0.5 * (_radius(iface.surfaces[0], u) + _radius(iface.surfaces[1], u))
+    return tuple(float(x) for x in r * u)
+
+
+def box(dim, cells, lo=-1.2, hi=1.2) -> Grid:
+    return Grid(dim, lo, hi, cells)
+
+
+def scalar_coeffs(dim, sigma=1.0, kappa=400.0) -> Coeffs:
+    return Coeffs(1, [[sigma] * dim], kappa)
+
+
+def bidomain_coeffs(dim, params: BidomainParams, dt: float) -> Coeffs:
+    kappa = 2.0 * params.Cm * params.beta / dt
+    return Coeffs(2, [[params.sigma_i] * dim, [params.sigma_e] * dim], kappa)
+
+
+# ----------------------------------------------------------------------------- named configs
+
+def config(name: str):
+    """Named workloads (interface, grid, coeffs-or-params) used by tests and the bench."""
+    if name == "star2d_128":
+        return star2d(n_nodes=256), box(2, 128), scalar_coeffs(2, 1.0, 400.0)
+    if name == "ellipsoid_128":
+        return ellipsoid(n_nodes=8192), box(3, 128), scalar_coeffs(3, 1.0, 400.0)
+    if name == "psphere_256":
+        return perturbed_sphere(n_nodes=32768), box(3, 256), scalar_coeffs(3, 1.0, 400.0)
+    if name == "shell_256":
+        return thick_shell(n_nodes=40960), box(3, 256), BidomainParams()
+    if name == "ellipsoid_bidomain_128":
+        return ellipsoid(n_nodes=8192), box(3, 128), BidomainParams()
+    raise KeyError(name)
+
+
+def seeded_vector(n, seed, lo=-1.0, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, size=n)

@@ -1,0 +1,341 @@
+"""Pins for oracle.kfbi: jumps, correction, extrapolation, the BIE operator and the Neumann solve.
+
+Each test fixes the oracle against something other than itself: closed-form
+piecewise solutions, exact polynomial reproduction, Bessel-function
+eigenvalues of the single-layer operator on a circle / sphere, a dense solve
+of the assembled operator, manufactured solutions and an exact reduction of
+the coupled system to a scalar one.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import boxsolve, geometry, kfbi
+from oracle.gmres import gmres
+from paper_2104_05024_amd import workloads as W
+
+
+def fd_derivs(f, x, eps=1e-4):
+    """Gradient and Hessian of a closed-form function by central differences (test helper)."""
+    d = x.shape[1]
+    g = np.zeros((len(x), d))
+    H = np.zeros((len(x), d, d))
+    for a in range(d):
+        e = np.zeros(d)
+        e[a] = eps
+        g[:, a] = (f(x + e) - f(x - e)) / (2 * eps)
+        for b in range(d):
+            e2 = np.zeros(d)
+            e2[b] = eps
+            H[:, a, b] = (f(x + e + e2) - f(x + e - e2) - f(x - e + e2) + f(x - e - e2)) / (4 * eps * eps)
+    return g, H
+
+
+# ----------------------------------------------------------------------------- jump relations
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_jump_relations_reproduce_exact_piecewise_function(dim):
+    """u- = u+ - (r - R) w on a circle/sphere: [u] = 0, [grad u] = w n,
+    [Hess u] = w P/R + n grad w^T + grad w n^T; with psi = sigma w, g = sigma P grad w
+    and [f] = -sigma tr[Hess u] the relations must reproduce [Hess u] exactly."""
+    R, sigma = 0.6, 1.7
+    surf = W.Surface((R,) * dim, +1, 10, [])
+    u = geometry.node_directions(dim, 37)
+    x = R * u
+    n, Wm = geometry.normal_and_shape(surf, x)
+    wf = lambda p: np.cos(p[:, 0] + 2 * p[:, 1]) + 0.3 * p[:, -1] ** 2
+    w = wf(x)
+    gw, _ = fd_derivs(wf, x, 1e-5)
+    P = np.eye(dim)[None] - n[:, :, None] * n[:, None, :]
+    Ht = w[:, None, None] * P / R + n[:, :, None] * gw[:, None, :] + gw[:, :, None] * n[:, None, :]
+    gsurf = np.einsum("nij,nj->ni", P, gw)
+    fj = -sigma * np.trace(Ht, axis1=1, axis2=2)
+    du, H = kfbi.jump_relations(sigma * w, sigma * gsurf, n, Wm, sigma, fjump=fj)
+    np.testing.assert_allclose(du, w[:, None] * n, atol=1e-13)
+    np.testing.assert_allclose(H, Ht, atol=1e-8)
+
+
+# ----------------------------------------------------------------------------- correction (P3)
+
+def _piecewise(dim):
+    L = 2.4
+    if dim == 2:
+        A = lambda x: np.exp(x[:, 0]) * np.sin(np.pi * x[:, 1]) + x[:, 0] ** 2
+        B = lambda x: np.sin(np.pi * (x[:, 0] + 1.2) / L) * np.sin(np.pi * (x[:, 1] + 1.2) / L) \
+            * np.cos(x[:, 0] + 0.5 * x[:, 1])
+    else:
+        A = lambda x: np.sin(x[:, 0]) * np.cos(x[:, 1]) * np.exp(x[:, 2]) + x[:, 2] ** 2
+        B = lambda x: np.prod(np.sin(np.pi * (x + 1.2) / L), axis=1) * np.cos(x[:, 0] - x[:, 2])
+    return A, B
+
+
+def _interface_problem_error(iface, grid, sigma, kappa):
+    A, B = _piecewise(grid.dim)
+    co = W.scalar_coeffs(grid.dim, sigma, kappa)
+    P = kfbi.Problem(iface, grid, co)
+    pts = geometry.grid_points(grid)
+
+    def src(F, x):
+        _, H = fd_derivs(F, x)
+        return -sigma * np.trace(H, axis1=1, axis2=2) + kappa * F(x)
+
+    f = np.where(P.inside, src(A, pts), src(B, pts))
+    cr = P.cross
+    gA, HA = fd_derivs(A, cr.z)
+    gB, HB = fd_derivs(B, cr.z)
+    ar = np.arange(cr.count)
+    rhs = f + P.correction([sigma] * grid.dim, A(cr.z) - B(cr.z), (gA - gB)[ar, cr.axis],
+                           (HA - HB)[ar, cr.axis, cr.axis])
+    u = boxsolve.box_solve(rhs[None], grid, co)[0]
+    exact = np.where(P.inside, A(pts), B(pts))
+    return np.max(np.abs(u - exact)), np.max(np.abs(boxsolve.box_solve(f[None], grid, co)[0] - exact))
+
+
+def test_correction_gives_second_order_2d():
+    errs = []
+    for I in (32, 64, 128):
+        e, e_uncorr = _interface_problem_error(W.star2d(n_nodes=2 * I), W.box(2, I), 1.0, 400.0)
+        errs.append(e)
+        assert e_uncorr > 20 * e              # without the correction the error is O(1)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.7, (errs, rates)
+
+
+def test_correction_gives_second_order_3d():
+    errs = []
+    for I in (16, 32, 64):
+        e, _ = _interface_problem_error(W.ellipsoid(0.6, 0.5, 0.4, n_nodes=64), W.box(3, I), 1.3, 50.0)
+        errs.append(e)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[-1] > 1.7, (errs, rates)
+
+
+# ----------------------------------------------------------------------------- extrapolation (P4)
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_extrapolation_exact_on_piecewise_quadratics(dim):
+    """Grid data from quadratic u+ (tissue) and u- (outside) with exact node jumps: the fitted
+    grad u+ must be exact to rounding."""
+    rng = np.random.default_rng(dim)
+    iface = W.star2d(n_nodes=64) if dim == 2 else W.ellipsoid(n_nodes=300)
+    grid = W.box(dim, 32 if dim == 2 else 24)
+    P = kfbi.Problem(iface, grid, W.scalar_coeffs(dim, 1.0, 1.0))
+    cp, cm = rng.normal(size=(2, 1 + dim + dim * dim))
+
+    def quad(c):
+        def f(x):
+            v = c[0] + x @ c[1:1 + dim]
+            Q = c[1 + dim:].reshape(dim, dim)
+            return v + np.einsum("na,ab,nb->n", x, Q, x)
+        return f
+
+    up, um = quad(cp), quad(cm)
+    pts = geometry.grid_points(grid)
+    u = np.where(P.inside, up(pts), um(pts))
+    q = P.nodes.X
+    Qp, Qm = cp[1 + dim:].reshape(dim, dim), cm[1 + dim:].reshape(dim, dim)
+    gp = cp[1:1 + dim][None] + q @ (Qp + Qp.T)
+    gm = cm[1:1 + dim][None] + q @ (Qm + Qm.T)
+    Hj = np.broadcast_to((Qp + Qp.T) - (Qm + Qm.T), (P.M, dim, dim))
+    D = [1.0] * dim
+    out = P.extrapolate(u, D, up(q) - um(q), gp - gm, Hj)
+    np.testing.assert_allclose(out, np.sum(P.nodes.n * gp, axis=1), atol=1e-9)
+
+
+# ----------------------------------------------------------------------------- transfer
+
+def test_transfer_2d_accuracy():
+    iface = W.star2d(n_nodes=256)
+    surf = iface.surfaces[0]
+    t = np.linspace(0.01, 6.2, 50)
+    uu = np.stack([np.cos(t), np.sin(t)], 1)
+    G, _, _ = geometry.radial(surf, uu)
+    pts = G[:, None] * uu
+    idx, w, wg = kfbi.transfer_2d_points(surf, 0, 256, pts)
+    tn = 2 * np.pi * np.arange(256) / 256
+    psi = np.cos(3 * tn) + 0.5 * np.sin(tn)
+    tau, speed = geometry.curve_tangent(surf, t)
+    val = np.sum(w * psi[idx], 1)
+    grd = np.einsum("nk,nkd->nd", psi[idx], wg)
+    np.testing.assert_allclose(val, np.cos(3 * t) + 0.5 * np.sin(t), atol=2e-6)
+    dpsi = (-3 * np.sin(3 * t) + 0.5 * np.cos(t)) / speed
+    np.testing.assert_allclose(grd, dpsi[:, None] * tau, atol=2e-4)
+
+
+def test_transfer_3d_exact_for_tangent_quadratics_on_a_plane_like_patch():
+    """On a large sphere the LSQ fit recovers psi = a.x to O(h^2) and its surface gradient P_n a."""
+    R = 0.9
+    iface = W.sphere(R, n_nodes=20000)
+    nd = geometry.Nodes(iface)
+    a = np.array([0.3, -1.1, 0.7])
+    psi = nd.X @ a
+    pts = nd.X[::97]
+    idx, w0, wg = kfbi.transfer_3d(nd.X, 0, pts, nd.n[::97], 0.01)
+    val = np.sum(w0 * psi[idx], 1)
+    grd = np.einsum("nk,nkd->nd", psi[idx], wg)
+    np.testing.assert_allclose(val, pts @ a, atol=1e-5)
+    n = nd.n[::97]
+    ref = a[None] - (n @ a)[:, None] * n
+    np.testing.assert_allclose(grd, ref, atol=5e-3)
+
+
+# ----------------------------------------------------------------------------- operator (P5)
+
+def _bessel_lambda_2d(m, x):
+    return special.ivp(m, x) * special.kv(m, x) / (special.ivp(m, x) * special.kv(m, x)
+                                                    - special.iv(m, x) * special.kvp(m, x))
+
+
+def _bessel_lambda_3d(l, x):
+    i, k = special.spherical_in(l, x), special.spherical_kn(l, x)
+    ip, kp = special.spherical_in(l, x, derivative=True), special.spherical_kn(l, x, derivative=True)
+    return ip * k / (ip * k - i * kp)
+
+
+def test_golden_bessel_values():
+    """Closed-form eigenvalues stored in tests/golden (single layer on a circle/sphere, kappa=400, R=0.5)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "single_layer_eigenvalues.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    for dim, mode, x, lam in rows:
+        f = _bessel_lambda_2d if dim == "2" else _bessel_lambda_3d
+        assert abs(f(int(mode), float(x)) - float(lam)) < 5e-7
+    assert abs((1 / math.tanh(10) - 0.1) / (1 / math.tanh(10) + 1) - _bessel_lambda_3d(0, 10.0)) < 1e-14
+
+
+def test_operator_matches_bessel_eigenvalues_2d():
+    errs = {0: [], 4: []}
+    for I in (32, 64, 128):
+        iface = W.circle2d(0.5, n_nodes=2 * I)
+        P = kfbi.Problem(iface, W.box(2, I), W.scalar_coeffs(2, 2.0, 800.0))
+        t = 2 * np.pi * np.arange(P.M) / P.M
+        for m in errs:
+            psi = np.cos(m * t)
+            lam = _bessel_lambda_2d(m, math.sqrt(800.0 / 2.0) * 0.5)
+            errs[m].append(np.max(np.abs(P.apply(psi)[0] - lam * psi)))
+    for m, e in errs.items():
+        assert e[-1] < 0.01 and e[0] / e[-1] > 6.0, (m, e)
+
+
+def test_operator_matches_bessel_eigenvalues_3d():
+    errs = {0: [], 2: []}
+    for I in (32, 64):
+        h = 2.4 / I
+        M = int(round(4 * np.pi * 0.25 / (1.2 * h) ** 2))
+        P = kfbi.Problem(W.sphere(0.5, n_nodes=M), W.box(3, I), W.scalar_coeffs(3, 1.0, 100.0))
+        X = P.nodes.X / 0.5
+        for l in errs:
+            psi = np.ones(P.M) if l == 0 else 3 * X[:, 2] ** 2 - 1
+            lam = _bessel_lambda_3d(l, 10.0 * 0.5)
+            e = P.apply(psi)[0] - lam * psi
+            errs[l].append(np.sqrt(np.mean(e ** 2)))
+    for l, e in errs.items():
+        assert e[-1] < 0.02 and e[0] / e[-1] > 2.4, (l, e)
+
+
+# ----------------------------------------------------------------------------- GMRES vs dense (P6)
+
+def test_gmres_matches_dense_solve_of_assembled_operator():
+    P = kfbi.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.scalar_coeffs(2, 1.0, 400.0))
+    M = P.M
+    A = np.stack([P.apply(e)[0] for e in np.eye(M)], axis=1)
+    g = np.random.default_rng(0).normal(size=M)
+    ref = np.linalg.solve(A, g)
+    psi, info = gmres(lambda v: P.apply(v).ravel(), g, np.zeros(M), tol=1e-13, restart=50)
+    cond = np.linalg.cond(A)
+    assert cond < 100
+    assert np.linalg.norm(psi - ref) <= 10 * 1e-13 * cond * np.linalg.norm(ref)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert sv.min() > 0.05                 # second-kind operator: spectrum bounded away from 0
+
+
+# ----------------------------------------------------------------------------- Neumann BVP (P7)
+
+def _mms_2d(I):
+    ue = lambda x: np.exp(x[:, 0]) * np.sin(np.pi * x[:, 1])
+    grad = lambda x: np.stack([ue(x), np.pi * np.exp(x[:, 0]) * np.cos(np.pi * x[:, 1])], 1)
+    P = kfbi.Problem(W.star2d(n_nodes=2 * I), W.box(2, I), W.scalar_coeffs(2, 1.0, 400.0))
+    pts = geometry.grid_points(P.grid)
+    f = (math.pi ** 2 - 1 + 400.0) * ue(pts)
+    g = np.sum(P.nodes.n * grad(P.nodes.X), 1)
+    u, psi, info = P.solve_neumann(g[None], f[None], tol=1e-10)
+    e = np.abs(u[0] - ue(pts))[P.inside]
+    return np.sqrt(np.mean(e * e)), e.max(), info, psi, P
+
+
+def test_neumann_mms_second_order_2d_and_flat_iterations():
+    res = [_mms_2d(I) for I in (64, 128, 256)]
+    l2 = [r[0] for r in res]
+    mx = [r[1] for r in res]
+    its = [r[2]["iters"] for r in res]
+    assert math.log2(l2[0] / l2[1]) > 1.8 and math.log2(l2[1] / l2[2]) > 1.8, l2
+    assert math.log2(mx[0] / mx[2]) / 2 > 1.7, mx
+    assert max(its) - min(its) <= 3 and max(its) <= 15, its
+    for r in res:
+        assert r[2]["rel_resid"] <= 1e-10
+
+
+def test_neumann_mms_3d_ellipsoid():
+    ue = lambda x: np.sin(x[:, 0]) * np.cos(x[:, 1]) * np.exp(x[:, 2])
+
+    def grad(x):
+        s, c, e = np.sin(x[:, 0]), np.cos(x[:, 1]), np.exp(x[:, 2])
+        return np.stack([np.cos(x[:, 0]) * c * e, -s * np.sin(x[:, 1]) * e, s * c * e], 1)
+
+    errs = []
+    for I in (32, 64):
+        P = kfbi.Problem(W.ellipsoid(n_nodes=int(8192 * (I / 128) ** 2)), W.box(3, I),
+                         W.scalar_coeffs(3, 1.0, 400.0))
+        pts = geometry.grid_points(P.grid)
+        f = 401.0 * ue(pts)
+        g = np.sum(P.nodes.n * grad(P.nodes.X), 1)
+        u, _, info = P.solve_neumann(g[None], f[None], tol=1e-10)
+        e = np.abs(u[0] - ue(pts))[P.inside]
+        errs.append(np.sqrt(np.mean(e * e)))
+        assert info["iters"] <= 15
+    assert math.log2(errs[0] / errs[1]) > 1.8, errs
+
+
+def test_flux_balance_scalar():
+    """kappa * int_Omega u = int_Omega f for -Delta u + kappa u = f, du/dn = 0 (integrate the PDE).
+    Node-sum quadrature over the tissue nodes: the relative defect is at quadrature level."""
+    defects = []
+    for I in (64, 128, 256):
+        P = kfbi.Problem(W.star2d(n_nodes=2 * I), W.box(2, I), W.scalar_coeffs(2, 1.0, 400.0))
+        pts = geometry.grid_points(P.grid)
+        f = 1.0 + pts[:, 0] ** 2 + 0.5 * pts[:, 1]
+        u, _, _ = P.solve_neumann(np.zeros((1, P.M)), f[None], tol=1e-12)
+        lhs = 400.0 * np.sum(u[0][P.inside])
+        rhs = np.sum(f[P.inside])
+        defects.append(abs(lhs - rhs) / abs(rhs))
+    assert max(defects) < 2e-4, defects        # an O(1) defect would mean a wrong flux
+
+
+# ----------------------------------------------------------------------------- coupled <-> scalar (P10)
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coupled_matches_scalar_reduction(dim):
+    """Isotropic sigma_i, sigma_e: V = Phi_i - Phi_e of the coupled solve solves the scalar problem
+    -Delta V + kappa (1/sigma_i + 1/sigma_e) V = f_i/sigma_i - f_e/sigma_e, dV/dn = g_i/sigma_i - g_e/sigma_e."""
+    si, se, kap = 1.0, 2.0, 200.0
+    if dim == 2:
+        iface, grid = W.star2d(n_nodes=128), W.box(2, 64)
+    else:
+        iface, grid = W.ellipsoid(n_nodes=512), W.box(3, 32)
+    Pc = kfbi.Problem(iface, grid, W.Coeffs(2, [[si] * dim, [se] * dim], kap))
+    Ps = kfbi.Problem(iface, grid, W.Coeffs(1, [[1.0] * dim], kap * (1 / si + 1 / se)))
+    pts = geometry.grid_points(grid)
+    V0 = np.exp(-20 * np.sum((pts - 0.1) ** 2, axis=1))
+    f = np.stack([kap * V0, -kap * V0])
+    g = np.zeros((2, Pc.M))
+    uc, _, _ = Pc.solve_neumann(g, f, tol=1e-13)
+    us, _, _ = Ps.solve_neumann(g[:1], (f[0] / si - f[1] / se)[None], tol=1e-13)
+    Vc = uc[0] - uc[1]
+    assert np.max(np.abs(Vc - us[0])[Pc.inside]) <= 1e-9 * np.max(np.abs(us[0]))
+    # the coupled operator itself maps psi to the scalar operator on psi_i/si - psi_e/se
+    psi = np.random.default_rng(1).normal(size=(2, Pc.M))
+    Ac = Pc.apply(psi)
+    As = Ps.apply(psi[0] / si - psi[1] / se)[0]
+    np.testing.assert_allclose(Ac[0] / si - Ac[1] / se, As, atol=1e-10 * np.max(np.abs(As)))
