@@ -1,0 +1,227 @@
+/*
+ * kfbi.h -- C ABI of the MI355X kernel-free boundary integral (KFBI) library.
+ *
+ * Method: A Kernel-free Boundary Integral Method for the Bidomain Equations
+ * (Gao, Cai, Henriquez, Ying).  The library solves the Neumann boundary value
+ * problem of the bidomain diffusion step (Sec. 3, eqs. pde1, bvp, BC)
+ *
+ *     -div(D_c grad u_c) + (K u)_c = f_c   in Omega,    n . D_c grad u_c = g_c  on dOmega,
+ *
+ * K = kappa (one component) or kappa [[1,-1],[-1,1]] (intra/extracellular pair),
+ * by the boundary integral equation A psi = g' of Sec. 4 (eq. bie) whose
+ * operator A is applied without a Green's function (Sec. 5, Algorithm 1):
+ * jump data from psi -> right-hand-side correction at irregular grid nodes ->
+ * fast DST-I box solve -> quadratic extrapolation of n.D grad u+ at the
+ * interface nodes.  Sign convention: the positive form above; the paper's
+ * right-hand side is -f.
+ *
+ * Conventions for every call
+ *  - Return value: KFBI_OK (0) or a negative KFBI_E* code; kfbi_strerror()
+ *    gives text and kfbi_last_error() a message for the calling thread.
+ *  - Grid arrays hold the (I-1)^d interior nodes of the box [lo,hi]^d with
+ *    I = cells intervals per axis, C order [comp][z][y][x] (x fastest), no
+ *    padding; u = 0 on the box boundary is implied.
+ *  - Interface arrays are [comp][M], nodes in descriptor order (surface 0
+ *    first).  Node j of a 2D curve sits at polar angle 2 pi j / M; 3D nodes
+ *    follow the spherical Fibonacci lattice z_j = 1 - (2j+1)/M, azimuth
+ *    j pi (3 - sqrt 5), mapped radially onto the surface.
+ *  - "device" pointers are HIP device allocations owned by the caller; the
+ *    library never frees them.  `stream` is a hipStream_t (NULL = default).
+ *    Calls are stream-ordered; outputs are valid once the stream has drained.
+ *  - A kfbi_problem / bidomain_ctx is not thread-safe; distinct handles are
+ *    independent.  All library workspace is allocated in kfbi_setup /
+ *    bidomain_create and released by the matching destroy call.
+ */
+#ifndef KFBI_H
+#define KFBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KFBI_OK = 0,
+  KFBI_EINVAL = -1,   /* bad argument: null pointer, dtype, NaN, size out of range      */
+  KFBI_EGEOM = -2,    /* geometry: interface within 3h of the box, an arm crossed twice, */
+                      /* a rank-deficient extrapolation stencil                           */
+  KFBI_ENOCONV = -3,  /* the iteration hit max_iters; outputs hold the last iterate       */
+  KFBI_EHIP = -4,     /* HIP runtime error                                                 */
+  KFBI_ENOMEM = -5,   /* host or device allocation failed                                  */
+  KFBI_ENODEV = -6    /* the call needs a GPU but the problem was set up host-only         */
+};
+
+enum { KFBI_F64 = 0, KFBI_F32 = 1 };
+
+#define KFBI_MAX_SURFACES 2
+#define KFBI_MAX_TERMS 16
+
+/* One closed star-shaped surface (curve in 2D) in polar form r = R(u), u = x/|x|:
+ *   R(u) = (sum_i u_i^2/axes_i^2)^(-1/2) * (1 + sum_t coef[t] prod_i u_i^exps[t][i]).
+ * orient = +1: the tissue Omega is inside; -1: outside (inner wall of a shell).
+ * n_nodes interface nodes are placed on it (Sec. 6, quasi-uniform nodes). */
+typedef struct {
+  double axes[3];
+  int32_t orient;
+  int32_t n_terms;
+  int64_t n_nodes;
+  double coef[KFBI_MAX_TERMS];
+  int32_t exps[KFBI_MAX_TERMS][3];
+} kfbi_surface;
+
+/* Omega = intersection of the per-surface regions (Sec. 4: Omega inside the box B). */
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int32_t n_surfaces;   /* 1 or 2 */
+  kfbi_surface surf[KFBI_MAX_SURFACES];
+} kfbi_interface;
+
+/* The box B = [lo,hi]^dim with `cells` intervals per axis (Sec. 5.2); the GPU path
+ * requires cells to be a power of two in [16, 1024]. */
+typedef struct {
+  int32_t dim;
+  int32_t cells;
+  double lo, hi;
+} kfbi_grid;
+
+/* ncomp = 1: -div(D[0] grad u) + kappa u;  ncomp = 2: the coupled pair of eq. bvp.
+ * D[c][axis] must be isotropic per component (D[c][0] = D[c][1] = D[c][2]). */
+typedef struct {
+  int32_t ncomp;
+  int32_t pad_;
+  double D[2][3];
+  double kappa;
+} kfbi_coeffs;
+
+typedef struct kfbi_problem_s *kfbi_problem;
+
+#define KFBI_SETUP_HOST_ONLY 1u   /* build the host tables only (no GPU calls) */
+
+/* kfbi_setup: build every static table of the method for (interface, grid, coeffs)
+ * -- interface nodes, normals, shape operators; grid-node sides; grid-line
+ * intersections (Sec. 6 implementation paragraph); density-transfer weights;
+ * correction records (Sec. 5.3); extrapolation stencils and weights (Sec. 5.4) --
+ * in FP64 on the host, deterministically, then (unless KFBI_SETUP_HOST_ONLY)
+ * upload them to the current HIP device and allocate all device workspace.
+ * *out receives a handle owned by the library (kfbi_destroy). */
+int kfbi_setup(const kfbi_interface *iface, const kfbi_grid *grid, const kfbi_coeffs *coeffs,
+               uint32_t flags, kfbi_problem *out);
+void kfbi_destroy(kfbi_problem p);
+
+/* Sizes: M interface nodes, N = cells-1 interior nodes per axis, crossings,
+ * irregular nodes.  Any pointer may be NULL. */
+int kfbi_query(kfbi_problem p, int64_t *M, int64_t *N, int64_t *n_crossings, int64_t *n_irregular);
+
+/* Host copy of a setup table, for inspection and parity tests.  Names:
+ * "inside"(i8,N^d) "nodes_X" "nodes_n"(f64,M*d) "nodes_W"(f64,M*d*d)
+ * "cross_axis" "cross_surf"(i64) "cross_pin" "cross_pout"(i64, linear interior index)
+ * "cross_z"(f64,nc*d) "z_idx"(i64,nc*K) "z_w0"(f64,nc*K) "z_wg"(f64,nc*K*d)
+ * "q_idx"(i64,M*Kn) "q_wg"(f64,M*Kn*d) "st_lin"(i64,M*S) "st_r" "st_wgrad"(f64,M*S*d)
+ * "irregular"(i64).  With dst == NULL only *count (elements) and *elem_bytes are set. */
+int kfbi_table(kfbi_problem p, const char *name, void *dst, int64_t *count, int32_t *elem_bytes);
+
+/* kfbi_apply: out = A psi, the KFBI matrix-vector product (Sec. 4 eq. bie left side;
+ * Algorithm 1, "boundary integral" block): jumps of the single-layer interface
+ * problem from psi (Sec. 5.1 eq. single), right-hand-side correction at irregular
+ * nodes (Sec. 5.3 eq. correct), DST-I box solve, and n.D grad u+ at the nodes by
+ * jump-corrected quadratic extrapolation (Sec. 5.4).  psi, out: device [ncomp][M]
+ * in `dtype` (KFBI_F64 or KFBI_F32: the whole product then runs in that precision). */
+int kfbi_apply(kfbi_problem p, const void *psi, void *out, int32_t dtype, void *stream);
+
+/* kfbi_box_solve: u = S f, the fast box solve alone (Sec. 5.2 eq. FDE with u = 0 on the box
+ * boundary; end of Sec. 5.3): DST-I along every axis, division by the mode eigenvalues
+ * (a closed-form 2x2 solve per mode for the coupled pair), inverse DST-I.  f, u: device
+ * [ncomp][N^d] in `dtype`; f and u may alias. */
+int kfbi_box_solve(kfbi_problem p, const void *f, void *u, int32_t dtype, void *stream);
+
+typedef struct {
+  double tol;           /* stop when ||g' - A psi||_2 <= tol ||g'||_2 (FP64 residual) */
+  int32_t restart;      /* GMRES(m) restart length, 1..64 */
+  int32_t max_iters;    /* total inner iterations */
+  int32_t precision;    /* 0: FP64 throughout; 1: FP32 inner GMRES + FP64 refinement */
+  int32_t x0;           /* 0: start from psi = 0 (Algorithm 1); 1: from psi_inout */
+  double inner_tol;     /* precision = 1: relative tolerance of each FP32 inner solve */
+  int32_t max_outer;    /* precision = 1: maximum FP64 refinement steps */
+  int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4) */
+  double gamma;         /* Richardson parameter, gamma in (0,1) */
+} kfbi_solve_opts;
+
+typedef struct {
+  int32_t iters;            /* inner iterations (FP64 or FP32) */
+  int32_t outer;            /* FP64 refinement steps (precision = 1) */
+  int32_t matvecs_fp64;
+  int32_t matvecs_fp32;
+  double rel_resid;         /* final ||g' - A64 psi|| / ||g'|| */
+  double gp_norm;           /* ||g'||_2 */
+  int32_t warm_start_used;  /* bidomain_step: 1 if the learned start was taken */
+  int32_t pad_;
+} kfbi_solve_info;
+
+/* kfbi_solve_neumann: solve the Neumann problem above (Algorithm 1 with GMRES):
+ *   u_V = box solve of f (f extended over the whole box; Sec. 5.1), g' = g - n.D grad u_V+,
+ *   A psi = g' by GMRES (FP64, or FP32-inner with FP64 refinement), u = box solve of f + C psi.
+ * For ncomp = 2 the pair is returned in the gauge mean_{Omega nodes}(u_2) = 0.
+ * g: device f64 [ncomp][M] (NULL = homogeneous); f, u: device f64 [ncomp][N^d];
+ * psi_inout: device f64 [ncomp][M], initial guess if opts->x0 = 1, solution on return.
+ * info may be NULL. Returns KFBI_ENOCONV (outputs filled) if max_iters is hit. */
+int kfbi_solve_neumann(kfbi_problem p, const double *g, const double *f, double *u,
+                       double *psi_inout, const kfbi_solve_opts *opts, kfbi_solve_info *info,
+                       void *stream);
+
+/* ----------------------------------------------------------------- bidomain */
+
+typedef struct {
+  double Cm, beta;                  /* membrane capacitance, surface-to-volume ratio */
+  double H, theta, alpha, zeta;     /* FitzHugh-Nagumo (Sec. 7): I_ion = H(q - V(V-theta)(1-V)),
+                                       dq/dt = alpha V - zeta q */
+  double newton_tol;                /* |F| tolerance of the backward-Euler Newton solve */
+  int32_t newton_maxit;
+  int32_t warm_start;               /* 0: psi^{n-1}; 1: learned (MLP) start with fallback; 2: zero */
+  kfbi_solve_opts solve;            /* diffusion solve options (tol, precision, ...) */
+} bidomain_params;
+
+typedef struct bidomain_s *bidomain_ctx;
+
+/* The coupled problem passed here must have ncomp = 2, isotropic sigma_i, sigma_e and
+ * kappa = 2 Cm beta / dt for the dt later given to bidomain_step. */
+int bidomain_create(kfbi_problem p, const bidomain_params *params, bidomain_ctx *out);
+void bidomain_destroy(bidomain_ctx b);
+
+/* State, all device f64, caller-owned: V, q: [N^d] (membrane potential and gate on every
+ * box node); phi: [2][N^d] output potentials (Phi_i, Phi_e) of the diffusion solve, may be
+ * NULL; psi_hist: [2][2][M] densities of the last two steps (slot 0 = newest), updated. */
+typedef struct {
+  double *V, *q, *phi, *psi_hist;
+} bidomain_state;
+
+/* bidomain_step: one Strang step (Sec. 3, eqs. ode1, diffusion, ode2): forward-Euler
+ * reaction over dt/2, implicit-midpoint diffusion over dt (backward Euler over dt/2 for
+ * w, then V <- 2 w_V - V), backward-Euler reaction over dt/2 solved by Newton. */
+int bidomain_step(bidomain_ctx b, bidomain_state *state, double dt, kfbi_solve_info *info,
+                  void *stream);
+
+/* Learned warm start (not in the paper): a per-node MLP (3 tanh layers of 128, BF16
+ * weights with FP32 accumulation) predicting a correction to 2 psi^{n-1} - psi^{n-2}.
+ * bidomain_record_sample stores (features, target) of the step just taken into a
+ * device ring of up to `capacity` steps; bidomain_train runs `epochs` passes of Adam
+ * (lr) over the stored samples on the GPU and returns the last mean loss. */
+int bidomain_mlp_init(bidomain_ctx b, int32_t capacity, uint64_t seed);
+int bidomain_train(bidomain_ctx b, int32_t epochs, double lr, double *loss_out, void *stream);
+int bidomain_mlp_params(bidomain_ctx b, float *host_dst, int64_t *count);
+
+/* ----------------------------------------------------------------- utilities */
+
+const char *kfbi_strerror(int code);
+const char *kfbi_last_error(void);
+
+/* Timing of the last kfbi_apply / box solve launches on the problem's stream, measured
+ * with HIP events: per-kernel average microseconds for the named kernel class
+ * ("dst_x", "dst_y", "dst_last", "correct", "gather", "jumps"). Returns KFBI_EINVAL if unknown. */
+int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
+int kfbi_profile(kfbi_problem p, int32_t enable);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFBI_H */

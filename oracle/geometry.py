@@ -213,7 +213,9 @@ def check_box_clearance(iface, grid, margin_cells=3):
 
 
 def _root_on_arm(surf, p, axis, h, iters=80):
-    """Safeguarded Newton for phi(p + t h e_axis) = 0, t in [0, 1], vectorised over arms."""
+    """Safeguarded Newton for phi(p + t h e_axis) = 0, t in [0, 1], vectorised over arms.
+
+    An end point with |phi| <= SIDE_TOL is taken as the crossing itself."""
     n = p.shape[0]
 
     def f(t):
@@ -225,7 +227,11 @@ def _root_on_arm(surf, p, axis, h, iters=80):
     f0, _ = f(np.zeros(n))
     f1, _ = f(np.ones(n))
     t = np.where(np.abs(f0) <= np.abs(f1), 0.0, 1.0)
-    bracket = f0 * f1 <= 0.0
+    # an end point on the boundary (|phi| <= SIDE_TOL) is the crossing itself: near such a
+    # node phi grows like t^2 along a tangent arm and the root is ill-conditioned
+    on0, on1 = np.abs(f0) <= SIDE_TOL, np.abs(f1) <= SIDE_TOL
+    t = np.where(on0, 0.0, np.where(on1, 1.0, t))
+    bracket = (f0 * f1 <= 0.0) & ~on0 & ~on1
     # orient so that f(lo) <= 0 <= f(hi)
     lo = np.where(f0 <= 0.0, 0.0, 1.0)
     hi = 1.0 - lo

@@ -1,0 +1,100 @@
+// Device-side state and kernel launchers of the KFBI library (HIP, gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "host_tables.h"
+
+namespace kfbi {
+
+struct HipError {
+  hipError_t code;
+  std::string where;
+};
+
+#define KFBI_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) throw ::kfbi::HipError{e_, #call};                  \
+  } while (0)
+
+// Grid fields inside the library use a padded layout: [comp][z][y][x] with row pitch
+// P = N + 1 (a power of two), so that every row starts on a 2 KB (FP64) boundary.
+// Caller-visible fields use the unpadded layout (pitch N).
+
+template <typename T>
+struct PrecTables {          // per-precision device copies of the numeric tables
+  T *z_w0 = nullptr, *z_wga = nullptr, *z_na = nullptr, *z_cw = nullptr;
+  T *q_wg = nullptr, *q_n = nullptr, *q_wt = nullptr;
+  T *arm_d = nullptr, *arm_s = nullptr;
+  T *st_nw = nullptr, *st_r = nullptr;
+  T *tw = nullptr, *sp = nullptr;        // DST twiddles exp(-2 pi i m/M) (complex) and sin(pi n/M)
+  T *rhs = nullptr, *work = nullptr;     // matvec right-hand side (zero off irregular nodes), work field
+  T *jz = nullptr, *jq = nullptr;        // jumps at crossings [comp][2][nc], at nodes [comp][d+nh][M]
+};
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  double total_ms = 0;
+  int64_t n = 0;
+};
+
+struct DevProblem {
+  HostTables ht;
+  bool on_device = false;
+  int dev = 0;
+  int dim = 0, ncomp = 1, Mfft = 0;
+  int64_t N = 0, M = 0, P = 0, nc = 0, nirr = 0, narm = 0;
+  int64_t comp_stride = 0;     // padded elements per component
+  int K = 0, Kn = 0, S = 0;
+  double h = 0, kappa = 0, sigma[2] = {1, 1};
+  double lam_scale = 1;        // (2/M)^d normalisation of the inverse transforms
+
+  // integer tables
+  int32_t *z_idx = nullptr, *z_axis = nullptr, *q_idx = nullptr;
+  int32_t *irr_pos = nullptr, *irr_ptr = nullptr, *arm_cross = nullptr;
+  int32_t *st_pos = nullptr;   // padded index, negative (-pos-1) for stencil nodes outside the tissue
+  int8_t *inside_pad = nullptr;  // padded-layout tissue mask
+  double *lam = nullptr;       // (4/h^2) sin^2(k pi / 2M), k = 1..N
+
+  PrecTables<double> f64;
+  PrecTables<float> f32;
+
+  // reductions / scratch
+  double *red = nullptr;       // small device scratch for dot products
+  double *host_red = nullptr;  // pinned host mirror
+
+  bool profile = false;
+  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps;
+  hipStream_t stream = nullptr;
+
+  template <typename T>
+  PrecTables<T> &tab();
+};
+
+template <>
+inline PrecTables<double> &DevProblem::tab<double>() { return f64; }
+template <>
+inline PrecTables<float> &DevProblem::tab<float>() { return f32; }
+
+// ---- launchers (defined in dst.hip / kfbi_kernels.hip)
+// Box solve: dst = S(src). Layout flags: true = caller (unpadded) layout, false = padded.
+template <typename T>
+void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st);
+
+template <typename T>
+void launch_jumps(DevProblem &p, const T *psi, hipStream_t st);
+template <typename T>
+void launch_correct(DevProblem &p, hipStream_t st);
+template <typename T>
+void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream_t st);
+template <typename T>
+void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st);
+
+void upload_tables(DevProblem &p);
+void free_tables(DevProblem &p);
+
+}  // namespace kfbi

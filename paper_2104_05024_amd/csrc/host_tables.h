@@ -1,0 +1,51 @@
+// Host-side static tables of one KFBI problem (FP64).  Built once by kfbi_setup.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kfbi.h"
+
+namespace kfbi {
+
+constexpr double kSideTol = 1e-12;   // grid nodes with phi <= kSideTol lie in the tissue
+constexpr double kTieTol = 1e-9;     // squared-distance ties (units of h^2) in stencil ranking
+constexpr double kRankTol = 1e-6;    // relative residual for accepting a stencil node
+constexpr int kLsqNodes = 10;        // nodes of the 3D least-squares density fit
+
+struct GeometryError {
+  std::string what;
+};
+
+struct HostTables {
+  int dim = 0, ncomp = 1, cells = 0;
+  int64_t N = 0, M = 0;
+  double lo = 0, hi = 0, h = 0, kappa = 0;
+  double D[2][3] = {{0}};
+  std::vector<kfbi_surface> surf;
+  std::vector<int64_t> offsets;            // first node of each surface (+ total)
+
+  std::vector<double> X, nrm, W;           // nodes: M*d, M*d, M*d*d
+  std::vector<int8_t> inside;              // N^d, 1 = tissue
+
+  int64_t nc = 0;                          // grid-line intersections
+  std::vector<int64_t> c_surf, c_axis, c_pin, c_pout;
+  std::vector<double> c_z, c_n, c_W;       // nc*d, nc*d, nc*d*d
+
+  int K = 0, Kn = 0;                       // transfer stencil sizes (crossings / nodes)
+  std::vector<int64_t> z_idx, q_idx;       // nc*K, M*Kn
+  std::vector<double> z_w0, z_wg, q_wg;    // nc*K, nc*K*d, M*Kn*d
+
+  int S = 0;                               // extrapolation stencil size (6 / 10)
+  std::vector<int64_t> st_lin;             // M*S linear interior index
+  std::vector<double> st_r, st_wgrad;      // M*S*d (physical offsets p_j - q), gradient weights
+  std::vector<int8_t> st_chi;              // M*S, 1 = stencil node outside the tissue
+
+  std::vector<int64_t> irregular;          // sorted linear indices
+};
+
+// Throws GeometryError on geometric failure, std::invalid_argument on bad input.
+void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const kfbi_coeffs &co,
+                       HostTables &t);
+
+}  // namespace kfbi

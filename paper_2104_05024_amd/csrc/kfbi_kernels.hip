@@ -1,0 +1,479 @@
+// Interface-side kernels of the KFBI matrix-vector product and the table upload.
+//
+//  k_jumps_cross : density -> jumps [u_a], [u_aa] at every grid-line intersection
+//                  (single-layer interface problem, Sec. 5.1 eq. single; jump relations
+//                  from [u] = 0 and [n.D grad u] = psi for isotropic D_c).
+//  k_jumps_nodes : density -> [grad u] and [Hess u] at every interface node.
+//  k_correct     : right-hand-side correction at irregular grid nodes (Sec. 5.3, eq.
+//                  correct): rhs_p = D_c sum_arms s_p/h^2 ([u_a] d + [u_aa] d^2 / 2).
+//                  One thread owns one irregular node, so no atomics are needed.
+//  k_gather      : n.D grad u+ at every interface node from its 6/10-node quadratic fit,
+//                  adding the Taylor-expanded jump to values on the "-" side
+//                  (Sec. 5.4, eqs. taylor-i-po, taylor-i-co, ji).
+#include <cmath>
+#include <stdexcept>
+
+#include "device.h"
+
+namespace kfbi {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc, int K,
+                                                        const int32_t *__restrict__ z_idx,
+                                                        const T *__restrict__ z_w0, const T *__restrict__ z_wga,
+                                                        const T *__restrict__ z_na, const T *__restrict__ z_cw,
+                                                        int ncomp, T is0, T is1, T *__restrict__ jz) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  T p0 = 0, g0 = 0, p1 = 0, g1 = 0;
+  for (int k = 0; k < K; ++k) {
+    const int32_t j = z_idx[k * nc + c];
+    const T w = z_w0[k * nc + c], wg = z_wga[k * nc + c];
+    const T a = psi[j];
+    p0 += w * a;
+    g0 += wg * a;
+    if (ncomp == 2) {
+      const T b = psi[M + j];
+      p1 += w * b;
+      g1 += wg * b;
+    }
+  }
+  const T na = z_na[c], cw = z_cw[c];
+  {
+    const T a = p0 * is0;
+    jz[c] = a * na;
+    jz[nc + c] = a * cw + (T)2 * na * g0 * is0;
+  }
+  if (ncomp == 2) {
+    const T a = p1 * is1;
+    jz[2 * nc + c] = a * na;
+    jz[3 * nc + c] = a * cw + (T)2 * na * g1 * is1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t *__restrict__ irr_pos,
+                                                    const int32_t *__restrict__ irr_ptr,
+                                                    const int32_t *__restrict__ arm_cross,
+                                                    const T *__restrict__ arm_d, const T *__restrict__ arm_s,
+                                                    const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
+                                                    T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nirr) return;
+  T a0 = 0, a1 = 0;
+  for (int32_t j = irr_ptr[r]; j < irr_ptr[r + 1]; ++j) {
+    const int32_t c = arm_cross[j];
+    const T d = arm_d[j], s = arm_s[j];
+    a0 += s * (jz[c] * d + (T)0.5 * jz[nc + c] * d * d);
+    if (ncomp == 2) a1 += s * (jz[2 * nc + c] * d + (T)0.5 * jz[3 * nc + c] * d * d);
+  }
+  const int64_t pos = irr_pos[r];
+  if (accumulate) {
+    rhs[pos] += D0 * a0;
+    if (ncomp == 2) rhs[comp_stride + pos] += D1 * a1;
+  } else {
+    rhs[pos] = D0 * a0;
+    if (ncomp == 2) rhs[comp_stride + pos] = D1 * a1;
+  }
+}
+
+template <int D>
+struct NH {
+  static constexpr int v = D == 2 ? 3 : 6;   // symmetric entries: xx yy (zz) xy (xz yz)
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void sym_index(int e, int &a, int &b) {
+  if (D == 2) {
+    const int A[3] = {0, 1, 0}, B[3] = {0, 1, 1};
+    a = A[e];
+    b = B[e];
+  } else {
+    const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+    a = A[e];
+    b = B[e];
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M, int Kn,
+                                                        const int32_t *__restrict__ q_idx,
+                                                        const T *__restrict__ q_wg, const T *__restrict__ q_n,
+                                                        const T *__restrict__ q_wt, int ncomp, T is0, T is1,
+                                                        T *__restrict__ jq) {
+  constexpr int NHv = NH<D>::v, STR = D + NHv;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M) return;
+  T n[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) n[a] = q_n[a * M + q];
+  for (int comp = 0; comp < ncomp; ++comp) {
+    const T *ps = psi + comp * M;
+    const T is = comp == 0 ? is0 : is1;
+    T g[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) g[a] = 0;
+    for (int k = 0; k < Kn; ++k) {
+      const T v = ps[q_idx[k * M + q]];
+#pragma unroll
+      for (int a = 0; a < D; ++a) g[a] += q_wg[(k * D + a) * M + q] * v;
+    }
+    const T amp = ps[q] * is;
+    T *o = jq + (int64_t)comp * STR * M;
+#pragma unroll
+    for (int a = 0; a < D; ++a) o[a * M + q] = amp * n[a];
+#pragma unroll
+    for (int e = 0; e < NHv; ++e) {
+      int a, b;
+      sym_index<T, D>(e, a, b);
+      o[(D + e) * M + q] = amp * q_wt[e * M + q] + (n[a] * g[b] + g[a] * n[b]) * is;
+    }
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M, int S,
+                                                   const int32_t *__restrict__ st_pos,
+                                                   const T *__restrict__ st_nw, const T *__restrict__ st_r,
+                                                   const T *__restrict__ jq, int ncomp, T s0, T s1, int with_jumps,
+                                                   T *__restrict__ out) {
+  constexpr int NHv = NH<D>::v, STR = D + NHv;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M) return;
+  for (int comp = 0; comp < ncomp; ++comp) {
+    const T *uc = u + comp * comp_stride;
+    const T *o = jq + (int64_t)comp * STR * M;
+    T du[D], H[D][D];
+    if (with_jumps) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) du[a] = o[a * M + q];
+#pragma unroll
+      for (int e = 0; e < NHv; ++e) {
+        int a, b;
+        sym_index<T, D>(e, a, b);
+        H[a][b] = H[b][a] = o[(D + e) * M + q];
+      }
+    }
+    T acc = 0;
+    for (int j = 0; j < S; ++j) {
+      const int32_t pe = st_pos[j * M + q];
+      const bool chi = pe < 0;
+      const int64_t pos = chi ? (int64_t)(-pe - 1) : (int64_t)pe;
+      T val = uc[pos];
+      if (with_jumps && chi) {
+        T r[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) r[a] = st_r[(j * D + a) * M + q];
+        T J = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          T hr = 0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) hr += H[a][b] * r[b];
+          J += r[a] * (du[a] + (T)0.5 * hr);
+        }
+        val += J;
+      }
+      acc += st_nw[j * M + q] * val;
+    }
+    out[comp * M + q] = (comp == 0 ? s0 : s1) * acc;
+  }
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+T *dalloc(size_t n) {
+  T *p = nullptr;
+  if (n == 0) n = 1;
+  KFBI_HIP(hipMalloc(&p, n * sizeof(T)));
+  return p;
+}
+template <typename T>
+T *dupload(const std::vector<T> &v) {
+  T *p = dalloc<T>(v.size());
+  if (!v.empty()) KFBI_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+template <typename T>
+void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_w0, const std::vector<double> &z_wga,
+                 const std::vector<double> &z_na, const std::vector<double> &z_cw, const std::vector<double> &q_wg,
+                 const std::vector<double> &q_n, const std::vector<double> &q_wt, const std::vector<double> &arm_d,
+                 const std::vector<double> &arm_s, const std::vector<double> &st_nw, const std::vector<double> &st_r,
+                 const std::vector<double> &tw, const std::vector<double> &sp) {
+  tb.z_w0 = dupload(cast_vec<T>(z_w0));
+  tb.z_wga = dupload(cast_vec<T>(z_wga));
+  tb.z_na = dupload(cast_vec<T>(z_na));
+  tb.z_cw = dupload(cast_vec<T>(z_cw));
+  tb.q_wg = dupload(cast_vec<T>(q_wg));
+  tb.q_n = dupload(cast_vec<T>(q_n));
+  tb.q_wt = dupload(cast_vec<T>(q_wt));
+  tb.arm_d = dupload(cast_vec<T>(arm_d));
+  tb.arm_s = dupload(cast_vec<T>(arm_s));
+  tb.st_nw = dupload(cast_vec<T>(st_nw));
+  tb.st_r = dupload(cast_vec<T>(st_r));
+  tb.tw = dupload(cast_vec<T>(tw));
+  tb.sp = dupload(cast_vec<T>(sp));
+  const size_t field = (size_t)p.ncomp * p.comp_stride;
+  tb.rhs = dalloc<T>(field);
+  tb.work = dalloc<T>(field);
+  KFBI_HIP(hipMemset(tb.rhs, 0, field * sizeof(T)));
+  KFBI_HIP(hipMemset(tb.work, 0, field * sizeof(T)));
+  const int nh = p.dim == 2 ? 3 : 6;
+  tb.jz = dalloc<T>((size_t)p.ncomp * 2 * std::max<int64_t>(p.nc, 1));
+  tb.jq = dalloc<T>((size_t)p.ncomp * (p.dim + nh) * p.M);
+}
+
+template <typename T>
+void free_prec(PrecTables<T> &tb) {
+  T **all[] = {&tb.z_w0, &tb.z_wga, &tb.z_na, &tb.z_cw, &tb.q_wg, &tb.q_n, &tb.q_wt, &tb.arm_d, &tb.arm_s,
+               &tb.st_nw, &tb.st_r, &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.jz, &tb.jq};
+  for (T **q : all) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_jumps(DevProblem &p, const T *psi, hipStream_t st) {
+  PrecTables<T> &tb = p.tab<T>();
+  const T is0 = (T)(1.0 / p.sigma[0]), is1 = (T)(1.0 / p.sigma[1]);
+  if (p.nc > 0) {
+    if (p.dim == 2)
+      k_jumps_cross<T, 2><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.K, p.z_idx, tb.z_w0, tb.z_wga, tb.z_na,
+                                                        tb.z_cw, p.ncomp, is0, is1, tb.jz);
+    else
+      k_jumps_cross<T, 3><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.K, p.z_idx, tb.z_w0, tb.z_wga, tb.z_na,
+                                                        tb.z_cw, p.ncomp, is0, is1, tb.jz);
+    KFBI_HIP(hipGetLastError());
+  }
+  if (p.dim == 2)
+    k_jumps_nodes<T, 2><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.Kn, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt, p.ncomp,
+                                                     is0, is1, tb.jq);
+  else
+    k_jumps_nodes<T, 3><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.Kn, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt, p.ncomp,
+                                                     is0, is1, tb.jq);
+  KFBI_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void correct_into(DevProblem &p, T *field, int accumulate, hipStream_t st) {
+  PrecTables<T> &tb = p.tab<T>();
+  if (p.nirr == 0) return;
+  k_correct<T><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s, tb.jz,
+                                               p.nc, p.ncomp, (T)p.sigma[0], (T)p.sigma[1], field, p.comp_stride,
+                                               accumulate);
+  KFBI_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_correct(DevProblem &p, hipStream_t st) {
+  correct_into<T>(p, p.tab<T>().rhs, 0, st);
+}
+
+template <typename T>
+void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st) {
+  correct_into<T>(p, field_padded, 1, st);
+}
+
+template <typename T>
+void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream_t st) {
+  PrecTables<T> &tb = p.tab<T>();
+  const T s0 = (T)p.sigma[0], s1 = (T)p.sigma[1];
+  if (p.dim == 2)
+    k_gather<T, 2><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.S, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
+                                                p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
+  else
+    k_gather<T, 3><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.S, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
+                                                p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
+  KFBI_HIP(hipGetLastError());
+}
+
+template void launch_jumps<double>(DevProblem &, const double *, hipStream_t);
+template void launch_jumps<float>(DevProblem &, const float *, hipStream_t);
+template void launch_correct<double>(DevProblem &, hipStream_t);
+template void launch_correct<float>(DevProblem &, hipStream_t);
+template void launch_add_correction<double>(DevProblem &, double *, hipStream_t);
+template void launch_add_correction<float>(DevProblem &, float *, hipStream_t);
+template void launch_gather<double>(DevProblem &, const double *, bool, double *, hipStream_t);
+template void launch_gather<float>(DevProblem &, const float *, bool, float *, hipStream_t);
+
+void upload_tables(DevProblem &p) {
+  const HostTables &t = p.ht;
+  const int d = t.dim;
+  p.dim = d;
+  p.ncomp = t.ncomp;
+  p.N = t.N;
+  p.M = t.M;
+  p.Mfft = t.cells;
+  p.P = t.cells;
+  p.comp_stride = p.P * (d == 3 ? p.N * p.N : p.N);
+  p.nc = t.nc;
+  p.nirr = (int64_t)t.irregular.size();
+  p.K = t.K;
+  p.Kn = t.Kn;
+  p.S = t.S;
+  p.h = t.h;
+  p.kappa = t.kappa;
+  p.sigma[0] = t.D[0][0];
+  p.sigma[1] = t.ncomp == 2 ? t.D[1][0] : t.D[0][0];
+  p.lam_scale = 1.0;
+  for (int a = 0; a < d; ++a) p.lam_scale *= 2.0 / (double)t.cells;
+  const int64_t N = p.N, M = p.M, nc = p.nc, P = p.P;
+  auto padpos = [&](int64_t lin) { return (lin % N) + P * (lin / N); };
+  if (padpos(N * (d == 3 ? N * N : N) - 1) >= (int64_t)1 << 31) throw std::invalid_argument("grid too large");
+
+  // crossings (SoA)
+  std::vector<int32_t> z_idx(nc * t.K), z_axis(nc);
+  std::vector<double> z_w0(nc * t.K), z_wga(nc * t.K), z_na(nc), z_cw(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int a = (int)t.c_axis[c];
+    z_axis[c] = a;
+    const double *n = &t.c_n[c * d], *W = &t.c_W[c * d * d];
+    double tr = 0;
+    for (int b = 0; b < d; ++b) tr += W[b * d + b];
+    z_na[c] = n[a];
+    z_cw[c] = W[a * d + a] - tr * n[a] * n[a];
+    for (int k = 0; k < t.K; ++k) {
+      z_idx[k * nc + c] = (int32_t)t.z_idx[c * t.K + k];
+      z_w0[k * nc + c] = t.z_w0[c * t.K + k];
+      z_wga[k * nc + c] = t.z_wg[(c * t.K + k) * d + a];
+    }
+  }
+  // correction records: CSR over irregular nodes
+  std::vector<std::vector<int64_t>> arms_of(t.irregular.size());
+  auto rank = [&](int64_t lin) {
+    return (int64_t)(std::lower_bound(t.irregular.begin(), t.irregular.end(), lin) - t.irregular.begin());
+  };
+  for (int64_t c = 0; c < nc; ++c) {
+    arms_of[rank(t.c_pin[c])].push_back(2 * c);       // tissue-side node, s = +1
+    arms_of[rank(t.c_pout[c])].push_back(2 * c + 1);  // "-"-side node, s = -1
+  }
+  std::vector<int32_t> irr_pos(t.irregular.size()), irr_ptr(t.irregular.size() + 1, 0), arm_cross;
+  std::vector<double> arm_d, arm_s;
+  const double ih2 = 1.0 / (t.h * t.h);
+  auto coord = [&](int64_t lin, int a) {
+    int64_t r = lin;
+    for (int b = 0; b < a; ++b) r /= N;
+    return t.lo + t.h * (double)(r % N + 1);
+  };
+  for (size_t r = 0; r < t.irregular.size(); ++r) {
+    irr_pos[r] = (int32_t)padpos(t.irregular[r]);
+    for (int64_t code : arms_of[r]) {
+      const int64_t c = code / 2;
+      const bool plus = (code % 2) == 0;
+      const int a = (int)t.c_axis[c];
+      const int64_t nb = plus ? t.c_pout[c] : t.c_pin[c];
+      arm_cross.push_back((int32_t)c);
+      arm_d.push_back(coord(nb, a) - t.c_z[c * d + a]);
+      arm_s.push_back(plus ? ih2 : -ih2);
+    }
+    irr_ptr[r + 1] = (int32_t)arm_cross.size();
+  }
+  p.narm = (int64_t)arm_cross.size();
+  // node jumps
+  const int nh = d == 2 ? 3 : 6;
+  std::vector<int32_t> q_idx(M * t.Kn);
+  std::vector<double> q_wg(M * t.Kn * d), q_n(M * d), q_wt(M * nh);
+  const int SA[6] = {0, 1, 2, 0, 0, 1}, SB[6] = {0, 1, 2, 1, 2, 2};
+  const int SA2[3] = {0, 1, 0}, SB2[3] = {0, 1, 1};
+  for (int64_t q = 0; q < M; ++q) {
+    const double *n = &t.nrm[q * d], *W = &t.W[q * d * d];
+    double tr = 0;
+    for (int b = 0; b < d; ++b) tr += W[b * d + b];
+    for (int a = 0; a < d; ++a) q_n[a * M + q] = n[a];
+    for (int e = 0; e < nh; ++e) {
+      const int a = d == 2 ? SA2[e] : SA[e], b = d == 2 ? SB2[e] : SB[e];
+      q_wt[e * M + q] = W[a * d + b] - tr * n[a] * n[b];
+    }
+    for (int k = 0; k < t.Kn; ++k) {
+      q_idx[k * M + q] = (int32_t)t.q_idx[q * t.Kn + k];
+      for (int a = 0; a < d; ++a) q_wg[(k * d + a) * M + q] = t.q_wg[(q * t.Kn + k) * d + a];
+    }
+  }
+  // gather stencils
+  std::vector<int32_t> st_pos(M * t.S);
+  std::vector<double> st_nw(M * t.S), st_r(M * t.S * d);
+  for (int64_t q = 0; q < M; ++q)
+    for (int j = 0; j < t.S; ++j) {
+      const int64_t pos = padpos(t.st_lin[q * t.S + j]);
+      st_pos[j * M + q] = t.st_chi[q * t.S + j] ? (int32_t)(-pos - 1) : (int32_t)pos;
+      double nw = 0;
+      for (int a = 0; a < d; ++a) {
+        nw += t.nrm[q * d + a] * t.st_wgrad[(q * t.S + j) * d + a];
+        st_r[(j * d + a) * M + q] = t.st_r[(q * t.S + j) * d + a];
+      }
+      st_nw[j * M + q] = nw;
+    }
+  // DST tables
+  const int Mf = p.Mfft;
+  std::vector<double> tw(2 * Mf), sp(Mf / 2 + 1), lam(N);
+  for (int m = 0; m < Mf; ++m) {
+    const double ang = -2.0 * M_PI * (double)m / (double)Mf;
+    tw[2 * m] = std::cos(ang);
+    tw[2 * m + 1] = std::sin(ang);
+  }
+  for (int n = 0; n <= Mf / 2; ++n) sp[n] = std::sin(M_PI * (double)n / (double)Mf);
+  for (int64_t k = 1; k <= N; ++k) {
+    const double s = std::sin((double)k * M_PI / (2.0 * Mf));
+    lam[k - 1] = 4.0 / (t.h * t.h) * s * s;
+  }
+  // tissue mask in the padded layout
+  std::vector<int8_t> ins_pad((size_t)p.comp_stride, 0);
+  for (int64_t lin = 0; lin < (int64_t)t.inside.size(); ++lin) ins_pad[padpos(lin)] = t.inside[lin];
+
+  p.z_idx = dupload(z_idx);
+  p.z_axis = dupload(z_axis);
+  p.q_idx = dupload(q_idx);
+  p.irr_pos = dupload(irr_pos);
+  p.irr_ptr = dupload(irr_ptr);
+  p.arm_cross = dupload(arm_cross);
+  p.st_pos = dupload(st_pos);
+  p.inside_pad = dupload(ins_pad);
+  p.lam = dupload(lam);
+  upload_prec<double>(p, p.f64, z_w0, z_wga, z_na, z_cw, q_wg, q_n, q_wt, arm_d, arm_s, st_nw, st_r, tw, sp);
+  upload_prec<float>(p, p.f32, z_w0, z_wga, z_na, z_cw, q_wg, q_n, q_wt, arm_d, arm_s, st_nw, st_r, tw, sp);
+  p.red = dalloc<double>(4096);
+  KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
+  Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps};
+  for (Timer *tm : ts) {
+    KFBI_HIP(hipEventCreate(&tm->a));
+    KFBI_HIP(hipEventCreate(&tm->b));
+  }
+}
+
+void free_tables(DevProblem &p) {
+  int32_t **ip[] = {&p.z_idx, &p.z_axis, &p.q_idx, &p.irr_pos, &p.irr_ptr, &p.arm_cross, &p.st_pos};
+  for (int32_t **q : ip) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  if (p.inside_pad) (void)hipFree(p.inside_pad);
+  if (p.lam) (void)hipFree(p.lam);
+  if (p.red) (void)hipFree(p.red);
+  if (p.host_red) (void)hipHostFree(p.host_red);
+  p.inside_pad = nullptr;
+  p.lam = nullptr;
+  p.red = nullptr;
+  p.host_red = nullptr;
+  free_prec(p.f64);
+  free_prec(p.f32);
+  Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps};
+  for (Timer *tm : ts) {
+    if (tm->a) (void)hipEventDestroy(tm->a);
+    if (tm->b) (void)hipEventDestroy(tm->b);
+    tm->a = tm->b = nullptr;
+  }
+}
+
+}  // namespace kfbi

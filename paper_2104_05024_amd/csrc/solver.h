@@ -1,0 +1,64 @@
+// Iterative solver and bidomain driver state (device vectors, FP64 Krylov workspace).
+#pragma once
+#include "device.h"
+
+namespace kfbi {
+
+struct Mlp;   // learned warm start (mlp.hip)
+
+struct Solver {
+  static constexpr int kMaxRestart = 64;
+  int64_t L = 0;               // ncomp * M
+  int nb = 0;                  // reduction blocks per dot product
+  double *V = nullptr;         // (kMaxRestart + 1) * L Krylov basis
+  double *r = nullptr, *w = nullptr, *t = nullptr, *gp = nullptr, *d = nullptr;
+  float *v32 = nullptr, *w32 = nullptr;
+  double *fpad = nullptr;      // padded FP64 field: source + correction of the final solve
+  double *partials = nullptr;  // [vector][block] partial sums
+  double *hdev = nullptr;      // device dot results (3 * (kMaxRestart + 2))
+  double *hhost = nullptr;     // pinned host mirror
+  double *ydev = nullptr;      // least-squares coefficients uploaded for the update
+  int64_t n_inside = 0;
+  int8_t *inside_plain = nullptr;
+
+  void init(DevProblem &p);
+  void release();
+
+  template <typename T>
+  void apply(DevProblem &p, const T *psi, T *out, hipStream_t st);
+  // y = A x with FP64 vectors; prec 1 runs the product in FP32
+  void apply_vec(DevProblem &p, int prec, const double *x, double *y, hipStream_t st);
+
+  double dot(const double *a, const double *b, hipStream_t st);
+  int gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
+            int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st);
+  int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
+                 int &its, int &matvecs, double &resid, hipStream_t st);
+  // g' = g - n.D grad (S f)+, with f already in fpad (padded). g may be null.
+  void bie_rhs(DevProblem &p, const double *g, hipStream_t st);
+  // psi solve of A psi = gp with the options; psi holds the start if x0 = 1.
+  int solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
+                    hipStream_t st);
+  // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added)
+  void reconstruct(DevProblem &p, const double *psi, hipStream_t st);
+  double gauge_mean(DevProblem &p, hipStream_t st);   // mean over tissue nodes of comp 1 of work
+  int solve_neumann(DevProblem &p, const double *g, const double *f, double *u, double *psi,
+                    const kfbi_solve_opts &o, kfbi_solve_info &info, hipStream_t st);
+};
+
+}  // namespace kfbi
+
+struct bidomain_s {
+  kfbi::DevProblem *prob = nullptr;
+  kfbi::Solver *solver = nullptr;
+  bidomain_params params{};
+  kfbi::Mlp *mlp = nullptr;
+  double *psi0 = nullptr;      // candidate start densities
+  double *psi_lin = nullptr;
+  void init();
+  void release();
+  int step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStream_t st);
+  void mlp_init(int capacity, uint64_t seed);
+  double mlp_train(int epochs, double lr, hipStream_t st);
+  int mlp_params(float *dst, int64_t *count);
+};

@@ -1,0 +1,518 @@
+// GMRES / Richardson on the KFBI operator, the Neumann solve of Algorithm 1, and the
+// Strang-split bidomain step (Secs. 3-6).  Krylov vectors, Arnoldi (classical Gram-Schmidt
+// with one re-orthogonalisation), Givens rotations and the least-squares update are FP64;
+// only the matrix-vector product may run in FP32 (inner solve of the refinement scheme).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <vector>
+
+#include "solver.h"
+
+namespace kfbi {
+namespace {
+
+constexpr int kB = 256;
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+template <typename T>
+T *dalloc(size_t n) {
+  T *p = nullptr;
+  KFBI_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+  return p;
+}
+
+// partial dot products: block (bx, k) reduces sum_i a_k[i] b[i] over its grid-stride slice
+__global__ __launch_bounds__(kB) void k_multidot(const double *__restrict__ A, int64_t lda,
+                                                 const double *__restrict__ b, int64_t n,
+                                                 double *__restrict__ partials) {
+  __shared__ double s[kB];
+  const int k = blockIdx.y;
+  const double *a = A + (int64_t)k * lda;
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) acc += a[i] * b[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kB) void k_finish(const double *__restrict__ partials, int nb,
+                                               double *__restrict__ out) {
+  __shared__ double s[kB];
+  const int k = blockIdx.x;
+  double acc = 0;
+  for (int i = threadIdx.x; i < nb; i += kB) acc += partials[(int64_t)k * nb + i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = s[0];
+}
+
+// w -= sum_k h[k] V_k   (sign = -1)   or   x += sum_k h[k] V_k   (sign = +1)
+__global__ __launch_bounds__(kB) void k_combine(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
+                                                const double *__restrict__ h, int K, double sign, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0;
+  for (int k = 0; k < K; ++k) acc += h[k] * V[(int64_t)k * ldv + i];
+  w[i] += sign * acc;
+}
+
+__global__ __launch_bounds__(kB) void k_scale_inv_sqrt(double *__restrict__ y, const double *__restrict__ x,
+                                                       const double *__restrict__ nrm2, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const double s = nrm2[0] > 0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
+  y[i] = x[i] * s;
+}
+
+__global__ __launch_bounds__(kB) void k_axpby(double *__restrict__ z, double a, const double *__restrict__ x,
+                                              double b, const double *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  z[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+template <typename A, typename B>
+__global__ __launch_bounds__(kB) void k_cast(const A *__restrict__ x, B *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) y[i] = (B)x[i];
+}
+
+// plain [comp][N^d] -> padded [comp][..][P]
+__global__ __launch_bounds__(kB) void k_to_padded(const double *__restrict__ f, double *__restrict__ fp,
+                                                  int64_t nplain, int64_t N, int64_t P, int64_t cs, int ncomp) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= nplain * ncomp) return;
+  const int64_t c = i / nplain, lin = i - c * nplain;
+  fp[c * cs + (lin % N) + P * (lin / N)] = f[i];
+}
+
+
+__global__ __launch_bounds__(kB) void k_masked_sum(const double *__restrict__ u, const int8_t *__restrict__ mask,
+                                                   int64_t n, double *__restrict__ partials) {
+  __shared__ double s[kB];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    if (mask[i]) acc += u[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// ---------------------------------------------------------------- FitzHugh-Nagumo kernels
+
+struct Fhn {
+  double Cm, H, theta, alpha, zeta, tol;
+  int maxit;
+};
+
+// Step 1 of the splitting (forward Euler over dt/2) fused with the diffusion source
+// f = (kappa V, -kappa V) written into the padded field.
+__global__ __launch_bounds__(kB) void k_fe_rhs(double *__restrict__ V, double *__restrict__ q,
+                                               double *__restrict__ fpad, int64_t n, int64_t N, int64_t P,
+                                               int64_t cs, double dth, double kappa, Fhn m) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const double v = V[i], g = q[i];
+  const double I = m.H * (g - v * (v - m.theta) * (1.0 - v));
+  const double v1 = v + dth * (-I / m.Cm);
+  const double q1 = g + dth * (m.alpha * v - m.zeta * g);
+  V[i] = v1;
+  q[i] = q1;
+  const int64_t pos = (i % N) + P * (i / N);
+  fpad[pos] = kappa * v1;
+  fpad[cs + pos] = -kappa * v1;
+}
+
+// Midpoint update V <- 2 (u_i - u_e) - V, then step 3 (backward Euler over dt/2, Newton on V
+// with q eliminated: q' = (q + dt/2 alpha V') / (1 + dt/2 zeta)); Newton stops once
+// |F| <= tol and takes one more step.  Optionally writes the gauged potentials.
+__global__ __launch_bounds__(kB) void k_mid_be(const double *__restrict__ u, double *__restrict__ V,
+                                               double *__restrict__ q, double *__restrict__ phi,
+                                               const double *__restrict__ mean, int64_t n, int64_t N, int64_t P,
+                                               int64_t cs, double dth, Fhn m) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int64_t pos = (i % N) + P * (i / N);
+  const double ui = u[pos], ue = u[cs + pos];
+  const double vb = 2.0 * (ui - ue) - V[i];
+  const double a = dth * m.alpha / (1.0 + dth * m.zeta);
+  const double qb = q[i] / (1.0 + dth * m.zeta);
+  const double c = dth * m.H / m.Cm;
+  double x = vb;
+  bool conv = false;
+  for (int it = 0; it < m.maxit; ++it) {
+    const double cub = x * (x - m.theta) * (1.0 - x);
+    const double F = x - vb + c * (qb + a * x - cub);
+    const double dcub = -3.0 * x * x + 2.0 * (1.0 + m.theta) * x - m.theta;
+    const double dF = 1.0 + c * (a - dcub);
+    const bool ok = fabs(F) <= m.tol;
+    x = x - F / dF;
+    if (ok) {
+      conv = true;
+      break;
+    }
+  }
+  (void)conv;
+  V[i] = x;
+  q[i] = qb + a * x;
+  if (phi) {
+    const double s = mean ? mean[0] : 0.0;
+    phi[i] = ui - s;
+    phi[n + i] = ue - s;
+  }
+}
+
+}  // namespace
+
+void Solver::init(DevProblem &p) {
+  L = (int64_t)p.ncomp * p.M;
+  nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (L + kB - 1) / kB));
+  V = dalloc<double>((size_t)(kMaxRestart + 1) * L);
+  r = dalloc<double>(L);
+  w = dalloc<double>(L);
+  t = dalloc<double>(L);
+  gp = dalloc<double>(L);
+  d = dalloc<double>(L);
+  v32 = dalloc<float>(L);
+  w32 = dalloc<float>(L);
+  fpad = dalloc<double>((size_t)p.ncomp * p.comp_stride);
+  KFBI_HIP(hipMemset(fpad, 0, (size_t)p.ncomp * p.comp_stride * sizeof(double)));
+  partials = dalloc<double>((size_t)(kMaxRestart + 2) * 512);
+  hdev = dalloc<double>(3 * (kMaxRestart + 2));
+  ydev = dalloc<double>(kMaxRestart + 2);
+  KFBI_HIP(hipHostMalloc(&hhost, 3 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
+  n_inside = 0;
+  for (int8_t v : p.ht.inside) n_inside += v;
+  inside_plain = dalloc<int8_t>(p.ht.inside.size());
+  KFBI_HIP(hipMemcpy(inside_plain, p.ht.inside.data(), p.ht.inside.size(), hipMemcpyHostToDevice));
+}
+
+void Solver::release() {
+  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &hdev, &ydev};
+  for (double **q : dp) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  if (v32) (void)hipFree(v32);
+  if (w32) (void)hipFree(w32);
+  if (inside_plain) (void)hipFree(inside_plain);
+  if (hhost) (void)hipHostFree(hhost);
+  v32 = w32 = nullptr;
+  inside_plain = nullptr;
+  hhost = nullptr;
+}
+
+template <typename T>
+void Solver::apply(DevProblem &p, const T *psi, T *out, hipStream_t st) {
+  PrecTables<T> &tb = p.tab<T>();
+  launch_jumps<T>(p, psi, st);
+  launch_correct<T>(p, st);
+  box_solve<T>(p, tb.rhs, false, tb.work, false, st);
+  launch_gather<T>(p, tb.work, true, out, st);
+}
+template void Solver::apply<double>(DevProblem &, const double *, double *, hipStream_t);
+template void Solver::apply<float>(DevProblem &, const float *, float *, hipStream_t);
+
+void Solver::apply_vec(DevProblem &p, int prec, const double *x, double *y, hipStream_t st) {
+  if (prec == 0) {
+    apply<double>(p, x, y, st);
+    return;
+  }
+  k_cast<double, float><<<nblk(L), kB, 0, st>>>(x, v32, L);
+  apply<float>(p, v32, w32, st);
+  k_cast<float, double><<<nblk(L), kB, 0, st>>>(w32, y, L);
+  KFBI_HIP(hipGetLastError());
+}
+
+double Solver::dot(const double *a, const double *b, hipStream_t st) {
+  k_multidot<<<dim3(nb, 1), kB, 0, st>>>(a, L, b, L, partials);
+  k_finish<<<1, kB, 0, st>>>(partials, nb, hdev);
+  KFBI_HIP(hipMemcpyAsync(hhost, hdev, sizeof(double), hipMemcpyDeviceToHost, st));
+  KFBI_HIP(hipStreamSynchronize(st));
+  return hhost[0];
+}
+
+int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
+                  int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st) {
+  const int m = std::max(1, std::min(restart, kMaxRestart));
+  its = 0;
+  if (bnorm == 0.0) {
+    KFBI_HIP(hipMemsetAsync(x, 0, L * sizeof(double), st));
+    resid = 0;
+    return KFBI_OK;
+  }
+  // r = b - A x
+  if (x_zero) {
+    KFBI_HIP(hipMemcpyAsync(r, b, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    apply_vec(p, prec, x, t, st);
+    ++matvecs;
+    k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
+  }
+  double beta = std::sqrt(dot(r, r, st));
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (beta > tol_abs && its < maxit) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    k_axpby<<<nblk(L), kB, 0, st>>>(V, 1.0 / beta, r, 0.0, nullptr, L);
+    int jend = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double *vj = V + (int64_t)j * L, *vn = V + (int64_t)(j + 1) * L;
+      apply_vec(p, prec, vj, vn, st);
+      ++matvecs;
+      ++its;
+      // classical Gram-Schmidt, twice; then the norm
+      for (int pass = 0; pass < 2; ++pass) {
+        k_multidot<<<dim3(nb, j + 1), kB, 0, st>>>(V, L, vn, L, partials);
+        k_finish<<<j + 1, kB, 0, st>>>(partials, nb, hdev + pass * (kMaxRestart + 2));
+        k_combine<<<nblk(L), kB, 0, st>>>(vn, V, L, hdev + pass * (kMaxRestart + 2), j + 1, -1.0, L);
+      }
+      k_multidot<<<dim3(nb, 1), kB, 0, st>>>(vn, L, vn, L, partials);
+      k_finish<<<1, kB, 0, st>>>(partials, nb, hdev + 2 * (kMaxRestart + 2));
+      k_scale_inv_sqrt<<<nblk(L), kB, 0, st>>>(vn, vn, hdev + 2 * (kMaxRestart + 2), L);
+      KFBI_HIP(hipGetLastError());
+      KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+      KFBI_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + hhost[(kMaxRestart + 2) + i];
+      const double hn = std::sqrt(std::max(0.0, hhost[2 * (kMaxRestart + 2)]));
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, c);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? c / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      jend = j + 1;
+      if (std::fabs(g[j + 1]) <= tol_abs || its >= maxit) break;
+      if (hn == 0.0) {
+        breakdown = true;
+        break;
+      }
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    KFBI_HIP(hipMemcpyAsync(ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, st));
+    k_combine<<<nblk(L), kB, 0, st>>>(x, V, L, ydev, jend, 1.0, L);
+    KFBI_HIP(hipGetLastError());
+    if (std::fabs(g[jend]) <= tol_abs || breakdown) {
+      beta = std::fabs(g[jend]);
+      KFBI_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    apply_vec(p, prec, x, t, st);
+    ++matvecs;
+    k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
+    beta = std::sqrt(dot(r, r, st));
+  }
+  resid = beta;
+  return beta <= tol_abs ? KFBI_OK : KFBI_ENOCONV;
+}
+
+int Solver::richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs,
+                       int maxit, int &its, int &matvecs, double &resid, hipStream_t st) {
+  its = 0;
+  for (;;) {
+    apply_vec(p, 0, x, t, st);
+    ++matvecs;
+    k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
+    resid = std::sqrt(dot(r, r, st));
+    if (resid <= tol_abs || its >= maxit) break;
+    k_axpby<<<nblk(L), kB, 0, st>>>(x, 1.0, x, 2.0 * gamma, r, L);
+    ++its;
+  }
+  (void)bnorm;
+  return resid <= tol_abs ? KFBI_OK : KFBI_ENOCONV;
+}
+
+void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st) {
+  box_solve<double>(p, fpad, false, p.f64.work, false, st);
+  launch_gather<double>(p, p.f64.work, false, t, st);
+  if (g)
+    k_axpby<<<nblk(L), kB, 0, st>>>(gp, 1.0, g, -1.0, t, L);
+  else
+    k_axpby<<<nblk(L), kB, 0, st>>>(gp, -1.0, t, 0.0, nullptr, L);
+  KFBI_HIP(hipGetLastError());
+}
+
+int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
+                          hipStream_t st) {
+  const double gn = std::sqrt(dot(gp, gp, st));
+  info.gp_norm = gn;
+  const double tol_abs = o.tol * gn;
+  int its = 0, mv = 0, rc = KFBI_OK;
+  double res = 0;
+  if (!x0) KFBI_HIP(hipMemsetAsync(psi, 0, L * sizeof(double), st));
+  if (o.method == 1) {
+    rc = richardson(p, gp, gn, psi, o.gamma, tol_abs, o.max_iters, its, mv, res, st);
+    info.iters = its;
+    info.matvecs_fp64 = mv;
+  } else if (o.precision == 0) {
+    rc = gmres(p, 0, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, its, mv, res, st);
+    info.iters = its;
+    info.matvecs_fp64 = mv;
+  } else {
+    // iterative refinement: FP64 residual, FP32-operator GMRES on the correction
+    int total = 0, mv64 = 0, mv32 = 0, outer = 0;
+    bool have_x = x0;
+    for (;;) {
+      if (have_x) {
+        apply_vec(p, 0, psi, t, st);
+        ++mv64;
+        k_axpby<<<nblk(L), kB, 0, st>>>(d, 1.0, gp, -1.0, t, L);
+      } else {
+        KFBI_HIP(hipMemcpyAsync(d, gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+      }
+      res = std::sqrt(dot(d, d, st));
+      if (res <= tol_abs || outer >= o.max_outer || total >= o.max_iters) break;
+      int it = 0, mvi = 0;
+      double r_in = 0;
+      KFBI_HIP(hipMemsetAsync(w, 0, L * sizeof(double), st));
+      const double tin = std::max(o.inner_tol * res, 0.5 * tol_abs);
+      gmres(p, 1, d, res, w, true, tin, o.restart, o.max_iters - total, it, mvi, r_in, st);
+      total += it;
+      mv32 += mvi;
+      k_axpby<<<nblk(L), kB, 0, st>>>(psi, 1.0, psi, 1.0, w, L);
+      have_x = true;
+      ++outer;
+    }
+    info.iters = total;
+    info.outer = outer;
+    info.matvecs_fp64 = mv64;
+    info.matvecs_fp32 = mv32;
+    rc = res <= tol_abs ? KFBI_OK : KFBI_ENOCONV;
+  }
+  info.rel_resid = gn > 0 ? res / gn : 0.0;
+  return rc;
+}
+
+void Solver::reconstruct(DevProblem &p, const double *psi, hipStream_t st) {
+  launch_jumps<double>(p, psi, st);
+  launch_add_correction<double>(p, fpad, st);
+  box_solve<double>(p, fpad, false, p.f64.work, false, st);
+}
+
+double Solver::gauge_mean(DevProblem &p, hipStream_t st) {
+  // mean over tissue nodes of comp 1 in the padded work field (mask in padded layout)
+  k_masked_sum<<<nb, kB, 0, st>>>(p.f64.work + p.comp_stride, p.inside_pad, p.comp_stride, partials);
+  k_finish<<<1, kB, 0, st>>>(partials, nb, hdev);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(hhost, hdev, sizeof(double), hipMemcpyDeviceToHost, st));
+  KFBI_HIP(hipStreamSynchronize(st));
+  return n_inside > 0 ? hhost[0] / (double)n_inside : 0.0;
+}
+
+namespace {
+__global__ __launch_bounds__(kB) void k_from_padded(const double *__restrict__ fp, double *__restrict__ f,
+                                                    int64_t nplain, int64_t N, int64_t P, int64_t cs, int ncomp,
+                                                    double shift) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= nplain * ncomp) return;
+  const int64_t c = i / nplain, lin = i - c * nplain;
+  f[i] = fp[c * cs + (lin % N) + P * (lin / N)] - shift;
+}
+}  // namespace
+
+int Solver::solve_neumann(DevProblem &p, const double *g, const double *f, double *u, double *psi,
+                          const kfbi_solve_opts &o, kfbi_solve_info &info, hipStream_t st) {
+  if (o.restart < 1 || o.max_iters < 0 || !(o.tol > 0)) throw std::invalid_argument("solve options");
+  const int64_t nplain = (int64_t)p.ht.inside.size();
+  k_to_padded<<<nblk(nplain * p.ncomp), kB, 0, st>>>(f, fpad, nplain, p.N, p.P, p.comp_stride, p.ncomp);
+  KFBI_HIP(hipGetLastError());
+  bie_rhs(p, g, st);
+  const int rc = solve_density(p, psi, o, o.x0 != 0, info, st);
+  reconstruct(p, psi, st);
+  const double shift = p.ncomp == 2 ? gauge_mean(p, st) : 0.0;
+  k_from_padded<<<nblk(nplain * p.ncomp), kB, 0, st>>>(p.f64.work, u, nplain, p.N, p.P, p.comp_stride, p.ncomp,
+                                                       shift);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipStreamSynchronize(st));
+  return rc;
+}
+
+}  // namespace kfbi
+
+using namespace kfbi;
+
+void bidomain_s::init() {
+  const int64_t L = solver->L;
+  KFBI_HIP(hipMalloc(&psi0, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&psi_lin, L * sizeof(double)));
+}
+
+void bidomain_s::release() {
+  if (psi0) (void)hipFree(psi0);
+  if (psi_lin) (void)hipFree(psi_lin);
+  psi0 = psi_lin = nullptr;
+  extern void mlp_release(bidomain_s *);
+  mlp_release(this);
+}
+
+extern bool mlp_warm_start(bidomain_s *b, const double *psi1, const double *psi2, double *out, hipStream_t st);
+extern void mlp_record(bidomain_s *b, const double *psi1, const double *psi2, const double *psi, hipStream_t st);
+
+int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStream_t st) {
+  DevProblem &p = *prob;
+  Solver &sv = *solver;
+  const int64_t n = (int64_t)p.ht.inside.size(), L = sv.L;
+  const double dth = 0.5 * dt;
+  Fhn m{params.Cm, params.H, params.theta, params.alpha, params.zeta, params.newton_tol, params.newton_maxit};
+  // step 1: reaction over dt/2 and the diffusion source
+  k_fe_rhs<<<nblk(n), kB, 0, st>>>(s.V, s.q, sv.fpad, n, p.N, p.P, p.comp_stride, dth, p.kappa, m);
+  KFBI_HIP(hipGetLastError());
+  // step 2: diffusion, backward Euler over dt/2 for w = (V^{n+1} + V^n)/2 (Neumann BVP)
+  sv.bie_rhs(p, nullptr, st);
+  double *hist1 = s.psi_hist, *hist2 = s.psi_hist + L;
+  kfbi_solve_opts o = params.solve;
+  bool x0 = true;
+  info.warm_start_used = 0;
+  if (params.warm_start == 2) {
+    x0 = false;
+  } else if (params.warm_start == 1 && mlp && mlp_warm_start(this, hist1, hist2, psi0, st)) {
+    info.warm_start_used = 1;
+  } else {
+    KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  const int rc = sv.solve_density(p, psi0, o, x0, info, st);
+  sv.reconstruct(p, psi0, st);
+  double *meanp = nullptr;
+  if (s.phi) {
+    const double mu = sv.gauge_mean(p, st);
+    sv.hhost[0] = mu;
+    KFBI_HIP(hipMemcpyAsync(sv.ydev, sv.hhost, sizeof(double), hipMemcpyHostToDevice, st));
+    meanp = sv.ydev;
+  }
+  // midpoint update and step 3: reaction over dt/2 (backward Euler)
+  k_mid_be<<<nblk(n), kB, 0, st>>>(p.f64.work, s.V, s.q, s.phi, meanp, n, p.N, p.P, p.comp_stride, dth, m);
+  KFBI_HIP(hipGetLastError());
+  if (mlp) mlp_record(this, hist1, hist2, psi0, st);
+  KFBI_HIP(hipMemcpyAsync(hist2, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  KFBI_HIP(hipMemcpyAsync(hist1, psi0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  KFBI_HIP(hipStreamSynchronize(st));
+  return rc;
+}

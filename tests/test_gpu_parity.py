@@ -1,0 +1,273 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (run on an MI355X).
+
+Every call goes through the C ABI (ctypes binding).  Tolerances: FP64 paths 1e-10
+relative (2-norm unless stated); FP32 paths as stated per test from the FP32 unit
+roundoff (6e-8) times the conditioning of the step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bidomain as obd
+from oracle import boxsolve as obs
+from oracle import geometry as ogeo
+from oracle import kfbi as ok
+from paper_2104_05024_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2104_05024_amd import kfbi as K  # noqa: E402
+
+DEV = torch.device("cuda:0")
+P_BIDO = W.BidomainParams()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def T(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+_CACHE = {}
+
+
+def problems(name):
+    """(GPU problem, oracle problem) for a named case, cached per session."""
+    if name in _CACHE:
+        return _CACHE[name]
+    cases = {
+        "star2d_128": (W.star2d(n_nodes=256), W.box(2, 128), W.scalar_coeffs(2, 1.0, 400.0)),
+        "star2d_64": (W.star2d(n_nodes=128), W.box(2, 64), W.scalar_coeffs(2, 1.0, 400.0)),
+        "circle2d_16": (W.circle2d(0.45, n_nodes=32), W.box(2, 16), W.scalar_coeffs(2, 1.0, 50.0)),
+        "ellipsoid_64": (W.ellipsoid(n_nodes=2048), W.box(3, 64), W.scalar_coeffs(3, 1.0, 400.0)),
+        "shell_64": (W.thick_shell(n_nodes=3000), W.box(3, 64), W.bidomain_coeffs(3, P_BIDO, 0.01)),
+        "ellipsoid_bido_32": (W.ellipsoid(n_nodes=512), W.box(3, 32), W.bidomain_coeffs(3, P_BIDO, 0.01)),
+        "psphere_32": (W.perturbed_sphere(n_nodes=1500), W.box(3, 32), W.scalar_coeffs(3, 1.0, 400.0)),
+        "ellipsoid_128": (W.ellipsoid(n_nodes=8192), W.box(3, 128), W.scalar_coeffs(3, 1.0, 400.0)),
+    }
+    iface, grid, co = cases[name]
+    say(f"[setup] {name}")
+    g = K.Problem(iface, grid, co)
+    o = ok.Problem(iface, grid, co)
+    _CACHE[name] = (g, o, iface, grid, co)
+    return _CACHE[name]
+
+
+# ----------------------------------------------------------------------------- box solve (a3-a5)
+
+@pytest.mark.parametrize("name", ["circle2d_16", "star2d_128", "ellipsoid_64", "shell_64"])
+def test_box_solve_matches_oracle(name):
+    g, o, iface, grid, co = problems(name)
+    f = np.random.default_rng(1).normal(size=(co.ncomp, grid.n ** grid.dim))
+    say(f"[box f64] {name}")
+    u = g.box_solve(T(f)).cpu().numpy()
+    ref = obs.box_solve(f, grid, co)
+    assert rel(u, ref) < 1e-12, rel(u, ref)
+    say(f"[box f32] {name}")
+    u32 = g.box_solve(T(f, torch.float32)).cpu().numpy()
+    assert rel(u32, ref) < 2e-6, rel(u32, ref)
+
+
+def test_box_solve_in_place_and_ragged_tile():
+    """N = 15 and 63 leave partial tiles in every pass; f and u may alias."""
+    g, o, iface, grid, co = problems("circle2d_16")
+    f = np.random.default_rng(2).normal(size=(1, grid.n ** 2))
+    t = T(f)
+    g.box_solve(t, out=t)
+    assert rel(t.cpu().numpy(), obs.box_solve(f, grid, co)) < 1e-12
+
+
+# ----------------------------------------------------------------------------- matvec (a1, a2, a6)
+
+@pytest.mark.parametrize("name", ["star2d_64", "star2d_128", "ellipsoid_64", "shell_64", "psphere_32"])
+def test_apply_f64_matches_oracle(name):
+    g, o, iface, grid, co = problems(name)
+    psi = np.random.default_rng(3).uniform(-1, 1, size=(co.ncomp, g.M))
+    say(f"[apply f64] {name}")
+    out = g.apply(T(psi)).cpu().numpy()
+    ref = o.apply(psi)
+    e = rel(out, ref)
+    say(f"    rel err {e:.2e}")
+    assert e < 1e-10, e
+
+
+@pytest.mark.parametrize("name", ["star2d_128", "shell_64"])
+def test_apply_f32_error_is_stated_bound(name):
+    g, o, iface, grid, co = problems(name)
+    psi = np.random.default_rng(4).uniform(-1, 1, size=(co.ncomp, g.M))
+    say(f"[apply f32] {name}")
+    out = g.apply(T(psi, torch.float32)).cpu().numpy()
+    e = rel(out, o.apply(psi))
+    say(f"    rel err {e:.2e}")
+    assert e < 1e-5, e
+
+
+def test_apply_is_deterministic():
+    g, o, iface, grid, co = problems("shell_64")
+    psi = T(np.random.default_rng(5).uniform(-1, 1, size=(2, g.M)))
+    a = g.apply(psi).cpu().numpy()
+    b = g.apply(psi).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_apply_zero_density_gives_zero():
+    g, o, iface, grid, co = problems("star2d_64")
+    out = g.apply(torch.zeros(1, g.M, dtype=torch.float64, device=DEV)).cpu().numpy()
+    assert np.all(out == 0)
+
+
+# ----------------------------------------------------------------------------- Neumann solve (a7-a9)
+
+def _mms2d(g, grid):
+    pts = ogeo.grid_points(grid)
+    ue = np.exp(pts[:, 0]) * np.sin(np.pi * pts[:, 1])
+    f = (np.pi ** 2 - 1 + 400.0) * ue
+    X = g.table("nodes_X").reshape(-1, 2)
+    n = g.table("nodes_n").reshape(-1, 2)
+    grad = np.stack([np.exp(X[:, 0]) * np.sin(np.pi * X[:, 1]), np.pi * np.exp(X[:, 0]) * np.cos(np.pi * X[:, 1])], 1)
+    return f[None], np.sum(n * grad, 1)[None], ue
+
+
+def test_solve_neumann_f64_matches_oracle_star2d():
+    g, o, iface, grid, co = problems("star2d_128")
+    f, gn, ue = _mms2d(g, grid)
+    say("[solve f64] star2d_128")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-13)
+    u = u.cpu().numpy()
+    uo, psio, infoo = o.solve_neumann(gn, f, tol=1e-13)
+    ins = o.inside
+    say(f"    iters gpu {info['iters']} oracle {infoo['iters']}; u err {rel(u[0][ins], uo[0][ins]):.2e}")
+    assert info["rel_resid"] <= 1e-13
+    assert rel(u[0][ins], uo[0][ins]) < 1e-10
+    assert rel(psi.cpu().numpy(), psio) < 1e-9
+    assert abs(info["iters"] - infoo["iters"]) <= 1
+    # and both solve the PDE to second-order accuracy
+    assert np.max(np.abs(u[0] - ue)[ins]) < 2e-4
+
+
+def test_solve_neumann_mixed_precision_reaches_fp64_residual():
+    g, o, iface, grid, co = problems("star2d_128")
+    f, gn, _ = _mms2d(g, grid)
+    say("[solve mixed] star2d_128")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-10, precision=1, inner_tol=1e-4)
+    uo, _, _ = o.solve_neumann(gn, f, tol=1e-13)
+    ins = o.inside
+    e = rel(u.cpu().numpy()[0][ins], uo[0][ins])
+    say(f"    outer {info['outer']} fp32 matvecs {info['matvecs_fp32']} fp64 {info['matvecs_fp64']} err {e:.2e}")
+    assert info["rel_resid"] <= 1e-10
+    assert info["matvecs_fp32"] > 0
+    assert e < 1e-9, e
+
+
+def test_solve_neumann_coupled_gauge_and_V():
+    g, o, iface, grid, co = problems("shell_64")
+    pts = ogeo.grid_points(grid)
+    V = np.exp(-30 * np.sum((pts - np.array([0.7, 0.0, 0.0])) ** 2, axis=1))
+    f = obd.diffusion_rhs(V, co.kappa)
+    gz = np.zeros((2, g.M))
+    say("[solve coupled] shell_64")
+    u, psi, info = g.solve_neumann(T(gz), T(f), tol=1e-12)
+    uo, _, _ = o.solve_neumann(gz, f, tol=1e-12)
+    u = u.cpu().numpy()
+    ins = o.inside
+    Vg, Vo = (u[0] - u[1])[ins], (uo[0] - uo[1])[ins]
+    say(f"    V err {rel(Vg, Vo):.2e}, iters {info['iters']}")
+    assert rel(Vg, Vo) < 1e-9
+    assert abs(np.mean(u[1][ins])) < 1e-12 * np.max(np.abs(u))
+    assert rel(u[:, ins], uo[:, ins]) < 1e-8
+
+
+def test_richardson_iteration_converges():
+    g, o, iface, grid, co = problems("star2d_64")
+    f, gn, _ = _mms2d(g, grid)
+    say("[richardson] star2d_64")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-8, method=1, gamma=0.8, max_iters=400)
+    uo, _, _ = o.solve_neumann(gn, f, tol=1e-12)
+    assert info["rel_resid"] <= 1e-8
+    assert rel(u.cpu().numpy()[0][o.inside], uo[0][o.inside]) < 1e-6
+
+
+def test_noconv_is_reported():
+    g, o, iface, grid, co = problems("star2d_64")
+    f, gn, _ = _mms2d(g, grid)
+    with pytest.raises(K.KfbiError) as e:
+        g.solve_neumann(T(gn), T(f), tol=1e-14, max_iters=2)
+    assert e.value.code == K.KFBI_ENOCONV
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-14, max_iters=2, allow_noconv=True)
+    assert info["iters"] == 2 and info["rel_resid"] > 1e-14
+
+
+# ----------------------------------------------------------------------------- bidomain step (a10)
+
+def test_bidomain_steps_match_oracle():
+    g, o, iface, grid, co = problems("ellipsoid_bido_32")
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+    V, q = T(V0), T(q0)
+    phi = torch.zeros(2, V0.size, dtype=torch.float64, device=DEV)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    Vo, qo, psi = V0.copy(), q0.copy(), None
+    for s in range(4):
+        say(f"[bidomain] step {s}")
+        info = bd.step(V, q, hist, 0.01, phi=phi)
+        Vo, qo, uo, psi, infoo = obd.step(o, P_BIDO, Vo, qo, 0.01, psi0=psi, tol=1e-12)
+        eV = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+        eq = np.max(np.abs(q.cpu().numpy() - qo)) / max(np.max(np.abs(qo)), 1e-30)
+        say(f"    V err {eV:.2e} q err {eq:.2e} iters {info['iters']} / {infoo['iters']}")
+        assert eV < 1e-9 and eq < 1e-9
+    ins = o.inside
+    assert rel(phi.cpu().numpy()[:, ins], uo[:, ins]) < 1e-8
+    bd.close()
+
+
+def test_bidomain_mixed_precision_step():
+    g, o, iface, grid, co = problems("ellipsoid_bido_32")
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-10, precision=1)
+    V, q = T(V0), T(q0)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    info = bd.step(V, q, hist, 0.01)
+    Vo, qo, _, _, _ = obd.step(o, P_BIDO, V0, q0, 0.01, tol=1e-12)
+    assert info["rel_resid"] <= 1e-10
+    assert np.max(np.abs(V.cpu().numpy() - Vo)) < 1e-8
+    bd.close()
+
+
+# ----------------------------------------------------------------------------- 128^3 full parity
+
+def test_apply_and_solve_full_size_ellipsoid_128():
+    g, o, iface, grid, co = problems("ellipsoid_128")
+    psi = np.random.default_rng(9).uniform(-1, 1, size=(1, g.M))
+    say("[apply f64] ellipsoid_128")
+    e = rel(g.apply(T(psi)).cpu().numpy(), o.apply(psi))
+    say(f"    rel err {e:.2e}")
+    assert e < 1e-10
+    pts = ogeo.grid_points(grid)
+    ue = np.sin(pts[:, 0]) * np.cos(pts[:, 1]) * np.exp(pts[:, 2])
+    X = g.table("nodes_X").reshape(-1, 3)
+    n = g.table("nodes_n").reshape(-1, 3)
+    gr = np.stack([np.cos(X[:, 0]) * np.cos(X[:, 1]) * np.exp(X[:, 2]),
+                   -np.sin(X[:, 0]) * np.sin(X[:, 1]) * np.exp(X[:, 2]),
+                   np.sin(X[:, 0]) * np.cos(X[:, 1]) * np.exp(X[:, 2])], 1)
+    gn = np.sum(n * gr, 1)[None]
+    f = (401.0 * ue)[None]
+    say("[solve f64] ellipsoid_128")
+    u, psi_g, info = g.solve_neumann(T(gn), T(f), tol=1e-12)
+    uo, _, _ = o.solve_neumann(gn, f, tol=1e-12)
+    ins = o.inside
+    e = rel(u.cpu().numpy()[0][ins], uo[0][ins])
+    say(f"    u err {e:.2e} iters {info['iters']}")
+    assert e < 1e-10
+    assert np.max(np.abs(u.cpu().numpy()[0] - ue)[ins]) < 1e-4
