@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark: FitzHugh-Nagumo bidomain steps/s on a 256^3 grid with the KFBI diffusion solve.
+
+Workload (synthetic, seeded): box [-1.2, 1.2]^3 with 256 cells per axis (255^3 unknowns per
+component, coupled intra/extracellular pair); a closed thick shell (outer ellipsoid
+0.9/0.7/0.6, inner wall 0.6 x ellipsoid with seeded smooth radial noise) carrying 40,960
+interface nodes; sigma_i = 1, sigma_e = 2, Cm = beta = 1, dt = 0.01 (kappa = 200);
+FHN theta = 0.13, H = 100, alpha = 0.25, zeta = 1; V = 1 in a ball of radius 0.25 at a
+seeded mid-wall point; GMRES(50) relative tolerance 1e-8 on ||g'||.
+
+A step is one whole Strang step (reaction, coupled KFBI Neumann solve, reaction) with all
+inputs resident in HBM.  Variants: plain (FP64 throughout, GMRES from psi^{n-1}),
+mixed (FP32 matvecs inside FP64 iterative refinement), learned (mixed + MLP warm start,
+when built).  Every variant ends each solve at the same FP64 relative residual.
+
+Prints one JSON line (see the "metric" key).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "bidomain steps/s at 256^3 (GMRES tol 1e-8), learned+mixed vs plain; HBM % peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--cells", type=int, default=256)
+    ap.add_argument("--nodes", type=int, default=40960)
+    ap.add_argument("--variants", default="plain,mixed,learned")
+    ap.add_argument("--train-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (first listed variant only, no CPU baseline)")
+    return ap.parse_args()
+
+
+def cpu_baseline(grid, co, box_solves_per_step):
+    """Oracle (FP64 NumPy/SciPy, single-threaded FFT) on a bounded sample: one coupled box solve
+    of the same 256^3 workload, scaled by the box solves per step of the GPU run."""
+    import numpy as np
+
+    from oracle import boxsolve
+    f = np.random.default_rng(0).normal(size=(co.ncomp, grid.n ** grid.dim))
+    t0 = time.perf_counter()
+    boxsolve.box_solve(f, grid, co)
+    dt_box = time.perf_counter() - t0
+    s_per_step = dt_box * box_solves_per_step
+    return {"value": 1.0 / s_per_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one coupled {grid.cells}^3 box solve by the oracle ({dt_box:.2f} s), scaled by "
+                      f"{box_solves_per_step:.1f} box solves per step (matvecs + volume + final solve); "
+                      f"interface work (<2% of a matvec) not included",
+            "host_cpu": platform.processor() or platform.machine(),
+            "host_cores_available": len(os.sched_getaffinity(0))}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2104_05024_amd import kfbi as K
+    from paper_2104_05024_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    dt = 0.01
+    p = W.BidomainParams()
+    iface = W.thick_shell(n_nodes=a.nodes)
+    grid = W.box(3, a.cells)
+    co = W.bidomain_coeffs(3, p, dt)
+    t0 = time.perf_counter()
+    prob = K.Problem(iface, grid, co)
+    setup_s = time.perf_counter() - t0
+    log(f"setup {setup_s:.1f} s: M={prob.M} crossings={prob.n_crossings} irregular={prob.n_irregular}")
+    V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.25)
+
+    variants = [v for v in a.variants.split(",") if v]
+    if a.profile_run:
+        variants = variants[:1]
+    results = {}
+    kt = {}
+    for name in variants:
+        if name == "learned":
+            try:
+                bd = K.Bidomain(prob, p, tol=1e-8, precision=1, warm_start=1)
+                bd.mlp_init(capacity=max(a.train_steps, 1), seed=3)
+            except K.KfbiError as e:
+                log(f"learned variant unavailable: {e}")
+                continue
+        else:
+            bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "mixed" else 0, warm_start=0)
+        V = torch.tensor(V0, device=dev)
+        q = torch.tensor(q0, device=dev)
+        hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=dev)
+        n_warm = a.warmup
+        if name == "learned":
+            n_warm = max(a.warmup, a.train_steps)
+        for i in range(n_warm):
+            bd.step(V, q, hist, dt)
+        if name == "learned":
+            loss = bd.train(epochs=200, lr=1e-3)
+            log(f"learned: trained on {a.train_steps} steps, loss {loss:.3e}")
+        prob.profile(True)
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(a.steps):
+            infos.append(bd.step(V, q, hist, dt))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt[name] = {k: prob.kernel_time(k) for k in ("dst_x", "dst_y", "dst_last", "jumps", "correct", "gather")}
+        prob.profile(False)
+        worst = max(i["rel_resid"] for i in infos)
+        results[name] = {
+            "steps_per_s": a.steps / el, "ms_per_step": 1000 * el / a.steps,
+            "mean_iters": float(np.mean([i["iters"] for i in infos])),
+            "mean_matvecs_fp64": float(np.mean([i["matvecs_fp64"] for i in infos])),
+            "mean_matvecs_fp32": float(np.mean([i["matvecs_fp32"] for i in infos])),
+            "max_final_rel_resid": worst,
+            "warm_start_used": int(sum(i["warm_start_used"] for i in infos)),
+            "V_max": float(V.max().item()),
+        }
+        log(f"{name}: {results[name]}")
+        bd.close()
+
+    head = "learned" if "learned" in results else ("mixed" if "mixed" in results else "plain")
+    r = results[head]
+    # roofline of the dominant FP64 pencil kernel (plain variant: every launch is FP64)
+    ref = "plain" if "plain" in kt else head
+    N = grid.n
+    field_bytes = co.ncomp * N ** 3 * 8
+    tot = {k: us * n for k, (us, n) in kt[ref].items() if k.startswith("dst")}
+    dom = max(tot, key=tot.get)
+    avg_us, launches = kt[ref][dom]
+    algo = 2.0 * field_bytes                      # read + write of the coupled field per launch
+    achieved = algo / (avg_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "kernel": f"k_{dom} (FP64, {ref} variant)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": algo, "avg_launch_us": round(avg_us, 2), "launches": launches,
+            "all_kernels_us": {k: round(v[0], 2) for k, v in kt[ref].items()}}
+    out = {
+        "metric": METRIC, "value": round(r["steps_per_s"], 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "plain" else "f32+f64",
+        "data": "synthetic (seeded thick-shell geometry and stimulus ball)",
+        "config": {"workload": f"FHN bidomain on a thick shell, {a.cells}^3 grid, {prob.M} interface nodes, "
+                               f"dt=0.01, GMRES(50) tol 1e-8", "variant": head, "cells": a.cells,
+                   "interface_nodes": prob.M, "crossings": prob.n_crossings, "parallelism": "single GPU"},
+        "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                     for k, v in results.items()},
+        "speedup_vs_plain": round(r["steps_per_s"] / results["plain"]["steps_per_s"], 3) if "plain" in results else None,
+        "roofline": roof,
+        "setup_s": round(setup_s, 2),
+    }
+    if not a.no_cpu_baseline and not a.profile_run:
+        per_step = results[ref]["mean_matvecs_fp64"] + results[ref]["mean_matvecs_fp32"] + 2
+        log("cpu baseline: timing the oracle's coupled box solve ...")
+        out["cpu_baseline"] = cpu_baseline(grid, co, per_step)
+    prob.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

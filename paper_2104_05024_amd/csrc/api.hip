@@ -190,13 +190,14 @@ int kfbi_solve_neumann(kfbi_problem p, const double *g, const double *f, double 
 
 int kfbi_profile(kfbi_problem p, int32_t enable) {
   if (!p) return fail(KFBI_EINVAL, "null problem");
-  p->p.profile = enable != 0;
-  Timer *ts[] = {&p->p.t_dst_x, &p->p.t_dst_y, &p->p.t_dst_last, &p->p.t_correct, &p->p.t_gather, &p->p.t_jumps};
-  for (Timer *t : ts) {
-    t->total_ms = 0;
-    t->n = 0;
-  }
-  return KFBI_OK;
+  return guard([&]() -> int {
+    if (!p->p.on_device) return fail(KFBI_ENODEV, "problem set up host-only");
+    p->p.profile = enable != 0;
+    Timer *ts[] = {&p->p.t_dst_x, &p->p.t_dst_y, &p->p.t_dst_last, &p->p.t_correct, &p->p.t_gather,
+                   &p->p.t_jumps};
+    for (Timer *t : ts) t->reset();
+    return KFBI_OK;
+  });
 }
 
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches) {
@@ -210,9 +211,12 @@ int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t
   else if (s == "gather") t = &p->p.t_gather;
   else if (s == "jumps") t = &p->p.t_jumps;
   else return fail(KFBI_EINVAL, "unknown kernel class");
-  if (avg_us) *avg_us = t->n ? 1000.0 * t->total_ms / (double)t->n : 0.0;
-  if (launches) *launches = t->n;
-  return KFBI_OK;
+  return guard([&]() -> int {
+    if (p->p.on_device) t->harvest();
+    if (avg_us) *avg_us = t->n ? 1000.0 * t->total_ms / (double)t->n : 0.0;
+    if (launches) *launches = t->n;
+    return KFBI_OK;
+  });
 }
 
 // ------------------------------------------------------------------ bidomain

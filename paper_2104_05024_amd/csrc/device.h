@@ -36,10 +36,48 @@ struct PrecTables {          // per-precision device copies of the numeric table
   T *jz = nullptr, *jq = nullptr;        // jumps at crossings [comp][2][nc], at nodes [comp][d+nh][M]
 };
 
+// Per-kernel-class launch timer: HIP events recorded around each launch on the launch
+// stream, without synchronising; durations are harvested when queried or when the pool fills.
 struct Timer {
-  hipEvent_t a = nullptr, b = nullptr;
+  static constexpr int kPairs = 2048;
+  std::vector<hipEvent_t> ev;
+  int used = 0;
   double total_ms = 0;
   int64_t n = 0;
+  void create() {
+    ev.resize(2 * kPairs);
+    for (auto &e : ev) KFBI_HIP(hipEventCreate(&e));
+  }
+  void destroy() {
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    used = 0;
+  }
+  void harvest() {
+    for (int i = 0; i < used; ++i) {
+      KFBI_HIP(hipEventSynchronize(ev[2 * i + 1]));
+      float ms = 0;
+      KFBI_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      total_ms += ms;
+      ++n;
+    }
+    used = 0;
+  }
+  void tic(bool on, hipStream_t st) {
+    if (!on) return;
+    if (used == kPairs) harvest();
+    KFBI_HIP(hipEventRecord(ev[2 * used], st));
+  }
+  void toc(bool on, hipStream_t st) {
+    if (!on) return;
+    KFBI_HIP(hipEventRecord(ev[2 * used + 1], st));
+    ++used;
+  }
+  void reset() {
+    harvest();
+    total_ms = 0;
+    n = 0;
+  }
 };
 
 struct DevProblem {

@@ -127,13 +127,13 @@ __device__ __forceinline__ void dft(C2<T> *v) {
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
 
-template <int M>
+template <typename T, int M>
 struct Shape {
   static constexpr int N = M - 1;
-  static constexpr int TPP = M / 16;       // threads per pencil pair
-  static constexpr int NP = 2048 / M;      // pencil pairs per workgroup
-  static constexpr int NT = NP * TPP;      // threads per workgroup (128)
-  static constexpr int PADM = M + M / 8;   // padded LDS length of one pair
+  static constexpr int TPP = M / 16;                          // threads per pencil pair
+  static constexpr int NP = (sizeof(T) == 8 ? 2048 : 4096) / M;  // pencil pairs per workgroup
+  static constexpr int NT = NP * TPP;                         // threads per workgroup (128 / 256)
+  static constexpr int PADM = M + M / 8;                      // padded LDS length of one pair
 };
 
 // One Stockham stage of radix R after Ns points have been combined.
@@ -238,53 +238,226 @@ __device__ __forceinline__ T &lane_of(C2<T> &c, int which) {
   return which ? c.y : c.x;
 }
 
+// 16-byte vector of T for wide global loads / stores
+template <typename T>
+struct alignas(16) V16 {
+  T v[16 / sizeof(T)];
+};
+
 // ---------------------------------------------------------------- pass kernels
+//
+// Every pass stages its whole tile through registers: all global loads of the tile are in
+// flight before the first LDS write, and all LDS reads of the result precede the global
+// stores.  Padded fields are accessed with 16-byte vectors; the pad column (x = N) is kept
+// at zero so that the y and z passes may carry it along.
 
 // DST along contiguous rows: pairs of consecutive rows of the flattened [comp][..][x] list.
-template <typename T, int M>
-__global__ __launch_bounds__(Shape<M>::NT) void k_dst_x(const T *__restrict__ in, int64_t in_pitch,
-                                                          T *__restrict__ out, int64_t out_pitch, int64_t nrows,
-                                                          const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
-  using Sh = Shape<M>;
-  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
+// PIN / POUT: input / output in the padded layout (row pitch M) instead of pitch N.
+template <typename T, int M, bool PIN, bool POUT>
+__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x(const T *__restrict__ in, T *__restrict__ out,
+                                                             int64_t nrows, const C2<T> *__restrict__ tw,
+                                                             const T *__restrict__ sp) {
+  using Sh = Shape<T, M>;
+  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM, VW = 16 / sizeof(T);
+  constexpr int ROWS = 2 * NP;
   __shared__ C2<T> sbuf[NP * PADM];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 2 * NP;
-  for (int e = tid; e < 2 * NP * N; e += NT) {
-    const int rr = e / N, n = e - rr * N;
-    const int64_t row = r0 + rr;
-    const T v = row < nrows ? in[row * in_pitch + n] : T(0);
-    lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = v;
+  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  if constexpr (PIN) {
+    constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
+    V16<T> reg[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / VPR, s = e - rr * VPR;
+      const int64_t row = r0 + rr;
+      if (e < NV && row < nrows)
+        reg[i] = *reinterpret_cast<const V16<T> *>(in + row * M + s * VW);
+      else
+#pragma unroll
+        for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < NV) {
+        const int rr = e / VPR, s = e - rr * VPR;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          const int n = s * VW + j;
+          if (n < N) lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i].v[j];
+        }
+      }
+    }
+  } else {
+    constexpr int NE = ROWS * N, PER = (NE + NT - 1) / NT;
+    T reg[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      reg[i] = (e < NE && row < nrows) ? in[row * N + n] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < NE) {
+        const int rr = e / N, n = e - rr * N;
+        lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i];
+      }
+    }
   }
   __syncthreads();
   dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
-  for (int e = tid; e < 2 * NP * N; e += NT) {
-    const int rr = e / N, n = e - rr * N;
-    const int64_t row = r0 + rr;
-    if (row < nrows) out[row * out_pitch + n] = lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1);
+  if constexpr (POUT) {
+    constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
+    V16<T> reg[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / VPR, s = e - rr * VPR;
+#pragma unroll
+      for (int j = 0; j < VW; ++j) {
+        const int n = s * VW + j;
+        reg[i].v[j] = (e < NV && n < N) ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / VPR, s = e - rr * VPR;
+      const int64_t row = r0 + rr;
+      if (e < NV && row < nrows) *reinterpret_cast<V16<T> *>(out + row * M + s * VW) = reg[i];
+    }
+  } else {
+    constexpr int NE = ROWS * N, PER = (NE + NT - 1) / NT;
+    T reg[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      reg[i] = e < NE ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      if (e < NE && row < nrows) out[row * N + n] = reg[i];
+    }
   }
 }
 
+// Tile mover for the strided passes: a tile is NR rows (stride RS elements) of TX consecutive
+// columns starting at column x0, for NC components (stride CS); element (row r, column xo,
+// component c) lives at LDS pair PAIR(xo, c), lane LANE(xo, c), position r + 1.
+template <typename T, int M, int TX, int NC>
+struct StridedTile {
+  using Sh = Shape<T, M>;
+  static constexpr int N = Sh::N, NT = Sh::NT, PADM = Sh::PADM, VW = 16 / sizeof(T);
+  static constexpr bool VEC = (TX % VW == 0) && (TX <= M);
+  static constexpr int NE = VEC ? N * NC * (TX / VW) : N * NC * TX;
+  static constexpr int PER = (NE + NT - 1) / NT;
+  __device__ static int pair_of(int xo, int c) { return NC == 2 ? xo : (xo >> 1); }
+  __device__ static int lane_sel(int xo, int c) { return NC == 2 ? c : (xo & 1); }
+
+  __device__ static void load(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid) {
+    if constexpr (VEC) {
+      constexpr int VPR = TX / VW;
+      V16<T> reg[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
+        if (e < NE)
+          reg[i] = *reinterpret_cast<const V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        if (e < NE) {
+          const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
+#pragma unroll
+          for (int j = 0; j < VW; ++j) {
+            const int xo = s * VW + j;
+            lane_of(sbuf[pair_of(xo, c) * PADM + pad(r + 1)], lane_sel(xo, c)) = reg[i].v[j];
+          }
+        }
+      }
+    } else {
+      T reg[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
+        reg[i] = (e < NE && x0 + xo < N) ? base[c * CS + (int64_t)r * RS + x0 + xo] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        if (e < NE) {
+          const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
+          lane_of(sbuf[pair_of(xo, c) * PADM + pad(r + 1)], lane_sel(xo, c)) = reg[i];
+        }
+      }
+    }
+  }
+
+  __device__ static void store(T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid) {
+    if constexpr (VEC) {
+      constexpr int VPR = TX / VW;
+      V16<T> reg[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          const int xo = s * VW + j;
+          reg[i].v[j] = (e < NE && x0 + xo < N)
+                            ? lane_of(sbuf[pair_of(xo, c) * PADM + pad(r + 1)], lane_sel(xo, c))
+                            : T(0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
+        if (e < NE) *reinterpret_cast<V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW) = reg[i];
+      }
+    } else {
+      T reg[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
+        reg[i] = e < NE ? lane_of(sbuf[pair_of(xo, c) * PADM + pad(r + 1)], lane_sel(xo, c)) : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
+        if (e < NE && x0 + xo < N) base[c * CS + (int64_t)r * RS + x0 + xo] = reg[i];
+      }
+    }
+  }
+};
+
 // DST along y (3D, in place): tile = 2 NP consecutive x columns of one (comp, z) plane.
 template <typename T, int M>
-__global__ __launch_bounds__(Shape<M>::NT) void k_dst_y(T *__restrict__ a, int64_t P, int64_t comp_stride,
-                                                          const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
-  using Sh = Shape<M>;
-  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM, TX = 2 * NP;
-  __shared__ C2<T> sbuf[NP * PADM];
+__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_y(T *__restrict__ a, int64_t P, int64_t comp_stride,
+                                                             const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
+  using Sh = Shape<T, M>;
+  using Tl = StridedTile<T, M, 2 * Sh::NP, 1>;
+  __shared__ C2<T> sbuf[Sh::NP * Sh::PADM];
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, z = blockIdx.y, c = blockIdx.z;
-  T *base = a + c * comp_stride + (int64_t)z * N * P;
-  for (int e = tid; e < N * TX; e += NT) {
-    const int y = e / TX, xo = e - y * TX, x = x0 + xo;
-    lane_of(sbuf[(xo >> 1) * PADM + pad(y + 1)], xo & 1) = x < N ? base[(int64_t)y * P + x] : T(0);
-  }
+  const int x0 = blockIdx.x * 2 * Sh::NP, z = blockIdx.y, c = blockIdx.z;
+  T *base = a + c * comp_stride + (int64_t)z * Sh::N * P;
+  Tl::load(base, P, 0, x0, sbuf, tid);
   __syncthreads();
-  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
-  for (int e = tid; e < N * TX; e += NT) {
-    const int y = e / TX, xo = e - y * TX, x = x0 + xo;
-    if (x < N) base[(int64_t)y * P + x] = lane_of(sbuf[(xo >> 1) * PADM + pad(y + 1)], xo & 1);
-  }
+  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * Sh::PADM, tid % Sh::TPP, tw, sp);
+  Tl::store(base, P, 0, x0, sbuf, tid);
 }
 
 struct ModeScale {
@@ -295,30 +468,19 @@ struct ModeScale {
 // Last axis (z in 3D, y in 2D), fused: forward DST -> mode solve -> inverse DST, in place.
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
 template <typename T, int M, int NC, int DIM>
-__global__ __launch_bounds__(Shape<M>::NT) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
-                                                             ModeScale ms, const C2<T> *__restrict__ tw,
-                                                             const T *__restrict__ sp) {
-  using Sh = Shape<M>;
+__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
+                                                                ModeScale ms, const C2<T> *__restrict__ tw,
+                                                                const T *__restrict__ sp) {
+  using Sh = Shape<T, M>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
   constexpr int64_t LS = DIM == 3 ? (int64_t)N : 1;  // rows of the last axis step by LS * P
+  using Tl = StridedTile<T, M, TX, NC>;
   __shared__ C2<T> sbuf[NP * PADM];
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX, y = DIM == 3 ? (int)blockIdx.y : 0;
   T *base = a + (DIM == 3 ? (int64_t)y * P : 0);
-  for (int e = tid; e < N * TX * NC; e += NT) {
-    int rest = e;
-    const int xo = rest % TX;
-    rest /= TX;
-    const int c = NC == 2 ? rest % 2 : 0;
-    const int zz = NC == 2 ? rest / 2 : rest;
-    const int x = x0 + xo;
-    const T v = x < N ? base[c * comp_stride + (int64_t)zz * LS * P + x] : T(0);
-    if (NC == 2)
-      lane_of(sbuf[xo * PADM + pad(zz + 1)], c) = v;
-    else
-      lane_of(sbuf[(xo >> 1) * PADM + pad(zz + 1)], xo & 1) = v;
-  }
+  Tl::load(base, LS * P, comp_stride, x0, sbuf, tid);
   __syncthreads();
   C2<T> *mine = sbuf + (tid / Sh::TPP) * PADM;
   const int lane = tid % Sh::TPP;
@@ -346,22 +508,12 @@ __global__ __launch_bounds__(Shape<M>::NT) void k_dst_last(T *__restrict__ a, in
   }
   __syncthreads();
   dst_pair<T, M>(mine, lane, tw, sp);
-  for (int e = tid; e < N * TX * NC; e += NT) {
-    int rest = e;
-    const int xo = rest % TX;
-    rest /= TX;
-    const int c = NC == 2 ? rest % 2 : 0;
-    const int zz = NC == 2 ? rest / 2 : rest;
-    const int x = x0 + xo;
-    if (x < N)
-      base[c * comp_stride + (int64_t)zz * LS * P + x] =
-          NC == 2 ? lane_of(sbuf[xo * PADM + pad(zz + 1)], c) : lane_of(sbuf[(xo >> 1) * PADM + pad(zz + 1)], xo & 1);
-  }
+  Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
 
 template <typename T, int M>
 void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st) {
-  using Sh = Shape<M>;
+  using Sh = Shape<T, M>;
   constexpr int N = Sh::N;
   PrecTables<T> &tb = p.tab<T>();
   T *A = tb.work;
@@ -371,21 +523,13 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
   const int64_t rows = (int64_t)p.ncomp * (p.dim == 3 ? (int64_t)N * N : N);
   const dim3 gx((unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP)));
   ModeScale ms{p.lam, p.sigma[0], p.ncomp == 2 ? p.sigma[1] : p.sigma[0], p.kappa, p.lam_scale};
-  auto tic = [&](Timer &t) {
-    if (p.profile) KFBI_HIP(hipEventRecord(t.a, st));
-  };
-  auto toc = [&](Timer &t) {
-    if (p.profile) {
-      KFBI_HIP(hipEventRecord(t.b, st));
-      KFBI_HIP(hipEventSynchronize(t.b));
-      float ms_ = 0;
-      KFBI_HIP(hipEventElapsedTime(&ms_, t.a, t.b));
-      t.total_ms += ms_;
-      t.n += 1;
-    }
-  };
+  auto tic = [&](Timer &t) { t.tic(p.profile, st); };
+  auto toc = [&](Timer &t) { t.toc(p.profile, st); };
   tic(p.t_dst_x);
-  k_dst_x<T, M><<<gx, Sh::NT, 0, st>>>(src, src_plain ? N : P, A, P, rows, tw, sp);
+  if (src_plain)
+    k_dst_x<T, M, false, true><<<gx, Sh::NT, 0, st>>>(src, A, rows, tw, sp);
+  else
+    k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(src, A, rows, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_x);
   const dim3 gy((N + 2 * Sh::NP - 1) / (2 * Sh::NP), N, p.ncomp);
@@ -414,7 +558,10 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
     toc(p.t_dst_y);
   }
   tic(p.t_dst_x);
-  k_dst_x<T, M><<<gx, Sh::NT, 0, st>>>(A, P, dst, dst_plain ? N : P, rows, tw, sp);
+  if (dst_plain)
+    k_dst_x<T, M, true, false><<<gx, Sh::NT, 0, st>>>(A, dst, rows, tw, sp);
+  else
+    k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(A, dst, rows, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_x);
 }

@@ -20,63 +20,81 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc, int K,
+// All stencil sizes are compile-time constants so that every index load of a thread is
+// issued before the dependent gathers (the kernels are latency-bound, not bandwidth-bound).
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc,
                                                         const int32_t *__restrict__ z_idx,
                                                         const T *__restrict__ z_w0, const T *__restrict__ z_wga,
                                                         const T *__restrict__ z_na, const T *__restrict__ z_cw,
                                                         int ncomp, T is0, T is1, T *__restrict__ jz) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  T p0 = 0, g0 = 0, p1 = 0, g1 = 0;
+  int32_t j[K];
+  T w[K], wg[K];
+#pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int32_t j = z_idx[k * nc + c];
-    const T w = z_w0[k * nc + c], wg = z_wga[k * nc + c];
-    const T a = psi[j];
-    p0 += w * a;
-    g0 += wg * a;
-    if (ncomp == 2) {
-      const T b = psi[M + j];
-      p1 += w * b;
-      g1 += wg * b;
-    }
+    j[k] = z_idx[k * nc + c];
+    w[k] = z_w0[k * nc + c];
+    wg[k] = z_wga[k * nc + c];
   }
   const T na = z_na[c], cw = z_cw[c];
-  {
-    const T a = p0 * is0;
-    jz[c] = a * na;
-    jz[nc + c] = a * cw + (T)2 * na * g0 * is0;
-  }
-  if (ncomp == 2) {
-    const T a = p1 * is1;
-    jz[2 * nc + c] = a * na;
-    jz[3 * nc + c] = a * cw + (T)2 * na * g1 * is1;
+  for (int comp = 0; comp < ncomp; ++comp) {
+    const T *ps = psi + comp * M;
+    T v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = ps[j[k]];
+    T pz = 0, ga = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      pz += w[k] * v[k];
+      ga += wg[k] * v[k];
+    }
+    const T is = comp == 0 ? is0 : is1;
+    const T a = pz * is;
+    jz[(2 * comp) * nc + c] = a * na;
+    jz[(2 * comp + 1) * nc + c] = a * cw + (T)2 * na * ga * is;
   }
 }
 
-template <typename T>
+// One thread per irregular node; at most 2D arms, loaded predicated and all at once.
+template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t *__restrict__ irr_pos,
                                                     const int32_t *__restrict__ irr_ptr,
                                                     const int32_t *__restrict__ arm_cross,
                                                     const T *__restrict__ arm_d, const T *__restrict__ arm_s,
                                                     const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
                                                     T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
+  constexpr int MAXA = 2 * D;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nirr) return;
-  T a0 = 0, a1 = 0;
-  for (int32_t j = irr_ptr[r]; j < irr_ptr[r + 1]; ++j) {
-    const int32_t c = arm_cross[j];
-    const T d = arm_d[j], s = arm_s[j];
-    a0 += s * (jz[c] * d + (T)0.5 * jz[nc + c] * d * d);
-    if (ncomp == 2) a1 += s * (jz[2 * nc + c] * d + (T)0.5 * jz[3 * nc + c] * d * d);
-  }
+  const int32_t b = irr_ptr[r], e = irr_ptr[r + 1];
   const int64_t pos = irr_pos[r];
-  if (accumulate) {
-    rhs[pos] += D0 * a0;
-    if (ncomp == 2) rhs[comp_stride + pos] += D1 * a1;
-  } else {
-    rhs[pos] = D0 * a0;
-    if (ncomp == 2) rhs[comp_stride + pos] = D1 * a1;
+  int32_t cr[MAXA];
+  T d[MAXA], sg[MAXA];
+#pragma unroll
+  for (int i = 0; i < MAXA; ++i) {
+    const bool ok = b + i < e;
+    cr[i] = ok ? arm_cross[b + i] : 0;
+    d[i] = ok ? arm_d[b + i] : T(0);
+    sg[i] = ok ? arm_s[b + i] : T(0);
+  }
+  for (int comp = 0; comp < ncomp; ++comp) {
+    T du[MAXA], duu[MAXA];
+#pragma unroll
+    for (int i = 0; i < MAXA; ++i) {
+      du[i] = jz[(2 * comp) * nc + cr[i]];
+      duu[i] = jz[(2 * comp + 1) * nc + cr[i]];
+    }
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < MAXA; ++i) acc += sg[i] * (du[i] * d[i] + (T)0.5 * duu[i] * d[i] * d[i]);
+    T *o = rhs + comp * comp_stride + pos;
+    const T val = (comp == 0 ? D0 : D1) * acc;
+    if (accumulate)
+      *o += val;
+    else
+      *o = val;
   }
 }
 
@@ -85,21 +103,19 @@ struct NH {
   static constexpr int v = D == 2 ? 3 : 6;   // symmetric entries: xx yy (zz) xy (xz yz)
 };
 
-template <typename T, int D>
+template <int D>
 __device__ __forceinline__ void sym_index(int e, int &a, int &b) {
   if (D == 2) {
-    const int A[3] = {0, 1, 0}, B[3] = {0, 1, 1};
-    a = A[e];
-    b = B[e];
+    a = e == 1 ? 1 : 0;
+    b = e == 0 ? 0 : 1;
   } else {
-    const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
-    a = A[e];
-    b = B[e];
+    a = e < 3 ? e : (e == 5 ? 1 : 0);
+    b = e < 3 ? e : (e == 3 ? 1 : 2);
   }
 }
 
-template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M, int Kn,
+template <typename T, int D, int KN>
+__global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M,
                                                         const int32_t *__restrict__ q_idx,
                                                         const T *__restrict__ q_wg, const T *__restrict__ q_n,
                                                         const T *__restrict__ q_wt, int ncomp, T is0, T is1,
@@ -107,19 +123,26 @@ __global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ ps
   constexpr int NHv = NH<D>::v, STR = D + NHv;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= M) return;
-  T n[D];
+  int32_t j[KN];
+#pragma unroll
+  for (int k = 0; k < KN; ++k) j[k] = q_idx[k * M + q];
+  T n[D], wt[NHv];
 #pragma unroll
   for (int a = 0; a < D; ++a) n[a] = q_n[a * M + q];
+#pragma unroll
+  for (int e = 0; e < NHv; ++e) wt[e] = q_wt[e * M + q];
   for (int comp = 0; comp < ncomp; ++comp) {
     const T *ps = psi + comp * M;
     const T is = comp == 0 ? is0 : is1;
+    T v[KN];
+#pragma unroll
+    for (int k = 0; k < KN; ++k) v[k] = ps[j[k]];
     T g[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) g[a] = 0;
-    for (int k = 0; k < Kn; ++k) {
-      const T v = ps[q_idx[k * M + q]];
+    for (int a = 0; a < D; ++a) {
+      g[a] = 0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) g[a] += q_wg[(k * D + a) * M + q] * v;
+      for (int k = 0; k < KN; ++k) g[a] += q_wg[(k * D + a) * M + q] * v[k];
     }
     const T amp = ps[q] * is;
     T *o = jq + (int64_t)comp * STR * M;
@@ -128,14 +151,14 @@ __global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ ps
 #pragma unroll
     for (int e = 0; e < NHv; ++e) {
       int a, b;
-      sym_index<T, D>(e, a, b);
-      o[(D + e) * M + q] = amp * q_wt[e * M + q] + (n[a] * g[b] + g[a] * n[b]) * is;
+      sym_index<D>(e, a, b);
+      o[(D + e) * M + q] = amp * wt[e] + (n[a] * g[b] + g[a] * n[b]) * is;
     }
   }
 }
 
-template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M, int S,
+template <typename T, int D, int S>
+__global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M,
                                                    const int32_t *__restrict__ st_pos,
                                                    const T *__restrict__ st_nw, const T *__restrict__ st_r,
                                                    const T *__restrict__ jq, int ncomp, T s0, T s1, int with_jumps,
@@ -143,27 +166,32 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int6
   constexpr int NHv = NH<D>::v, STR = D + NHv;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= M) return;
+  int32_t pe[S];
+  T nw[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    pe[j] = st_pos[j * M + q];
+    nw[j] = st_nw[j * M + q];
+  }
   for (int comp = 0; comp < ncomp; ++comp) {
     const T *uc = u + comp * comp_stride;
-    const T *o = jq + (int64_t)comp * STR * M;
-    T du[D], H[D][D];
+    T val[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) val[j] = uc[pe[j] < 0 ? -pe[j] - 1 : pe[j]];
     if (with_jumps) {
+      const T *o = jq + (int64_t)comp * STR * M;
+      T du[D], H[D][D];
 #pragma unroll
       for (int a = 0; a < D; ++a) du[a] = o[a * M + q];
 #pragma unroll
       for (int e = 0; e < NHv; ++e) {
         int a, b;
-        sym_index<T, D>(e, a, b);
+        sym_index<D>(e, a, b);
         H[a][b] = H[b][a] = o[(D + e) * M + q];
       }
-    }
-    T acc = 0;
-    for (int j = 0; j < S; ++j) {
-      const int32_t pe = st_pos[j * M + q];
-      const bool chi = pe < 0;
-      const int64_t pos = chi ? (int64_t)(-pe - 1) : (int64_t)pe;
-      T val = uc[pos];
-      if (with_jumps && chi) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        if (pe[j] >= 0) continue;
         T r[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) r[a] = st_r[(j * D + a) * M + q];
@@ -175,10 +203,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int6
           for (int b = 0; b < D; ++b) hr += H[a][b] * r[b];
           J += r[a] * (du[a] + (T)0.5 * hr);
         }
-        val += J;
+        val[j] += J;
       }
-      acc += st_nw[j * M + q] * val;
     }
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc += nw[j] * val[j];
     out[comp * M + q] = (comp == 0 ? s0 : s1) * acc;
   }
 }
@@ -250,19 +280,19 @@ void launch_jumps(DevProblem &p, const T *psi, hipStream_t st) {
   const T is0 = (T)(1.0 / p.sigma[0]), is1 = (T)(1.0 / p.sigma[1]);
   if (p.nc > 0) {
     if (p.dim == 2)
-      k_jumps_cross<T, 2><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.K, p.z_idx, tb.z_w0, tb.z_wga, tb.z_na,
-                                                        tb.z_cw, p.ncomp, is0, is1, tb.jz);
+      k_jumps_cross<T, 2, 4><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_w0, tb.z_wga, tb.z_na,
+                                                           tb.z_cw, p.ncomp, is0, is1, tb.jz);
     else
-      k_jumps_cross<T, 3><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.K, p.z_idx, tb.z_w0, tb.z_wga, tb.z_na,
-                                                        tb.z_cw, p.ncomp, is0, is1, tb.jz);
+      k_jumps_cross<T, 3, kLsqNodes><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_w0, tb.z_wga,
+                                                                   tb.z_na, tb.z_cw, p.ncomp, is0, is1, tb.jz);
     KFBI_HIP(hipGetLastError());
   }
   if (p.dim == 2)
-    k_jumps_nodes<T, 2><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.Kn, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt, p.ncomp,
-                                                     is0, is1, tb.jq);
+    k_jumps_nodes<T, 2, 5><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt, p.ncomp,
+                                                        is0, is1, tb.jq);
   else
-    k_jumps_nodes<T, 3><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.Kn, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt, p.ncomp,
-                                                     is0, is1, tb.jq);
+    k_jumps_nodes<T, 3, kLsqNodes><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt,
+                                                                p.ncomp, is0, is1, tb.jq);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -270,9 +300,14 @@ template <typename T>
 static void correct_into(DevProblem &p, T *field, int accumulate, hipStream_t st) {
   PrecTables<T> &tb = p.tab<T>();
   if (p.nirr == 0) return;
-  k_correct<T><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s, tb.jz,
-                                               p.nc, p.ncomp, (T)p.sigma[0], (T)p.sigma[1], field, p.comp_stride,
-                                               accumulate);
+  if (p.dim == 2)
+    k_correct<T, 2><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s,
+                                                    tb.jz, p.nc, p.ncomp, (T)p.sigma[0], (T)p.sigma[1], field,
+                                                    p.comp_stride, accumulate);
+  else
+    k_correct<T, 3><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s,
+                                                    tb.jz, p.nc, p.ncomp, (T)p.sigma[0], (T)p.sigma[1], field,
+                                                    p.comp_stride, accumulate);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -291,11 +326,11 @@ void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream
   PrecTables<T> &tb = p.tab<T>();
   const T s0 = (T)p.sigma[0], s1 = (T)p.sigma[1];
   if (p.dim == 2)
-    k_gather<T, 2><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.S, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
-                                                p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
+    k_gather<T, 2, 6><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
+                                                   p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
   else
-    k_gather<T, 3><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.S, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
-                                                p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
+    k_gather<T, 3, 10><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
+                                                    p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -446,10 +481,7 @@ void upload_tables(DevProblem &p) {
   p.red = dalloc<double>(4096);
   KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps};
-  for (Timer *tm : ts) {
-    KFBI_HIP(hipEventCreate(&tm->a));
-    KFBI_HIP(hipEventCreate(&tm->b));
-  }
+  for (Timer *tm : ts) tm->create();
 }
 
 void free_tables(DevProblem &p) {
@@ -469,11 +501,7 @@ void free_tables(DevProblem &p) {
   free_prec(p.f64);
   free_prec(p.f32);
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps};
-  for (Timer *tm : ts) {
-    if (tm->a) (void)hipEventDestroy(tm->a);
-    if (tm->b) (void)hipEventDestroy(tm->b);
-    tm->a = tm->b = nullptr;
-  }
+  for (Timer *tm : ts) tm->destroy();
 }
 
 }  // namespace kfbi

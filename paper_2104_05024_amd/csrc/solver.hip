@@ -219,10 +219,16 @@ void Solver::release() {
 template <typename T>
 void Solver::apply(DevProblem &p, const T *psi, T *out, hipStream_t st) {
   PrecTables<T> &tb = p.tab<T>();
+  p.t_jumps.tic(p.profile, st);
   launch_jumps<T>(p, psi, st);
+  p.t_jumps.toc(p.profile, st);
+  p.t_correct.tic(p.profile, st);
   launch_correct<T>(p, st);
+  p.t_correct.toc(p.profile, st);
   box_solve<T>(p, tb.rhs, false, tb.work, false, st);
+  p.t_gather.tic(p.profile, st);
   launch_gather<T>(p, tb.work, true, out, st);
+  p.t_gather.toc(p.profile, st);
 }
 template void Solver::apply<double>(DevProblem &, const double *, double *, hipStream_t);
 template void Solver::apply<float>(DevProblem &, const float *, float *, hipStream_t);

@@ -198,3 +198,18 @@ def config(name: str):
 
 def seeded_vector(n, seed, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+def grid_points(grid):
+    """(N^d, d) coordinates of the interior nodes in [z][y][x] order (input generation only)."""
+    c = grid.lo + grid.h * np.arange(1, grid.cells, dtype=np.float64)
+    mesh = np.meshgrid(*([c] * grid.dim), indexing="ij")
+    return np.stack([m.ravel() for m in reversed(mesh)], axis=1)
+
+
+def ball_state(grid, center, radius=0.1):
+    """Initial bidomain state: V = 1 inside a ball, 0 elsewhere; q = 0."""
+    pts = grid_points(grid)
+    r2 = np.sum((pts - np.asarray(center)[None, :]) ** 2, axis=1)
+    V = np.where(r2 < radius * radius, 1.0, 0.0)
+    return V, np.zeros_like(V)
