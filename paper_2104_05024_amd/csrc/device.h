@@ -33,6 +33,7 @@ struct PrecTables {          // per-precision device copies of the numeric table
   T *st_nw = nullptr, *st_r = nullptr;
   T *tw = nullptr, *sp = nullptr;        // DST twiddles exp(-2 pi i m/M) (complex) and sin(pi n/M)
   T *rhs = nullptr, *work = nullptr;     // matvec right-hand side (zero off irregular nodes), work field
+  T *xbuf = nullptr;                     // sparse matvec: x-forward output, zero outside the rhs rows
   T *jz = nullptr, *jq = nullptr;        // jumps at crossings [comp][2][nc], at nodes [comp][d+nh][M]
 };
 
@@ -96,6 +97,12 @@ struct DevProblem {
   int32_t *irr_pos = nullptr, *irr_ptr = nullptr, *arm_cross = nullptr;
   int32_t *st_pos = nullptr;   // padded index, negative (-pos-1) for stencil nodes outside the tissue
   int8_t *inside_pad = nullptr;  // padded-layout tissue mask
+  // sparse matvec box solve (3D): rows of the flattened [comp][z][y] row list that carry
+  // irregular nodes (in) / extrapolation-stencil nodes (out), and their [z][y] byte masks
+  bool sparse = true;
+  int32_t *rows_in = nullptr, *rows_out = nullptr;
+  int64_t n_rows_in = 0, n_rows_out = 0;
+  uint8_t *mask_in = nullptr, *mask_out = nullptr;
   double *lam = nullptr;       // (4/h^2) sin^2(k pi / 2M), k = 1..N
 
   PrecTables<double> f64;
@@ -122,6 +129,11 @@ inline PrecTables<float> &DevProblem::tab<float>() { return f32; }
 // Box solve: dst = S(src). Layout flags: true = caller (unpadded) layout, false = padded.
 template <typename T>
 void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st);
+
+// Box solve of the matrix-vector product: rhs (padded, sparse) -> work (padded); only the
+// extrapolation-stencil values of work are meaningful afterwards.
+template <typename T>
+void box_solve_matvec(DevProblem &p, hipStream_t st);
 
 template <typename T>
 void launch_jumps(DevProblem &p, const T *psi, hipStream_t st);

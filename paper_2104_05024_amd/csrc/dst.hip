@@ -127,13 +127,27 @@ __device__ __forceinline__ void dft(C2<T> *v) {
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
 
+// 1/x from the hardware reciprocal estimate refined by Newton steps (two in FP64, one in FP32):
+// within an ulp or two of the IEEE quotient at a fraction of the cost of a full division.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <typename T, int M>
 struct Shape {
   static constexpr int N = M - 1;
   static constexpr int TPP = M / 16;                          // threads per pencil pair
   static constexpr int NP = (sizeof(T) == 8 ? 2048 : 4096) / M;  // pencil pairs per workgroup
   static constexpr int NT = NP * TPP;                         // threads per workgroup (128 / 256)
-  static constexpr int PADM = M + M / 8;                      // padded LDS length of one pair
+  static constexpr int PADM = M + M / 8 + 1;                  // padded LDS length of one pair (odd:
+                                                              // pairs start on different banks)
 };
 
 // One Stockham stage of radix R after Ns points have been combined.
@@ -184,9 +198,14 @@ __device__ __forceinline__ T shfl_w(T v, int s, int w) { return __shfl(v, s, w);
 // DST-I (unnormalised: y_k = sum_n x_n sin(pi n k / M)) of one pencil pair held in LDS as
 // complex values at positions 1..N; result at the same positions.  All threads of the
 // workgroup must call it (it contains barriers).
-template <typename T, int M>
+template <typename T>
+struct NoHook {
+  __device__ __forceinline__ void operator()(int, C2<T> &) const {}
+};
+
+template <typename T, int M, typename Hook = NoHook<T>>
 __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__restrict__ tw,
-                                         const T *__restrict__ sp) {
+                                         const T *__restrict__ sp, const Hook &hook = Hook()) {
   constexpr int TPP = M / 16;
   // pre-processing: (n, M-n) pairs are owned by one thread, so no barrier inside
 #pragma unroll
@@ -223,12 +242,20 @@ __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__re
   const C2<T> excl = inc - tot;
   const C2<T> E0 = {shfl_w(e0.x, 0, TPP), shfl_w(e0.y, 0, TPP)};
   const C2<T> half0 = (T)0.5 * E0;
+  // the hook sees every output (position m = mode index) before it is written back
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = 8 * lane + i;
+    od[i] = (excl + od[i]) - half0;
+    hook(2 * k + 1, od[i]);
+    if (k > 0) hook(2 * k, ev[i]);
+  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = 8 * lane + i;
     if (k > 0) buf[pad(2 * k)] = ev[i];
-    buf[pad(2 * k + 1)] = (excl + od[i]) - half0;
+    buf[pad(2 * k + 1)] = od[i];
   }
   __syncthreads();
 }
@@ -362,26 +389,40 @@ struct StridedTile {
   __device__ static int pair_of(int xo, int c) { return NC == 2 ? xo : (xo >> 1); }
   __device__ static int lane_sel(int xo, int c) { return NC == 2 ? c : (xo & 1); }
 
-  __device__ static void load(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid) {
+  // rmask (optional): rows r with rmask[r] == 0 are known to be zero and are not read.
+  // Vector path: NC = 1 pairs adjacent columns, so the elements of a 16-byte vector form whole
+  // complex LDS words; NC = 2 loads both components of the same columns in one thread.
+  __device__ static void load(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
+                              const uint8_t *__restrict__ rmask = nullptr) {
     if constexpr (VEC) {
-      constexpr int VPR = TX / VW;
-      V16<T> reg[PER];
+      constexpr int VPR = TX / VW, NU = N * VPR, PU = (NU + NT - 1) / NT;
+      V16<T> reg[PU][NC];
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
+      for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
-        const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
-        if (e < NE)
-          reg[i] = *reinterpret_cast<const V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW);
+        const int s = e % VPR, r = e / VPR;
+        const bool ok = e < NU && (!rmask || rmask[r]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (ok)
+            reg[i][c] = *reinterpret_cast<const V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW);
+          else
+#pragma unroll
+            for (int j = 0; j < VW; ++j) reg[i][c].v[j] = T(0);
+        }
       }
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
+      for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
-        if (e < NE) {
-          const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
+        if (e < NU) {
+          const int s = e % VPR, r = e / VPR;
+          if constexpr (NC == 2) {
 #pragma unroll
-          for (int j = 0; j < VW; ++j) {
-            const int xo = s * VW + j;
-            lane_of(sbuf[pair_of(xo, c) * PADM + pad(r + 1)], lane_sel(xo, c)) = reg[i].v[j];
+            for (int j = 0; j < VW; ++j) sbuf[(s * VW + j) * PADM + pad(r + 1)] = {reg[i][0].v[j], reg[i][1].v[j]};
+          } else {
+#pragma unroll
+            for (int j = 0; j < VW / 2; ++j)
+              sbuf[(s * (VW / 2) + j) * PADM + pad(r + 1)] = {reg[i][0].v[2 * j], reg[i][0].v[2 * j + 1]};
           }
         }
       }
@@ -391,7 +432,7 @@ struct StridedTile {
       for (int i = 0; i < PER; ++i) {
         const int e = tid + i * NT;
         const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
-        reg[i] = (e < NE && x0 + xo < N) ? base[c * CS + (int64_t)r * RS + x0 + xo] : T(0);
+        reg[i] = (e < NE && x0 + xo < N && (!rmask || rmask[r])) ? base[c * CS + (int64_t)r * RS + x0 + xo] : T(0);
       }
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
@@ -404,27 +445,43 @@ struct StridedTile {
     }
   }
 
-  __device__ static void store(T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid) {
+  // rmask (optional): only rows r with rmask[r] != 0 are written
+  __device__ static void store(T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
+                               const uint8_t *__restrict__ rmask = nullptr) {
     if constexpr (VEC) {
-      constexpr int VPR = TX / VW;
-      V16<T> reg[PER];
+      constexpr int VPR = TX / VW, NU = N * VPR, PU = (NU + NT - 1) / NT;
+      V16<T> reg[PU][NC];
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
+      for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
-        const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
+        const int s = e % VPR, r = e / VPR;
+        if (e < NU) {
+          if constexpr (NC == 2) {
 #pragma unroll
-        for (int j = 0; j < VW; ++j) {
-          const int xo = s * VW + j;
-          reg[i].v[j] = (e < NE && x0 + xo < N)
-                            ? lane_of(sbuf[pair_of(xo, c) * PADM + pad(r + 1)], lane_sel(xo, c))
-                            : T(0);
+            for (int j = 0; j < VW; ++j) {
+              const C2<T> v = sbuf[(s * VW + j) * PADM + pad(r + 1)];
+              const bool live = x0 + s * VW + j < N;
+              reg[i][0].v[j] = live ? v.x : T(0);
+              reg[i][1].v[j] = live ? v.y : T(0);
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < VW / 2; ++j) {
+              const C2<T> v = sbuf[(s * (VW / 2) + j) * PADM + pad(r + 1)];
+              reg[i][0].v[2 * j] = x0 + s * VW + 2 * j < N ? v.x : T(0);
+              reg[i][0].v[2 * j + 1] = x0 + s * VW + 2 * j + 1 < N ? v.y : T(0);
+            }
+          }
         }
       }
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
+      for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
-        const int s = e % VPR, rc = e / VPR, c = rc % NC, r = rc / NC;
-        if (e < NE) *reinterpret_cast<V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW) = reg[i];
+        const int s = e % VPR, r = e / VPR;
+        if (e < NU && (!rmask || rmask[r]))
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            *reinterpret_cast<V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW) = reg[i][c];
       }
     } else {
       T reg[PER];
@@ -438,26 +495,31 @@ struct StridedTile {
       for (int i = 0; i < PER; ++i) {
         const int e = tid + i * NT;
         const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
-        if (e < NE && x0 + xo < N) base[c * CS + (int64_t)r * RS + x0 + xo] = reg[i];
+        if (e < NE && x0 + xo < N && (!rmask || rmask[r])) base[c * CS + (int64_t)r * RS + x0 + xo] = reg[i];
       }
     }
   }
 };
 
-// DST along y (3D, in place): tile = 2 NP consecutive x columns of one (comp, z) plane.
+// DST along y (3D): tile = 2 NP consecutive x columns of one (comp, z) plane.  in and out
+// may alias.  mask_in / mask_out (optional, [z][y] bytes): rows known to be zero on input are
+// not read; only rows flagged on output are written.
 template <typename T, int M>
-__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_y(T *__restrict__ a, int64_t P, int64_t comp_stride,
-                                                             const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
+__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_y(const T *__restrict__ in, T *__restrict__ out,
+                                                               int64_t P, int64_t comp_stride,
+                                                               const uint8_t *__restrict__ mask_in,
+                                                               const uint8_t *__restrict__ mask_out,
+                                                               const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
   using Sh = Shape<T, M>;
   using Tl = StridedTile<T, M, 2 * Sh::NP, 1>;
   __shared__ C2<T> sbuf[Sh::NP * Sh::PADM];
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * 2 * Sh::NP, z = blockIdx.y, c = blockIdx.z;
-  T *base = a + c * comp_stride + (int64_t)z * Sh::N * P;
-  Tl::load(base, P, 0, x0, sbuf, tid);
+  const int64_t off = c * comp_stride + (int64_t)z * Sh::N * P;
+  Tl::load(in + off, P, 0, x0, sbuf, tid, mask_in ? mask_in + (int64_t)z * Sh::N : nullptr);
   __syncthreads();
   dst_pair<T, M>(sbuf + (tid / Sh::TPP) * Sh::PADM, tid % Sh::TPP, tw, sp);
-  Tl::store(base, P, 0, x0, sbuf, tid);
+  Tl::store(out + off, P, 0, x0, sbuf, tid, mask_out ? mask_out + (int64_t)z * Sh::N : nullptr);
 }
 
 struct ModeScale {
@@ -466,49 +528,120 @@ struct ModeScale {
 };
 
 // Last axis (z in 3D, y in 2D), fused: forward DST -> mode solve -> inverse DST, in place.
+// The mode solve is u^ = f^ / (D L + kappa) (one component) or the closed-form inverse of
+// [[a_i + kappa, -kappa], [-kappa, a_e + kappa]], a_c = D_c L (coupled pair), with
+// L = lambda_kx + lambda_ky (+ lambda_kz) and norm = (2/M)^d for the inverse transforms.
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
 template <typename T, int M, int NC, int DIM>
 __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
-                                                                ModeScale ms, const C2<T> *__restrict__ tw,
-                                                                const T *__restrict__ sp) {
+                                                                  ModeScale ms, const C2<T> *__restrict__ tw,
+                                                                  const T *__restrict__ sp) {
   using Sh = Shape<T, M>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
   constexpr int64_t LS = DIM == 3 ? (int64_t)N : 1;  // rows of the last axis step by LS * P
   using Tl = StridedTile<T, M, TX, NC>;
   __shared__ C2<T> sbuf[NP * PADM];
+  __shared__ T slam[M];
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX, y = DIM == 3 ? (int)blockIdx.y : 0;
   T *base = a + (DIM == 3 ? (int64_t)y * P : 0);
+  for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   Tl::load(base, LS * P, comp_stride, x0, sbuf, tid);
   __syncthreads();
-  C2<T> *mine = sbuf + (tid / Sh::TPP) * PADM;
-  const int lane = tid % Sh::TPP;
+  const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
+  C2<T> *mine = sbuf + pr * PADM;
   dst_pair<T, M>(mine, lane, tw, sp);
-  // mode solve: pair p, position m (= mode index along the last axis)
-  for (int e = tid; e < NP * N; e += NT) {
-    const int pr = e / N, m = e - pr * N + 1;
-    C2<T> &v = sbuf[pr * PADM + pad(m)];
-    const double lyz = (DIM == 3 ? ms.lam[y] : 0.0) + ms.lam[m - 1];
+  // mode solve on the thread's own pencil pair, positions m = mode index along the last axis
+  {
+    const T ly = DIM == 3 ? slam[y] : T(0);
+    T L0, L1;
     if (NC == 2) {
       const int x = x0 + pr;
-      const double L = ms.lam[x < N ? x : 0] + lyz;
-      const double ai = ms.D0 * L, ae = ms.D1 * L, k = ms.kappa;
-      const double det = ai * ae + k * (ai + ae);
-      const double fi = (double)v.x, fe = (double)v.y;
-      const double s = ms.norm / det;
-      v.x = (T)(s * ((ae + k) * fi + k * fe));
-      v.y = (T)(s * (k * fi + (ai + k) * fe));
+      L0 = L1 = (x < N ? slam[x] : T(0)) + ly;
     } else {
       const int xa = x0 + 2 * pr, xb = xa + 1;
-      const double La = ms.lam[xa < N ? xa : 0] + lyz, Lb = ms.lam[xb < N ? xb : 0] + lyz;
-      v.x = (T)((double)v.x * ms.norm / (ms.D0 * La + ms.kappa));
-      v.y = (T)((double)v.y * ms.norm / (ms.D0 * Lb + ms.kappa));
+      L0 = (xa < N ? slam[xa] : T(0)) + ly;
+      L1 = (xb < N ? slam[xb] : T(0)) + ly;
+    }
+    const T D0 = (T)ms.D0, D1 = (T)ms.D1, kap = (T)ms.kappa, nrm = (T)ms.norm;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+      const int m = 1 + lane + Sh::TPP * i;
+      if (m > N) continue;
+      C2<T> &v = mine[pad(m)];
+      const T lz = slam[m - 1];
+      if (NC == 2) {
+        const T L = L0 + lz, ai = D0 * L, ae = D1 * L;
+        const T s = nrm * recip(ai * ae + kap * (ai + ae));
+        const T fi = v.x, fe = v.y;
+        v.x = s * ((ae + kap) * fi + kap * fe);
+        v.y = s * (kap * fi + (ai + kap) * fe);
+      } else {
+        v.x *= nrm * recip(D0 * (L0 + lz) + kap);
+        v.y *= nrm * recip(D0 * (L1 + lz) + kap);
+      }
     }
   }
   __syncthreads();
   dst_pair<T, M>(mine, lane, tw, sp);
   Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
+}
+
+// DST along contiguous rows listed in `rows` (indices into the flattened [comp][..] row list),
+// padded layout in and out; used by the sparse passes of the matrix-vector product.
+template <typename T, int M>
+__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__restrict__ in, T *__restrict__ out,
+                                                                    const int32_t *__restrict__ rows, int64_t nlist,
+                                                                    const C2<T> *__restrict__ tw,
+                                                                    const T *__restrict__ sp) {
+  using Sh = Shape<T, M>;
+  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM, VW = 16 / sizeof(T);
+  constexpr int ROWS = 2 * NP, VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
+  __shared__ C2<T> sbuf[NP * PADM];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  V16<T> reg[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    const int rr = e / VPR, s = e - rr * VPR;
+    if (e < NV && r0 + rr < nlist)
+      reg[i] = *reinterpret_cast<const V16<T> *>(in + (int64_t)rows[r0 + rr] * M + s * VW);
+    else
+#pragma unroll
+      for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (e < NV) {
+      const int rr = e / VPR, s = e - rr * VPR;
+#pragma unroll
+      for (int j = 0; j < VW; ++j) {
+        const int n = s * VW + j;
+        if (n < N) lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i].v[j];
+      }
+    }
+  }
+  __syncthreads();
+  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    const int rr = e / VPR, s = e - rr * VPR;
+#pragma unroll
+    for (int j = 0; j < VW; ++j) {
+      const int n = s * VW + j;
+      reg[i].v[j] = (e < NV && n < N) ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    const int rr = e / VPR, s = e - rr * VPR;
+    if (e < NV && r0 + rr < nlist) *reinterpret_cast<V16<T> *>(out + (int64_t)rows[r0 + rr] * M + s * VW) = reg[i];
+  }
 }
 
 template <typename T, int M>
@@ -535,7 +668,7 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
   const dim3 gy((N + 2 * Sh::NP - 1) / (2 * Sh::NP), N, p.ncomp);
   if (p.dim == 3) {
     tic(p.t_dst_y);
-    k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, P, cs, tw, sp);
+    k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, nullptr, tw, sp);
     KFBI_HIP(hipGetLastError());
     toc(p.t_dst_y);
   }
@@ -553,7 +686,7 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
   toc(p.t_dst_last);
   if (p.dim == 3) {
     tic(p.t_dst_y);
-    k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, P, cs, tw, sp);
+    k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, nullptr, tw, sp);
     KFBI_HIP(hipGetLastError());
     toc(p.t_dst_y);
   }
@@ -562,6 +695,51 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
     k_dst_x<T, M, true, false><<<gx, Sh::NT, 0, st>>>(A, dst, rows, tw, sp);
   else
     k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(A, dst, rows, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  toc(p.t_dst_x);
+}
+
+// Box solve inside the matrix-vector product: the right-hand side is zero outside the rows
+// that hold irregular nodes, and only the rows that hold extrapolation-stencil nodes are read
+// afterwards.  x forward runs on the first rows only (into a buffer whose other rows stay zero),
+// y forward skips reading zero rows, y inverse writes and x inverse transforms only the second
+// rows.  The values at every stencil node are identical to the full solve.
+template <typename T, int M>
+void run_box_sparse(DevProblem &p, hipStream_t st) {
+  using Sh = Shape<T, M>;
+  constexpr int N = Sh::N;
+  PrecTables<T> &tb = p.tab<T>();
+  T *A = tb.work, *X = tb.xbuf;
+  const C2<T> *tw = reinterpret_cast<const C2<T> *>(tb.tw);
+  const T *sp = tb.sp;
+  const int64_t P = p.P, cs = p.comp_stride;
+  ModeScale ms{p.lam, p.sigma[0], p.ncomp == 2 ? p.sigma[1] : p.sigma[0], p.kappa, p.lam_scale};
+  auto tic = [&](Timer &t) { t.tic(p.profile, st); };
+  auto toc = [&](Timer &t) { t.toc(p.profile, st); };
+  const unsigned gin = (unsigned)((p.n_rows_in + 2 * Sh::NP - 1) / (2 * Sh::NP));
+  const unsigned gout = (unsigned)((p.n_rows_out + 2 * Sh::NP - 1) / (2 * Sh::NP));
+  tic(p.t_dst_x);
+  if (gin) k_dst_x_rows<T, M><<<gin, Sh::NT, 0, st>>>(tb.rhs, X, p.rows_in, p.n_rows_in, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  toc(p.t_dst_x);
+  const dim3 gy((N + 2 * Sh::NP - 1) / (2 * Sh::NP), N, p.ncomp);
+  tic(p.t_dst_y);
+  k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(X, A, P, cs, p.mask_in, nullptr, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  toc(p.t_dst_y);
+  const int tx = p.ncomp == 2 ? Sh::NP : 2 * Sh::NP;
+  const dim3 gl((N + tx - 1) / tx, N, 1);
+  tic(p.t_dst_last);
+  if (p.ncomp == 2) k_dst_last<T, M, 2, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
+  else k_dst_last<T, M, 1, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  toc(p.t_dst_last);
+  tic(p.t_dst_y);
+  k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, p.mask_out, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  toc(p.t_dst_y);
+  tic(p.t_dst_x);
+  if (gout) k_dst_x_rows<T, M><<<gout, Sh::NT, 0, st>>>(A, A, p.rows_out, p.n_rows_out, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_x);
 }
@@ -584,5 +762,25 @@ void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_pla
 
 template void box_solve<double>(DevProblem &, const double *, bool, double *, bool, hipStream_t);
 template void box_solve<float>(DevProblem &, const float *, bool, float *, bool, hipStream_t);
+
+template <typename T>
+void box_solve_matvec(DevProblem &p, hipStream_t st) {
+  if (p.dim != 3 || !p.sparse) {
+    box_solve<T>(p, p.tab<T>().rhs, false, p.tab<T>().work, false, st);
+    return;
+  }
+  switch (p.Mfft) {
+    case 16: run_box_sparse<T, 16>(p, st); break;
+    case 32: run_box_sparse<T, 32>(p, st); break;
+    case 64: run_box_sparse<T, 64>(p, st); break;
+    case 128: run_box_sparse<T, 128>(p, st); break;
+    case 256: run_box_sparse<T, 256>(p, st); break;
+    case 512: run_box_sparse<T, 512>(p, st); break;
+    case 1024: run_box_sparse<T, 1024>(p, st); break;
+    default: throw std::invalid_argument("unsupported grid size");
+  }
+}
+template void box_solve_matvec<double>(DevProblem &, hipStream_t);
+template void box_solve_matvec<float>(DevProblem &, hipStream_t);
 
 }  // namespace kfbi

@@ -257,6 +257,10 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_
   tb.work = dalloc<T>(field);
   KFBI_HIP(hipMemset(tb.rhs, 0, field * sizeof(T)));
   KFBI_HIP(hipMemset(tb.work, 0, field * sizeof(T)));
+  if (p.dim == 3) {
+    tb.xbuf = dalloc<T>(field);
+    KFBI_HIP(hipMemset(tb.xbuf, 0, field * sizeof(T)));
+  }
   const int nh = p.dim == 2 ? 3 : 6;
   tb.jz = dalloc<T>((size_t)p.ncomp * 2 * std::max<int64_t>(p.nc, 1));
   tb.jq = dalloc<T>((size_t)p.ncomp * (p.dim + nh) * p.M);
@@ -265,7 +269,7 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_
 template <typename T>
 void free_prec(PrecTables<T> &tb) {
   T **all[] = {&tb.z_w0, &tb.z_wga, &tb.z_na, &tb.z_cw, &tb.q_wg, &tb.q_n, &tb.q_wt, &tb.arm_d, &tb.arm_s,
-               &tb.st_nw, &tb.st_r, &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.jz, &tb.jq};
+               &tb.st_nw, &tb.st_r, &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.jz, &tb.jq};
   for (T **q : all) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -467,6 +471,24 @@ void upload_tables(DevProblem &p) {
   std::vector<int8_t> ins_pad((size_t)p.comp_stride, 0);
   for (int64_t lin = 0; lin < (int64_t)t.inside.size(); ++lin) ins_pad[padpos(lin)] = t.inside[lin];
 
+  // sparse matvec rows: irregular-node rows (right-hand side) and stencil rows (output)
+  if (d == 3) {
+    std::vector<uint8_t> min_(N * N, 0), mout(N * N, 0);
+    for (int64_t lin : t.irregular) min_[lin / N] = 1;
+    for (int64_t lin : t.st_lin) mout[lin / N] = 1;
+    std::vector<int32_t> rin, rout;
+    for (int c = 0; c < t.ncomp; ++c)
+      for (int64_t r = 0; r < N * N; ++r) {
+        if (min_[r]) rin.push_back((int32_t)(c * N * N + r));
+        if (mout[r]) rout.push_back((int32_t)(c * N * N + r));
+      }
+    p.n_rows_in = (int64_t)rin.size();
+    p.n_rows_out = (int64_t)rout.size();
+    p.rows_in = dupload(rin);
+    p.rows_out = dupload(rout);
+    p.mask_in = dupload(min_);
+    p.mask_out = dupload(mout);
+  }
   p.z_idx = dupload(z_idx);
   p.z_axis = dupload(z_axis);
   p.q_idx = dupload(q_idx);
@@ -485,7 +507,13 @@ void upload_tables(DevProblem &p) {
 }
 
 void free_tables(DevProblem &p) {
-  int32_t **ip[] = {&p.z_idx, &p.z_axis, &p.q_idx, &p.irr_pos, &p.irr_ptr, &p.arm_cross, &p.st_pos};
+  int32_t **ip[] = {&p.z_idx, &p.z_axis, &p.q_idx, &p.irr_pos, &p.irr_ptr, &p.arm_cross, &p.st_pos,
+                    &p.rows_in, &p.rows_out};
+  uint8_t **up[] = {&p.mask_in, &p.mask_out};
+  for (uint8_t **q : up) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
   for (int32_t **q : ip) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;

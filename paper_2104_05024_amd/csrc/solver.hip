@@ -225,7 +225,7 @@ void Solver::apply(DevProblem &p, const T *psi, T *out, hipStream_t st) {
   p.t_correct.tic(p.profile, st);
   launch_correct<T>(p, st);
   p.t_correct.toc(p.profile, st);
-  box_solve<T>(p, tb.rhs, false, tb.work, false, st);
+  box_solve_matvec<T>(p, st);
   p.t_gather.tic(p.profile, st);
   launch_gather<T>(p, tb.work, true, out, st);
   p.t_gather.toc(p.profile, st);
