@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--nodes", type=int, default=40960)
     ap.add_argument("--variants", default="plain,mixed,learned")
     ap.add_argument("--train-steps", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (first listed variant only, no CPU baseline)")
     return ap.parse_args()
@@ -115,7 +116,7 @@ def main():
         for i in range(n_warm):
             bd.step(V, q, hist, dt)
         if name == "learned":
-            loss = bd.train(epochs=200, lr=1e-3)
+            loss = bd.train(epochs=a.epochs, lr=1e-3)
             log(f"learned: trained on {a.train_steps} steps, loss {loss:.3e}")
         prob.profile(True)
         infos = []

@@ -201,14 +201,32 @@ typedef struct {
 int bidomain_step(bidomain_ctx b, bidomain_state *state, double dt, kfbi_solve_info *info,
                   void *stream);
 
-/* Learned warm start (not in the paper): a per-node MLP (3 tanh layers of 128, BF16
- * weights with FP32 accumulation) predicting a correction to 2 psi^{n-1} - psi^{n-2}.
- * bidomain_record_sample stores (features, target) of the step just taken into a
- * device ring of up to `capacity` steps; bidomain_train runs `epochs` passes of Adam
- * (lr) over the stored samples on the GPU and returns the last mean loss. */
+/* Learned warm start (not in the paper, which starts GMRES from zero).  The change of the
+ * density between steps solves A (psi^n - psi^{n-1}) = g'^n - g'^{n-1}; the start is
+ *   psi0 = psi^{n-1} + s_d sum_f K_{c,f}(x) F_f(x)
+ * with change fields F = ((psi^{n-1} - psi^{n-2}) / s_d, (g'^n - g'^{n-1}) / s_g) per
+ * component (s_d, s_g their max norms) and per-node coefficients K = net(n, h tr W) from
+ * a small MLP of the static geometry only (3 tanh layers of 128, linear output of 16,
+ * BF16 weights and activations on MFMA with FP32 accumulation, FP32 master weights).
+ * bidomain_mlp_init allocates the network (output layer zero: the untrained start is
+ * psi^{n-1}) and a device ring of `capacity` recorded steps; every bidomain_step from the
+ * third on records (F, (psi^n - psi^{n-1}) / s_d).  bidomain_train runs `epochs` full-batch
+ * Adam steps (lr, beta = 0.9 / 0.999) on the mean of (K F - target)^2 / 2 over nodes,
+ * components and recorded steps, returns the last loss in loss_out and switches the
+ * learned start on.  bidomain_step checks the predicted start against psi^{n-1} every 8
+ * uses (FP32 residuals) and switches back for good if it loses. */
 int bidomain_mlp_init(bidomain_ctx b, int32_t capacity, uint64_t seed);
 int bidomain_train(bidomain_ctx b, int32_t epochs, double lr, double *loss_out, void *stream);
+/* FP32 master parameters: per layer W [out][in] row-major then b; layer shapes
+ * [128][16], [128][128], [128][128], [16][128] (inputs beyond dim + 1 are zero padding).
+ * host_dst NULL: only *count is set. */
 int bidomain_mlp_params(bidomain_ctx b, float *host_dst, int64_t *count);
+/* Test hook: run the network on R <= M host input rows X ([R][16] f32, rounded to BF16 on
+ * upload) and return its outputs Y ([R][16] f32).  With dY ([R][16] f32) non-NULL also
+ * back-propagate dY and return in grad the gradients of sum(dY * Y) with respect to the
+ * parameters (order and count of bidomain_mlp_params).  The weights are left unchanged. */
+int bidomain_mlp_eval(bidomain_ctx b, const float *X, int64_t R, float *Y, const float *dY, float *grad,
+                      void *stream);
 
 /* ----------------------------------------------------------------- utilities */
 

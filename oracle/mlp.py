@@ -5,13 +5,22 @@ Not part of the paper: the paper starts every BIE iteration from psi = 0
 network the library uses to predict a better initial density, so that the
 library's forward / backward / Adam kernels can be checked against it.
 
-Features of interface node i (ncomp components, d dimensions):
-    psi^{n-1}_c(i)/s, psi^{n-2}_c(i)/s, g'_c(i)/s_g      for every component c
-    n(i) (d entries),  h * tr W(i)
-with s = max|psi^{n-1}| and s_g = max|g'| (1 if zero).  The network predicts
-y_c(i); the initial density is  2 psi^{n-1} - psi^{n-2} + s y.
-Architecture: three tanh layers of width 128 and a linear output layer.
-Loss: mean over nodes and outputs of (y - target)^2 / 2.
+The previous solve left A psi^{n-1} = g'^{n-1}, so psi^n - psi^{n-1} =
+A^{-1}(g'^n - g'^{n-1}), and A is one half of the identity plus a compact part
+(Sec. 4, eq. bie).  The network approximates this change by a *local linear*
+map whose coefficients depend on the local geometry only:
+
+    geometry rows  G(i) = (n(i), h tr W(i))                      (static)
+    change fields  F_c(i) = ((psi^{n-1} - psi^{n-2})_c / s_d,  (g'^n - g'^{n-1})_c / s_g)
+    coefficients   K(i) = net(G(i))   (2 ncomp x ncomp entries used)
+    prediction     y_c(i) = sum_f K_{c,f}(i) F_f(i),   psi0 = psi^{n-1} + s_d y
+
+with s_d = max|psi^{n-1} - psi^{n-2}| and s_g = max|g'^n - g'^{n-1}|.  Applying
+geometry-dependent weights to the fields' changes keeps the start as smooth as
+the fields; a start with node-to-node noise slows GMRES down even when its
+residual is small.  Architecture of net: three tanh layers of width 128 and a
+linear output layer.  Loss: mean over nodes, components and recorded steps of
+(y - target)^2 / 2, target = (psi^n - psi^{n-1}) / s_d.
 """
 from __future__ import annotations
 
@@ -21,43 +30,61 @@ HIDDEN = 128
 LAYERS = 3
 
 
-def n_features(ncomp, dim):
-    return 3 * ncomp + dim + 1
+def geometry_rows(normals, trW, h):
+    """Static network inputs per node: the unit normal and h tr W."""
+    return np.concatenate([normals, (h * trW)[:, None]], axis=1)
 
 
-def features(psi1, psi2, gp, normals, trW, h):
-    """Per-node input rows (M, F) and the density scale s."""
-    psi1 = np.atleast_2d(psi1)
-    psi2 = np.atleast_2d(psi2)
-    gp = np.atleast_2d(gp)
-    s = np.max(np.abs(psi1))
-    s = s if s > 0 else 1.0
-    sg = np.max(np.abs(gp))
+def change_fields(psi1, psi2, gp, gp_prev):
+    """Per-node change fields F (M, 2 ncomp) and the scale s_d."""
+    psi1, psi2 = np.atleast_2d(psi1), np.atleast_2d(psi2)
+    gp, gp_prev = np.atleast_2d(gp), np.atleast_2d(gp_prev)
+    dpsi, dg = psi1 - psi2, gp - gp_prev
+    sd = np.max(np.abs(dpsi))
+    sd = sd if sd > 0 else 1.0
+    sg = np.max(np.abs(dg))
     sg = sg if sg > 0 else 1.0
     cols = []
     for c in range(psi1.shape[0]):
-        cols += [psi1[c] / s, psi2[c] / s, gp[c] / sg]
-    cols += [normals[:, a] for a in range(normals.shape[1])]
-    cols += [h * trW]
-    return np.stack(cols, axis=1), s
+        cols += [dpsi[c] / sd, dg[c] / sg]
+    return np.stack(cols, axis=1), sd
 
 
-def target(psi, psi1, psi2, s):
-    return ((np.atleast_2d(psi) - (2 * np.atleast_2d(psi1) - np.atleast_2d(psi2))) / s).T
+def combine(K, F, ncomp):
+    """y_c = sum_f K[:, c nf + f] F[:, f] with nf = F.shape[1] fields."""
+    nf = F.shape[1]
+    return np.stack([np.sum(K[:, c * nf:(c + 1) * nf] * F, axis=1) for c in range(ncomp)], axis=1)
 
 
-def predict_density(y, psi1, psi2, s):
-    return 2 * np.atleast_2d(psi1) - np.atleast_2d(psi2) + s * y.T
+def combine_grad(dy, F, n_out):
+    """dL/dK from dL/dy (zero in the unused outputs)."""
+    nf = F.shape[1]
+    dK = np.zeros((F.shape[0], n_out))
+    for c in range(dy.shape[1]):
+        dK[:, c * nf:(c + 1) * nf] = dy[:, c:c + 1] * F
+    return dK
 
 
-def init_params(n_in, n_out, seed=3):
-    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases."""
+def target(psi, psi1, sd):
+    return ((np.atleast_2d(psi) - np.atleast_2d(psi1)) / sd).T
+
+
+def predict_density(y, psi1, sd):
+    return np.atleast_2d(psi1) + sd * y.T
+
+
+def init_params(n_in, n_out, seed=3, zero_last=True):
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases; the output layer starts at
+    zero so that the untrained network predicts no change (psi0 = psi^{n-1})."""
     rng = np.random.default_rng(seed)
     dims = [n_in] + [HIDDEN] * LAYERS + [n_out]
     params = []
     for i in range(len(dims) - 1):
         b = 1.0 / np.sqrt(dims[i])
-        params.append([rng.uniform(-b, b, size=(dims[i + 1], dims[i])), np.zeros(dims[i + 1])])
+        W = rng.uniform(-b, b, size=(dims[i + 1], dims[i]))
+        if zero_last and i == len(dims) - 2:
+            W[:] = 0.0
+        params.append([W, np.zeros(dims[i + 1])])
     return params
 
 
@@ -72,22 +99,29 @@ def forward(params, x):
     return a, acts
 
 
-def loss(y, t):
-    return 0.5 * np.mean((y - t) ** 2)
-
-
-def backward(params, acts, t):
-    """Gradients of ``loss`` with respect to every weight and bias."""
-    y = acts[-1]
-    g = (y - t) / y.size
+def backward_from(params, acts, dy):
+    """Gradients of sum(dy * output) with respect to every weight and bias."""
+    g = dy
     grads = [None] * len(params)
     for i in reversed(range(len(params))):
         W, _ = params[i]
-        a_in = acts[i]
-        grads[i] = [g.T @ a_in, g.sum(axis=0)]
+        grads[i] = [g.T @ acts[i], g.sum(axis=0)]
         if i > 0:
             g = (g @ W) * (1.0 - acts[i] ** 2)
     return grads
+
+
+def loss_and_grad(params, G, samples, ncomp):
+    """Mean squared loss over recorded steps [(F, T), ...] and its parameter gradients."""
+    K, acts = forward(params, G)
+    n = G.shape[0] * ncomp * len(samples)
+    dK = np.zeros_like(K)
+    loss = 0.0
+    for F, T in samples:
+        d = combine(K, F, ncomp) - T
+        loss += 0.5 * np.sum(d * d) / n
+        dK += combine_grad(d / n, F, K.shape[1])
+    return loss, backward_from(params, acts, dK)
 
 
 def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -18,6 +18,9 @@ thread_local std::string g_last_error;
 
 using namespace kfbi;
 
+int mlp_eval(bidomain_s *b, const float *X_host, int64_t R, float *Y_host, float *grad_host, const float *dY_host,
+             hipStream_t st);
+
 struct kfbi_problem_s {
   DevProblem p;
   Solver solver;
@@ -272,6 +275,14 @@ int bidomain_train(bidomain_ctx b, int32_t epochs, double lr, double *loss_out, 
     const double l = b->mlp_train(epochs, lr, (hipStream_t)stream);
     if (loss_out) *loss_out = l;
     return KFBI_OK;
+  });
+}
+
+int bidomain_mlp_eval(bidomain_ctx b, const float *X, int64_t R, float *Y, const float *dY, float *grad,
+                      void *stream) {
+  return guard([&]() -> int {
+    if (!b || !b->mlp || !X || R < 1) return fail(KFBI_EINVAL, "argument");
+    return mlp_eval(b, X, R, Y, grad, dY, (hipStream_t)stream);
   });
 }
 

@@ -30,6 +30,7 @@ struct Solver {
   void apply_vec(DevProblem &p, int prec, const double *x, double *y, hipStream_t st);
 
   double dot(const double *a, const double *b, hipStream_t st);
+  double residual_norm(const double *b, const double *Ax, hipStream_t st);   // ||b - Ax||_2 (uses d)
   int gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
             int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st);
   int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
@@ -55,6 +56,8 @@ struct bidomain_s {
   kfbi::Mlp *mlp = nullptr;
   double *psi0 = nullptr;      // candidate start densities
   double *psi_lin = nullptr;
+  double *gp_prev = nullptr;   // BIE right-hand side of the previous step (warm-start feature)
+  int64_t steps_done = 0;
   void init();
   void release();
   int step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStream_t st);

@@ -244,6 +244,12 @@ void Solver::apply_vec(DevProblem &p, int prec, const double *x, double *y, hipS
   KFBI_HIP(hipGetLastError());
 }
 
+double Solver::residual_norm(const double *b, const double *Ax, hipStream_t st) {
+  k_axpby<<<nblk(L), kB, 0, st>>>(d, 1.0, b, -1.0, Ax, L);
+  KFBI_HIP(hipGetLastError());
+  return std::sqrt(dot(d, d, st));
+}
+
 double Solver::dot(const double *a, const double *b, hipStream_t st) {
   k_multidot<<<dim3(nb, 1), kB, 0, st>>>(a, L, b, L, partials);
   k_finish<<<1, kB, 0, st>>>(partials, nb, hdev);
@@ -469,17 +475,22 @@ void bidomain_s::init() {
   const int64_t L = solver->L;
   KFBI_HIP(hipMalloc(&psi0, L * sizeof(double)));
   KFBI_HIP(hipMalloc(&psi_lin, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&gp_prev, L * sizeof(double)));
+  KFBI_HIP(hipMemset(gp_prev, 0, L * sizeof(double)));
 }
 
 void bidomain_s::release() {
   if (psi0) (void)hipFree(psi0);
   if (psi_lin) (void)hipFree(psi_lin);
-  psi0 = psi_lin = nullptr;
+  if (gp_prev) (void)hipFree(gp_prev);
+  psi0 = psi_lin = gp_prev = nullptr;
   extern void mlp_release(bidomain_s *);
   mlp_release(this);
 }
 
 extern bool mlp_warm_start(bidomain_s *b, const double *psi1, const double *psi2, double *out, hipStream_t st);
+extern bool mlp_should_check(bidomain_s *b);
+extern void mlp_disable(bidomain_s *b);
 extern void mlp_record(bidomain_s *b, const double *psi1, const double *psi2, const double *psi, hipStream_t st);
 
 int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStream_t st) {
@@ -499,12 +510,28 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   info.warm_start_used = 0;
   if (params.warm_start == 2) {
     x0 = false;
-  } else if (params.warm_start == 1 && mlp && mlp_warm_start(this, hist1, hist2, psi0, st)) {
+  } else if (params.warm_start == 1 && mlp && steps_done >= 2 && mlp_warm_start(this, hist1, hist2, psi0, st)) {
     info.warm_start_used = 1;
+    // fallback check: every few steps compare the FP32 residuals of the predicted start and of
+    // psi^{n-1}; if the prediction loses, use psi^{n-1} and switch the network off
+    if (mlp_should_check(this)) {
+      sv.apply_vec(p, 1, psi0, sv.t, st);
+      const double rp = sv.residual_norm(sv.gp, sv.t, st);
+      sv.apply_vec(p, 1, hist1, sv.t, st);
+      const double rh = sv.residual_norm(sv.gp, sv.t, st);
+      info.matvecs_fp32 += 2;
+      if (!(rp < rh)) {
+        mlp_disable(this);
+        info.warm_start_used = 0;
+        KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+      }
+    }
   } else {
     KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
+  const int extra32 = info.matvecs_fp32;
   const int rc = sv.solve_density(p, psi0, o, x0, info, st);
+  info.matvecs_fp32 += extra32;
   sv.reconstruct(p, psi0, st);
   double *meanp = nullptr;
   if (s.phi) {
@@ -516,7 +543,10 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   // midpoint update and step 3: reaction over dt/2 (backward Euler)
   k_mid_be<<<nblk(n), kB, 0, st>>>(p.f64.work, s.V, s.q, s.phi, meanp, n, p.N, p.P, p.comp_stride, dth, m);
   KFBI_HIP(hipGetLastError());
-  if (mlp) mlp_record(this, hist1, hist2, psi0, st);
+  // record (features, target) once two earlier densities and g'^{n-1} exist
+  if (mlp && steps_done >= 2) mlp_record(this, hist1, hist2, psi0, st);
+  KFBI_HIP(hipMemcpyAsync(gp_prev, sv.gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  ++steps_done;
   KFBI_HIP(hipMemcpyAsync(hist2, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   KFBI_HIP(hipMemcpyAsync(hist1, psi0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   KFBI_HIP(hipStreamSynchronize(st));

@@ -22,7 +22,8 @@ MAX_TERMS = 16
 EXPORTED = [
     "kfbi_setup", "kfbi_destroy", "kfbi_query", "kfbi_table", "kfbi_apply", "kfbi_box_solve", "kfbi_solve_neumann",
     "bidomain_create", "bidomain_destroy", "bidomain_step", "bidomain_mlp_init", "bidomain_train",
-    "bidomain_mlp_params", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time", "kfbi_profile",
+    "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
+    "kfbi_profile",
 ]
 
 
@@ -102,6 +103,7 @@ def lib():
     L.bidomain_mlp_init.argtypes = [vp, i32, C.c_uint64]
     L.bidomain_train.argtypes = [vp, i32, dp, C.POINTER(dp), vp]
     L.bidomain_mlp_params.argtypes = [vp, C.POINTER(C.c_float), i64p]
+    L.bidomain_mlp_eval.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
     L.kfbi_strerror.argtypes = [C.c_int]
     L.kfbi_strerror.restype = C.c_char_p
     L.kfbi_last_error.restype = C.c_char_p
@@ -304,6 +306,22 @@ class Bidomain:
         loss = C.c_double()
         _check(lib().bidomain_train(self._h, epochs, lr, C.byref(loss), _stream()))
         return loss.value
+
+    def mlp_eval(self, X, dY=None):
+        """Network outputs on host rows X [R][16]; with dY [R][16] also the parameter gradients
+        of sum(dY * outputs), in mlp_params order."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        R = X.shape[0]
+        Y = np.zeros((R, 16), dtype=np.float32)
+        grad = None
+        dYp = None
+        if dY is not None:
+            dYp = np.ascontiguousarray(dY, dtype=np.float32)
+            grad = np.zeros(self.mlp_params().size, dtype=np.float32)
+        _check(lib().bidomain_mlp_eval(self._h, X.ctypes.data_as(C.c_void_p), R, Y.ctypes.data_as(C.c_void_p),
+                                       dYp.ctypes.data_as(C.c_void_p) if dYp is not None else None,
+                                       grad.ctypes.data_as(C.c_void_p) if grad is not None else None, _stream()))
+        return Y, grad
 
     def mlp_params(self):
         n = C.c_int64()

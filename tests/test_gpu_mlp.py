@@ -1,0 +1,211 @@
+"""GPU parity of the learned warm start (BF16 MFMA network kernels, loss gradient, Adam)
+against the FP64 oracle, and what the trained network gains over starting GMRES from
+psi^{n-1}."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bidomain as obd
+from oracle import kfbi as okfbi
+from oracle import mlp as omlp
+from paper_2104_05024_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2104_05024_amd import kfbi as K  # noqa: E402
+
+DEV = torch.device("cuda:0")
+P = W.BidomainParams()
+DIMS = [(128, 16), (128, 128), (128, 128), (16, 128)]   # padded [out][in] of the GPU layers
+NFEAT = 4                                                # 3D geometry rows: n, h tr W
+STEPS = 5                                                # records steps 2, 3, 4
+
+
+def say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def bf16(x):
+    """Round to bfloat16 (nearest even), as the GPU stores weights and activations."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unpack(flat):
+    """GPU parameter vector -> oracle params [[W (out x in), b]] without the input padding."""
+    params, off = [], 0
+    for l, (o, i) in enumerate(DIMS):
+        Wl = flat[off:off + o * i].reshape(o, i)
+        off += o * i
+        bl = flat[off:off + o]
+        off += o
+        if l == 0:
+            Wl = Wl[:, :NFEAT]
+        params.append([Wl.astype(np.float64), bl.astype(np.float64)])
+    return params
+
+
+def as_bf16_net(params):
+    return [[bf16(Wl), bl] for Wl, bl in params]
+
+
+@pytest.fixture(scope="module")
+def recorded():
+    """The same five Strang steps on the GPU (recording) and in the oracle (building the
+    samples (F, T) of steps 2..4 from its own densities and BIE right-hand sides)."""
+    iface, grid = W.ellipsoid(n_nodes=512), W.box(3, 32)
+    co = W.bidomain_coeffs(3, P, 0.01)
+    say("[setup] mlp ellipsoid 32")
+    prob = K.Problem(iface, grid, co)
+    bd = K.Bidomain(prob, P, tol=1e-10, precision=0, warm_start=1)
+    bd.mlp_init(capacity=8, seed=3)
+    V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.3)
+    V, q = torch.tensor(V0, device=DEV), torch.tensor(q0, device=DEV)
+    hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=DEV)
+    for _ in range(STEPS):
+        bd.step(V, q, hist, 0.01)
+    say("[setup] oracle steps")
+    op = okfbi.Problem(iface, grid, co)
+    Vo, qo = V0.copy(), q0.copy()
+    psis, gps = [], []
+    psi = None
+    for _ in range(STEPS):
+        Vh, _ = obd.reaction_forward_euler(Vo, qo, 0.005, P)
+        gp, _ = op.bie_rhs(np.zeros((2, op.M)), obd.diffusion_rhs(Vh, co.kappa))
+        Vo, qo, _, psi, _ = obd.step(op, P, Vo, qo, 0.01, psi0=None if psi is None else psi.ravel(), tol=1e-12)
+        psis.append(psi)
+        gps.append(gp)
+    samples = []
+    for n in range(2, STEPS):
+        F, sd = omlp.change_fields(psis[n - 1], psis[n - 2], gps[n], gps[n - 1])
+        samples.append((F, omlp.target(psis[n], psis[n - 1], sd)))
+    G = omlp.geometry_rows(op.nodes.n, np.trace(op.nodes.W, axis1=1, axis2=2), grid.h)
+    yield prob, bd, G, samples
+    bd.close()
+    prob.close()
+
+
+def test_first_epoch_loss_and_adam_update_match_oracle(recorded):
+    """Untrained: K = 0, so the loss is mean(T^2)/2 and only the output layer has a gradient;
+    the first Adam step moves each of its weights by lr against the gradient's sign."""
+    prob, bd, G, samples = recorded
+    p0 = bd.mlp_params()
+    net0 = unpack(p0)
+    assert np.all(net0[3][0] == 0) and np.all(net0[3][1] == 0)
+    loss_o, grads_o = omlp.loss_and_grad(as_bf16_net(net0), bf16(G), samples, 2)
+    lr = 1e-3
+    say("[mlp epoch 1]")
+    loss = bd.train(epochs=1, lr=lr)
+    say(f"    loss gpu {loss:.6e} oracle {loss_o:.6e}")
+    assert loss == pytest.approx(loss_o, rel=1e-4)
+    net1 = unpack(bd.mlp_params())
+    for l in range(3):
+        for j in range(2):
+            assert np.array_equal(net1[l][j], net0[l][j]), (l, j)
+    for j, name in ((0, "W"), (1, "b")):
+        g = grads_o[3][j]
+        d = net1[3][j] - net0[3][j]
+        big = np.abs(g) > 1e-2 * np.max(np.abs(g))
+        agree = np.mean(np.sign(d[big]) == -np.sign(g[big]))
+        say(f"    output {name}: {big.sum()} clear gradient entries, sign agreement {agree:.4f}")
+        assert agree >= 0.99
+        np.testing.assert_allclose(np.abs(d[big]), lr, rtol=2e-2)
+
+
+def test_training_loss_matches_oracle_after_epochs(recorded):
+    """After more epochs, the loss the GPU reports for its own parameters matches the oracle's
+    loss of those parameters (BF16-rounded) on the oracle's samples."""
+    prob, bd, G, samples = recorded
+    say("[mlp epochs]")
+    bd.train(epochs=30, lr=3e-3)
+    net = unpack(bd.mlp_params())
+    loss_next = bd.train(epochs=1, lr=0.0)       # lr = 0: reports the loss, leaves the weights
+    loss_o, _ = omlp.loss_and_grad(as_bf16_net(net), bf16(G), samples, 2)
+    say(f"    loss gpu {loss_next:.6e} oracle {loss_o:.6e}")
+    assert loss_next == pytest.approx(loss_o, rel=2e-2)
+    assert np.array_equal(unpack(bd.mlp_params())[3][0], net[3][0])
+
+
+def test_forward_matches_oracle_with_bf16_weights(recorded):
+    prob, bd, _, _ = recorded
+    net = unpack(bd.mlp_params())
+    assert np.any(net[3][0] != 0)                # trained by the tests above or here
+    rng = np.random.default_rng(0)
+    X = np.zeros((300, 16), dtype=np.float32)
+    X[:, :NFEAT] = rng.uniform(-1, 1, size=(300, NFEAT))
+    say("[mlp fwd]")
+    Y, _ = bd.mlp_eval(X)
+    yo, _ = omlp.forward(as_bf16_net(net), bf16(X[:, :NFEAT]))
+    e = np.linalg.norm(Y - yo) / np.linalg.norm(yo)
+    say(f"    rel err {e:.2e}")
+    assert e < 2e-2
+    assert np.all(Y[:, 8:] == 0)                 # outputs beyond 2 ncomp x ncomp never train
+
+
+def test_gradients_match_oracle(recorded):
+    prob, bd, _, _ = recorded
+    rng = np.random.default_rng(1)
+    R = 500
+    X = np.zeros((R, 16), dtype=np.float32)
+    X[:, :NFEAT] = rng.uniform(-1, 1, size=(R, NFEAT))
+    dY = rng.normal(size=(R, 16)).astype(np.float32)
+    say("[mlp bwd]")
+    before = bd.mlp_params()
+    _, g = bd.mlp_eval(X, dY)
+    assert np.array_equal(bd.mlp_params(), before)
+    net = as_bf16_net(unpack(before))
+    _, acts = omlp.forward(net, bf16(X[:, :NFEAT]))
+    go = omlp.backward_from(net, acts, bf16(dY))
+    gg = unpack(g)
+    for l in range(4):
+        for j in range(2):
+            a, b = gg[l][j].ravel(), go[l][j].ravel()
+            cos = float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+            rel = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            say(f"    layer {l} {'W' if j == 0 else 'b'} cosine {cos:.5f} rel {rel:.2e}")
+            assert cos > 0.995 and rel < 0.1, (l, j, cos, rel)
+
+
+def test_trained_start_saves_iterations_on_propagating_wave():
+    """64^3 thick shell: record 24 steps, train; over the next 8 steps the learned start is taken
+    and GMRES needs fewer iterations than a run started from psi^{n-1} on the same states,
+    ending at the same FP64 residual."""
+    iface, grid = W.thick_shell(n_nodes=3000), W.box(3, 64)
+    say("[setup] mlp shell 64")
+    prob = K.Problem(iface, grid, W.bidomain_coeffs(3, P, 0.01))
+    bd = K.Bidomain(prob, P, tol=1e-10, precision=1, warm_start=1)
+    bd.mlp_init(capacity=24, seed=3)
+    V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.25)
+    V, q = torch.tensor(V0, device=DEV), torch.tensor(q0, device=DEV)
+    hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=DEV)
+    for s in range(26):
+        bd.step(V, q, hist, 0.01)
+    l0 = bd.train(epochs=1, lr=1e-3)
+    l1 = bd.train(epochs=150, lr=1e-3)
+    say(f"[mlp train] loss after 1 epoch {l0:.3e}, after 151 {l1:.3e}")
+    assert l1 < 0.5 * l0
+    ctl = K.Bidomain(prob, P, tol=1e-10, precision=1, warm_start=0)
+    Vc, qc, hc = V.clone(), q.clone(), hist.clone()
+    its_l, its_c, used = [], [], 0
+    for s in range(8):
+        info = bd.step(V, q, hist, 0.01)
+        its_l.append(info["iters"])
+        used += info["warm_start_used"]
+        assert info["rel_resid"] <= 1e-10
+        ic = ctl.step(Vc, qc, hc, 0.01)
+        its_c.append(ic["iters"])
+        assert ic["rel_resid"] <= 1e-10
+    dV = (V - Vc).abs().max().item()
+    say(f"    learned-start iters {its_l} (used {used}/8), psi^(n-1) start {its_c}, max|dV| {dV:.1e}")
+    assert used == 8
+    assert np.mean(its_l) < np.mean(its_c)
+    assert dV < 1e-8
+    ctl.close()
+    bd.close()
+    prob.close()

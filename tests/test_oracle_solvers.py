@@ -120,13 +120,13 @@ def test_bidomain_step_gauge_and_midpoint_update():
 # ----------------------------------------------------------------------------- MLP
 
 def test_mlp_gradients_match_central_differences():
+    """Parameter gradients of the recorded-steps loss against central differences."""
     rng = np.random.default_rng(5)
-    F = mlp.n_features(2, 3)
-    x = rng.normal(size=(17, F))
-    t = rng.normal(size=(17, 2))
-    params = mlp.init_params(F, 2, seed=3)
-    y, acts = mlp.forward(params, x)
-    grads = mlp.backward(params, acts, t)
+    M, ncomp = 23, 2
+    G = rng.normal(size=(M, 4))
+    samples = [(rng.normal(size=(M, 2 * ncomp)), rng.normal(size=(M, ncomp))) for _ in range(3)]
+    params = mlp.init_params(4, 16, seed=3, zero_last=False)
+    loss, grads = mlp.loss_and_grad(params, G, samples, ncomp)
     eps = 1e-6
     for li, (W_, b_) in enumerate(params):
         for arr, garr in ((W_, grads[li][0]), (b_, grads[li][1])):
@@ -135,11 +135,18 @@ def test_mlp_gradients_match_central_differences():
             for k in rng.choice(flat.size, size=min(6, flat.size), replace=False):
                 old = flat[k]
                 flat[k] = old + eps
-                lp = mlp.loss(mlp.forward(params, x)[0], t)
+                lp = mlp.loss_and_grad(params, G, samples, ncomp)[0]
                 flat[k] = old - eps
-                lm = mlp.loss(mlp.forward(params, x)[0], t)
+                lm = mlp.loss_and_grad(params, G, samples, ncomp)[0]
                 flat[k] = old
                 assert abs((lp - lm) / (2 * eps) - gflat[k]) <= 1e-7 * max(1.0, abs(gflat[k]))
+
+
+def test_untrained_network_predicts_no_change():
+    rng = np.random.default_rng(7)
+    params = mlp.init_params(4, 16, seed=3)
+    K, _ = mlp.forward(params, rng.normal(size=(9, 4)))
+    assert np.all(K == 0)
 
 
 def test_adam_first_step_is_lr_times_sign():
@@ -151,14 +158,19 @@ def test_adam_first_step_is_lr_times_sign():
     np.testing.assert_allclose(params[0][1], [0.49], atol=1e-5)
 
 
-def test_features_and_prediction_roundtrip():
+def test_change_fields_and_prediction_roundtrip():
+    """With K the identity on the density-change field, the prediction is the linear
+    extrapolation 2 psi^{n-1} - psi^{n-2}; the target of psi^n inverts the prediction."""
     rng = np.random.default_rng(6)
     M = 40
-    psi1, psi2, psi, gp = rng.normal(size=(4, 2, M))
-    n = rng.normal(size=(M, 3))
-    n /= np.linalg.norm(n, axis=1)[:, None]
-    x, s = mlp.features(psi1, psi2, gp, n, rng.normal(size=M), 0.01)
-    assert x.shape == (M, mlp.n_features(2, 3))
-    assert np.max(np.abs(x[:, [0, 3]])) == pytest.approx(1.0)
-    t = mlp.target(psi, psi1, psi2, s)
-    np.testing.assert_allclose(mlp.predict_density(t, psi1, psi2, s), psi, atol=1e-14)
+    psi1, psi2, psi, gp, gq = rng.normal(size=(5, 2, M))
+    F, sd = mlp.change_fields(psi1, psi2, gp, gq)
+    assert F.shape == (M, 4) and sd == pytest.approx(np.max(np.abs(psi1 - psi2)))
+    assert np.max(np.abs(F[:, [0, 2]])) == pytest.approx(1.0)
+    K = np.zeros((M, 16))
+    K[:, 0] = 1.0                 # comp 0 <- its density change
+    K[:, 4 + 2] = 1.0             # comp 1 <- its density change
+    y = mlp.combine(K, F, 2)
+    np.testing.assert_allclose(mlp.predict_density(y, psi1, sd), 2 * psi1 - psi2, atol=1e-13)
+    t = mlp.target(psi, psi1, sd)
+    np.testing.assert_allclose(mlp.predict_density(t, psi1, sd), psi, atol=1e-13)
