@@ -156,6 +156,7 @@ typedef struct {
   double gp_norm;           /* ||g'||_2 */
   int32_t warm_start_used;  /* bidomain_step: 1 if the learned start was taken */
   int32_t pad_;
+  double start_resid;       /* ||g' - A64 psi0|| / ||g'|| of the start density (1 for a zero start) */
 } kfbi_solve_info;
 
 /* kfbi_solve_neumann: solve the Neumann problem above (Algorithm 1 with GMRES):
@@ -213,8 +214,10 @@ int bidomain_step(bidomain_ctx b, bidomain_state *state, double dt, kfbi_solve_i
  * third on records (F, (psi^n - psi^{n-1}) / s_d).  bidomain_train runs `epochs` full-batch
  * Adam steps (lr, beta = 0.9 / 0.999) on the mean of (K F - target)^2 / 2 over nodes,
  * components and recorded steps, returns the last loss in loss_out and switches the
- * learned start on.  bidomain_step checks the predicted start against psi^{n-1} every 8
- * uses (FP32 residuals) and switches back for good if it loses. */
+ * learned start on.  bidomain_step switches back to psi^{n-1} until the next training when
+ * either check fails: every 8th use, the FP32 residual of the prediction must be below that of
+ * psi^{n-1}; after every 8 uses, their mean solve cost (FP64 matvecs + FP32 matvecs / 2) must
+ * be below the mean cost of the last 8 solves started from psi^{n-1}. */
 int bidomain_mlp_init(bidomain_ctx b, int32_t capacity, uint64_t seed);
 int bidomain_train(bidomain_ctx b, int32_t epochs, double lr, double *loss_out, void *stream);
 /* FP32 master parameters: per layer W [out][in] row-major then b; layer shapes

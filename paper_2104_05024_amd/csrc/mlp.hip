@@ -36,6 +36,10 @@ struct Mlp {
   int cap = 0, count = 0, head = 0, adam_t = 0;
   bool enabled = true, k_valid = false;
   int since_check = 0, check_every = 8, fallbacks = 0;
+  // solve cost (FP64 matvecs + FP32 matvecs / 2) of the last 8 steps started from psi^{n-1}
+  // and of the learned starts since the last cost check
+  double plain_ring[8] = {0, 0, 0, 0, 0, 0, 0, 0}, learned_cost = 0;
+  int plain_n = 0, learned_n = 0;
   // parameters: fp32 master, bf16 copies, gradients and Adam moments
   float *W[4] = {}, *b[4] = {}, *gW[4] = {}, *gb[4] = {}, *mW[4] = {}, *vW[4] = {}, *mb[4] = {}, *vb[4] = {};
   uint16_t *Wb[4] = {};
@@ -591,6 +595,8 @@ double bidomain_s::mlp_train(int epochs, double lr, hipStream_t st) {
   m.k_valid = true;
   m.enabled = true;
   m.since_check = 0;
+  m.learned_cost = 0;
+  m.learned_n = 0;
   return last;
 }
 
@@ -649,6 +655,31 @@ void mlp_disable(bidomain_s *b) {
   if (b->mlp) {
     b->mlp->enabled = false;
     b->mlp->fallbacks += 1;
+  }
+}
+
+// Cost bookkeeping after each solve: every check_every learned solves, compare their mean cost
+// with that of the last 8 solves started from psi^{n-1}; switch the learned start off if it is
+// not cheaper.
+void mlp_note_cost(bidomain_s *b, double cost, bool learned) {
+  Mlp &m = *b->mlp;
+  if (!learned) {
+    m.plain_ring[m.plain_n % 8] = cost;
+    m.plain_n += 1;
+    return;
+  }
+  m.learned_cost += cost;
+  m.learned_n += 1;
+  if (m.learned_n >= m.check_every) {
+    const int np = std::min(m.plain_n, 8);
+    double pc = 0;
+    for (int i = 0; i < np; ++i) pc += m.plain_ring[i];
+    if (np > 0 && m.learned_cost / m.learned_n >= pc / np) {
+      m.enabled = false;
+      m.fallbacks += 1;
+    }
+    m.learned_cost = 0;
+    m.learned_n = 0;
   }
 }
 

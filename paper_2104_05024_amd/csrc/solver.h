@@ -32,9 +32,10 @@ struct Solver {
   double dot(const double *a, const double *b, hipStream_t st);
   double residual_norm(const double *b, const double *Ax, hipStream_t st);   // ||b - Ax||_2 (uses d)
   int gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
-            int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st);
+            int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
+            double *beta0 = nullptr);
   int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
-                 int &its, int &matvecs, double &resid, hipStream_t st);
+                 int &its, int &matvecs, double &resid, hipStream_t st, double *r0 = nullptr);
   // g' = g - n.D grad (S f)+, with f already in fpad (padded). g may be null.
   void bie_rhs(DevProblem &p, const double *g, hipStream_t st);
   // psi solve of A psi = gp with the options; psi holds the start if x0 = 1.

@@ -259,12 +259,14 @@ double Solver::dot(const double *a, const double *b, hipStream_t st) {
 }
 
 int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
-                  int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st) {
+                  int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
+                  double *beta0) {
   const int m = std::max(1, std::min(restart, kMaxRestart));
   its = 0;
   if (bnorm == 0.0) {
     KFBI_HIP(hipMemsetAsync(x, 0, L * sizeof(double), st));
     resid = 0;
+    if (beta0) *beta0 = 0;
     return KFBI_OK;
   }
   // r = b - A x
@@ -276,6 +278,7 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
     k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
   }
   double beta = std::sqrt(dot(r, r, st));
+  if (beta0) *beta0 = beta;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   while (beta > tol_abs && its < maxit) {
     std::fill(H.begin(), H.end(), 0.0);
@@ -347,13 +350,14 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
 }
 
 int Solver::richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs,
-                       int maxit, int &its, int &matvecs, double &resid, hipStream_t st) {
+                       int maxit, int &its, int &matvecs, double &resid, hipStream_t st, double *r0) {
   its = 0;
   for (;;) {
     apply_vec(p, 0, x, t, st);
     ++matvecs;
     k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
     resid = std::sqrt(dot(r, r, st));
+    if (r0 && its == 0) *r0 = resid;
     if (resid <= tol_abs || its >= maxit) break;
     k_axpby<<<nblk(L), kB, 0, st>>>(x, 1.0, x, 2.0 * gamma, r, L);
     ++its;
@@ -378,14 +382,14 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
   info.gp_norm = gn;
   const double tol_abs = o.tol * gn;
   int its = 0, mv = 0, rc = KFBI_OK;
-  double res = 0;
+  double res = 0, res0 = gn;
   if (!x0) KFBI_HIP(hipMemsetAsync(psi, 0, L * sizeof(double), st));
   if (o.method == 1) {
-    rc = richardson(p, gp, gn, psi, o.gamma, tol_abs, o.max_iters, its, mv, res, st);
+    rc = richardson(p, gp, gn, psi, o.gamma, tol_abs, o.max_iters, its, mv, res, st, &res0);
     info.iters = its;
     info.matvecs_fp64 = mv;
   } else if (o.precision == 0) {
-    rc = gmres(p, 0, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, its, mv, res, st);
+    rc = gmres(p, 0, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, its, mv, res, st, &res0);
     info.iters = its;
     info.matvecs_fp64 = mv;
   } else {
@@ -401,6 +405,7 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
         KFBI_HIP(hipMemcpyAsync(d, gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
       }
       res = std::sqrt(dot(d, d, st));
+      if (outer == 0) res0 = res;
       if (res <= tol_abs || outer >= o.max_outer || total >= o.max_iters) break;
       int it = 0, mvi = 0;
       double r_in = 0;
@@ -420,6 +425,7 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
     rc = res <= tol_abs ? KFBI_OK : KFBI_ENOCONV;
   }
   info.rel_resid = gn > 0 ? res / gn : 0.0;
+  info.start_resid = gn > 0 ? res0 / gn : 0.0;
   return rc;
 }
 
@@ -492,6 +498,7 @@ extern bool mlp_warm_start(bidomain_s *b, const double *psi1, const double *psi2
 extern bool mlp_should_check(bidomain_s *b);
 extern void mlp_disable(bidomain_s *b);
 extern void mlp_record(bidomain_s *b, const double *psi1, const double *psi2, const double *psi, hipStream_t st);
+extern void mlp_note_cost(bidomain_s *b, double cost, bool learned);
 
 int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStream_t st) {
   DevProblem &p = *prob;
@@ -544,7 +551,10 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   k_mid_be<<<nblk(n), kB, 0, st>>>(p.f64.work, s.V, s.q, s.phi, meanp, n, p.N, p.P, p.comp_stride, dth, m);
   KFBI_HIP(hipGetLastError());
   // record (features, target) once two earlier densities and g'^{n-1} exist
-  if (mlp && steps_done >= 2) mlp_record(this, hist1, hist2, psi0, st);
+  if (mlp && steps_done >= 2) {
+    mlp_record(this, hist1, hist2, psi0, st);
+    if (params.warm_start == 1) mlp_note_cost(this, info.matvecs_fp64 + 0.5 * info.matvecs_fp32, info.warm_start_used);
+  }
   KFBI_HIP(hipMemcpyAsync(gp_prev, sv.gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   ++steps_done;
   KFBI_HIP(hipMemcpyAsync(hist2, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));

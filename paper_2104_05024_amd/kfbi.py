@@ -59,7 +59,7 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("matvecs_fp64", C.c_int32),
                 ("matvecs_fp32", C.c_int32), ("rel_resid", C.c_double), ("gp_norm", C.c_double),
-                ("warm_start_used", C.c_int32), ("pad_", C.c_int32)]
+                ("warm_start_used", C.c_int32), ("pad_", C.c_int32), ("start_resid", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
