@@ -544,7 +544,14 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ 
   __shared__ C2<T> sbuf[NP * PADM];
   __shared__ T slam[M];
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y = DIM == 3 ? (int)blockIdx.y : 0;
+  // A tile row of TX columns is half of a 128-byte line; the tile sharing the line is given
+  // to the workgroup dispatched 8 later, i.e. on the same XCD (round-robin dispatch), so the
+  // second half of the line comes from that XCD's L2 instead of a second HBM fetch.
+  int64_t id = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  const int64_t total = (int64_t)gridDim.x * gridDim.y;
+  if (id < (total & ~int64_t(15))) id = (id & ~int64_t(15)) + 2 * (id & 7) + ((id >> 3) & 1);
+  const int bx = (int)(id % gridDim.x);
+  const int x0 = bx * TX, y = DIM == 3 ? (int)(id / gridDim.x) : 0;
   T *base = a + (DIM == 3 ? (int64_t)y * P : 0);
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   Tl::load(base, LS * P, comp_stride, x0, sbuf, tid);
