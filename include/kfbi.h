@@ -236,9 +236,11 @@ int bidomain_mlp_eval(bidomain_ctx b, const float *X, int64_t R, float *Y, const
 const char *kfbi_strerror(int code);
 const char *kfbi_last_error(void);
 
-/* Timing of the last kfbi_apply / box solve launches on the problem's stream, measured
- * with HIP events: per-kernel average microseconds for the named kernel class
- * ("dst_x", "dst_y", "dst_last", "correct", "gather", "jumps"). Returns KFBI_EINVAL if unknown. */
+/* Timing of the kernel launches on the problem's stream since profiling was enabled, measured
+ * with HIP events around each launch: average microseconds and launch count for the named
+ * kernel class ("dst_x", "dst_y", "dst_last" (dense passes), "dst_x_rows", "dst_y_sparse"
+ * (row-masked passes of the matrix-vector product), "correct", "gather", "jumps").
+ * Returns KFBI_EINVAL if the name is unknown. */
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
 int kfbi_profile(kfbi_problem p, int32_t enable);
 

@@ -113,7 +113,7 @@ struct DevProblem {
   double *host_red = nullptr;  // pinned host mirror
 
   bool profile = false;
-  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps;
+  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse;
   hipStream_t stream = nullptr;
 
   template <typename T>

@@ -725,15 +725,15 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   auto toc = [&](Timer &t) { t.toc(p.profile, st); };
   const unsigned gin = (unsigned)((p.n_rows_in + 2 * Sh::NP - 1) / (2 * Sh::NP));
   const unsigned gout = (unsigned)((p.n_rows_out + 2 * Sh::NP - 1) / (2 * Sh::NP));
-  tic(p.t_dst_x);
+  tic(p.t_dst_x_rows);
   if (gin) k_dst_x_rows<T, M><<<gin, Sh::NT, 0, st>>>(tb.rhs, X, p.rows_in, p.n_rows_in, tw, sp);
   KFBI_HIP(hipGetLastError());
-  toc(p.t_dst_x);
+  toc(p.t_dst_x_rows);
   const dim3 gy((N + 2 * Sh::NP - 1) / (2 * Sh::NP), N, p.ncomp);
-  tic(p.t_dst_y);
+  tic(p.t_dst_y_sparse);
   k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(X, A, P, cs, p.mask_in, nullptr, tw, sp);
   KFBI_HIP(hipGetLastError());
-  toc(p.t_dst_y);
+  toc(p.t_dst_y_sparse);
   const int tx = p.ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 gl((N + tx - 1) / tx, N, 1);
   tic(p.t_dst_last);
@@ -741,14 +741,14 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   else k_dst_last<T, M, 1, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_last);
-  tic(p.t_dst_y);
+  tic(p.t_dst_y_sparse);
   k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, p.mask_out, tw, sp);
   KFBI_HIP(hipGetLastError());
-  toc(p.t_dst_y);
-  tic(p.t_dst_x);
+  toc(p.t_dst_y_sparse);
+  tic(p.t_dst_x_rows);
   if (gout) k_dst_x_rows<T, M><<<gout, Sh::NT, 0, st>>>(A, A, p.rows_out, p.n_rows_out, tw, sp);
   KFBI_HIP(hipGetLastError());
-  toc(p.t_dst_x);
+  toc(p.t_dst_x_rows);
 }
 
 }  // namespace

@@ -502,7 +502,8 @@ void upload_tables(DevProblem &p) {
   upload_prec<float>(p, p.f32, z_w0, z_wga, z_na, z_cw, q_wg, q_n, q_wt, arm_d, arm_s, st_nw, st_r, tw, sp);
   p.red = dalloc<double>(4096);
   KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
-  Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps};
+  Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
+                 &p.t_dst_y_sparse};
   for (Timer *tm : ts) tm->create();
 }
 
@@ -528,7 +529,8 @@ void free_tables(DevProblem &p) {
   p.host_red = nullptr;
   free_prec(p.f64);
   free_prec(p.f32);
-  Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps};
+  Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
+                 &p.t_dst_y_sparse};
   for (Timer *tm : ts) tm->destroy();
 }
 
