@@ -231,6 +231,35 @@ int bidomain_mlp_params(bidomain_ctx b, float *host_dst, int64_t *count);
 int bidomain_mlp_eval(bidomain_ctx b, const float *X, int64_t R, float *Y, const float *dY, float *grad,
                       void *stream);
 
+/* ----------------------------------------------------------------- batched 2D problems */
+
+/* A batch of independent two-dimensional one-component Neumann problems (the scalar form
+ * of the interface problem, Sec. 2 and 4) with uneven grid sizes (cells = 2^k in [16, 1024])
+ * and shapes, solved together: problems of one grid size share each DST pass launch; the
+ * jump, correction and gather kernels of all problems run as one launch each over a work
+ * list; GMRES runs in lockstep for all problems with one Arnoldi step captured once as a
+ * hipGraph and replayed.  Concatenated layouts: interface arrays [problem][M_p] (offsets from
+ * kfbi_batch_query), grid arrays [problem][N_p^2] in the caller layout (x fastest). */
+typedef struct kfbi_batch_s *kfbi_batch;
+
+int kfbi_batch_setup(int32_t n, const kfbi_interface *ifaces, const kfbi_grid *grids, const kfbi_coeffs *coeffs,
+                     kfbi_batch *out);
+void kfbi_batch_destroy(kfbi_batch b);
+/* problem i: nodes M, grid unknowns per axis N, offsets into the concatenated interface and
+ * grid arrays; i = -1 returns the totals in iface_offset / grid_offset. */
+int kfbi_batch_query(kfbi_batch b, int32_t i, int64_t *M, int64_t *N, int64_t *iface_offset,
+                     int64_t *grid_offset);
+/* A psi for every problem (device, concatenated, KFBI_F64 or KFBI_F32). */
+int kfbi_batch_apply(kfbi_batch b, const void *psi, void *out, int32_t dtype, void *stream);
+/* Every problem's Neumann solve (FP64 device arrays, concatenated; g may be NULL for zero
+ * Neumann data); opts as for kfbi_solve_neumann (method 0 only), the tolerance relative to
+ * each problem's own ||g'||; info: one record per problem.  KFBI_ENOCONV if any problem did
+ * not converge (all outputs are still written). */
+int kfbi_batch_solve_neumann(kfbi_batch b, const double *g, const double *f, double *u, double *psi,
+                             const kfbi_solve_opts *opts, kfbi_solve_info *info, void *stream);
+/* enable != 0 (default): replay the captured Arnoldi step; 0: launch its kernels directly. */
+int kfbi_batch_graph(kfbi_batch b, int32_t enable);
+
 /* ----------------------------------------------------------------- utilities */
 
 const char *kfbi_strerror(int code);

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "device.h"
+#include "batch.h"
 #include "solver.h"
 
 namespace kfbi {
@@ -24,6 +25,10 @@ int mlp_eval(bidomain_s *b, const float *X_host, int64_t R, float *Y_host, float
 struct kfbi_problem_s {
   DevProblem p;
   Solver solver;
+};
+
+struct kfbi_batch_s {
+  Batch b;
 };
 
 namespace {
@@ -189,6 +194,77 @@ int kfbi_solve_neumann(kfbi_problem p, const double *g, const double *f, double 
     if (info) *info = inf;
     return rc;
   });
+}
+
+int kfbi_batch_setup(int32_t n, const kfbi_interface *ifaces, const kfbi_grid *grids, const kfbi_coeffs *coeffs,
+                     kfbi_batch *out) {
+  return guard([&]() -> int {
+    if (!ifaces || !grids || !coeffs || !out || n < 1) return fail(KFBI_EINVAL, "argument");
+    *out = nullptr;
+    std::unique_ptr<kfbi_batch_s> h(new kfbi_batch_s());
+    try {
+      h->b.init(n, ifaces, grids, coeffs);
+    } catch (...) {
+      h->b.release();
+      throw;
+    }
+    *out = h.release();
+    return KFBI_OK;
+  });
+}
+
+void kfbi_batch_destroy(kfbi_batch b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  b->b.release();
+  delete b;
+}
+
+int kfbi_batch_query(kfbi_batch b, int32_t i, int64_t *M, int64_t *N, int64_t *iface_offset, int64_t *grid_offset) {
+  if (!b || i < -1 || i >= b->b.np) return fail(KFBI_EINVAL, "argument");
+  if (i == -1) {
+    if (M) *M = b->b.L;
+    if (N) *N = 0;
+    if (iface_offset) *iface_offset = b->b.L;
+    if (grid_offset) *grid_offset = b->b.goff[b->b.np];
+    return KFBI_OK;
+  }
+  if (M) *M = b->b.probs[i]->M;
+  if (N) *N = b->b.probs[i]->N;
+  if (iface_offset) *iface_offset = b->b.off[i];
+  if (grid_offset) *grid_offset = b->b.goff[i];
+  return KFBI_OK;
+}
+
+int kfbi_batch_apply(kfbi_batch b, const void *psi, void *out, int32_t dtype, void *stream) {
+  return guard([&]() -> int {
+    if (!b || !psi || !out) return fail(KFBI_EINVAL, "argument");
+    const hipStream_t st = (hipStream_t)stream;
+    if (dtype == KFBI_F64) b->b.matvec<double>((const double *)psi, (double *)out, st);
+    else if (dtype == KFBI_F32) b->b.matvec<float>((const float *)psi, (float *)out, st);
+    else return fail(KFBI_EINVAL, "dtype");
+    KFBI_HIP(hipStreamSynchronize(st));
+    return KFBI_OK;
+  });
+}
+
+int kfbi_batch_solve_neumann(kfbi_batch b, const double *g, const double *f, double *u, double *psi,
+                             const kfbi_solve_opts *opts, kfbi_solve_info *info, void *stream) {
+  return guard([&]() -> int {
+    if (!b || !f || !u || !psi || !opts) return fail(KFBI_EINVAL, "argument");
+    if (opts->method != 0) return fail(KFBI_EINVAL, "batched solves use GMRES");
+    if (opts->restart < 1 || opts->restart > Batch::kMaxRestart || opts->max_iters < 1 || !(opts->tol > 0))
+      return fail(KFBI_EINVAL, "solve options");
+    const int rc = b->b.solve(g, f, u, psi, *opts, info, (hipStream_t)stream);
+    if (rc == KFBI_ENOCONV) g_last_error = "some problems of the batch did not converge";
+    return rc;
+  });
+}
+
+int kfbi_batch_graph(kfbi_batch b, int32_t enable) {
+  if (!b) return fail(KFBI_EINVAL, "argument");
+  b->b.use_graph = enable != 0;
+  return KFBI_OK;
 }
 
 int kfbi_profile(kfbi_problem p, int32_t enable) {

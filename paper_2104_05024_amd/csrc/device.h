@@ -125,6 +125,39 @@ inline PrecTables<double> &DevProblem::tab<double>() { return f64; }
 template <>
 inline PrecTables<float> &DevProblem::tab<float>() { return f32; }
 
+// Mode solve parameters of one problem: eigenvalues (4/h^2) sin^2(k pi / 2M), k = 1..N,
+// diagonal conductivities of the (one or two) components, kappa, and the (2/M)^d factor.
+struct ModeParams {
+  const double *lam;
+  double D0, D1, kappa, norm;
+};
+
+// One two-dimensional, one-component problem of a batch as the batched interface kernels see
+// it: its tables, its fields inside the size-group buffers, and its offset in the
+// concatenated interface vectors.
+template <typename T>
+struct BatchItem {
+  const int32_t *z_idx;
+  const T *z_w0, *z_wga, *z_na, *z_cw;
+  const int32_t *irr_pos, *irr_ptr, *arm_cross;
+  const T *arm_d, *arm_s;
+  const int32_t *q_idx;
+  const T *q_wg, *q_n, *q_wt;
+  const int32_t *st_pos;
+  const T *st_nw, *st_r;
+  T *jz, *jq;
+  T *rhs, *fpad, *work;        // padded fields inside the group buffers
+  int64_t M, nc, nirr, ioff;
+  T sigma, isig;
+};
+
+// Prefix sums over the problems of a batch (device arrays of n + 1 entries) and totals.
+struct BatchCounts {
+  const int64_t *cum_nc = nullptr, *cum_M = nullptr, *cum_nirr = nullptr;
+  int n = 0;
+  int64_t tot_nc = 0, tot_M = 0, tot_nirr = 0;
+};
+
 // ---- launchers (defined in dst.hip / kfbi_kernels.hip)
 // Box solve: dst = S(src). Layout flags: true = caller (unpadded) layout, false = padded.
 template <typename T>
@@ -143,6 +176,19 @@ template <typename T>
 void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream_t st);
 template <typename T>
 void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st);
+
+// Batched 2D launches: jumps of every problem (crossings and nodes) in one launch; the
+// correction into rhs (overwrite, target 0) or fpad (accumulate, target 1); the gather from work.
+template <typename T>
+void launch_batch_jumps(const BatchItem<T> *items, const BatchCounts &c, const T *psi, hipStream_t st);
+template <typename T>
+void launch_batch_correct(const BatchItem<T> *items, const BatchCounts &c, int target, hipStream_t st);
+template <typename T>
+void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, T *out, hipStream_t st);
+// Grouped 2D box solve of G equal-size problems (padded layout, stride cs, msv on the device).
+template <typename T>
+void box_solve_group(int Mfft, int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw,
+                     const T *sp, hipStream_t st);
 
 void upload_tables(DevProblem &p);
 void free_tables(DevProblem &p);

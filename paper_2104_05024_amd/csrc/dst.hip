@@ -522,20 +522,21 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_y(const T *__restrict
   Tl::store(out + off, P, 0, x0, sbuf, tid, mask_out ? mask_out + (int64_t)z * Sh::N : nullptr);
 }
 
-struct ModeScale {
-  const double *lam;   // (4/h^2) sin^2(k pi / 2M), k = 1..N
-  double D0, D1, kappa, norm;
-};
+using ModeScale = ModeParams;
 
 // Last axis (z in 3D, y in 2D), fused: forward DST -> mode solve -> inverse DST, in place.
 // The mode solve is u^ = f^ / (D L + kappa) (one component) or the closed-form inverse of
 // [[a_i + kappa, -kappa], [-kappa, a_e + kappa]], a_c = D_c L (coupled pair), with
 // L = lambda_kx + lambda_ky (+ lambda_kz) and norm = (2/M)^d for the inverse transforms.
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
+// In 2D, blockIdx.y may index the problems of a batch of equal-size fields at stride pstride,
+// each with its own mode parameters msv[problem] (msv = nullptr: one problem, parameters ms).
 template <typename T, int M, int NC, int DIM>
 __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
-                                                                  ModeScale ms, const C2<T> *__restrict__ tw,
-                                                                  const T *__restrict__ sp) {
+                                                                  ModeScale ms0, const C2<T> *__restrict__ tw,
+                                                                  const T *__restrict__ sp,
+                                                                  const ModeScale *__restrict__ msv = nullptr,
+                                                                  int64_t pstride = 0) {
   using Sh = Shape<T, M>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
@@ -550,9 +551,10 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ 
   int64_t id = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
   const int64_t total = (int64_t)gridDim.x * gridDim.y;
   if (id < (total & ~int64_t(15))) id = (id & ~int64_t(15)) + 2 * (id & 7) + ((id >> 3) & 1);
-  const int bx = (int)(id % gridDim.x);
-  const int x0 = bx * TX, y = DIM == 3 ? (int)(id / gridDim.x) : 0;
-  T *base = a + (DIM == 3 ? (int64_t)y * P : 0);
+  const int bx = (int)(id % gridDim.x), by = (int)(id / gridDim.x);
+  const int x0 = bx * TX, y = DIM == 3 ? by : 0;
+  T *base = a + (DIM == 3 ? (int64_t)y * P : (int64_t)by * pstride);
+  const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   Tl::load(base, LS * P, comp_stride, x0, sbuf, tid);
   __syncthreads();
@@ -751,7 +753,47 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   toc(p.t_dst_x_rows);
 }
 
+// Grouped 2D box solve of G one-component problems of equal size, stored at stride cs in
+// padded layout: one launch per pass for the whole group.
+template <typename T, int M>
+void run_box_group(int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw_, const T *sp,
+                   hipStream_t st) {
+  using Sh = Shape<T, M>;
+  constexpr int N = Sh::N;
+  const C2<T> *tw = reinterpret_cast<const C2<T> *>(tw_);
+  const int64_t rows = (int64_t)G * N;
+  if (cs != (int64_t)N * M) throw std::invalid_argument("group stride");
+  const dim3 gx((unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP)));
+  k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(src, dst, rows, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  const int tx = 2 * Sh::NP;
+  const dim3 gl((N + tx - 1) / tx, G, 1);
+  k_dst_last<T, M, 1, 2><<<gl, Sh::NT, 0, st>>>(dst, M, cs, ModeParams{}, tw, sp, msv, cs);
+  KFBI_HIP(hipGetLastError());
+  k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(dst, dst, rows, tw, sp);
+  KFBI_HIP(hipGetLastError());
+}
+
 }  // namespace
+
+template <typename T>
+void box_solve_group(int Mfft, int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw,
+                     const T *sp, hipStream_t st) {
+  switch (Mfft) {
+    case 16: run_box_group<T, 16>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 32: run_box_group<T, 32>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 64: run_box_group<T, 64>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 128: run_box_group<T, 128>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 256: run_box_group<T, 256>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 512: run_box_group<T, 512>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 1024: run_box_group<T, 1024>(G, src, dst, cs, msv, tw, sp, st); break;
+    default: throw std::invalid_argument("unsupported grid size");
+  }
+}
+template void box_solve_group<double>(int, int, const double *, double *, int64_t, const ModeParams *,
+                                      const double *, const double *, hipStream_t);
+template void box_solve_group<float>(int, int, const float *, float *, int64_t, const ModeParams *, const float *,
+                                     const float *, hipStream_t);
 
 template <typename T>
 void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st) {

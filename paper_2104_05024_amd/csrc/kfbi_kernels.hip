@@ -23,13 +23,11 @@ constexpr int kBlock = 256;
 // All stencil sizes are compile-time constants so that every index load of a thread is
 // issued before the dependent gathers (the kernels are latency-bound, not bandwidth-bound).
 template <typename T, int D, int K>
-__global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc,
-                                                        const int32_t *__restrict__ z_idx,
-                                                        const T *__restrict__ z_w0, const T *__restrict__ z_wga,
-                                                        const T *__restrict__ z_na, const T *__restrict__ z_cw,
-                                                        int ncomp, T is0, T is1, T *__restrict__ jz) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
+__device__ __forceinline__ void jumps_cross_at(int64_t c, const T *__restrict__ psi, int64_t M, int64_t nc,
+                                               const int32_t *__restrict__ z_idx, const T *__restrict__ z_w0,
+                                               const T *__restrict__ z_wga, const T *__restrict__ z_na,
+                                               const T *__restrict__ z_cw, int ncomp, T is0, T is1,
+                                               T *__restrict__ jz) {
   int32_t j[K];
   T w[K], wg[K];
 #pragma unroll
@@ -57,17 +55,24 @@ __global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ ps
   }
 }
 
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc,
+                                                        const int32_t *__restrict__ z_idx,
+                                                        const T *__restrict__ z_w0, const T *__restrict__ z_wga,
+                                                        const T *__restrict__ z_na, const T *__restrict__ z_cw,
+                                                        int ncomp, T is0, T is1, T *__restrict__ jz) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) jumps_cross_at<T, D, K>(c, psi, M, nc, z_idx, z_w0, z_wga, z_na, z_cw, ncomp, is0, is1, jz);
+}
+
 // One thread per irregular node; at most 2D arms, loaded predicated and all at once.
 template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t *__restrict__ irr_pos,
-                                                    const int32_t *__restrict__ irr_ptr,
-                                                    const int32_t *__restrict__ arm_cross,
-                                                    const T *__restrict__ arm_d, const T *__restrict__ arm_s,
-                                                    const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
-                                                    T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
+__device__ __forceinline__ void correct_at(int64_t r, const int32_t *__restrict__ irr_pos,
+                                           const int32_t *__restrict__ irr_ptr, const int32_t *__restrict__ arm_cross,
+                                           const T *__restrict__ arm_d, const T *__restrict__ arm_s,
+                                           const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
+                                           T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
   constexpr int MAXA = 2 * D;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nirr) return;
   const int32_t b = irr_ptr[r], e = irr_ptr[r + 1];
   const int64_t pos = irr_pos[r];
   int32_t cr[MAXA];
@@ -98,6 +103,19 @@ __global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t 
   }
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t *__restrict__ irr_pos,
+                                                    const int32_t *__restrict__ irr_ptr,
+                                                    const int32_t *__restrict__ arm_cross,
+                                                    const T *__restrict__ arm_d, const T *__restrict__ arm_s,
+                                                    const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
+                                                    T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nirr)
+    correct_at<T, D>(r, irr_pos, irr_ptr, arm_cross, arm_d, arm_s, jz, nc, ncomp, D0, D1, rhs, comp_stride,
+                     accumulate);
+}
+
 template <int D>
 struct NH {
   static constexpr int v = D == 2 ? 3 : 6;   // symmetric entries: xx yy (zz) xy (xz yz)
@@ -115,14 +133,11 @@ __device__ __forceinline__ void sym_index(int e, int &a, int &b) {
 }
 
 template <typename T, int D, int KN>
-__global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M,
-                                                        const int32_t *__restrict__ q_idx,
-                                                        const T *__restrict__ q_wg, const T *__restrict__ q_n,
-                                                        const T *__restrict__ q_wt, int ncomp, T is0, T is1,
-                                                        T *__restrict__ jq) {
+__device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ psi, int64_t M,
+                                               const int32_t *__restrict__ q_idx, const T *__restrict__ q_wg,
+                                               const T *__restrict__ q_n, const T *__restrict__ q_wt, int ncomp,
+                                               T is0, T is1, T *__restrict__ jq) {
   constexpr int NHv = NH<D>::v, STR = D + NHv;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= M) return;
   int32_t j[KN];
 #pragma unroll
   for (int k = 0; k < KN; ++k) j[k] = q_idx[k * M + q];
@@ -157,15 +172,22 @@ __global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ ps
   }
 }
 
-template <typename T, int D, int S>
-__global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M,
-                                                   const int32_t *__restrict__ st_pos,
-                                                   const T *__restrict__ st_nw, const T *__restrict__ st_r,
-                                                   const T *__restrict__ jq, int ncomp, T s0, T s1, int with_jumps,
-                                                   T *__restrict__ out) {
-  constexpr int NHv = NH<D>::v, STR = D + NHv;
+template <typename T, int D, int KN>
+__global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M,
+                                                        const int32_t *__restrict__ q_idx,
+                                                        const T *__restrict__ q_wg, const T *__restrict__ q_n,
+                                                        const T *__restrict__ q_wt, int ncomp, T is0, T is1,
+                                                        T *__restrict__ jq) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= M) return;
+  if (q < M) jumps_nodes_at<T, D, KN>(q, psi, M, q_idx, q_wg, q_n, q_wt, ncomp, is0, is1, jq);
+}
+
+template <typename T, int D, int S>
+__device__ __forceinline__ void gather_at(int64_t q, const T *__restrict__ u, int64_t comp_stride, int64_t M,
+                                          const int32_t *__restrict__ st_pos, const T *__restrict__ st_nw,
+                                          const T *__restrict__ st_r, const T *__restrict__ jq, int ncomp, T s0,
+                                          T s1, int with_jumps, T *__restrict__ out) {
+  constexpr int NHv = NH<D>::v, STR = D + NHv;
   int32_t pe[S];
   T nw[S];
 #pragma unroll
@@ -213,7 +235,70 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int6
   }
 }
 
+template <typename T, int D, int S>
+__global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M,
+                                                   const int32_t *__restrict__ st_pos,
+                                                   const T *__restrict__ st_nw, const T *__restrict__ st_r,
+                                                   const T *__restrict__ jq, int ncomp, T s0, T s1, int with_jumps,
+                                                   T *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < M) gather_at<T, D, S>(q, u, comp_stride, M, st_pos, st_nw, st_r, jq, ncomp, s0, s1, with_jumps, out);
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Problem of a flattened batch item: the largest p with cum[p] <= i (cum[0] = 0 <= i < cum[n]).
+__device__ __forceinline__ int batch_problem(const int64_t *__restrict__ cum, int n, int64_t i) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (cum[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Work list of one launch: all crossings of all problems, then all their nodes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_batch_jumps(const BatchItem<T> *__restrict__ items, BatchCounts c,
+                                                        const T *__restrict__ psi) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < c.tot_nc) {
+    const int p = batch_problem(c.cum_nc, c.n, i);
+    const BatchItem<T> &it = items[p];
+    jumps_cross_at<T, 2, 4>(i - c.cum_nc[p], psi + it.ioff, it.M, it.nc, it.z_idx, it.z_w0, it.z_wga, it.z_na,
+                            it.z_cw, 1, it.isig, it.isig, it.jz);
+    return;
+  }
+  i -= c.tot_nc;
+  if (i >= c.tot_M) return;
+  const int p = batch_problem(c.cum_M, c.n, i);
+  const BatchItem<T> &it = items[p];
+  jumps_nodes_at<T, 2, 5>(i - c.cum_M[p], psi + it.ioff, it.M, it.q_idx, it.q_wg, it.q_n, it.q_wt, 1, it.isig,
+                          it.isig, it.jq);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_batch_correct(const BatchItem<T> *__restrict__ items, BatchCounts c,
+                                                          int target) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.tot_nirr) return;
+  const int p = batch_problem(c.cum_nirr, c.n, i);
+  const BatchItem<T> &it = items[p];
+  correct_at<T, 2>(i - c.cum_nirr[p], it.irr_pos, it.irr_ptr, it.arm_cross, it.arm_d, it.arm_s, it.jz, it.nc, 1,
+                   it.sigma, it.sigma, target ? it.fpad : it.rhs, 0, target);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchItem<T> *__restrict__ items, BatchCounts c,
+                                                         int with_jumps, T *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.tot_M) return;
+  const int p = batch_problem(c.cum_M, c.n, i);
+  const BatchItem<T> &it = items[p];
+  gather_at<T, 2, 6>(i - c.cum_M[p], it.work, 0, it.M, it.st_pos, it.st_nw, it.st_r, it.jq, 1, it.sigma, it.sigma,
+                     with_jumps, out + it.ioff);
+}
 
 template <typename T>
 T *dalloc(size_t n) {
@@ -337,6 +422,33 @@ void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream
                                                     p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
   KFBI_HIP(hipGetLastError());
 }
+
+template <typename T>
+void launch_batch_jumps(const BatchItem<T> *items, const BatchCounts &c, const T *psi, hipStream_t st) {
+  const int64_t n = c.tot_nc + c.tot_M;
+  if (n == 0) return;
+  k_batch_jumps<T><<<nblk(n), kBlock, 0, st>>>(items, c, psi);
+  KFBI_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_batch_correct(const BatchItem<T> *items, const BatchCounts &c, int target, hipStream_t st) {
+  if (c.tot_nirr == 0) return;
+  k_batch_correct<T><<<nblk(c.tot_nirr), kBlock, 0, st>>>(items, c, target);
+  KFBI_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, T *out, hipStream_t st) {
+  if (c.tot_M == 0) return;
+  k_batch_gather<T><<<nblk(c.tot_M), kBlock, 0, st>>>(items, c, with_jumps ? 1 : 0, out);
+  KFBI_HIP(hipGetLastError());
+}
+template void launch_batch_jumps<double>(const BatchItem<double> *, const BatchCounts &, const double *, hipStream_t);
+template void launch_batch_jumps<float>(const BatchItem<float> *, const BatchCounts &, const float *, hipStream_t);
+template void launch_batch_correct<double>(const BatchItem<double> *, const BatchCounts &, int, hipStream_t);
+template void launch_batch_correct<float>(const BatchItem<float> *, const BatchCounts &, int, hipStream_t);
+template void launch_batch_gather<double>(const BatchItem<double> *, const BatchCounts &, bool, double *,
+                                          hipStream_t);
+template void launch_batch_gather<float>(const BatchItem<float> *, const BatchCounts &, bool, float *, hipStream_t);
 
 template void launch_jumps<double>(DevProblem &, const double *, hipStream_t);
 template void launch_jumps<float>(DevProblem &, const float *, hipStream_t);

@@ -23,6 +23,8 @@ EXPORTED = [
     "kfbi_setup", "kfbi_destroy", "kfbi_query", "kfbi_table", "kfbi_apply", "kfbi_box_solve", "kfbi_solve_neumann",
     "bidomain_create", "bidomain_destroy", "bidomain_step", "bidomain_mlp_init", "bidomain_train",
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
+    "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
+    "kfbi_batch_graph",
     "kfbi_profile",
 ]
 
@@ -109,6 +111,14 @@ def lib():
     L.kfbi_last_error.restype = C.c_char_p
     L.kfbi_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dp), i64p]
     L.kfbi_profile.argtypes = [vp, i32]
+    L.kfbi_batch_setup.argtypes = [i32, C.POINTER(Interface), C.POINTER(GridDesc), C.POINTER(CoeffsDesc),
+                                   C.POINTER(vp)]
+    L.kfbi_batch_destroy.argtypes = [vp]
+    L.kfbi_batch_destroy.restype = None
+    L.kfbi_batch_query.argtypes = [vp, i32, i64p, i64p, i64p, i64p]
+    L.kfbi_batch_apply.argtypes = [vp, vp, vp, i32, vp]
+    L.kfbi_batch_solve_neumann.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    L.kfbi_batch_graph.argtypes = [vp, i32]
     _lib = L
     return L
 
@@ -255,6 +265,74 @@ class Problem:
         us, n = C.c_double(), C.c_int64()
         _check(lib().kfbi_kernel_time(self._h, name.encode(), C.byref(us), C.byref(n)))
         return us.value, n.value
+
+
+class Batch:
+    """Many 2D one-component Neumann problems solved together (size-grouped DST launches,
+    work-list interface kernels, lockstep GMRES with a captured Arnoldi step)."""
+
+    def __init__(self, problems):
+        """problems: list of (interface, grid, coeffs) with dim 2 and one component."""
+        n = len(problems)
+        self.n = n
+        self._ifs = (Interface * n)(*[interface_desc(p[0]) for p in problems])
+        self._grs = (GridDesc * n)(*[grid_desc(p[1]) for p in problems])
+        self._cos = (CoeffsDesc * n)(*[coeffs_desc(p[2]) for p in problems])
+        self._h = C.c_void_p()
+        _check(lib().kfbi_batch_setup(n, self._ifs, self._grs, self._cos, C.byref(self._h)))
+        self.M, self.N, self.ioff, self.goff = [], [], [], []
+        for i in range(n):
+            M, N, io, go = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+            _check(lib().kfbi_batch_query(self._h, i, C.byref(M), C.byref(N), C.byref(io), C.byref(go)))
+            self.M.append(M.value)
+            self.N.append(N.value)
+            self.ioff.append(io.value)
+            self.goff.append(go.value)
+        L, G = C.c_int64(), C.c_int64()
+        _check(lib().kfbi_batch_query(self._h, -1, None, None, C.byref(L), C.byref(G)))
+        self.L, self.G = L.value, G.value
+
+    def close(self):
+        if self._h:
+            lib().kfbi_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def graph(self, enable=True):
+        _check(lib().kfbi_batch_graph(self._h, 1 if enable else 0))
+
+    def apply(self, psi, out=None):
+        """A psi for every problem; psi is a concatenated (L,) torch tensor (float64 / float32)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(psi)
+        dt = {torch.float64: KFBI_F64, torch.float32: KFBI_F32}[psi.dtype]
+        assert psi.is_contiguous() and out.is_contiguous() and psi.numel() == self.L
+        _check(lib().kfbi_batch_apply(self._h, _ptr(psi), _ptr(out), dt, _stream()))
+        return out
+
+    def solve_neumann(self, g, f, psi=None, u=None, allow_noconv=False, **opts):
+        """g: (L,) or None, f: (G,) concatenated float64 tensors; returns u, psi, [info per problem]."""
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        if psi is None:
+            psi = torch.zeros(self.L, dtype=torch.float64, device=f.device)
+            opts.setdefault("x0", 0)
+        else:
+            opts.setdefault("x0", 1)
+        assert f.numel() == self.G and psi.numel() == self.L
+        o = solve_opts(**opts)
+        infos = (SolveInfo * self.n)()
+        rc = lib().kfbi_batch_solve_neumann(self._h, _ptr(g), _ptr(f), _ptr(u), _ptr(psi), C.byref(o), infos,
+                                            _stream())
+        _check(rc, allow=(KFBI_ENOCONV,) if allow_noconv else ())
+        return u, psi, [i.as_dict() for i in infos]
 
 
 _INT_TABLES = {"cross_axis", "cross_surf", "cross_pin", "cross_pout", "z_idx", "q_idx", "st_lin", "irregular"}

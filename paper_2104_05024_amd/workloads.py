@@ -196,6 +196,38 @@ def config(name: str):
     raise KeyError(name)
 
 
+def _min_curvature_radius(R0, A, L, samples=4096):
+    """Smallest radius of curvature of the polar curve r = R0 + A cos(L t) (draw check only)."""
+    t = np.linspace(0.0, 2.0 * np.pi, samples, endpoint=False)
+    r = R0 + A * np.cos(L * t)
+    r1 = -A * L * np.sin(L * t)
+    r2 = -A * L * L * np.cos(L * t)
+    curv = np.abs(r * r + 2 * r1 * r1 - r * r2) / (r * r + r1 * r1) ** 1.5
+    return float(1.0 / np.max(curv))
+
+
+def batch_2d(n=64, seed=2, sizes=(64, 128, 256, 512, 1024)):
+    """Seeded batch of 2D Neumann problems of uneven sizes and shapes.
+
+    Per problem: cells drawn uniformly from ``sizes``, a star r = 0.7 + A cos(L t) with
+    L in 3..8 lobes and A ~ U[0.05, 0.2], kappa log-uniform in [50, 2000], sigma = 1 and
+    M = 2 cells nodes.  A draw whose smallest radius of curvature is below 2h is drawn again.
+    Returns a list of (interface, grid, coeffs).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        cells = int(rng.choice(sizes))
+        L = int(rng.integers(3, 9))
+        A = float(rng.uniform(0.05, 0.2))
+        kappa = float(np.exp(rng.uniform(np.log(50.0), np.log(2000.0))))
+        grid = box(2, cells)
+        if _min_curvature_radius(0.7, A, L) < 2.0 * grid.h:
+            continue
+        out.append((star2d(0.7, A, L, n_nodes=2 * cells), grid, scalar_coeffs(2, 1.0, kappa)))
+    return out
+
+
 def seeded_vector(n, seed, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
 

@@ -130,19 +130,19 @@ def test_apply_zero_density_gives_zero():
 
 # ----------------------------------------------------------------------------- Neumann solve (a7-a9)
 
-def _mms2d(g, grid):
+def _mms2d(o, grid):
+    """u = e^x sin(pi y): source on the grid and Neumann data at the oracle's nodes."""
     pts = ogeo.grid_points(grid)
     ue = np.exp(pts[:, 0]) * np.sin(np.pi * pts[:, 1])
     f = (np.pi ** 2 - 1 + 400.0) * ue
-    X = g.table("nodes_X").reshape(-1, 2)
-    n = g.table("nodes_n").reshape(-1, 2)
+    X, n = o.nodes.X, o.nodes.n
     grad = np.stack([np.exp(X[:, 0]) * np.sin(np.pi * X[:, 1]), np.pi * np.exp(X[:, 0]) * np.cos(np.pi * X[:, 1])], 1)
     return f[None], np.sum(n * grad, 1)[None], ue
 
 
 def test_solve_neumann_f64_matches_oracle_star2d():
     g, o, iface, grid, co = problems("star2d_128")
-    f, gn, ue = _mms2d(g, grid)
+    f, gn, ue = _mms2d(o, grid)
     say("[solve f64] star2d_128")
     u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-13)
     u = u.cpu().numpy()
@@ -159,7 +159,7 @@ def test_solve_neumann_f64_matches_oracle_star2d():
 
 def test_solve_neumann_mixed_precision_reaches_fp64_residual():
     g, o, iface, grid, co = problems("star2d_128")
-    f, gn, _ = _mms2d(g, grid)
+    f, gn, _ = _mms2d(o, grid)
     say("[solve mixed] star2d_128")
     u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-10, precision=1, inner_tol=1e-4)
     uo, _, _ = o.solve_neumann(gn, f, tol=1e-13)
@@ -191,7 +191,7 @@ def test_solve_neumann_coupled_gauge_and_V():
 
 def test_richardson_iteration_converges():
     g, o, iface, grid, co = problems("star2d_64")
-    f, gn, _ = _mms2d(g, grid)
+    f, gn, _ = _mms2d(o, grid)
     say("[richardson] star2d_64")
     u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-8, method=1, gamma=0.8, max_iters=400)
     uo, _, _ = o.solve_neumann(gn, f, tol=1e-12)
@@ -201,7 +201,7 @@ def test_richardson_iteration_converges():
 
 def test_noconv_is_reported():
     g, o, iface, grid, co = problems("star2d_64")
-    f, gn, _ = _mms2d(g, grid)
+    f, gn, _ = _mms2d(o, grid)
     with pytest.raises(K.KfbiError) as e:
         g.solve_neumann(T(gn), T(f), tol=1e-14, max_iters=2)
     assert e.value.code == K.KFBI_ENOCONV
@@ -256,8 +256,7 @@ def test_apply_and_solve_full_size_ellipsoid_128():
     assert e < 1e-10
     pts = ogeo.grid_points(grid)
     ue = np.sin(pts[:, 0]) * np.cos(pts[:, 1]) * np.exp(pts[:, 2])
-    X = g.table("nodes_X").reshape(-1, 3)
-    n = g.table("nodes_n").reshape(-1, 3)
+    X, n = o.nodes.X, o.nodes.n
     gr = np.stack([np.cos(X[:, 0]) * np.cos(X[:, 1]) * np.exp(X[:, 2]),
                    -np.sin(X[:, 0]) * np.sin(X[:, 1]) * np.exp(X[:, 2]),
                    np.sin(X[:, 0]) * np.cos(X[:, 1]) * np.exp(X[:, 2])], 1)

@@ -142,3 +142,23 @@ def test_crossings_are_on_the_surface_and_between_sides(name, cells):
     lo = np.minimum(pts[cr.p_in], pts[cr.p_out]) - 1e-15
     hi = np.maximum(pts[cr.p_in], pts[cr.p_out]) + 1e-15
     assert np.all((cr.z >= lo) & (cr.z <= hi))
+
+
+def test_batch_2d_draws_are_seeded_and_resolved():
+    """The batch generator is deterministic, covers the sizes, and every drawn star keeps its
+    smallest radius of curvature above 2h, checked with the oracle's shape operator (in 2D
+    tr W is the curvature) on points of the curve, independently of the generator's formula."""
+    a, b = W.batch_2d(), W.batch_2d()
+    assert len(a) == 64
+    assert [(g.cells, c.kappa) for _, g, c in a] == [(g.cells, c.kappa) for _, g, c in b]
+    assert {g.cells for _, g, _ in a} == {64, 128, 256, 512, 1024}
+    t = np.linspace(0, 2 * np.pi, 4096, endpoint=False)
+    u = np.stack([np.cos(t), np.sin(t)], axis=1)
+    for iface, grid, co in a:
+        assert 50.0 <= co.kappa <= 2000.0
+        assert iface.n_nodes == 2 * grid.cells
+        surf = iface.surfaces[0]
+        G, _, _ = geometry.radial(surf, u)
+        _, Wm = geometry.normal_and_shape(surf, G[:, None] * u)
+        curv = np.abs(np.trace(Wm, axis1=1, axis2=2))
+        assert 1.0 / np.max(curv) >= 2.0 * grid.h * (1 - 1e-3)
