@@ -125,7 +125,10 @@ __device__ __forceinline__ void dft(C2<T> *v) {
   }
 }
 
-__device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
+#ifndef KFBI_LDS_PAD_SHIFT
+#define KFBI_LDS_PAD_SHIFT 4
+#endif
+__device__ __forceinline__ int pad(int i) { return i + (i >> KFBI_LDS_PAD_SHIFT); }
 
 // 1/x from the hardware reciprocal estimate refined by Newton steps (two in FP64, one in FP32):
 // within an ulp or two of the IEEE quotient at a fraction of the cost of a full division.
@@ -146,7 +149,7 @@ struct Shape {
   static constexpr int TPP = M / 16;                          // threads per pencil pair
   static constexpr int NP = (sizeof(T) == 8 ? 2048 : 4096) / M;  // pencil pairs per workgroup
   static constexpr int NT = NP * TPP;                         // threads per workgroup (128 / 256)
-  static constexpr int PADM = M + M / 8 + 1;                  // padded LDS length of one pair (odd:
+  static constexpr int PADM = M + (M >> KFBI_LDS_PAD_SHIFT) + 1;                  // padded LDS length of one pair (odd:
                                                               // pairs start on different banks)
 };
 
@@ -207,11 +210,14 @@ template <typename T, int M, typename Hook = NoHook<T>>
 __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__restrict__ tw,
                                          const T *__restrict__ sp, const Hook &hook = Hook()) {
   constexpr int TPP = M / 16;
-  // pre-processing: (n, M-n) pairs are owned by one thread, so no barrier inside
+  // pre-processing: (n, M-n) pairs are owned by one thread, so no barrier inside; the hook
+  // sees every input value (position m = 1..N) as it is read
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int n = 1 + lane + TPP * i;
-    const C2<T> a = buf[pad(n)], b = buf[pad(M - n)];
+    C2<T> a = buf[pad(n)], b = buf[pad(M - n)];
+    hook(n, a);
+    hook(M - n, b);
     const T s = sp[n];
     const C2<T> sum = s * (a + b), dif = (T)0.5 * (a - b);
     buf[pad(n)] = sum + dif;
@@ -242,14 +248,8 @@ __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__re
   const C2<T> excl = inc - tot;
   const C2<T> E0 = {shfl_w(e0.x, 0, TPP), shfl_w(e0.y, 0, TPP)};
   const C2<T> half0 = (T)0.5 * E0;
-  // the hook sees every output (position m = mode index) before it is written back
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int k = 8 * lane + i;
-    od[i] = (excl + od[i]) - half0;
-    hook(2 * k + 1, od[i]);
-    if (k > 0) hook(2 * k, ev[i]);
-  }
+  for (int i = 0; i < 8; ++i) od[i] = (excl + od[i]) - half0;
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -524,6 +524,27 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_y(const T *__restrict
 
 using ModeScale = ModeParams;
 
+// Mode solve applied to each value as the inverse transform reads it (position m = mode index
+// along the last axis): u^ = f^ / (D L + kappa), or the closed-form inverse of the coupled 2x2.
+template <typename T, int NC>
+struct ModeHook {
+  const T *slam;
+  T L0, L1, D0, D1, kap, nrm;
+  __device__ __forceinline__ void operator()(int m, C2<T> &v) const {
+    const T lz = slam[m - 1];
+    if (NC == 2) {
+      const T L = L0 + lz, ai = D0 * L, ae = D1 * L;
+      const T s = nrm * recip(ai * ae + kap * (ai + ae));
+      const T fi = v.x, fe = v.y;
+      v.x = s * ((ae + kap) * fi + kap * fe);
+      v.y = s * (kap * fi + (ai + kap) * fe);
+    } else {
+      v.x *= nrm * recip(D0 * (L0 + lz) + kap);
+      v.y *= nrm * recip(D0 * (L1 + lz) + kap);
+    }
+  }
+};
+
 // Last axis (z in 3D, y in 2D), fused: forward DST -> mode solve -> inverse DST, in place.
 // The mode solve is u^ = f^ / (D L + kappa) (one component) or the closed-form inverse of
 // [[a_i + kappa, -kappa], [-kappa, a_e + kappa]], a_c = D_c L (coupled pair), with
@@ -561,39 +582,25 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ 
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
   C2<T> *mine = sbuf + pr * PADM;
   dst_pair<T, M>(mine, lane, tw, sp);
-  // mode solve on the thread's own pencil pair, positions m = mode index along the last axis
+  // inverse transform with the mode solve applied as it reads the spectrum
+  ModeHook<T, NC> mh;
+  mh.slam = slam;
   {
     const T ly = DIM == 3 ? slam[y] : T(0);
-    T L0, L1;
     if (NC == 2) {
       const int x = x0 + pr;
-      L0 = L1 = (x < N ? slam[x] : T(0)) + ly;
+      mh.L0 = mh.L1 = (x < N ? slam[x] : T(0)) + ly;
     } else {
       const int xa = x0 + 2 * pr, xb = xa + 1;
-      L0 = (xa < N ? slam[xa] : T(0)) + ly;
-      L1 = (xb < N ? slam[xb] : T(0)) + ly;
-    }
-    const T D0 = (T)ms.D0, D1 = (T)ms.D1, kap = (T)ms.kappa, nrm = (T)ms.norm;
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-      const int m = 1 + lane + Sh::TPP * i;
-      if (m > N) continue;
-      C2<T> &v = mine[pad(m)];
-      const T lz = slam[m - 1];
-      if (NC == 2) {
-        const T L = L0 + lz, ai = D0 * L, ae = D1 * L;
-        const T s = nrm * recip(ai * ae + kap * (ai + ae));
-        const T fi = v.x, fe = v.y;
-        v.x = s * ((ae + kap) * fi + kap * fe);
-        v.y = s * (kap * fi + (ai + kap) * fe);
-      } else {
-        v.x *= nrm * recip(D0 * (L0 + lz) + kap);
-        v.y *= nrm * recip(D0 * (L1 + lz) + kap);
-      }
+      mh.L0 = (xa < N ? slam[xa] : T(0)) + ly;
+      mh.L1 = (xb < N ? slam[xb] : T(0)) + ly;
     }
   }
-  __syncthreads();
-  dst_pair<T, M>(mine, lane, tw, sp);
+  mh.D0 = (T)ms.D0;
+  mh.D1 = (T)ms.D1;
+  mh.kap = (T)ms.kappa;
+  mh.nrm = (T)ms.norm;
+  dst_pair<T, M>(mine, lane, tw, sp, mh);
   Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
 
