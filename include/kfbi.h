@@ -97,6 +97,7 @@ typedef struct {
 typedef struct kfbi_problem_s *kfbi_problem;
 
 #define KFBI_SETUP_HOST_ONLY 1u   /* build the host tables only (no GPU calls) */
+#define KFBI_SETUP_NO_AUTOTUNE 2u /* keep the default DST tile widths (no timed launches at setup) */
 
 /* kfbi_setup: build every static table of the method for (interface, grid, coeffs)
  * -- interface nodes, normals, shape operators; grid-node sides; grid-line
@@ -271,6 +272,12 @@ const char *kfbi_last_error(void);
  * (row-masked passes of the matrix-vector product), "correct", "gather", "jumps").
  * Returns KFBI_EINVAL if the name is unknown. */
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
+/* DST tile widths (1 or 2: multiples of the base pencil pairs per workgroup) of the x, y and
+ * last-axis passes for dtype KFBI_F64 / KFBI_F32, as chosen by the autotuner at setup (each
+ * dense pass timed at both widths on the problem's own buffers); kfbi_set_tiles overrides them.
+ * Results do not depend on the widths (each pencil is transformed the same way). */
+int kfbi_get_tiles(kfbi_problem p, int32_t dtype, int32_t widths[3]);
+int kfbi_set_tiles(kfbi_problem p, int32_t dtype, const int32_t widths[3]);
 int kfbi_profile(kfbi_problem p, int32_t enable);
 
 #ifdef __cplusplus

@@ -89,6 +89,7 @@ int kfbi_setup(const kfbi_interface *iface, const kfbi_grid *grid, const kfbi_co
       try {
         upload_tables(h->p);
         h->solver.init(h->p);
+        if (!(flags & KFBI_SETUP_NO_AUTOTUNE)) autotune_tiles(h->p, nullptr);
       } catch (...) {
         h->solver.release();
         free_tables(h->p);
@@ -194,6 +195,20 @@ int kfbi_solve_neumann(kfbi_problem p, const double *g, const double *f, double 
     if (info) *info = inf;
     return rc;
   });
+}
+
+int kfbi_get_tiles(kfbi_problem p, int32_t dtype, int32_t widths[3]) {
+  if (!p || !widths || (dtype != KFBI_F64 && dtype != KFBI_F32)) return fail(KFBI_EINVAL, "argument");
+  for (int k = 0; k < 3; ++k) widths[k] = p->p.tile_w[dtype == KFBI_F64 ? 0 : 1][k];
+  return KFBI_OK;
+}
+
+int kfbi_set_tiles(kfbi_problem p, int32_t dtype, const int32_t widths[3]) {
+  if (!p || !widths || (dtype != KFBI_F64 && dtype != KFBI_F32)) return fail(KFBI_EINVAL, "argument");
+  for (int k = 0; k < 3; ++k)
+    if (widths[k] != 1 && widths[k] != 2) return fail(KFBI_EINVAL, "tile widths are 1 or 2");
+  for (int k = 0; k < 3; ++k) p->p.tile_w[dtype == KFBI_F64 ? 0 : 1][k] = widths[k];
+  return KFBI_OK;
 }
 
 int kfbi_batch_setup(int32_t n, const kfbi_interface *ifaces, const kfbi_grid *grids, const kfbi_coeffs *coeffs,

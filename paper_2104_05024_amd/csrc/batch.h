@@ -21,6 +21,7 @@ struct Group {
   double *rhs64 = nullptr, *fpad64 = nullptr, *work64 = nullptr;
   float *rhs32 = nullptr, *fpad32 = nullptr, *work32 = nullptr;
   ModeParams *msv = nullptr;   // per-slot mode parameters (device)
+  int tile_w[2][3] = {{1, 1, 1}, {1, 1, 1}};   // autotuned tile widths [FP64 / FP32][x, -, last]
   template <typename T>
   T *rhs() const;
   template <typename T>

@@ -310,6 +310,13 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
   nrm = balloc<double>(n);
   jdev = balloc<int>(1);
   KFBI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  // tile widths of every size group, timed on the group's own buffers
+  for (Group &g : groups) {
+    const DevProblem &p0 = *probs[g.members[0]];
+    const int G = (int)g.members.size();
+    autotune_group<double>(g.Mfft, G, g.work64, g.cs, g.msv, p0.f64.tw, p0.f64.sp, g.tile_w[0], cap);
+    autotune_group<float>(g.Mfft, G, g.work32, g.cs, g.msv, p0.f32.tw, p0.f32.sp, g.tile_w[1], cap);
+  }
 }
 
 void Batch::release() {
@@ -346,7 +353,8 @@ void Batch::matvec(const T *in, T *out, hipStream_t st) {
   for (const Group &g : groups) {
     const DevProblem &p0 = *probs[g.members[0]];
     const PrecTables<T> &tb = const_cast<DevProblem &>(p0).tab<T>();
-    box_solve_group<T>(g.Mfft, (int)g.members.size(), g.rhs<T>(), g.work<T>(), g.cs, g.msv, tb.tw, tb.sp, st);
+    box_solve_group<T>(g.Mfft, (int)g.members.size(), g.rhs<T>(), g.work<T>(), g.cs, g.msv, tb.tw, tb.sp,
+                       g.tile_w[sizeof(T) == 8 ? 0 : 1], st);
   }
   launch_batch_gather<T>(items<T>(), counts, true, out, st);
 }
@@ -534,7 +542,7 @@ int Batch::solve(const double *g, const double *f, double *u, double *psi, const
   for (const Group &gr : groups) {
     const DevProblem &p0 = *probs[gr.members[0]];
     box_solve_group<double>(gr.Mfft, (int)gr.members.size(), gr.fpad64, gr.work64, gr.cs, gr.msv, p0.f64.tw,
-                            p0.f64.sp, st);
+                            p0.f64.sp, gr.tile_w[0], st);
   }
   launch_batch_gather<double>(items64, counts, false, t, st);
   if (g) k_axpby<<<nb(L), kB, 0, st>>>(gp, 1.0, g, -1.0, t, L);
@@ -600,7 +608,7 @@ int Batch::solve(const double *g, const double *f, double *u, double *psi, const
   for (const Group &gr : groups) {
     const DevProblem &p0 = *probs[gr.members[0]];
     box_solve_group<double>(gr.Mfft, (int)gr.members.size(), gr.fpad64, gr.work64, gr.cs, gr.msv, p0.f64.tw,
-                            p0.f64.sp, st);
+                            p0.f64.sp, gr.tile_w[0], st);
   }
   pack(u, 1, false, st);
   KFBI_HIP(hipStreamSynchronize(st));

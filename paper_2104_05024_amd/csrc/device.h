@@ -112,6 +112,9 @@ struct DevProblem {
   double *red = nullptr;       // small device scratch for dot products
   double *host_red = nullptr;  // pinned host mirror
 
+  // tile width multiplier (1 or 2) per precision (0: FP64, 1: FP32) and pass (x, y, last axis)
+  int tile_w[2][3] = {{1, 1, 1}, {1, 1, 1}};
+
   bool profile = false;
   Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse;
   hipStream_t stream = nullptr;
@@ -186,9 +189,16 @@ void launch_batch_correct(const BatchItem<T> *items, const BatchCounts &c, int t
 template <typename T>
 void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, T *out, hipStream_t st);
 // Grouped 2D box solve of G equal-size problems (padded layout, stride cs, msv on the device).
+// w: tile widths of the x and last-axis passes (w[0], w[2]).
 template <typename T>
 void box_solve_group(int Mfft, int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw,
-                     const T *sp, hipStream_t st);
+                     const T *sp, const int *w, hipStream_t st);
+// Autotuner: time each dense pass at both tile widths and keep the faster (cached per process
+// by dimension, grid size, components and precision); clears the work buffers afterwards.
+void autotune_tiles(DevProblem &p, hipStream_t st);
+template <typename T>
+void autotune_group(int Mfft, int G, T *a, int64_t cs, const ModeParams *msv, const T *tw, const T *sp, int *w,
+                    hipStream_t st);
 
 void upload_tables(DevProblem &p);
 void free_tables(DevProblem &p);

@@ -19,6 +19,11 @@
 //   x (contiguous rows) -> y (tiles of columns, one z-plane) -> z fused with the mode
 //   scaling and the inverse z transform -> y inverse -> x inverse.
 // Each pass reads and writes its tile once; y and z passes work in place.
+#include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+
 #include "device.h"
 
 namespace kfbi {
@@ -128,6 +133,9 @@ __device__ __forceinline__ void dft(C2<T> *v) {
 #ifndef KFBI_LDS_PAD_SHIFT
 #define KFBI_LDS_PAD_SHIFT 4
 #endif
+#ifndef KFBI_LDS_PAIR_SKEW
+#define KFBI_LDS_PAIR_SKEW 1
+#endif
 __device__ __forceinline__ int pad(int i) { return i + (i >> KFBI_LDS_PAD_SHIFT); }
 
 // 1/x from the hardware reciprocal estimate refined by Newton steps (two in FP64, one in FP32):
@@ -143,13 +151,14 @@ __device__ __forceinline__ float recip(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
-template <typename T, int M>
+// W: tile-width multiplier picked by the autotuner (1 or 2 times the base pairs per workgroup)
+template <typename T, int M, int W = 1>
 struct Shape {
   static constexpr int N = M - 1;
   static constexpr int TPP = M / 16;                          // threads per pencil pair
-  static constexpr int NP = (sizeof(T) == 8 ? 2048 : 4096) / M;  // pencil pairs per workgroup
-  static constexpr int NT = NP * TPP;                         // threads per workgroup (128 / 256)
-  static constexpr int PADM = M + (M >> KFBI_LDS_PAD_SHIFT) + 1;                  // padded LDS length of one pair (odd:
+  static constexpr int NP = W * (sizeof(T) == 8 ? 2048 : 4096) / M;  // pencil pairs per workgroup
+  static constexpr int NT = NP * TPP;                         // threads per workgroup (W x 128 / 256)
+  static constexpr int PADM = M + (M >> KFBI_LDS_PAD_SHIFT) + KFBI_LDS_PAIR_SKEW;                  // padded LDS length of one pair (odd:
                                                               // pairs start on different banks)
 };
 
@@ -280,11 +289,11 @@ struct alignas(16) V16 {
 
 // DST along contiguous rows: pairs of consecutive rows of the flattened [comp][..][x] list.
 // PIN / POUT: input / output in the padded layout (row pitch M) instead of pitch N.
-template <typename T, int M, bool PIN, bool POUT>
-__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x(const T *__restrict__ in, T *__restrict__ out,
+template <typename T, int M, bool PIN, bool POUT, int W = 1>
+__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restrict__ in, T *__restrict__ out,
                                                              int64_t nrows, const C2<T> *__restrict__ tw,
                                                              const T *__restrict__ sp) {
-  using Sh = Shape<T, M>;
+  using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM, VW = 16 / sizeof(T);
   constexpr int ROWS = 2 * NP;
   __shared__ C2<T> sbuf[NP * PADM];
@@ -379,9 +388,9 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x(const T *__restrict
 // Tile mover for the strided passes: a tile is NR rows (stride RS elements) of TX consecutive
 // columns starting at column x0, for NC components (stride CS); element (row r, column xo,
 // component c) lives at LDS pair PAIR(xo, c), lane LANE(xo, c), position r + 1.
-template <typename T, int M, int TX, int NC>
+template <typename T, int M, int TX, int NC, int W = 1>
 struct StridedTile {
-  using Sh = Shape<T, M>;
+  using Sh = Shape<T, M, W>;
   static constexpr int N = Sh::N, NT = Sh::NT, PADM = Sh::PADM, VW = 16 / sizeof(T);
   static constexpr bool VEC = (TX % VW == 0) && (TX <= M);
   static constexpr int NE = VEC ? N * NC * (TX / VW) : N * NC * TX;
@@ -504,14 +513,14 @@ struct StridedTile {
 // DST along y (3D): tile = 2 NP consecutive x columns of one (comp, z) plane.  in and out
 // may alias.  mask_in / mask_out (optional, [z][y] bytes): rows known to be zero on input are
 // not read; only rows flagged on output are written.
-template <typename T, int M>
-__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_y(const T *__restrict__ in, T *__restrict__ out,
+template <typename T, int M, int W = 1>
+__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restrict__ in, T *__restrict__ out,
                                                                int64_t P, int64_t comp_stride,
                                                                const uint8_t *__restrict__ mask_in,
                                                                const uint8_t *__restrict__ mask_out,
                                                                const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
-  using Sh = Shape<T, M>;
-  using Tl = StridedTile<T, M, 2 * Sh::NP, 1>;
+  using Sh = Shape<T, M, W>;
+  using Tl = StridedTile<T, M, 2 * Sh::NP, 1, W>;
   __shared__ C2<T> sbuf[Sh::NP * Sh::PADM];
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * 2 * Sh::NP, z = blockIdx.y, c = blockIdx.z;
@@ -552,23 +561,23 @@ struct ModeHook {
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
 // In 2D, blockIdx.y may index the problems of a batch of equal-size fields at stride pstride,
 // each with its own mode parameters msv[problem] (msv = nullptr: one problem, parameters ms).
-template <typename T, int M, int NC, int DIM>
-__global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
+template <typename T, int M, int NC, int DIM, int W = 1>
+__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
                                                                   ModeScale ms0, const C2<T> *__restrict__ tw,
                                                                   const T *__restrict__ sp,
                                                                   const ModeScale *__restrict__ msv = nullptr,
                                                                   int64_t pstride = 0) {
-  using Sh = Shape<T, M>;
+  using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
   constexpr int64_t LS = DIM == 3 ? (int64_t)N : 1;  // rows of the last axis step by LS * P
-  using Tl = StridedTile<T, M, TX, NC>;
+  using Tl = StridedTile<T, M, TX, NC, W>;
   __shared__ C2<T> sbuf[NP * PADM];
   __shared__ T slam[M];
   const int tid = threadIdx.x;
-  // A tile row of TX columns is half of a 128-byte line; the tile sharing the line is given
-  // to the workgroup dispatched 8 later, i.e. on the same XCD (round-robin dispatch), so the
-  // second half of the line comes from that XCD's L2 instead of a second HBM fetch.
+  // At W = 1 a tile row of TX columns is half of a 128-byte line; the tile sharing the line is
+  // given to the workgroup dispatched 8 later, i.e. on the same XCD (round-robin dispatch), so
+  // the second half of the line comes from that XCD's L2 instead of a second HBM fetch.
   int64_t id = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
   const int64_t total = (int64_t)gridDim.x * gridDim.y;
   if (id < (total & ~int64_t(15))) id = (id & ~int64_t(15)) + 2 * (id & 7) + ((id >> 3) & 1);
@@ -660,58 +669,107 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
   }
 }
 
+// ---------------------------------------------------------------- launchers
+//
+// Every dense pass exists at two tile widths (W = 1, 2: pencil pairs per workgroup); the
+// width per (grid size, precision, pass) is picked by autotune_tiles() from timed launches.
+
+template <typename T>
+constexpr int prec_index() { return sizeof(T) == 8 ? 0 : 1; }
+
+// x pass over `rows` contiguous rows (padded in/out unless stated)
+template <typename T, int M, int W>
+void launch_x(const T *in, bool in_plain, T *out, bool out_plain, int64_t rows, const C2<T> *tw, const T *sp,
+              hipStream_t st) {
+  using Sh = Shape<T, M, W>;
+  const dim3 g((unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP)));
+  if (in_plain) k_dst_x<T, M, false, true, W><<<g, Sh::NT, 0, st>>>(in, out, rows, tw, sp);
+  else if (out_plain) k_dst_x<T, M, true, false, W><<<g, Sh::NT, 0, st>>>(in, out, rows, tw, sp);
+  else k_dst_x<T, M, true, true, W><<<g, Sh::NT, 0, st>>>(in, out, rows, tw, sp);
+  KFBI_HIP(hipGetLastError());
+}
+
+template <typename T, int M, int W>
+void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8_t *mask_in,
+              const uint8_t *mask_out, const C2<T> *tw, const T *sp, hipStream_t st) {
+  using Sh = Shape<T, M, W>;
+  const dim3 g((Sh::N + 2 * Sh::NP - 1) / (2 * Sh::NP), Sh::N, ncomp);
+  k_dst_y<T, M, W><<<g, Sh::NT, 0, st>>>(in, out, P, cs, mask_in, mask_out, tw, sp);
+  KFBI_HIP(hipGetLastError());
+}
+
+// fused last-axis pass; nprob > 1 only in 2D (batched groups with per-problem msv)
+template <typename T, int M, int W>
+void launch_last(T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
+                 const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st) {
+  using Sh = Shape<T, M, W>;
+  const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
+  const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
+  if (dim == 3) {
+    if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp);
+    else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp);
+  } else {
+    if (ncomp == 2) k_dst_last<T, M, 2, 2, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp, msv, pstride);
+    else k_dst_last<T, M, 1, 2, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp, msv, pstride);
+  }
+  KFBI_HIP(hipGetLastError());
+}
+
+template <typename T, int M>
+void pass_x(int w, const T *in, bool in_plain, T *out, bool out_plain, int64_t rows, const C2<T> *tw, const T *sp,
+            hipStream_t st) {
+  if (w == 2) launch_x<T, M, 2>(in, in_plain, out, out_plain, rows, tw, sp, st);
+  else launch_x<T, M, 1>(in, in_plain, out, out_plain, rows, tw, sp, st);
+}
+template <typename T, int M>
+void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8_t *mi, const uint8_t *mo,
+            const C2<T> *tw, const T *sp, hipStream_t st) {
+  if (w == 2) launch_y<T, M, 2>(in, out, P, cs, ncomp, mi, mo, tw, sp, st);
+  else launch_y<T, M, 1>(in, out, P, cs, ncomp, mi, mo, tw, sp, st);
+}
+template <typename T, int M>
+void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
+               const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st) {
+  if (w == 2) launch_last<T, M, 2>(a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
+  else launch_last<T, M, 1>(a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
+}
+
+template <typename T>
+ModeScale mode_of(const DevProblem &p) {
+  return ModeScale{p.lam, p.sigma[0], p.ncomp == 2 ? p.sigma[1] : p.sigma[0], p.kappa, p.lam_scale};
+}
+
 template <typename T, int M>
 void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st) {
-  using Sh = Shape<T, M>;
-  constexpr int N = Sh::N;
+  constexpr int N = M - 1;
   PrecTables<T> &tb = p.tab<T>();
   T *A = tb.work;
   const C2<T> *tw = reinterpret_cast<const C2<T> *>(tb.tw);
   const T *sp = tb.sp;
   const int64_t P = p.P, cs = p.comp_stride;
   const int64_t rows = (int64_t)p.ncomp * (p.dim == 3 ? (int64_t)N * N : N);
-  const dim3 gx((unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP)));
-  ModeScale ms{p.lam, p.sigma[0], p.ncomp == 2 ? p.sigma[1] : p.sigma[0], p.kappa, p.lam_scale};
+  const int *w = p.tile_w[prec_index<T>()];
+  const ModeScale ms = mode_of<T>(p);
   auto tic = [&](Timer &t) { t.tic(p.profile, st); };
   auto toc = [&](Timer &t) { t.toc(p.profile, st); };
   tic(p.t_dst_x);
-  if (src_plain)
-    k_dst_x<T, M, false, true><<<gx, Sh::NT, 0, st>>>(src, A, rows, tw, sp);
-  else
-    k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(src, A, rows, tw, sp);
-  KFBI_HIP(hipGetLastError());
+  pass_x<T, M>(w[0], src, src_plain, A, false, rows, tw, sp, st);
   toc(p.t_dst_x);
-  const dim3 gy((N + 2 * Sh::NP - 1) / (2 * Sh::NP), N, p.ncomp);
   if (p.dim == 3) {
     tic(p.t_dst_y);
-    k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, nullptr, tw, sp);
-    KFBI_HIP(hipGetLastError());
+    pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
     toc(p.t_dst_y);
   }
-  const int tx = p.ncomp == 2 ? Sh::NP : 2 * Sh::NP;
-  const dim3 gl((N + tx - 1) / tx, p.dim == 3 ? N : 1, 1);
   tic(p.t_dst_last);
-  if (p.dim == 3) {
-    if (p.ncomp == 2) k_dst_last<T, M, 2, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
-    else k_dst_last<T, M, 1, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
-  } else {
-    if (p.ncomp == 2) k_dst_last<T, M, 2, 2><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
-    else k_dst_last<T, M, 1, 2><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
-  }
-  KFBI_HIP(hipGetLastError());
+  pass_last<T, M>(w[2], A, p.dim, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st);
   toc(p.t_dst_last);
   if (p.dim == 3) {
     tic(p.t_dst_y);
-    k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, nullptr, tw, sp);
-    KFBI_HIP(hipGetLastError());
+    pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
     toc(p.t_dst_y);
   }
   tic(p.t_dst_x);
-  if (dst_plain)
-    k_dst_x<T, M, true, false><<<gx, Sh::NT, 0, st>>>(A, dst, rows, tw, sp);
-  else
-    k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(A, dst, rows, tw, sp);
-  KFBI_HIP(hipGetLastError());
+  pass_x<T, M>(w[0], A, false, dst, dst_plain, rows, tw, sp, st);
   toc(p.t_dst_x);
 }
 
@@ -723,13 +781,13 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
 template <typename T, int M>
 void run_box_sparse(DevProblem &p, hipStream_t st) {
   using Sh = Shape<T, M>;
-  constexpr int N = Sh::N;
   PrecTables<T> &tb = p.tab<T>();
   T *A = tb.work, *X = tb.xbuf;
   const C2<T> *tw = reinterpret_cast<const C2<T> *>(tb.tw);
   const T *sp = tb.sp;
   const int64_t P = p.P, cs = p.comp_stride;
-  ModeScale ms{p.lam, p.sigma[0], p.ncomp == 2 ? p.sigma[1] : p.sigma[0], p.kappa, p.lam_scale};
+  const int *w = p.tile_w[prec_index<T>()];
+  const ModeScale ms = mode_of<T>(p);
   auto tic = [&](Timer &t) { t.tic(p.profile, st); };
   auto toc = [&](Timer &t) { t.toc(p.profile, st); };
   const unsigned gin = (unsigned)((p.n_rows_in + 2 * Sh::NP - 1) / (2 * Sh::NP));
@@ -738,21 +796,14 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   if (gin) k_dst_x_rows<T, M><<<gin, Sh::NT, 0, st>>>(tb.rhs, X, p.rows_in, p.n_rows_in, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_x_rows);
-  const dim3 gy((N + 2 * Sh::NP - 1) / (2 * Sh::NP), N, p.ncomp);
   tic(p.t_dst_y_sparse);
-  k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(X, A, P, cs, p.mask_in, nullptr, tw, sp);
-  KFBI_HIP(hipGetLastError());
+  pass_y<T, M>(w[1], X, A, P, cs, p.ncomp, p.mask_in, nullptr, tw, sp, st);
   toc(p.t_dst_y_sparse);
-  const int tx = p.ncomp == 2 ? Sh::NP : 2 * Sh::NP;
-  const dim3 gl((N + tx - 1) / tx, N, 1);
   tic(p.t_dst_last);
-  if (p.ncomp == 2) k_dst_last<T, M, 2, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
-  else k_dst_last<T, M, 1, 3><<<gl, Sh::NT, 0, st>>>(A, P, cs, ms, tw, sp);
-  KFBI_HIP(hipGetLastError());
+  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st);
   toc(p.t_dst_last);
   tic(p.t_dst_y_sparse);
-  k_dst_y<T, M><<<gy, Sh::NT, 0, st>>>(A, A, P, cs, nullptr, p.mask_out, tw, sp);
-  KFBI_HIP(hipGetLastError());
+  pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st);
   toc(p.t_dst_y_sparse);
   tic(p.t_dst_x_rows);
   if (gout) k_dst_x_rows<T, M><<<gout, Sh::NT, 0, st>>>(A, A, p.rows_out, p.n_rows_out, tw, sp);
@@ -764,43 +815,137 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
 // padded layout: one launch per pass for the whole group.
 template <typename T, int M>
 void run_box_group(int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw_, const T *sp,
-                   hipStream_t st) {
-  using Sh = Shape<T, M>;
-  constexpr int N = Sh::N;
+                   const int *w, hipStream_t st) {
+  constexpr int N = M - 1;
   const C2<T> *tw = reinterpret_cast<const C2<T> *>(tw_);
   const int64_t rows = (int64_t)G * N;
   if (cs != (int64_t)N * M) throw std::invalid_argument("group stride");
-  const dim3 gx((unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP)));
-  k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(src, dst, rows, tw, sp);
-  KFBI_HIP(hipGetLastError());
-  const int tx = 2 * Sh::NP;
-  const dim3 gl((N + tx - 1) / tx, G, 1);
-  k_dst_last<T, M, 1, 2><<<gl, Sh::NT, 0, st>>>(dst, M, cs, ModeParams{}, tw, sp, msv, cs);
-  KFBI_HIP(hipGetLastError());
-  k_dst_x<T, M, true, true><<<gx, Sh::NT, 0, st>>>(dst, dst, rows, tw, sp);
-  KFBI_HIP(hipGetLastError());
+  pass_x<T, M>(w[0], src, false, dst, false, rows, tw, sp, st);
+  pass_last<T, M>(w[2], dst, 2, 1, M, cs, ModeParams{}, tw, sp, msv, G, cs, st);
+  pass_x<T, M>(w[0], dst, false, dst, false, rows, tw, sp, st);
+}
+
+// Time one pass at width w (median of three launches after one warm-up), in place on `a`.
+template <typename T, int M>
+float time_pass(int pass, int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, int64_t rows, const ModeScale &ms,
+                const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, hipStream_t st) {
+  hipEvent_t e0, e1;
+  KFBI_HIP(hipEventCreate(&e0));
+  KFBI_HIP(hipEventCreate(&e1));
+  float t[3];
+  for (int r = -1; r < 3; ++r) {
+    KFBI_HIP(hipEventRecord(e0, st));
+    if (pass == 0) pass_x<T, M>(w, a, false, a, false, rows, tw, sp, st);
+    else if (pass == 1) pass_y<T, M>(w, a, a, P, cs, ncomp, nullptr, nullptr, tw, sp, st);
+    else pass_last<T, M>(w, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, cs, st);
+    KFBI_HIP(hipEventRecord(e1, st));
+    KFBI_HIP(hipEventSynchronize(e1));
+    if (r >= 0) KFBI_HIP(hipEventElapsedTime(&t[r], e0, e1));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(t, t + 3);
+  return t[1];
+}
+
+template <typename T, int M>
+void tune(int *w, T *a, int dim, int ncomp, int64_t P, int64_t cs, int64_t rows, const ModeScale &ms,
+          const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, hipStream_t st) {
+  for (int pass = 0; pass < 3; ++pass) {
+    if (pass == 1 && dim != 3) continue;
+    const float t1 = time_pass<T, M>(pass, 1, a, dim, ncomp, P, cs, rows, ms, tw, sp, msv, nprob, st);
+    const float t2 = time_pass<T, M>(pass, 2, a, dim, ncomp, P, cs, rows, ms, tw, sp, msv, nprob, st);
+    w[pass] = t2 < 0.97f * t1 ? 2 : 1;   // the wider tile must win clearly
+  }
+}
+
+template <typename T>
+void autotune_prec(DevProblem &p, hipStream_t st) {
+  PrecTables<T> &tb = p.tab<T>();
+  T *A = tb.work;
+  const C2<T> *tw = reinterpret_cast<const C2<T> *>(tb.tw);
+  const int64_t N = p.N;
+  const int64_t rows = (int64_t)p.ncomp * (p.dim == 3 ? N * N : N);
+  const ModeScale ms = mode_of<T>(p);
+  int *w = p.tile_w[prec_index<T>()];
+  switch (p.Mfft) {
+#define KFBI_TUNE_CASE(MM) \
+    case MM: tune<T, MM>(w, A, p.dim, p.ncomp, p.P, p.comp_stride, rows, ms, tw, tb.sp, nullptr, 1, st); break;
+    KFBI_TUNE_CASE(16) KFBI_TUNE_CASE(32) KFBI_TUNE_CASE(64) KFBI_TUNE_CASE(128) KFBI_TUNE_CASE(256)
+    KFBI_TUNE_CASE(512) KFBI_TUNE_CASE(1024)
+#undef KFBI_TUNE_CASE
+    default: throw std::invalid_argument("unsupported grid size");
+  }
 }
 
 }  // namespace
 
+// Tile widths per (dimension, grid size, components, precision): measured once per process.
+void autotune_tiles(DevProblem &p, hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::array<int, 4>, std::array<int, 3>> cache;
+  for (int prec = 0; prec < 2; ++prec) {
+    const std::array<int, 4> key{p.dim, (int)p.Mfft, p.ncomp, prec};
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = cache.find(key);
+      if (it != cache.end()) {
+        for (int k = 0; k < 3; ++k) p.tile_w[prec][k] = it->second[k];
+        continue;
+      }
+    }
+    if (prec == 0) autotune_prec<double>(p, st);
+    else autotune_prec<float>(p, st);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = {p.tile_w[prec][0], p.tile_w[prec][1], p.tile_w[prec][2]};
+  }
+  // the timing launches ran in place on the work buffers: leave them zeroed
+  const size_t field = (size_t)p.ncomp * p.comp_stride;
+  KFBI_HIP(hipMemsetAsync(p.f64.work, 0, field * sizeof(double), st));
+  KFBI_HIP(hipMemsetAsync(p.f32.work, 0, field * sizeof(float), st));
+  KFBI_HIP(hipStreamSynchronize(st));
+}
+
+// Batched groups: widths of the x and last-axis passes for one group, timed on its buffers.
+template <typename T>
+void autotune_group(int Mfft, int G, T *a, int64_t cs, const ModeParams *msv, const T *tw_, const T *sp, int *w,
+                    hipStream_t st) {
+  const C2<T> *tw = reinterpret_cast<const C2<T> *>(tw_);
+  const int64_t rows = (int64_t)G * (Mfft - 1);
+  switch (Mfft) {
+#define KFBI_TUNE_CASE(MM) \
+    case MM: tune<T, MM>(w, a, 2, 1, MM, cs, rows, ModeParams{}, tw, sp, msv, G, st); break;
+    KFBI_TUNE_CASE(16) KFBI_TUNE_CASE(32) KFBI_TUNE_CASE(64) KFBI_TUNE_CASE(128) KFBI_TUNE_CASE(256)
+    KFBI_TUNE_CASE(512) KFBI_TUNE_CASE(1024)
+#undef KFBI_TUNE_CASE
+    default: throw std::invalid_argument("unsupported grid size");
+  }
+  KFBI_HIP(hipMemsetAsync(a, 0, (size_t)G * cs * sizeof(T), st));
+  KFBI_HIP(hipStreamSynchronize(st));
+}
+template void autotune_group<double>(int, int, double *, int64_t, const ModeParams *, const double *,
+                                     const double *, int *, hipStream_t);
+template void autotune_group<float>(int, int, float *, int64_t, const ModeParams *, const float *, const float *,
+                                    int *, hipStream_t);
+
 template <typename T>
 void box_solve_group(int Mfft, int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw,
-                     const T *sp, hipStream_t st) {
+                     const T *sp, const int *w, hipStream_t st) {
   switch (Mfft) {
-    case 16: run_box_group<T, 16>(G, src, dst, cs, msv, tw, sp, st); break;
-    case 32: run_box_group<T, 32>(G, src, dst, cs, msv, tw, sp, st); break;
-    case 64: run_box_group<T, 64>(G, src, dst, cs, msv, tw, sp, st); break;
-    case 128: run_box_group<T, 128>(G, src, dst, cs, msv, tw, sp, st); break;
-    case 256: run_box_group<T, 256>(G, src, dst, cs, msv, tw, sp, st); break;
-    case 512: run_box_group<T, 512>(G, src, dst, cs, msv, tw, sp, st); break;
-    case 1024: run_box_group<T, 1024>(G, src, dst, cs, msv, tw, sp, st); break;
+    case 16: run_box_group<T, 16>(G, src, dst, cs, msv, tw, sp, w, st); break;
+    case 32: run_box_group<T, 32>(G, src, dst, cs, msv, tw, sp, w, st); break;
+    case 64: run_box_group<T, 64>(G, src, dst, cs, msv, tw, sp, w, st); break;
+    case 128: run_box_group<T, 128>(G, src, dst, cs, msv, tw, sp, w, st); break;
+    case 256: run_box_group<T, 256>(G, src, dst, cs, msv, tw, sp, w, st); break;
+    case 512: run_box_group<T, 512>(G, src, dst, cs, msv, tw, sp, w, st); break;
+    case 1024: run_box_group<T, 1024>(G, src, dst, cs, msv, tw, sp, w, st); break;
     default: throw std::invalid_argument("unsupported grid size");
   }
 }
 template void box_solve_group<double>(int, int, const double *, double *, int64_t, const ModeParams *,
-                                      const double *, const double *, hipStream_t);
+                                      const double *, const double *, const int *, hipStream_t);
 template void box_solve_group<float>(int, int, const float *, float *, int64_t, const ModeParams *, const float *,
-                                     const float *, hipStream_t);
+                                     const float *, const int *, hipStream_t);
 
 template <typename T>
 void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st) {

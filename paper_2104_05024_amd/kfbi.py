@@ -24,7 +24,7 @@ EXPORTED = [
     "bidomain_create", "bidomain_destroy", "bidomain_step", "bidomain_mlp_init", "bidomain_train",
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
     "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
-    "kfbi_batch_graph",
+    "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles",
     "kfbi_profile",
 ]
 
@@ -111,6 +111,8 @@ def lib():
     L.kfbi_last_error.restype = C.c_char_p
     L.kfbi_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dp), i64p]
     L.kfbi_profile.argtypes = [vp, i32]
+    L.kfbi_get_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
+    L.kfbi_set_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.kfbi_batch_setup.argtypes = [i32, C.POINTER(Interface), C.POINTER(GridDesc), C.POINTER(CoeffsDesc),
                                    C.POINTER(vp)]
     L.kfbi_batch_destroy.argtypes = [vp]
@@ -260,6 +262,16 @@ class Problem:
 
     def profile(self, enable=True):
         _check(lib().kfbi_profile(self._h, 1 if enable else 0))
+
+    def tiles(self, dtype=KFBI_F64):
+        """Autotuned DST tile widths (x, y, last-axis pass) for KFBI_F64 / KFBI_F32."""
+        w = (C.c_int32 * 3)()
+        _check(lib().kfbi_get_tiles(self._h, dtype, w))
+        return tuple(w)
+
+    def set_tiles(self, widths, dtype=KFBI_F64):
+        w = (C.c_int32 * 3)(*widths)
+        _check(lib().kfbi_set_tiles(self._h, dtype, w))
 
     def kernel_time(self, name):
         us, n = C.c_double(), C.c_int64()

@@ -270,3 +270,27 @@ def test_apply_and_solve_full_size_ellipsoid_128():
     say(f"    u err {e:.2e} iters {info['iters']}")
     assert e < 1e-10
     assert np.max(np.abs(u.cpu().numpy()[0] - ue)[ins]) < 1e-4
+
+
+# ----------------------------------------------------------------------------- autotuned tiles
+
+@pytest.mark.parametrize("name", ["star2d_64", "ellipsoid_64", "shell_64"])
+def test_tile_widths_do_not_change_results(name):
+    """Every tile width the autotuner may pick transforms each pencil the same way: the box
+    solve and the matrix-vector product are bitwise identical for all width choices."""
+    g, o, iface, grid, co = problems(name)
+    chosen = {dt: g.tiles(dt) for dt in (K.KFBI_F64, K.KFBI_F32)}
+    say(f"[tiles] {name}: autotuned FP64 {chosen[K.KFBI_F64]} FP32 {chosen[K.KFBI_F32]}")
+    rng = np.random.default_rng(11)
+    f = rng.normal(size=(g.ncomp, g.N ** g.dim))
+    psi = rng.normal(size=(g.ncomp, g.M))
+    for dt, tdt in ((K.KFBI_F64, torch.float64), (K.KFBI_F32, torch.float32)):
+        ref = None
+        for widths in ((1, 1, 1), (2, 2, 2), (1, 2, 1), (2, 1, 2)):
+            g.set_tiles(widths, dt)
+            out = (g.box_solve(T(f, tdt)), g.apply(T(psi, tdt)))
+            if ref is None:
+                ref = out
+            else:
+                assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (dt, widths)
+        g.set_tiles(chosen[dt], dt)
