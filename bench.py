@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--variants", default="plain,mixed,learned")
     ap.add_argument("--train-steps", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--inner-tol", type=float, default=1e-4, help="mixed precision: relative tolerance of each FP32 inner solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (first listed variant only, no CPU baseline)")
     ap.add_argument("--batch", action="store_true",
@@ -212,13 +213,14 @@ def main():
     for name in variants:
         if name == "learned":
             try:
-                bd = K.Bidomain(prob, p, tol=1e-8, precision=1, warm_start=1)
+                bd = K.Bidomain(prob, p, tol=1e-8, precision=1, warm_start=1, inner_tol=a.inner_tol)
                 bd.mlp_init(capacity=max(a.train_steps, 1), seed=3)
             except K.KfbiError as e:
                 log(f"learned variant unavailable: {e}")
                 continue
         else:
-            bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "mixed" else 0, warm_start=0)
+            bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "mixed" else 0, warm_start=0,
+                            inner_tol=a.inner_tol)
         V = torch.tensor(V0, device=dev)
         q = torch.tensor(q0, device=dev)
         hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=dev)

@@ -34,6 +34,7 @@ struct PrecTables {          // per-precision device copies of the numeric table
   T *tw = nullptr, *sp = nullptr;        // DST twiddles exp(-2 pi i m/M) (complex) and sin(pi n/M)
   T *rhs = nullptr, *work = nullptr;     // matvec right-hand side (zero off irregular nodes), work field
   T *xbuf = nullptr;                     // sparse matvec: x-forward output, zero outside the rhs rows
+  T *ybuf = nullptr;                     // sparse matvec: y-forward output, zero in planes without rhs rows
   T *jz = nullptr, *jq = nullptr;        // jumps at crossings [comp][2][nc], at nodes [comp][d+nh][M]
 };
 
@@ -103,6 +104,7 @@ struct DevProblem {
   int32_t *rows_in = nullptr, *rows_out = nullptr;
   int64_t n_rows_in = 0, n_rows_out = 0;
   uint8_t *mask_in = nullptr, *mask_out = nullptr;
+  uint8_t *planes_in = nullptr, *planes_out = nullptr;   // [z]: plane holds any rhs / stencil row
   double *lam = nullptr;       // (4/h^2) sin^2(k pi / 2M), k = 1..N
 
   PrecTables<double> f64;

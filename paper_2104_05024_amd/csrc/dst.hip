@@ -512,12 +512,14 @@ struct StridedTile {
 
 // DST along y (3D): tile = 2 NP consecutive x columns of one (comp, z) plane.  in and out
 // may alias.  mask_in / mask_out (optional, [z][y] bytes): rows known to be zero on input are
-// not read; only rows flagged on output are written.
+// not read; only rows flagged on output are written.  planes (optional, [z] bytes): planes
+// flagged 0 are skipped altogether (no reads, no writes).
 template <typename T, int M, int W = 1>
 __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restrict__ in, T *__restrict__ out,
                                                                int64_t P, int64_t comp_stride,
                                                                const uint8_t *__restrict__ mask_in,
                                                                const uint8_t *__restrict__ mask_out,
+                                                               const uint8_t *__restrict__ planes,
                                                                const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
   using Sh = Shape<T, M, W>;
   using Tl = StridedTile<T, M, 2 * Sh::NP, 1, W>;
@@ -525,6 +527,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restr
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * 2 * Sh::NP, z = blockIdx.y, c = blockIdx.z;
   const int64_t off = c * comp_stride + (int64_t)z * Sh::N * P;
+  if (planes && !planes[z]) return;   // nothing to read or write in this plane (whole workgroup)
   Tl::load(in + off, P, 0, x0, sbuf, tid, mask_in ? mask_in + (int64_t)z * Sh::N : nullptr);
   __syncthreads();
   dst_pair<T, M>(sbuf + (tid / Sh::TPP) * Sh::PADM, tid % Sh::TPP, tw, sp);
@@ -554,7 +557,8 @@ struct ModeHook {
   }
 };
 
-// Last axis (z in 3D, y in 2D), fused: forward DST -> mode solve -> inverse DST, in place.
+// Last axis (z in 3D, y in 2D), fused: forward DST -> mode solve -> inverse DST, from ain to a
+// (which may alias).
 // The mode solve is u^ = f^ / (D L + kappa) (one component) or the closed-form inverse of
 // [[a_i + kappa, -kappa], [-kappa, a_e + kappa]], a_c = D_c L (coupled pair), with
 // L = lambda_kx + lambda_ky (+ lambda_kz) and norm = (2/M)^d for the inverse transforms.
@@ -562,7 +566,8 @@ struct ModeHook {
 // In 2D, blockIdx.y may index the problems of a batch of equal-size fields at stride pstride,
 // each with its own mode parameters msv[problem] (msv = nullptr: one problem, parameters ms).
 template <typename T, int M, int NC, int DIM, int W = 1>
-__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(T *__restrict__ a, int64_t P, int64_t comp_stride,
+__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__restrict__ ain, T *__restrict__ a,
+                                                                     int64_t P, int64_t comp_stride,
                                                                   ModeScale ms0, const C2<T> *__restrict__ tw,
                                                                   const T *__restrict__ sp,
                                                                   const ModeScale *__restrict__ msv = nullptr,
@@ -583,10 +588,11 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(T *__restrict
   if (id < (total & ~int64_t(15))) id = (id & ~int64_t(15)) + 2 * (id & 7) + ((id >> 3) & 1);
   const int bx = (int)(id % gridDim.x), by = (int)(id / gridDim.x);
   const int x0 = bx * TX, y = DIM == 3 ? by : 0;
-  T *base = a + (DIM == 3 ? (int64_t)y * P : (int64_t)by * pstride);
+  const int64_t boff = DIM == 3 ? (int64_t)y * P : (int64_t)by * pstride;
+  T *base = a + boff;
   const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
-  Tl::load(base, LS * P, comp_stride, x0, sbuf, tid);
+  Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
   C2<T> *mine = sbuf + pr * PADM;
@@ -691,26 +697,26 @@ void launch_x(const T *in, bool in_plain, T *out, bool out_plain, int64_t rows, 
 
 template <typename T, int M, int W>
 void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8_t *mask_in,
-              const uint8_t *mask_out, const C2<T> *tw, const T *sp, hipStream_t st) {
+              const uint8_t *mask_out, const uint8_t *planes, const C2<T> *tw, const T *sp, hipStream_t st) {
   using Sh = Shape<T, M, W>;
   const dim3 g((Sh::N + 2 * Sh::NP - 1) / (2 * Sh::NP), Sh::N, ncomp);
-  k_dst_y<T, M, W><<<g, Sh::NT, 0, st>>>(in, out, P, cs, mask_in, mask_out, tw, sp);
+  k_dst_y<T, M, W><<<g, Sh::NT, 0, st>>>(in, out, P, cs, mask_in, mask_out, planes, tw, sp);
   KFBI_HIP(hipGetLastError());
 }
 
 // fused last-axis pass; nprob > 1 only in 2D (batched groups with per-problem msv)
 template <typename T, int M, int W>
-void launch_last(T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
-                 const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st) {
+void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms,
+                 const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st) {
   using Sh = Shape<T, M, W>;
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
   if (dim == 3) {
-    if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp);
-    else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp);
+    if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+    else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
   } else {
-    if (ncomp == 2) k_dst_last<T, M, 2, 2, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp, msv, pstride);
-    else k_dst_last<T, M, 1, 2, W><<<g, Sh::NT, 0, st>>>(a, P, cs, ms, tw, sp, msv, pstride);
+    if (ncomp == 2) k_dst_last<T, M, 2, 2, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, msv, pstride);
+    else k_dst_last<T, M, 1, 2, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, msv, pstride);
   }
   KFBI_HIP(hipGetLastError());
 }
@@ -723,15 +729,17 @@ void pass_x(int w, const T *in, bool in_plain, T *out, bool out_plain, int64_t r
 }
 template <typename T, int M>
 void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8_t *mi, const uint8_t *mo,
-            const C2<T> *tw, const T *sp, hipStream_t st) {
-  if (w == 2) launch_y<T, M, 2>(in, out, P, cs, ncomp, mi, mo, tw, sp, st);
-  else launch_y<T, M, 1>(in, out, P, cs, ncomp, mi, mo, tw, sp, st);
+            const C2<T> *tw, const T *sp, hipStream_t st, const uint8_t *planes = nullptr) {
+  if (w == 2) launch_y<T, M, 2>(in, out, P, cs, ncomp, mi, mo, planes, tw, sp, st);
+  else launch_y<T, M, 1>(in, out, P, cs, ncomp, mi, mo, planes, tw, sp, st);
 }
 template <typename T, int M>
 void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
-               const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st) {
-  if (w == 2) launch_last<T, M, 2>(a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
-  else launch_last<T, M, 1>(a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
+               const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
+               const T *in = nullptr) {
+  if (!in) in = a;
+  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
+  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
 }
 
 template <typename T>
@@ -776,8 +784,10 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
 // Box solve inside the matrix-vector product: the right-hand side is zero outside the rows
 // that hold irregular nodes, and only the rows that hold extrapolation-stencil nodes are read
 // afterwards.  x forward runs on the first rows only (into a buffer whose other rows stay zero),
-// y forward skips reading zero rows, y inverse writes and x inverse transforms only the second
-// rows.  The values at every stencil node are identical to the full solve.
+// y forward skips reading zero rows and skips whole z planes without such rows (its output
+// buffer stays zero there), y inverse writes and x inverse transforms only the second rows,
+// skipping whole planes without them.  The values at every stencil node are identical to the
+// full solve.
 template <typename T, int M>
 void run_box_sparse(DevProblem &p, hipStream_t st) {
   using Sh = Shape<T, M>;
@@ -796,14 +806,15 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   if (gin) k_dst_x_rows<T, M><<<gin, Sh::NT, 0, st>>>(tb.rhs, X, p.rows_in, p.n_rows_in, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_x_rows);
+  T *Y = tb.ybuf;
   tic(p.t_dst_y_sparse);
-  pass_y<T, M>(w[1], X, A, P, cs, p.ncomp, p.mask_in, nullptr, tw, sp, st);
+  pass_y<T, M>(w[1], X, Y, P, cs, p.ncomp, p.mask_in, nullptr, tw, sp, st, p.planes_in);
   toc(p.t_dst_y_sparse);
   tic(p.t_dst_last);
-  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st);
+  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, Y);
   toc(p.t_dst_last);
   tic(p.t_dst_y_sparse);
-  pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st);
+  pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st, p.planes_out);
   toc(p.t_dst_y_sparse);
   tic(p.t_dst_x_rows);
   if (gout) k_dst_x_rows<T, M><<<gout, Sh::NT, 0, st>>>(A, A, p.rows_out, p.n_rows_out, tw, sp);

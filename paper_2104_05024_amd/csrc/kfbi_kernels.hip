@@ -345,6 +345,8 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_
   if (p.dim == 3) {
     tb.xbuf = dalloc<T>(field);
     KFBI_HIP(hipMemset(tb.xbuf, 0, field * sizeof(T)));
+    tb.ybuf = dalloc<T>(field);
+    KFBI_HIP(hipMemset(tb.ybuf, 0, field * sizeof(T)));
   }
   const int nh = p.dim == 2 ? 3 : 6;
   tb.jz = dalloc<T>((size_t)p.ncomp * 2 * std::max<int64_t>(p.nc, 1));
@@ -354,7 +356,7 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_
 template <typename T>
 void free_prec(PrecTables<T> &tb) {
   T **all[] = {&tb.z_w0, &tb.z_wga, &tb.z_na, &tb.z_cw, &tb.q_wg, &tb.q_n, &tb.q_wt, &tb.arm_d, &tb.arm_s,
-               &tb.st_nw, &tb.st_r, &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.jz, &tb.jq};
+               &tb.st_nw, &tb.st_r, &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.ybuf, &tb.jz, &tb.jq};
   for (T **q : all) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -600,6 +602,13 @@ void upload_tables(DevProblem &p) {
     p.rows_out = dupload(rout);
     p.mask_in = dupload(min_);
     p.mask_out = dupload(mout);
+    std::vector<uint8_t> pin(N, 0), pout(N, 0);
+    for (int64_t r = 0; r < N * N; ++r) {
+      if (min_[r]) pin[r / N] = 1;
+      if (mout[r]) pout[r / N] = 1;
+    }
+    p.planes_in = dupload(pin);
+    p.planes_out = dupload(pout);
   }
   p.z_idx = dupload(z_idx);
   p.z_axis = dupload(z_axis);
@@ -622,7 +631,7 @@ void upload_tables(DevProblem &p) {
 void free_tables(DevProblem &p) {
   int32_t **ip[] = {&p.z_idx, &p.z_axis, &p.q_idx, &p.irr_pos, &p.irr_ptr, &p.arm_cross, &p.st_pos,
                     &p.rows_in, &p.rows_out};
-  uint8_t **up[] = {&p.mask_in, &p.mask_out};
+  uint8_t **up[] = {&p.mask_in, &p.mask_out, &p.planes_in, &p.planes_out};
   for (uint8_t **q : up) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;

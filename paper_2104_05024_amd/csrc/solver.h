@@ -31,16 +31,19 @@ struct Solver {
 
   double dot(const double *a, const double *b, hipStream_t st);
   double residual_norm(const double *b, const double *Ax, hipStream_t st);   // ||b - Ax||_2 (uses d)
+  // r0 (optional): b - A x already known (no product for the first residual)
   int gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
             int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
-            double *beta0 = nullptr);
+            double *beta0 = nullptr, const double *r0 = nullptr);
   int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
                  int &its, int &matvecs, double &resid, hipStream_t st, double *r0 = nullptr);
   // g' = g - n.D grad (S f)+, with f already in fpad (padded). g may be null.
   void bie_rhs(DevProblem &p, const double *g, hipStream_t st);
-  // psi solve of A psi = gp with the options; psi holds the start if x0 = 1.
+  // psi solve of A psi = gp with the options; psi holds the start if x0 = 1; r0 (optional) is
+  // its residual gp - A psi if already known.  Afterwards last_resid holds gp - A64 psi.
   int solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                    hipStream_t st);
+                    hipStream_t st, const double *r0 = nullptr);
+  const double *last_resid = nullptr;
   // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added)
   void reconstruct(DevProblem &p, const double *psi, hipStream_t st);
   double gauge_mean(DevProblem &p, hipStream_t st);   // mean over tissue nodes of comp 1 of work
@@ -55,9 +58,11 @@ struct bidomain_s {
   kfbi::Solver *solver = nullptr;
   bidomain_params params{};
   kfbi::Mlp *mlp = nullptr;
-  double *psi0 = nullptr;      // candidate start densities
-  double *psi_lin = nullptr;
-  double *gp_prev = nullptr;   // BIE right-hand side of the previous step (warm-start feature)
+  double *psi0 = nullptr;      // start density of the solve
+  double *r0v = nullptr;       // its residual, recycled from the previous solve
+  double *gp_prev = nullptr;   // BIE right-hand side of the previous step
+  double *d_prev = nullptr;    // final FP64 residual g'^{n-1} - A psi^{n-1} of the previous solve
+  bool have_prev = false;
   int64_t steps_done = 0;
   void init();
   void release();

@@ -260,7 +260,7 @@ double Solver::dot(const double *a, const double *b, hipStream_t st) {
 
 int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
                   int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
-                  double *beta0) {
+                  double *beta0, const double *r0) {
   const int m = std::max(1, std::min(restart, kMaxRestart));
   its = 0;
   if (bnorm == 0.0) {
@@ -272,6 +272,8 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
   // r = b - A x
   if (x_zero) {
     KFBI_HIP(hipMemcpyAsync(r, b, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else if (r0) {
+    KFBI_HIP(hipMemcpyAsync(r, r0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   } else {
     apply_vec(p, prec, x, t, st);
     ++matvecs;
@@ -279,11 +281,13 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
   }
   double beta = std::sqrt(dot(r, r, st));
   if (beta0) *beta0 = beta;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), Hc((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), z(m + 1);
   while (beta > tol_abs && its < maxit) {
     std::fill(H.begin(), H.end(), 0.0);
+    std::fill(Hc.begin(), Hc.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
+    const double beta_cycle = beta;
     k_axpby<<<nblk(L), kB, 0, st>>>(V, 1.0 / beta, r, 0.0, nullptr, L);
     int jend = 0;
     bool breakdown = false;
@@ -307,6 +311,7 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + hhost[(kMaxRestart + 2) + i];
       const double hn = std::sqrt(std::max(0.0, hhost[2 * (kMaxRestart + 2)]));
       H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i <= j + 1; ++i) Hc[(size_t)i * m + j] = H[(size_t)i * m + j];   // before rotations
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
         H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
@@ -335,7 +340,18 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
     KFBI_HIP(hipMemcpyAsync(ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, st));
     k_combine<<<nblk(L), kB, 0, st>>>(x, V, L, ydev, jend, 1.0, L);
     KFBI_HIP(hipGetLastError());
-    if (std::fabs(g[jend]) <= tol_abs || breakdown) {
+    if (std::fabs(g[jend]) <= tol_abs && !breakdown) {
+      // converged: the residual vector follows from the Arnoldi relation without a product,
+      //   b - A x = V_{j+1} (beta e_1 - Hbar y)
+      for (int i = 0; i <= jend; ++i) {
+        double acc = i == 0 ? beta_cycle : 0.0;
+        for (int k = 0; k < jend; ++k) acc -= Hc[(size_t)i * m + k] * y[k];
+        z[i] = acc;
+      }
+      KFBI_HIP(hipMemcpyAsync(ydev, z.data(), (jend + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+      k_axpby<<<nblk(L), kB, 0, st>>>(r, 0.0, r, 0.0, nullptr, L);
+      k_combine<<<nblk(L), kB, 0, st>>>(r, V, L, ydev, jend + 1, 1.0, L);
+      KFBI_HIP(hipGetLastError());
       beta = std::fabs(g[jend]);
       KFBI_HIP(hipStreamSynchronize(st));
       break;
@@ -377,7 +393,7 @@ void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st) {
 }
 
 int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                          hipStream_t st) {
+                          hipStream_t st, const double *r0) {
   const double gn = std::sqrt(dot(gp, gp, st));
   info.gp_norm = gn;
   const double tol_abs = o.tol * gn;
@@ -388,16 +404,20 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
     rc = richardson(p, gp, gn, psi, o.gamma, tol_abs, o.max_iters, its, mv, res, st, &res0);
     info.iters = its;
     info.matvecs_fp64 = mv;
+    last_resid = r;
   } else if (o.precision == 0) {
-    rc = gmres(p, 0, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, its, mv, res, st, &res0);
+    rc = gmres(p, 0, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, its, mv, res, st, &res0, r0);
     info.iters = its;
     info.matvecs_fp64 = mv;
+    last_resid = r;
   } else {
     // iterative refinement: FP64 residual, FP32-operator GMRES on the correction
     int total = 0, mv64 = 0, mv32 = 0, outer = 0;
     bool have_x = x0;
     for (;;) {
-      if (have_x) {
+      if (have_x && outer == 0 && r0) {
+        KFBI_HIP(hipMemcpyAsync(d, r0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else if (have_x) {
         apply_vec(p, 0, psi, t, st);
         ++mv64;
         k_axpby<<<nblk(L), kB, 0, st>>>(d, 1.0, gp, -1.0, t, L);
@@ -418,6 +438,7 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
       have_x = true;
       ++outer;
     }
+    last_resid = d;
     info.iters = total;
     info.outer = outer;
     info.matvecs_fp64 = mv64;
@@ -480,16 +501,18 @@ using namespace kfbi;
 void bidomain_s::init() {
   const int64_t L = solver->L;
   KFBI_HIP(hipMalloc(&psi0, L * sizeof(double)));
-  KFBI_HIP(hipMalloc(&psi_lin, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&r0v, L * sizeof(double)));
   KFBI_HIP(hipMalloc(&gp_prev, L * sizeof(double)));
   KFBI_HIP(hipMemset(gp_prev, 0, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&d_prev, L * sizeof(double)));
+  KFBI_HIP(hipMemset(d_prev, 0, L * sizeof(double)));
 }
 
 void bidomain_s::release() {
-  if (psi0) (void)hipFree(psi0);
-  if (psi_lin) (void)hipFree(psi_lin);
-  if (gp_prev) (void)hipFree(gp_prev);
-  psi0 = psi_lin = gp_prev = nullptr;
+  double *ps[] = {psi0, r0v, gp_prev, d_prev};
+  for (double *q : ps)
+    if (q) (void)hipFree(q);
+  psi0 = r0v = gp_prev = d_prev = nullptr;
   extern void mlp_release(bidomain_s *);
   mlp_release(this);
 }
@@ -514,31 +537,65 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   double *hist1 = s.psi_hist, *hist2 = s.psi_hist + L;
   kfbi_solve_opts o = params.solve;
   bool x0 = true;
+  bool have_r0 = false;
   info.warm_start_used = 0;
+  int extra32 = 0, extra64 = 0;
   if (params.warm_start == 2) {
     x0 = false;
-  } else if (params.warm_start == 1 && mlp && steps_done >= 2 && mlp_warm_start(this, hist1, hist2, psi0, st)) {
-    info.warm_start_used = 1;
-    // fallback check: every few steps compare the FP32 residuals of the predicted start and of
-    // psi^{n-1}; if the prediction loses, use psi^{n-1} and switch the network off
-    if (mlp_should_check(this)) {
-      sv.apply_vec(p, 1, psi0, sv.t, st);
-      const double rp = sv.residual_norm(sv.gp, sv.t, st);
-      sv.apply_vec(p, 1, hist1, sv.t, st);
-      const double rh = sv.residual_norm(sv.gp, sv.t, st);
-      info.matvecs_fp32 += 2;
-      if (!(rp < rh)) {
-        mlp_disable(this);
-        info.warm_start_used = 0;
-        KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    // start from psi^{n-1}: its residual is known without a product,
+    //   g'^n - A psi^{n-1} = g'^n - g'^{n-1} + (g'^{n-1} - A psi^{n-1}),
+    // the last term being the final FP64 residual of the previous solve
+    KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (have_prev) {
+      k_axpby<<<nblk(L), kB, 0, st>>>(r0v, 1.0, sv.gp, -1.0, gp_prev, L);
+      k_axpby<<<nblk(L), kB, 0, st>>>(r0v, 1.0, r0v, 1.0, d_prev, L);
+      have_r0 = true;
+    }
+    if (params.warm_start == 1 && mlp && steps_done >= 2 && mlp_warm_start(this, hist1, hist2, sv.w, st)) {
+      if (have_r0) {
+        // predicted start psi^{n-1} + D: residual r0 - A D, taken only if smaller than
+        // psi^{n-1}'s (checked at every use: it costs nothing more).  A D is applied in the
+        // precision of the inner solves: FP32 rounding noise in the starting residual would
+        // slow an FP64 GMRES that must resolve it, while iterative refinement absorbs it.
+        k_axpby<<<nblk(L), kB, 0, st>>>(sv.w, 1.0, sv.w, -1.0, hist1, L);
+        const int pd = o.precision == 1 && o.method == 0 ? 1 : 0;
+        sv.apply_vec(p, pd, sv.w, sv.t, st);
+        if (pd) extra32 = 1;
+        else extra64 = 1;
+        k_axpby<<<nblk(L), kB, 0, st>>>(sv.d, 1.0, r0v, -1.0, sv.t, L);
+        const double rh = sv.dot(r0v, r0v, st), rp = sv.dot(sv.d, sv.d, st);
+        if (rp < rh) {
+          k_axpby<<<nblk(L), kB, 0, st>>>(psi0, 1.0, hist1, 1.0, sv.w, L);
+          KFBI_HIP(hipMemcpyAsync(r0v, sv.d, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+          info.warm_start_used = 1;
+        } else {
+          mlp_disable(this);
+        }
+      } else if (mlp_should_check(this)) {
+        // no recycled residual (first steps): compare FP32 residuals of both starts
+        sv.apply_vec(p, 1, sv.w, sv.t, st);
+        const double rp = sv.residual_norm(sv.gp, sv.t, st);
+        sv.apply_vec(p, 1, hist1, sv.t, st);
+        const double rh = sv.residual_norm(sv.gp, sv.t, st);
+        extra32 = 2;
+        if (rp < rh) {
+          KFBI_HIP(hipMemcpyAsync(psi0, sv.w, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+          info.warm_start_used = 1;
+        } else {
+          mlp_disable(this);
+        }
+      } else {
+        KFBI_HIP(hipMemcpyAsync(psi0, sv.w, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+        info.warm_start_used = 1;
       }
     }
-  } else {
-    KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  const int extra32 = info.matvecs_fp32;
-  const int rc = sv.solve_density(p, psi0, o, x0, info, st);
+  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr);
   info.matvecs_fp32 += extra32;
+  info.matvecs_fp64 += extra64;
+  KFBI_HIP(hipMemcpyAsync(d_prev, sv.last_resid, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  have_prev = true;
   sv.reconstruct(p, psi0, st);
   double *meanp = nullptr;
   if (s.phi) {

@@ -202,17 +202,21 @@ def test_trained_start_gain_fp64():
     smaller than that of psi^{n-1}, the same final residual bound and the same solution.  GMRES
     contracts about tenfold per iteration on this operator, so a 4x better start is worth less
     than one iteration; the count stays within one of the psi^{n-1} start (training sums its
-    gradients with atomics, so the last digits of the network vary from run to run)."""
+    gradients with atomics, so the last digits of the network vary from run to run).  The
+    prediction's residual costs one FP64 product that the recycled residual of psi^{n-1} does
+    not, so the cost check may switch the learned start off after its first 8 uses."""
     say("[mlp gain fp64] shell 64")
     _, li, losses, Vl = _shell_run(0, 1, True)
     _, ci, _, Vc = _shell_run(0, 0, False)
     say(f"    loss after 1 epoch {losses[0]:.3e}, after 151 {losses[1]:.3e}")
     assert losses[1] < 0.1 * losses[0]
-    rl = [i["start_resid"] for i in li]
-    rc = [i["start_resid"] for i in ci]
-    say(f"    start residual learned {np.mean(rl):.2e} vs psi^(n-1) {np.mean(rc):.2e}")
+    used = [k for k, i in enumerate(li) if i["warm_start_used"]]
+    rl = [li[k]["start_resid"] for k in used]
+    rc = [ci[k]["start_resid"] for k in used]
+    say(f"    learned start used in steps {used}")
+    say(f"    start residual learned {np.mean(rl):.2e} vs psi^(n-1) {np.mean(rc):.2e} (same steps)")
     say(f"    iterations learned {[i['iters'] for i in li]} vs psi^(n-1) {[i['iters'] for i in ci]}")
-    assert all(i["warm_start_used"] == 1 for i in li[:8])
+    assert used[:8] == list(range(8))
     assert all(i["rel_resid"] <= 1e-10 for i in li + ci)
     assert np.mean(rl) < 0.5 * np.mean(rc)
     assert np.mean([i["iters"] for i in li]) <= np.mean([i["iters"] for i in ci]) + 1.0
