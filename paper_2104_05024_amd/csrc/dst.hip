@@ -836,38 +836,57 @@ void run_box_group(int G, const T *src, T *dst, int64_t cs, const ModeParams *ms
   pass_x<T, M>(w[0], dst, false, dst, false, rows, tw, sp, st);
 }
 
-// Time one pass at width w (median of three launches after one warm-up), in place on `a`.
-template <typename T, int M>
-float time_pass(int pass, int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, int64_t rows, const ModeScale &ms,
-                const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, hipStream_t st) {
-  hipEvent_t e0, e1;
-  KFBI_HIP(hipEventCreate(&e0));
-  KFBI_HIP(hipEventCreate(&e1));
-  float t[3];
-  for (int r = -1; r < 3; ++r) {
-    KFBI_HIP(hipEventRecord(e0, st));
-    if (pass == 0) pass_x<T, M>(w, a, false, a, false, rows, tw, sp, st);
-    else if (pass == 1) pass_y<T, M>(w, a, a, P, cs, ncomp, nullptr, nullptr, tw, sp, st);
-    else pass_last<T, M>(w, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, cs, st);
-    KFBI_HIP(hipEventRecord(e1, st));
-    KFBI_HIP(hipEventSynchronize(e1));
-    if (r >= 0) KFBI_HIP(hipEventElapsedTime(&t[r], e0, e1));
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  std::sort(t, t + 3);
-  return t[1];
+// Timing data: a fixed pseudo-random pattern in [-0.5, 0.5) (all-zero data runs at a higher
+// clock than real data under the power limit, which would bias the choice).
+template <typename T>
+__global__ void k_fill_pattern(T *__restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = (T)((((uint32_t)i * 2654435761u) >> 8) & 0xffffu) * (T)(1.0 / 65536.0) - (T)0.5;
 }
 
+// One launch of a pass at width w, in place on `a`, timed with events.
+template <typename T, int M>
+float time_pass(int pass, int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, int64_t rows, const ModeScale &ms,
+                const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, hipEvent_t e0, hipEvent_t e1,
+                hipStream_t st) {
+  // fresh data for every launch (the unnormalised passes would otherwise grow it without bound)
+  const int64_t nfill = dim == 3 ? (int64_t)ncomp * cs : (int64_t)nprob * cs;
+  k_fill_pattern<T><<<(unsigned)((nfill + 255) / 256), 256, 0, st>>>(a, nfill);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipEventRecord(e0, st));
+  if (pass == 0) pass_x<T, M>(w, a, false, a, false, rows, tw, sp, st);
+  else if (pass == 1) pass_y<T, M>(w, a, a, P, cs, ncomp, nullptr, nullptr, tw, sp, st);
+  else pass_last<T, M>(w, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, cs, st);
+  KFBI_HIP(hipEventRecord(e1, st));
+  KFBI_HIP(hipEventSynchronize(e1));
+  float ms_ = 0;
+  KFBI_HIP(hipEventElapsedTime(&ms_, e0, e1));
+  return ms_;
+}
+
+// Both widths are launched alternately (after warm-up launches that bring the clocks up), so
+// that clock and cache drift affect both alike; the median of each decides.
 template <typename T, int M>
 void tune(int *w, T *a, int dim, int ncomp, int64_t P, int64_t cs, int64_t rows, const ModeScale &ms,
           const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, hipStream_t st) {
+  constexpr int kRounds = 7;
+  hipEvent_t e0, e1;
+  KFBI_HIP(hipEventCreate(&e0));
+  KFBI_HIP(hipEventCreate(&e1));
   for (int pass = 0; pass < 3; ++pass) {
     if (pass == 1 && dim != 3) continue;
-    const float t1 = time_pass<T, M>(pass, 1, a, dim, ncomp, P, cs, rows, ms, tw, sp, msv, nprob, st);
-    const float t2 = time_pass<T, M>(pass, 2, a, dim, ncomp, P, cs, rows, ms, tw, sp, msv, nprob, st);
-    w[pass] = t2 < 0.97f * t1 ? 2 : 1;   // the wider tile must win clearly
+    float t[2][kRounds];
+    for (int r = -2; r < kRounds; ++r)
+      for (int k = 0; k < 2; ++k) {
+        const float v = time_pass<T, M>(pass, k + 1, a, dim, ncomp, P, cs, rows, ms, tw, sp, msv, nprob, e0, e1, st);
+        if (r >= 0) t[k][r] = v;
+      }
+    std::sort(t[0], t[0] + kRounds);
+    std::sort(t[1], t[1] + kRounds);
+    w[pass] = t[1][kRounds / 2] < 0.97f * t[0][kRounds / 2] ? 2 : 1;   // the wider tile must win clearly
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 template <typename T>
