@@ -294,3 +294,59 @@ def test_tile_widths_do_not_change_results(name):
             else:
                 assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (dt, widths)
         g.set_tiles(chosen[dt], dt)
+
+
+# ----------------------------------------------------------------------------- full sizes (256^3)
+
+def test_full_size_shell_256_apply_matches_oracle():
+    """The bench workload itself (thick shell, 256^3, 40,960 nodes, coupled pair): the
+    matrix-vector product in the launch configuration the bench times, against the oracle's
+    (its setup takes about a minute on the host)."""
+    iface, grid = W.thick_shell(n_nodes=40960), W.box(3, 256)
+    co = W.bidomain_coeffs(3, P_BIDO, 0.01)
+    say("[setup] shell_256 (GPU)")
+    g = K.Problem(iface, grid, co)
+    say("[setup] shell_256 (oracle)")
+    o = ok.Problem(iface, grid, co)
+    psi = np.random.default_rng(12).uniform(-1, 1, size=(2, g.M))
+    say("[apply] shell_256")
+    ref = o.apply(psi)
+    e64 = rel(g.apply(T(psi)).cpu().numpy(), ref)
+    e32 = rel(g.apply(T(psi, torch.float32)).double().cpu().numpy(), ref)
+    say(f"    rel err FP64 {e64:.2e}, FP32 {e32:.2e}")
+    assert e64 < 1e-10
+    assert e32 < 1e-5
+    g.close()
+
+
+def test_full_size_perturbed_sphere_256_mixed_precision():
+    """C3 at full size: FP32 products inside FP64 refinement reach the FP64 relative residual
+    1e-10, agree with the FP64 solve, and solve the manufactured problem to second order."""
+    iface, grid = W.perturbed_sphere(n_nodes=32768), W.box(3, 256)
+    co = W.scalar_coeffs(3, 1.0, 400.0)
+    say("[setup] psphere_256")
+    g = K.Problem(iface, grid, co)
+    pts = ogeo.grid_points(grid)
+    ue = np.sin(pts[:, 0]) * np.cos(pts[:, 1]) * np.exp(pts[:, 2])
+    nodes = ogeo.Nodes(iface)
+    X, n = nodes.X, nodes.n
+    gr = np.stack([np.cos(X[:, 0]) * np.cos(X[:, 1]) * np.exp(X[:, 2]),
+                   -np.sin(X[:, 0]) * np.sin(X[:, 1]) * np.exp(X[:, 2]),
+                   np.sin(X[:, 0]) * np.cos(X[:, 1]) * np.exp(X[:, 2])], 1)
+    gn = np.sum(n * gr, 1)[None]
+    f = (401.0 * ue)[None]
+    say("[solve mixed] psphere_256")
+    u32, _, i32 = g.solve_neumann(T(gn), T(f), tol=1e-10, precision=1, inner_tol=1e-4)
+    say("[solve f64] psphere_256")
+    u64, _, i64 = g.solve_neumann(T(gn), T(f), tol=1e-10)
+    ins = ogeo.classify(iface, grid).all(axis=0)
+    u32, u64 = u32.cpu().numpy()[0], u64.cpu().numpy()[0]
+    e = rel(u32[ins], u64[ins])
+    err = np.max(np.abs(u32 - ue)[ins])
+    say(f"    outer {i32['outer']} fp32 {i32['matvecs_fp32']} fp64 {i32['matvecs_fp64']}; "
+        f"mixed vs FP64 {e:.2e}; max error vs exact {err:.2e}")
+    assert i32["rel_resid"] <= 1e-10 and i64["rel_resid"] <= 1e-10
+    assert e < 1e-8
+    # the 128^3 ellipsoid case reaches 1e-4 at h = 0.01875; here h is half of that
+    assert err < 1e-4
+    g.close()
