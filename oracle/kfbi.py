@@ -14,12 +14,14 @@ The pieces, in the order of Algorithm 1:
   nodes in the tangent plane (3D).
 * jump relations of the single-layer interface problem (Sec. 5.1, eq.
   single: [u] = 0, [n.D grad u] = psi, homogeneous equation on both sides).
-  For isotropic D_c = sigma_c the interface conditions give
-  [grad u] = (psi/sigma) n and
-  [Hess u] = (psi/sigma)(W - tr(W) n n^T) + (n g^T + g n^T)/sigma - ([f]/sigma) n n^T,
+  For a diagonal D_c the interface conditions give [grad u] = a n with
+  a = psi / (n.D n) and [Hess u] = a W + n b^T + b n^T + c n n^T,
+  b = (g - 2 a W D n) / (n.D n), c fixed by tr(D [Hess u]) = -[f];
   g = surface gradient of psi, W = shape operator (derived by differentiating
   [u] = 0 twice and the flux jump once along the boundary, and using the PDE
-  for the normal-normal part).
+  for the normal-normal part).  For isotropic D = sigma this is
+  [grad u] = (psi/sigma) n,
+  [Hess u] = (psi/sigma)(W - tr(W) n n^T) + (n g^T + g n^T)/sigma - ([f]/sigma) n n^T.
 * right-hand-side correction at irregular nodes (Sec. 5.3, eq. correct):
   for a node p whose arm to the neighbour q crosses the boundary at z,
   rhs_p += s_p (D_a/h^2) ([u] + [u_a] d + 1/2 [u_aa] d^2), d = q_a - z_a,
@@ -202,10 +204,8 @@ class Problem:
         d = grid.dim
         if iface.dim != d:
             raise ValueError("interface and grid dimensions differ")
-        for c in range(coeffs.ncomp):
-            if any(abs(v - coeffs.D[c][0]) > 0 for v in coeffs.D[c][:d]):
-                raise ValueError("jump relations implemented for isotropic D_c only")
-        self.sigma = [float(coeffs.D[c][0]) for c in range(coeffs.ncomp)]
+        # diagonal conductivity per component and axis
+        self.sigma = [np.asarray(coeffs.D[c][:d], dtype=np.float64) for c in range(coeffs.ncomp)]
         geometry.check_box_clearance(iface, grid)
         self.nodes = geometry.Nodes(iface)
         side = geometry.classify(iface, grid)
@@ -351,15 +351,35 @@ class Problem:
         return u, psi.reshape(self.coeffs.ncomp, self.M), info
 
 
-def jump_relations(psi, g, n, W, sigma, fjump=None):
-    """Single-layer jumps from density psi, its surface gradient g, normal n and shape operator W."""
-    a = psi / sigma
+def jump_relations(psi, g, n, W, D, fjump=None):
+    """Single-layer jumps from density psi, its surface gradient g, normal n, shape operator W
+    and the diagonal conductivity D (a scalar or one value per axis) of the component.
+
+    With [u] = 0 and [n.D grad u] = psi (Sec. 5.1, eq. single):
+      [grad u] = a n,  a = psi / (n.D n)   (tangential derivatives of [u] vanish);
+      tangential block of [Hess u] = a W    (second tangential derivatives of [u] = 0);
+      n.D [Hess u] t = g.t - a t.W D n for tangent t (tangential derivative of the flux jump,
+      d n / dt = W t), i.e. the mixed part b = (g - 2 a W D n) / (n.D n);
+      tr(D [Hess u]) = -[f]                (the equation on both sides, [u] = 0), which fixes
+      the normal-normal part c;
+    so [Hess u] = a W + n b^T + b n^T + c n n^T.
+    """
+    psi = np.asarray(psi, dtype=np.float64)
     d = n.shape[1]
-    trW = np.trace(W, axis1=1, axis2=2)
+    Dv = np.broadcast_to(np.asarray(D, dtype=np.float64).ravel()[:d] if np.ndim(D) else
+                         np.full(d, float(D)), (d,))
+    Dn = n * Dv[None, :]
+    nDn = np.sum(n * Dn, axis=1)
+    a = psi / nDn
+    WDn = np.einsum("nij,nj->ni", W, Dn)
+    b = (g - 2.0 * a[:, None] * WDn) / nDn[:, None]
+    trDW = np.einsum("i,nii->n", Dv, W)
+    rhs_c = -a * trDW - 2.0 * np.sum(b * Dn, axis=1)
+    if fjump is not None:
+        rhs_c = rhs_c - fjump
+    c = rhs_c / nDn
     nn = n[:, :, None] * n[:, None, :]
     du = a[:, None] * n
-    H = a[:, None, None] * (W - trW[:, None, None] * nn) \
-        + (n[:, :, None] * g[:, None, :] + g[:, :, None] * n[:, None, :]) / sigma
-    if fjump is not None:
-        H = H - (fjump / sigma)[:, None, None] * nn
+    H = a[:, None, None] * W + n[:, :, None] * b[:, None, :] + b[:, :, None] * n[:, None, :] \
+        + c[:, None, None] * nn
     return du, H

@@ -36,25 +36,51 @@ def fd_derivs(f, x, eps=1e-4):
 # ----------------------------------------------------------------------------- jump relations
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_jump_relations_reproduce_exact_piecewise_function(dim):
+@pytest.mark.parametrize("aniso", [False, True])
+def test_jump_relations_reproduce_exact_piecewise_function(dim, aniso):
     """u- = u+ - (r - R) w on a circle/sphere: [u] = 0, [grad u] = w n,
-    [Hess u] = w P/R + n grad w^T + grad w n^T; with psi = sigma w, g = sigma P grad w
-    and [f] = -sigma tr[Hess u] the relations must reproduce [Hess u] exactly."""
-    R, sigma = 0.6, 1.7
+    [Hess u] = w P/R + n grad w^T + grad w n^T, whatever D is.  With psi = w n.D n (the flux
+    jump), g its surface gradient (finite differences of psi extended radially) and
+    [f] = -tr(D [Hess u]) the relations must reproduce [grad u] and [Hess u]."""
+    R = 0.6
+    D = np.array([1.7, 0.4, 2.9][:dim]) if aniso else np.full(dim, 1.7)
     surf = W.Surface((R,) * dim, +1, 10, [])
     u = geometry.node_directions(dim, 37)
     x = R * u
     n, Wm = geometry.normal_and_shape(surf, x)
     wf = lambda p: np.cos(p[:, 0] + 2 * p[:, 1]) + 0.3 * p[:, -1] ** 2
+    psif = lambda p: wf(p) * np.sum((p / np.linalg.norm(p, axis=1)[:, None]) ** 2 * D[None, :], axis=1)
     w = wf(x)
     gw, _ = fd_derivs(wf, x, 1e-5)
+    gpsi, _ = fd_derivs(psif, x, 1e-5)
     P = np.eye(dim)[None] - n[:, :, None] * n[:, None, :]
     Ht = w[:, None, None] * P / R + n[:, :, None] * gw[:, None, :] + gw[:, :, None] * n[:, None, :]
-    gsurf = np.einsum("nij,nj->ni", P, gw)
-    fj = -sigma * np.trace(Ht, axis1=1, axis2=2)
-    du, H = kfbi.jump_relations(sigma * w, sigma * gsurf, n, Wm, sigma, fjump=fj)
-    np.testing.assert_allclose(du, w[:, None] * n, atol=1e-13)
+    gsurf = np.einsum("nij,nj->ni", P, gpsi)
+    fj = -np.einsum("i,nii->n", D, Ht)
+    du, H = kfbi.jump_relations(psif(x), gsurf, n, Wm, D, fjump=fj)
+    np.testing.assert_allclose(du, w[:, None] * n, atol=1e-12)
     np.testing.assert_allclose(H, Ht, atol=1e-8)
+
+
+def test_jump_relations_isotropic_closed_form():
+    """For D = sigma I the general relations reduce to the isotropic closed form
+    (psi/sigma)(W - tr W nn^T) + (n g^T + g n^T)/sigma."""
+    rng = np.random.default_rng(3)
+    surf = W.ellipsoid(0.9, 0.7, 0.5).surfaces[0]
+    u = geometry.node_directions(3, 50)
+    G, _, _ = geometry.radial(surf, u)
+    x = G[:, None] * u
+    n, Wm = geometry.normal_and_shape(surf, x)
+    psi = rng.normal(size=50)
+    g = np.einsum("nij,nj->ni", np.eye(3)[None] - n[:, :, None] * n[:, None, :], rng.normal(size=(50, 3)))
+    sigma = 2.3
+    du, H = kfbi.jump_relations(psi, g, n, Wm, sigma)
+    trW = np.trace(Wm, axis1=1, axis2=2)
+    nn = n[:, :, None] * n[:, None, :]
+    Hc = (psi / sigma)[:, None, None] * (Wm - trW[:, None, None] * nn) \
+        + (n[:, :, None] * g[:, None, :] + g[:, :, None] * n[:, None, :]) / sigma
+    np.testing.assert_allclose(du, (psi / sigma)[:, None] * n, atol=1e-14)
+    np.testing.assert_allclose(H, Hc, atol=1e-12)
 
 
 # ----------------------------------------------------------------------------- correction (P3)
@@ -339,3 +365,50 @@ def test_coupled_matches_scalar_reduction(dim):
     Ac = Pc.apply(psi)
     As = Ps.apply(psi[0] / si - psi[1] / se)[0]
     np.testing.assert_allclose(Ac[0] / si - Ac[1] / se, As, atol=1e-10 * np.max(np.abs(As)))
+
+
+# ----------------------------------------------------------------------------- anisotropic D (next row)
+
+def _aniso_coeffs(dim, D, kappa):
+    return W.Coeffs(1, [list(D)], kappa)
+
+
+def test_neumann_mms_anisotropic_2d_second_order():
+    """-div(D grad u) + kappa u = f with D = diag(3, 0.5) (the paper's 30 : 5 ratio, scaled) and
+    flux data g = n.D grad u: second-order convergence of u, iterations flat in h."""
+    D, kappa = (3.0, 0.5), 400.0
+    ue = lambda x: np.exp(x[:, 0]) * np.sin(np.pi * x[:, 1])
+    grad = lambda x: np.stack([ue(x), np.pi * np.exp(x[:, 0]) * np.cos(np.pi * x[:, 1])], 1)
+    errs, its = [], []
+    for I in (64, 128, 256):
+        P = kfbi.Problem(W.star2d(n_nodes=2 * I), W.box(2, I), _aniso_coeffs(2, D, kappa))
+        pts = geometry.grid_points(P.grid)
+        f = (-D[0] + D[1] * math.pi ** 2 + kappa) * ue(pts)
+        g = np.sum(P.nodes.n * np.asarray(D)[None, :] * grad(P.nodes.X), 1)
+        u, _, info = P.solve_neumann(g[None], f[None], tol=1e-10)
+        e = np.abs(u[0] - ue(pts))[P.inside]
+        errs.append(np.sqrt(np.mean(e * e)))
+        its.append(info["iters"])
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.8, (errs, rates)
+    assert max(its) - min(its) <= 4, its
+
+
+def test_neumann_mms_anisotropic_3d():
+    D, kappa = (3.0, 0.5, 0.5), 400.0
+    ue = lambda x: np.sin(x[:, 0]) * np.cos(x[:, 1]) * np.exp(x[:, 2])
+
+    def grad(x):
+        s, c, e = np.sin(x[:, 0]), np.cos(x[:, 1]), np.exp(x[:, 2])
+        return np.stack([np.cos(x[:, 0]) * c * e, -s * np.sin(x[:, 1]) * e, s * c * e], 1)
+
+    errs = []
+    for I in (32, 64):
+        P = kfbi.Problem(W.ellipsoid(n_nodes=int(8192 * (I / 128) ** 2)), W.box(3, I), _aniso_coeffs(3, D, kappa))
+        pts = geometry.grid_points(P.grid)
+        f = (D[0] + D[1] - D[2] + kappa) * ue(pts)
+        g = np.sum(P.nodes.n * np.asarray(D)[None, :] * grad(P.nodes.X), 1)
+        u, _, info = P.solve_neumann(g[None], f[None], tol=1e-10)
+        e = np.abs(u[0] - ue(pts))[P.inside]
+        errs.append(np.sqrt(np.mean(e * e)))
+    assert math.log2(errs[0] / errs[1]) > 1.8, errs
