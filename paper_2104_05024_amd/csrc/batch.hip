@@ -203,7 +203,12 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
     std::vector<ModeParams> ms;
     for (int i : g.members) {
       const DevProblem &p = *probs[i];
-      ms.push_back(ModeParams{p.lam, p.sigma[0], p.sigma[0], p.kappa, p.lam_scale});
+      ModeParams m{};
+      m.lam = p.lam;
+      for (int a = 0; a < 3; ++a) m.D0[a] = m.D1[a] = p.D[0][a];
+      m.kappa = p.kappa;
+      m.norm = p.lam_scale;
+      ms.push_back(m);
     }
     g.msv = balloc<ModeParams>(ms.size());
     KFBI_HIP(hipMemcpy(g.msv, ms.data(), ms.size() * sizeof(ModeParams), hipMemcpyHostToDevice));
@@ -247,19 +252,18 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
   std::vector<PackItem> pk(n);
   auto fill = [&](auto &it, auto &tb, auto *rhs, auto *fpad, auto *work, const DevProblem &p, int i) {
     it.z_idx = p.z_idx;
-    it.z_w0 = tb.z_w0;
-    it.z_wga = tb.z_wga;
-    it.z_na = tb.z_na;
-    it.z_cw = tb.z_cw;
+    it.z_A = tb.z_A;
+    it.z_B = tb.z_B;
     it.irr_pos = p.irr_pos;
     it.irr_ptr = p.irr_ptr;
     it.arm_cross = p.arm_cross;
     it.arm_d = tb.arm_d;
     it.arm_s = tb.arm_s;
+    it.narm = p.narm;
     it.q_idx = p.q_idx;
     it.q_wg = tb.q_wg;
-    it.q_n = tb.q_n;
-    it.q_wt = tb.q_wt;
+    it.q_c = tb.q_c;
+    it.q_G = tb.q_G;
     it.st_pos = p.st_pos;
     it.st_nw = tb.st_nw;
     it.st_r = tb.st_r;
@@ -272,9 +276,6 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
     it.nc = p.nc;
     it.nirr = p.nirr;
     it.ioff = off[i];
-    using T = std::remove_pointer_t<decltype(rhs)>;
-    it.sigma = (T)p.sigma[0];
-    it.isig = (T)(1.0 / p.sigma[0]);
   };
   for (int i = 0; i < n; ++i) {
     const DevProblem &p = *probs[i];

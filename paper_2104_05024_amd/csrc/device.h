@@ -27,10 +27,11 @@ struct HipError {
 
 template <typename T>
 struct PrecTables {          // per-precision device copies of the numeric tables
-  T *z_w0 = nullptr, *z_wga = nullptr, *z_na = nullptr, *z_cw = nullptr;
-  T *q_wg = nullptr, *q_n = nullptr, *q_wt = nullptr;
-  T *arm_d = nullptr, *arm_s = nullptr;
-  T *st_nw = nullptr, *st_r = nullptr;
+  T *z_A = nullptr, *z_B = nullptr;      // crossing jumps [comp][K][nc]: [u_a] = sum A psi, [u_aa] = sum B psi
+  T *q_wg = nullptr;                     // node surface-gradient weights [Kn][d][M]
+  T *q_c = nullptr, *q_G = nullptr;      // node jumps [comp][d + NH][M] on psi_q, [comp][d + NH][d][M] on g
+  T *arm_d = nullptr, *arm_s = nullptr;  // arm offsets [narm]; s D_{c,a} / h^2 [comp][narm]
+  T *st_nw = nullptr, *st_r = nullptr;   // gather weights n.D_c grad [comp][S][M]; offsets [S][d][M]
   T *tw = nullptr, *sp = nullptr;        // DST twiddles exp(-2 pi i m/M) (complex) and sin(pi n/M)
   T *rhs = nullptr, *work = nullptr;     // matvec right-hand side (zero off irregular nodes), work field
   T *xbuf = nullptr;                     // sparse matvec: x-forward output, zero outside the rhs rows
@@ -90,7 +91,7 @@ struct DevProblem {
   int64_t N = 0, M = 0, P = 0, nc = 0, nirr = 0, narm = 0;
   int64_t comp_stride = 0;     // padded elements per component
   int K = 0, Kn = 0, S = 0;
-  double h = 0, kappa = 0, sigma[2] = {1, 1};
+  double h = 0, kappa = 0, D[2][3] = {{1, 1, 1}, {1, 1, 1}};   // diagonal conductivity per component
   double lam_scale = 1;        // (2/M)^d normalisation of the inverse transforms
 
   // integer tables
@@ -131,10 +132,11 @@ template <>
 inline PrecTables<float> &DevProblem::tab<float>() { return f32; }
 
 // Mode solve parameters of one problem: eigenvalues (4/h^2) sin^2(k pi / 2M), k = 1..N,
-// diagonal conductivities of the (one or two) components, kappa, and the (2/M)^d factor.
+// diagonal conductivities of the (one or two) components per axis, kappa, and the (2/M)^d
+// factor; the mode sum of component c is sum_a D_{c,a} lambda_{k_a}.
 struct ModeParams {
   const double *lam;
-  double D0, D1, kappa, norm;
+  double D0[3], D1[3], kappa, norm;   // conductivity per axis of component 0 and 1
 };
 
 // One two-dimensional, one-component problem of a batch as the batched interface kernels see
@@ -143,17 +145,17 @@ struct ModeParams {
 template <typename T>
 struct BatchItem {
   const int32_t *z_idx;
-  const T *z_w0, *z_wga, *z_na, *z_cw;
+  const T *z_A, *z_B;
   const int32_t *irr_pos, *irr_ptr, *arm_cross;
   const T *arm_d, *arm_s;
+  int64_t narm;
   const int32_t *q_idx;
-  const T *q_wg, *q_n, *q_wt;
+  const T *q_wg, *q_c, *q_G;
   const int32_t *st_pos;
   const T *st_nw, *st_r;
   T *jz, *jq;
   T *rhs, *fpad, *work;        // padded fields inside the group buffers
   int64_t M, nc, nirr, ioff;
-  T sigma, isig;
 };
 
 // Prefix sums over the problems of a batch (device arrays of n + 1 entries) and totals.

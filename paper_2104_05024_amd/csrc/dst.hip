@@ -537,22 +537,23 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restr
 using ModeScale = ModeParams;
 
 // Mode solve applied to each value as the inverse transform reads it (position m = mode index
-// along the last axis): u^ = f^ / (D L + kappa), or the closed-form inverse of the coupled 2x2.
+// along the last axis): u^ = f^ / (L + kappa), or the closed-form inverse of the coupled 2x2,
+// with the mode sums L = b + dz lambda_m (b: the other axes' part, fixed per pencil).
 template <typename T, int NC>
 struct ModeHook {
   const T *slam;
-  T L0, L1, D0, D1, kap, nrm;
+  T b0, b1, dz0, dz1, kap, nrm;   // NC = 2: components 0 / 1 of one column; NC = 1: columns a / b
   __device__ __forceinline__ void operator()(int m, C2<T> &v) const {
     const T lz = slam[m - 1];
     if (NC == 2) {
-      const T L = L0 + lz, ai = D0 * L, ae = D1 * L;
+      const T ai = b0 + dz0 * lz, ae = b1 + dz1 * lz;
       const T s = nrm * recip(ai * ae + kap * (ai + ae));
       const T fi = v.x, fe = v.y;
       v.x = s * ((ae + kap) * fi + kap * fe);
       v.y = s * (kap * fi + (ai + kap) * fe);
     } else {
-      v.x *= nrm * recip(D0 * (L0 + lz) + kap);
-      v.y *= nrm * recip(D0 * (L1 + lz) + kap);
+      v.x *= nrm * recip(b0 + dz0 * lz + kap);
+      v.y *= nrm * recip(b1 + dz0 * lz + kap);
     }
   }
 };
@@ -602,17 +603,23 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   mh.slam = slam;
   {
     const T ly = DIM == 3 ? slam[y] : T(0);
+    const int last = DIM - 1;
     if (NC == 2) {
       const int x = x0 + pr;
-      mh.L0 = mh.L1 = (x < N ? slam[x] : T(0)) + ly;
+      const T lx = x < N ? slam[x] : T(0);
+      mh.b0 = (T)ms.D0[0] * lx + (DIM == 3 ? (T)ms.D0[1] * ly : T(0));
+      mh.b1 = (T)ms.D1[0] * lx + (DIM == 3 ? (T)ms.D1[1] * ly : T(0));
+      mh.dz0 = (T)ms.D0[last];
+      mh.dz1 = (T)ms.D1[last];
     } else {
       const int xa = x0 + 2 * pr, xb = xa + 1;
-      mh.L0 = (xa < N ? slam[xa] : T(0)) + ly;
-      mh.L1 = (xb < N ? slam[xb] : T(0)) + ly;
+      const T la = xa < N ? slam[xa] : T(0), lb = xb < N ? slam[xb] : T(0);
+      const T yy = DIM == 3 ? (T)ms.D0[1] * ly : T(0);
+      mh.b0 = (T)ms.D0[0] * la + yy;
+      mh.b1 = (T)ms.D0[0] * lb + yy;
+      mh.dz0 = mh.dz1 = (T)ms.D0[last];
     }
   }
-  mh.D0 = (T)ms.D0;
-  mh.D1 = (T)ms.D1;
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
   dst_pair<T, M>(mine, lane, tw, sp, mh);
@@ -744,7 +751,15 @@ void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const Mod
 
 template <typename T>
 ModeScale mode_of(const DevProblem &p) {
-  return ModeScale{p.lam, p.sigma[0], p.ncomp == 2 ? p.sigma[1] : p.sigma[0], p.kappa, p.lam_scale};
+  ModeScale m{};
+  m.lam = p.lam;
+  for (int a = 0; a < 3; ++a) {
+    m.D0[a] = p.D[0][a];
+    m.D1[a] = p.D[p.ncomp == 2 ? 1 : 0][a];
+  }
+  m.kappa = p.kappa;
+  m.norm = p.lam_scale;
+  return m;
 }
 
 template <typename T, int M>

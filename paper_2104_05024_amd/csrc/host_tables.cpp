@@ -419,8 +419,8 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   if (!(co.kappa >= 0) || !std::isfinite(co.kappa)) throw std::invalid_argument("kappa");
   for (int c = 0; c < co.ncomp; ++c)
     for (int a = 0; a < d; ++a)
-      if (!(co.D[c][a] > 0) || co.D[c][a] != co.D[c][0])
-        throw std::invalid_argument("D must be positive and isotropic per component");
+      if (!(co.D[c][a] > 0) || !std::isfinite(co.D[c][a]))
+        throw std::invalid_argument("D must be positive per component and axis");
   t.dim = d;
   t.ncomp = co.ncomp;
   t.cells = grid.cells;

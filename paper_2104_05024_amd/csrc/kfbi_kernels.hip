@@ -2,10 +2,10 @@
 //
 //  k_jumps_cross : density -> jumps [u_a], [u_aa] at every grid-line intersection
 //                  (single-layer interface problem, Sec. 5.1 eq. single; jump relations
-//                  from [u] = 0 and [n.D grad u] = psi for isotropic D_c).
+//                  from [u] = 0 and [n.D grad u] = psi for diagonal D_c).
 //  k_jumps_nodes : density -> [grad u] and [Hess u] at every interface node.
 //  k_correct     : right-hand-side correction at irregular grid nodes (Sec. 5.3, eq.
-//                  correct): rhs_p = D_c sum_arms s_p/h^2 ([u_a] d + [u_aa] d^2 / 2).
+//                  correct): rhs_p = sum_arms s_p D_{c,a}/h^2 ([u_a] d + [u_aa] d^2 / 2).
 //                  One thread owns one irregular node, so no atomics are needed.
 //  k_gather      : n.D grad u+ at every interface node from its 6/10-node quadratic fit,
 //                  adding the Taylor-expanded jump to values on the "-" side
@@ -22,84 +22,78 @@ constexpr int kBlock = 256;
 
 // All stencil sizes are compile-time constants so that every index load of a thread is
 // issued before the dependent gathers (the kernels are latency-bound, not bandwidth-bound).
-template <typename T, int D, int K>
+// The jump relations enter through per-point weights built at setup (linear in the density
+// values of the transfer stencil), so these kernels hold no geometry and serve any diagonal D.
+
+// [u_a], [u_aa] at one crossing for every component: two weighted sums of the density values.
+template <typename T, int K>
 __device__ __forceinline__ void jumps_cross_at(int64_t c, const T *__restrict__ psi, int64_t M, int64_t nc,
-                                               const int32_t *__restrict__ z_idx, const T *__restrict__ z_w0,
-                                               const T *__restrict__ z_wga, const T *__restrict__ z_na,
-                                               const T *__restrict__ z_cw, int ncomp, T is0, T is1,
-                                               T *__restrict__ jz) {
+                                               const int32_t *__restrict__ z_idx, const T *__restrict__ zA,
+                                               const T *__restrict__ zB, int ncomp, T *__restrict__ jz) {
   int32_t j[K];
-  T w[K], wg[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    j[k] = z_idx[k * nc + c];
-    w[k] = z_w0[k * nc + c];
-    wg[k] = z_wga[k * nc + c];
-  }
-  const T na = z_na[c], cw = z_cw[c];
+  for (int k = 0; k < K; ++k) j[k] = z_idx[k * nc + c];
   for (int comp = 0; comp < ncomp; ++comp) {
     const T *ps = psi + comp * M;
+    const T *A = zA + (int64_t)comp * K * nc, *B = zB + (int64_t)comp * K * nc;
     T v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = ps[j[k]];
-    T pz = 0, ga = 0;
+    T ju = 0, juu = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      pz += w[k] * v[k];
-      ga += wg[k] * v[k];
+      ju += A[k * nc + c] * v[k];
+      juu += B[k * nc + c] * v[k];
     }
-    const T is = comp == 0 ? is0 : is1;
-    const T a = pz * is;
-    jz[(2 * comp) * nc + c] = a * na;
-    jz[(2 * comp + 1) * nc + c] = a * cw + (T)2 * na * ga * is;
+    jz[(2 * comp) * nc + c] = ju;
+    jz[(2 * comp + 1) * nc + c] = juu;
   }
 }
 
-template <typename T, int D, int K>
+template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc,
-                                                        const int32_t *__restrict__ z_idx,
-                                                        const T *__restrict__ z_w0, const T *__restrict__ z_wga,
-                                                        const T *__restrict__ z_na, const T *__restrict__ z_cw,
-                                                        int ncomp, T is0, T is1, T *__restrict__ jz) {
+                                                        const int32_t *__restrict__ z_idx, const T *__restrict__ zA,
+                                                        const T *__restrict__ zB, int ncomp, T *__restrict__ jz) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < nc) jumps_cross_at<T, D, K>(c, psi, M, nc, z_idx, z_w0, z_wga, z_na, z_cw, ncomp, is0, is1, jz);
+  if (c < nc) jumps_cross_at<T, K>(c, psi, M, nc, z_idx, zA, zB, ncomp, jz);
 }
 
 // One thread per irregular node; at most 2D arms, loaded predicated and all at once.
+// arm_s[comp][arm] = s_p D_{c,a} / h^2 for the arm's axis a.
 template <typename T, int D>
 __device__ __forceinline__ void correct_at(int64_t r, const int32_t *__restrict__ irr_pos,
                                            const int32_t *__restrict__ irr_ptr, const int32_t *__restrict__ arm_cross,
-                                           const T *__restrict__ arm_d, const T *__restrict__ arm_s,
-                                           const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
-                                           T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
+                                           const T *__restrict__ arm_d, const T *__restrict__ arm_s, int64_t narm,
+                                           const T *__restrict__ jz, int64_t nc, int ncomp, T *__restrict__ rhs,
+                                           int64_t comp_stride, int accumulate) {
   constexpr int MAXA = 2 * D;
   const int32_t b = irr_ptr[r], e = irr_ptr[r + 1];
   const int64_t pos = irr_pos[r];
   int32_t cr[MAXA];
-  T d[MAXA], sg[MAXA];
+  T d[MAXA];
 #pragma unroll
   for (int i = 0; i < MAXA; ++i) {
     const bool ok = b + i < e;
     cr[i] = ok ? arm_cross[b + i] : 0;
     d[i] = ok ? arm_d[b + i] : T(0);
-    sg[i] = ok ? arm_s[b + i] : T(0);
   }
   for (int comp = 0; comp < ncomp; ++comp) {
-    T du[MAXA], duu[MAXA];
+    T du[MAXA], duu[MAXA], sg[MAXA];
 #pragma unroll
     for (int i = 0; i < MAXA; ++i) {
+      const bool ok = b + i < e;
       du[i] = jz[(2 * comp) * nc + cr[i]];
       duu[i] = jz[(2 * comp + 1) * nc + cr[i]];
+      sg[i] = ok ? arm_s[comp * narm + b + i] : T(0);
     }
     T acc = 0;
 #pragma unroll
     for (int i = 0; i < MAXA; ++i) acc += sg[i] * (du[i] * d[i] + (T)0.5 * duu[i] * d[i] * d[i]);
     T *o = rhs + comp * comp_stride + pos;
-    const T val = (comp == 0 ? D0 : D1) * acc;
     if (accumulate)
-      *o += val;
+      *o += acc;
     else
-      *o = val;
+      *o = acc;
   }
 }
 
@@ -108,11 +102,11 @@ __global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t 
                                                     const int32_t *__restrict__ irr_ptr,
                                                     const int32_t *__restrict__ arm_cross,
                                                     const T *__restrict__ arm_d, const T *__restrict__ arm_s,
-                                                    const T *__restrict__ jz, int64_t nc, int ncomp, T D0, T D1,
+                                                    int64_t narm, const T *__restrict__ jz, int64_t nc, int ncomp,
                                                     T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nirr)
-    correct_at<T, D>(r, irr_pos, irr_ptr, arm_cross, arm_d, arm_s, jz, nc, ncomp, D0, D1, rhs, comp_stride,
+    correct_at<T, D>(r, irr_pos, irr_ptr, arm_cross, arm_d, arm_s, narm, jz, nc, ncomp, rhs, comp_stride,
                      accumulate);
 }
 
@@ -132,23 +126,19 @@ __device__ __forceinline__ void sym_index(int e, int &a, int &b) {
   }
 }
 
+// [grad u] (D entries) and [Hess u] (NH entries) at one node for every component:
+// out_j = psi_q qc[j] + sum_f g_f qG[j][f], g = surface gradient of psi from the transfer fit.
 template <typename T, int D, int KN>
 __device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ psi, int64_t M,
                                                const int32_t *__restrict__ q_idx, const T *__restrict__ q_wg,
-                                               const T *__restrict__ q_n, const T *__restrict__ q_wt, int ncomp,
-                                               T is0, T is1, T *__restrict__ jq) {
-  constexpr int NHv = NH<D>::v, STR = D + NHv;
+                                               const T *__restrict__ q_c, const T *__restrict__ q_G, int ncomp,
+                                               T *__restrict__ jq) {
+  constexpr int J = D + NH<D>::v;
   int32_t j[KN];
 #pragma unroll
   for (int k = 0; k < KN; ++k) j[k] = q_idx[k * M + q];
-  T n[D], wt[NHv];
-#pragma unroll
-  for (int a = 0; a < D; ++a) n[a] = q_n[a * M + q];
-#pragma unroll
-  for (int e = 0; e < NHv; ++e) wt[e] = q_wt[e * M + q];
   for (int comp = 0; comp < ncomp; ++comp) {
     const T *ps = psi + comp * M;
-    const T is = comp == 0 ? is0 : is1;
     T v[KN];
 #pragma unroll
     for (int k = 0; k < KN; ++k) v[k] = ps[j[k]];
@@ -159,15 +149,15 @@ __device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ 
 #pragma unroll
       for (int k = 0; k < KN; ++k) g[a] += q_wg[(k * D + a) * M + q] * v[k];
     }
-    const T amp = ps[q] * is;
-    T *o = jq + (int64_t)comp * STR * M;
+    const T pq = ps[q];
+    const T *C = q_c + (int64_t)comp * J * M, *G = q_G + (int64_t)comp * J * D * M;
+    T *o = jq + (int64_t)comp * J * M;
 #pragma unroll
-    for (int a = 0; a < D; ++a) o[a * M + q] = amp * n[a];
+    for (int e = 0; e < J; ++e) {
+      T acc = pq * C[e * M + q];
 #pragma unroll
-    for (int e = 0; e < NHv; ++e) {
-      int a, b;
-      sym_index<D>(e, a, b);
-      o[(D + e) * M + q] = amp * wt[e] + (n[a] * g[b] + g[a] * n[b]) * is;
+      for (int f = 0; f < D; ++f) acc += g[f] * G[(e * D + f) * M + q];
+      o[e * M + q] = acc;
     }
   }
 }
@@ -175,26 +165,22 @@ __device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ 
 template <typename T, int D, int KN>
 __global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M,
                                                         const int32_t *__restrict__ q_idx,
-                                                        const T *__restrict__ q_wg, const T *__restrict__ q_n,
-                                                        const T *__restrict__ q_wt, int ncomp, T is0, T is1,
-                                                        T *__restrict__ jq) {
+                                                        const T *__restrict__ q_wg, const T *__restrict__ q_c,
+                                                        const T *__restrict__ q_G, int ncomp, T *__restrict__ jq) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < M) jumps_nodes_at<T, D, KN>(q, psi, M, q_idx, q_wg, q_n, q_wt, ncomp, is0, is1, jq);
+  if (q < M) jumps_nodes_at<T, D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, ncomp, jq);
 }
 
+// n.D_c grad u+ at one node: st_nw[comp][j] = sum_a n_a D_{c,a} (gradient weight of node j)_a.
 template <typename T, int D, int S>
 __device__ __forceinline__ void gather_at(int64_t q, const T *__restrict__ u, int64_t comp_stride, int64_t M,
                                           const int32_t *__restrict__ st_pos, const T *__restrict__ st_nw,
-                                          const T *__restrict__ st_r, const T *__restrict__ jq, int ncomp, T s0,
-                                          T s1, int with_jumps, T *__restrict__ out) {
+                                          const T *__restrict__ st_r, const T *__restrict__ jq, int ncomp,
+                                          int with_jumps, T *__restrict__ out) {
   constexpr int NHv = NH<D>::v, STR = D + NHv;
   int32_t pe[S];
-  T nw[S];
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    pe[j] = st_pos[j * M + q];
-    nw[j] = st_nw[j * M + q];
-  }
+  for (int j = 0; j < S; ++j) pe[j] = st_pos[j * M + q];
   for (int comp = 0; comp < ncomp; ++comp) {
     const T *uc = u + comp * comp_stride;
     T val[S];
@@ -217,21 +203,22 @@ __device__ __forceinline__ void gather_at(int64_t q, const T *__restrict__ u, in
         T r[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) r[a] = st_r[(j * D + a) * M + q];
-        T J = 0;
+        T Jv = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           T hr = 0;
 #pragma unroll
           for (int b = 0; b < D; ++b) hr += H[a][b] * r[b];
-          J += r[a] * (du[a] + (T)0.5 * hr);
+          Jv += r[a] * (du[a] + (T)0.5 * hr);
         }
-        val[j] += J;
+        val[j] += Jv;
       }
     }
+    const T *nw = st_nw + (int64_t)comp * S * M;
     T acc = 0;
 #pragma unroll
-    for (int j = 0; j < S; ++j) acc += nw[j] * val[j];
-    out[comp * M + q] = (comp == 0 ? s0 : s1) * acc;
+    for (int j = 0; j < S; ++j) acc += nw[j * M + q] * val[j];
+    out[comp * M + q] = acc;
   }
 }
 
@@ -239,10 +226,10 @@ template <typename T, int D, int S>
 __global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M,
                                                    const int32_t *__restrict__ st_pos,
                                                    const T *__restrict__ st_nw, const T *__restrict__ st_r,
-                                                   const T *__restrict__ jq, int ncomp, T s0, T s1, int with_jumps,
+                                                   const T *__restrict__ jq, int ncomp, int with_jumps,
                                                    T *__restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < M) gather_at<T, D, S>(q, u, comp_stride, M, st_pos, st_nw, st_r, jq, ncomp, s0, s1, with_jumps, out);
+  if (q < M) gather_at<T, D, S>(q, u, comp_stride, M, st_pos, st_nw, st_r, jq, ncomp, with_jumps, out);
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -266,16 +253,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_jumps(const BatchItem<T> *__re
   if (i < c.tot_nc) {
     const int p = batch_problem(c.cum_nc, c.n, i);
     const BatchItem<T> &it = items[p];
-    jumps_cross_at<T, 2, 4>(i - c.cum_nc[p], psi + it.ioff, it.M, it.nc, it.z_idx, it.z_w0, it.z_wga, it.z_na,
-                            it.z_cw, 1, it.isig, it.isig, it.jz);
+    jumps_cross_at<T, 4>(i - c.cum_nc[p], psi + it.ioff, it.M, it.nc, it.z_idx, it.z_A, it.z_B, 1, it.jz);
     return;
   }
   i -= c.tot_nc;
   if (i >= c.tot_M) return;
   const int p = batch_problem(c.cum_M, c.n, i);
   const BatchItem<T> &it = items[p];
-  jumps_nodes_at<T, 2, 5>(i - c.cum_M[p], psi + it.ioff, it.M, it.q_idx, it.q_wg, it.q_n, it.q_wt, 1, it.isig,
-                          it.isig, it.jq);
+  jumps_nodes_at<T, 2, 5>(i - c.cum_M[p], psi + it.ioff, it.M, it.q_idx, it.q_wg, it.q_c, it.q_G, 1, it.jq);
 }
 
 template <typename T>
@@ -285,8 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_correct(const BatchItem<T> *__
   if (i >= c.tot_nirr) return;
   const int p = batch_problem(c.cum_nirr, c.n, i);
   const BatchItem<T> &it = items[p];
-  correct_at<T, 2>(i - c.cum_nirr[p], it.irr_pos, it.irr_ptr, it.arm_cross, it.arm_d, it.arm_s, it.jz, it.nc, 1,
-                   it.sigma, it.sigma, target ? it.fpad : it.rhs, 0, target);
+  correct_at<T, 2>(i - c.cum_nirr[p], it.irr_pos, it.irr_ptr, it.arm_cross, it.arm_d, it.arm_s, it.narm, it.jz,
+                   it.nc, 1, target ? it.fpad : it.rhs, 0, target);
 }
 
 template <typename T>
@@ -296,8 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchItem<T> *__r
   if (i >= c.tot_M) return;
   const int p = batch_problem(c.cum_M, c.n, i);
   const BatchItem<T> &it = items[p];
-  gather_at<T, 2, 6>(i - c.cum_M[p], it.work, 0, it.M, it.st_pos, it.st_nw, it.st_r, it.jq, 1, it.sigma, it.sigma,
-                     with_jumps, out + it.ioff);
+  gather_at<T, 2, 6>(i - c.cum_M[p], it.work, 0, it.M, it.st_pos, it.st_nw, it.st_r, it.jq, 1, with_jumps,
+                     out + it.ioff);
 }
 
 template <typename T>
@@ -318,25 +303,24 @@ std::vector<T> cast_vec(const std::vector<double> &v) {
   return std::vector<T>(v.begin(), v.end());
 }
 
+// Numeric tables in FP64 (as built on the host) and their device copies in one precision.
+struct NumTables {
+  std::vector<double> z_A, z_B, q_wg, q_c, q_G, arm_d, arm_s, st_nw, st_r, tw, sp;
+};
+
 template <typename T>
-void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_w0, const std::vector<double> &z_wga,
-                 const std::vector<double> &z_na, const std::vector<double> &z_cw, const std::vector<double> &q_wg,
-                 const std::vector<double> &q_n, const std::vector<double> &q_wt, const std::vector<double> &arm_d,
-                 const std::vector<double> &arm_s, const std::vector<double> &st_nw, const std::vector<double> &st_r,
-                 const std::vector<double> &tw, const std::vector<double> &sp) {
-  tb.z_w0 = dupload(cast_vec<T>(z_w0));
-  tb.z_wga = dupload(cast_vec<T>(z_wga));
-  tb.z_na = dupload(cast_vec<T>(z_na));
-  tb.z_cw = dupload(cast_vec<T>(z_cw));
-  tb.q_wg = dupload(cast_vec<T>(q_wg));
-  tb.q_n = dupload(cast_vec<T>(q_n));
-  tb.q_wt = dupload(cast_vec<T>(q_wt));
-  tb.arm_d = dupload(cast_vec<T>(arm_d));
-  tb.arm_s = dupload(cast_vec<T>(arm_s));
-  tb.st_nw = dupload(cast_vec<T>(st_nw));
-  tb.st_r = dupload(cast_vec<T>(st_r));
-  tb.tw = dupload(cast_vec<T>(tw));
-  tb.sp = dupload(cast_vec<T>(sp));
+void upload_prec(DevProblem &p, PrecTables<T> &tb, const NumTables &h) {
+  tb.z_A = dupload(cast_vec<T>(h.z_A));
+  tb.z_B = dupload(cast_vec<T>(h.z_B));
+  tb.q_wg = dupload(cast_vec<T>(h.q_wg));
+  tb.q_c = dupload(cast_vec<T>(h.q_c));
+  tb.q_G = dupload(cast_vec<T>(h.q_G));
+  tb.arm_d = dupload(cast_vec<T>(h.arm_d));
+  tb.arm_s = dupload(cast_vec<T>(h.arm_s));
+  tb.st_nw = dupload(cast_vec<T>(h.st_nw));
+  tb.st_r = dupload(cast_vec<T>(h.st_r));
+  tb.tw = dupload(cast_vec<T>(h.tw));
+  tb.sp = dupload(cast_vec<T>(h.sp));
   const size_t field = (size_t)p.ncomp * p.comp_stride;
   tb.rhs = dalloc<T>(field);
   tb.work = dalloc<T>(field);
@@ -355,8 +339,8 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const std::vector<double> &z_
 
 template <typename T>
 void free_prec(PrecTables<T> &tb) {
-  T **all[] = {&tb.z_w0, &tb.z_wga, &tb.z_na, &tb.z_cw, &tb.q_wg, &tb.q_n, &tb.q_wt, &tb.arm_d, &tb.arm_s,
-               &tb.st_nw, &tb.st_r, &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.ybuf, &tb.jz, &tb.jq};
+  T **all[] = {&tb.z_A, &tb.z_B, &tb.q_wg, &tb.q_c, &tb.q_G, &tb.arm_d, &tb.arm_s, &tb.st_nw, &tb.st_r,
+               &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.ybuf, &tb.jz, &tb.jq};
   for (T **q : all) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -368,22 +352,19 @@ void free_prec(PrecTables<T> &tb) {
 template <typename T>
 void launch_jumps(DevProblem &p, const T *psi, hipStream_t st) {
   PrecTables<T> &tb = p.tab<T>();
-  const T is0 = (T)(1.0 / p.sigma[0]), is1 = (T)(1.0 / p.sigma[1]);
   if (p.nc > 0) {
     if (p.dim == 2)
-      k_jumps_cross<T, 2, 4><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_w0, tb.z_wga, tb.z_na,
-                                                           tb.z_cw, p.ncomp, is0, is1, tb.jz);
+      k_jumps_cross<T, 4><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_A, tb.z_B, p.ncomp, tb.jz);
     else
-      k_jumps_cross<T, 3, kLsqNodes><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_w0, tb.z_wga,
-                                                                   tb.z_na, tb.z_cw, p.ncomp, is0, is1, tb.jz);
+      k_jumps_cross<T, kLsqNodes><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_A, tb.z_B, p.ncomp,
+                                                                 tb.jz);
     KFBI_HIP(hipGetLastError());
   }
   if (p.dim == 2)
-    k_jumps_nodes<T, 2, 5><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt, p.ncomp,
-                                                        is0, is1, tb.jq);
+    k_jumps_nodes<T, 2, 5><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_c, tb.q_G, p.ncomp, tb.jq);
   else
-    k_jumps_nodes<T, 3, kLsqNodes><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_n, tb.q_wt,
-                                                                p.ncomp, is0, is1, tb.jq);
+    k_jumps_nodes<T, 3, kLsqNodes><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_c, tb.q_G,
+                                                                p.ncomp, tb.jq);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -393,12 +374,10 @@ static void correct_into(DevProblem &p, T *field, int accumulate, hipStream_t st
   if (p.nirr == 0) return;
   if (p.dim == 2)
     k_correct<T, 2><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s,
-                                                    tb.jz, p.nc, p.ncomp, (T)p.sigma[0], (T)p.sigma[1], field,
-                                                    p.comp_stride, accumulate);
+                                                    p.narm, tb.jz, p.nc, p.ncomp, field, p.comp_stride, accumulate);
   else
     k_correct<T, 3><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s,
-                                                    tb.jz, p.nc, p.ncomp, (T)p.sigma[0], (T)p.sigma[1], field,
-                                                    p.comp_stride, accumulate);
+                                                    p.narm, tb.jz, p.nc, p.ncomp, field, p.comp_stride, accumulate);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -415,13 +394,12 @@ void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st) {
 template <typename T>
 void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream_t st) {
   PrecTables<T> &tb = p.tab<T>();
-  const T s0 = (T)p.sigma[0], s1 = (T)p.sigma[1];
   if (p.dim == 2)
     k_gather<T, 2, 6><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
-                                                   p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
+                                                   p.ncomp, with_jumps ? 1 : 0, out);
   else
     k_gather<T, 3, 10><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
-                                                    p.ncomp, s0, s1, with_jumps ? 1 : 0, out);
+                                                    p.ncomp, with_jumps ? 1 : 0, out);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -461,11 +439,49 @@ template void launch_add_correction<float>(DevProblem &, float *, hipStream_t);
 template void launch_gather<double>(DevProblem &, const double *, bool, double *, hipStream_t);
 template void launch_gather<float>(DevProblem &, const float *, bool, float *, hipStream_t);
 
+// Jump-relation coefficients of one component at a point with normal n and shape operator W
+// (diagonal conductivity Dv): with a = psi / (n.D n),
+//   [grad u] = a n,
+//   [Hess u] = a W + n b^T + b n^T + c n n^T,  b = (g - 2 a W D n) / (n.D n),
+//   c = (-a tr(D W) - 2 b.D n) / (n.D n),
+// written as [Hess u]_ab = psi alpha_ab + sum_f g_f beta_ab,f (g = surface gradient of psi).
+struct JumpCoef {
+  int d;
+  double nDn, n[3], Dn[3], WDn[3], W[9], trDW, WDnDn;
+  JumpCoef(int d_, const double *nrm, const double *Wm, const double *Dv) : d(d_) {
+    nDn = 0;
+    for (int a = 0; a < d; ++a) {
+      n[a] = nrm[a];
+      Dn[a] = Dv[a] * nrm[a];
+      nDn += n[a] * Dn[a];
+    }
+    trDW = 0;
+    WDnDn = 0;
+    for (int a = 0; a < d; ++a) {
+      WDn[a] = 0;
+      for (int b = 0; b < d; ++b) {
+        W[a * d + b] = Wm[a * d + b];
+        WDn[a] += Wm[a * d + b] * Dn[b];
+      }
+      trDW += Dv[a] * Wm[a * d + a];
+    }
+    for (int a = 0; a < d; ++a) WDnDn += WDn[a] * Dn[a];
+  }
+  double grad(int a) const { return n[a] / nDn; }
+  double alpha(int a, int b) const {
+    return (W[a * d + b] - 2.0 * (n[a] * WDn[b] + WDn[a] * n[b]) / nDn - trDW * n[a] * n[b] / nDn +
+            4.0 * WDnDn * n[a] * n[b] / (nDn * nDn)) / nDn;
+  }
+  double beta(int a, int b, int f) const {
+    return ((a == f ? n[b] : 0.0) + (b == f ? n[a] : 0.0)) / nDn - 2.0 * Dn[f] * n[a] * n[b] / (nDn * nDn);
+  }
+};
+
 void upload_tables(DevProblem &p) {
   const HostTables &t = p.ht;
-  const int d = t.dim;
+  const int d = t.dim, nc_ = t.ncomp;
   p.dim = d;
-  p.ncomp = t.ncomp;
+  p.ncomp = nc_;
   p.N = t.N;
   p.M = t.M;
   p.Mfft = t.cells;
@@ -478,32 +494,36 @@ void upload_tables(DevProblem &p) {
   p.S = t.S;
   p.h = t.h;
   p.kappa = t.kappa;
-  p.sigma[0] = t.D[0][0];
-  p.sigma[1] = t.ncomp == 2 ? t.D[1][0] : t.D[0][0];
+  for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < 3; ++a) p.D[c][a] = t.D[c < nc_ ? c : 0][a < d ? a : 0];
   p.lam_scale = 1.0;
   for (int a = 0; a < d; ++a) p.lam_scale *= 2.0 / (double)t.cells;
-  const int64_t N = p.N, M = p.M, nc = p.nc, P = p.P;
+  const int64_t N = p.N, M = p.M, nc = p.nc, P = p.P, K = t.K, Kn = t.Kn, S = t.S;
   auto padpos = [&](int64_t lin) { return (lin % N) + P * (lin / N); };
   if (padpos(N * (d == 3 ? N * N : N) - 1) >= (int64_t)1 << 31) throw std::invalid_argument("grid too large");
+  NumTables h;
 
-  // crossings (SoA)
-  std::vector<int32_t> z_idx(nc * t.K), z_axis(nc);
-  std::vector<double> z_w0(nc * t.K), z_wga(nc * t.K), z_na(nc), z_cw(nc);
+  // crossings: [u_a] and [u_aa] (a = the arm's axis) as weights on the transfer stencil
+  std::vector<int32_t> z_idx(nc * K), z_axis(nc);
+  h.z_A.assign((size_t)nc_ * K * nc, 0.0);
+  h.z_B.assign((size_t)nc_ * K * nc, 0.0);
   for (int64_t c = 0; c < nc; ++c) {
     const int a = (int)t.c_axis[c];
     z_axis[c] = a;
-    const double *n = &t.c_n[c * d], *W = &t.c_W[c * d * d];
-    double tr = 0;
-    for (int b = 0; b < d; ++b) tr += W[b * d + b];
-    z_na[c] = n[a];
-    z_cw[c] = W[a * d + a] - tr * n[a] * n[a];
-    for (int k = 0; k < t.K; ++k) {
-      z_idx[k * nc + c] = (int32_t)t.z_idx[c * t.K + k];
-      z_w0[k * nc + c] = t.z_w0[c * t.K + k];
-      z_wga[k * nc + c] = t.z_wg[(c * t.K + k) * d + a];
+    for (int k = 0; k < K; ++k) z_idx[k * nc + c] = (int32_t)t.z_idx[c * K + k];
+    for (int comp = 0; comp < nc_; ++comp) {
+      const JumpCoef jc(d, &t.c_n[c * d], &t.c_W[c * d * d], t.D[comp]);
+      const double al = jc.alpha(a, a);
+      for (int k = 0; k < K; ++k) {
+        const double w0 = t.z_w0[c * K + k];
+        double bk = w0 * al;
+        for (int f = 0; f < d; ++f) bk += t.z_wg[(c * K + k) * d + f] * jc.beta(a, a, f);
+        h.z_A[((size_t)comp * K + k) * nc + c] = w0 * jc.grad(a);
+        h.z_B[((size_t)comp * K + k) * nc + c] = bk;
+      }
     }
   }
-  // correction records: CSR over irregular nodes
+  // correction records: CSR over irregular nodes; arm_s[comp][arm] = s D_{comp,a} / h^2
   std::vector<std::vector<int64_t>> arms_of(t.irregular.size());
   auto rank = [&](int64_t lin) {
     return (int64_t)(std::lower_bound(t.irregular.begin(), t.irregular.end(), lin) - t.irregular.begin());
@@ -513,7 +533,8 @@ void upload_tables(DevProblem &p) {
     arms_of[rank(t.c_pout[c])].push_back(2 * c + 1);  // "-"-side node, s = -1
   }
   std::vector<int32_t> irr_pos(t.irregular.size()), irr_ptr(t.irregular.size() + 1, 0), arm_cross;
-  std::vector<double> arm_d, arm_s;
+  std::vector<int> arm_axis;
+  std::vector<double> arm_sign;
   const double ih2 = 1.0 / (t.h * t.h);
   auto coord = [&](int64_t lin, int a) {
     int64_t r = lin;
@@ -528,58 +549,69 @@ void upload_tables(DevProblem &p) {
       const int a = (int)t.c_axis[c];
       const int64_t nb = plus ? t.c_pout[c] : t.c_pin[c];
       arm_cross.push_back((int32_t)c);
-      arm_d.push_back(coord(nb, a) - t.c_z[c * d + a]);
-      arm_s.push_back(plus ? ih2 : -ih2);
+      h.arm_d.push_back(coord(nb, a) - t.c_z[c * d + a]);
+      arm_axis.push_back(a);
+      arm_sign.push_back(plus ? ih2 : -ih2);
     }
     irr_ptr[r + 1] = (int32_t)arm_cross.size();
   }
   p.narm = (int64_t)arm_cross.size();
-  // node jumps
-  const int nh = d == 2 ? 3 : 6;
-  std::vector<int32_t> q_idx(M * t.Kn);
-  std::vector<double> q_wg(M * t.Kn * d), q_n(M * d), q_wt(M * nh);
+  h.arm_s.assign((size_t)nc_ * std::max<int64_t>(p.narm, 1), 0.0);
+  for (int comp = 0; comp < nc_; ++comp)
+    for (int64_t i = 0; i < p.narm; ++i) h.arm_s[comp * p.narm + i] = arm_sign[i] * t.D[comp][arm_axis[i]];
+  // node jumps: [grad u] and [Hess u] from psi at the node and the surface gradient g
+  const int nh = d == 2 ? 3 : 6, J = d + nh;
   const int SA[6] = {0, 1, 2, 0, 0, 1}, SB[6] = {0, 1, 2, 1, 2, 2};
   const int SA2[3] = {0, 1, 0}, SB2[3] = {0, 1, 1};
+  std::vector<int32_t> q_idx(M * Kn);
+  h.q_wg.assign((size_t)M * Kn * d, 0.0);
+  h.q_c.assign((size_t)nc_ * J * M, 0.0);
+  h.q_G.assign((size_t)nc_ * J * d * M, 0.0);
   for (int64_t q = 0; q < M; ++q) {
-    const double *n = &t.nrm[q * d], *W = &t.W[q * d * d];
-    double tr = 0;
-    for (int b = 0; b < d; ++b) tr += W[b * d + b];
-    for (int a = 0; a < d; ++a) q_n[a * M + q] = n[a];
-    for (int e = 0; e < nh; ++e) {
-      const int a = d == 2 ? SA2[e] : SA[e], b = d == 2 ? SB2[e] : SB[e];
-      q_wt[e * M + q] = W[a * d + b] - tr * n[a] * n[b];
+    for (int k = 0; k < Kn; ++k) {
+      q_idx[k * M + q] = (int32_t)t.q_idx[q * Kn + k];
+      for (int a = 0; a < d; ++a) h.q_wg[(k * d + a) * M + q] = t.q_wg[(q * Kn + k) * d + a];
     }
-    for (int k = 0; k < t.Kn; ++k) {
-      q_idx[k * M + q] = (int32_t)t.q_idx[q * t.Kn + k];
-      for (int a = 0; a < d; ++a) q_wg[(k * d + a) * M + q] = t.q_wg[(q * t.Kn + k) * d + a];
+    for (int comp = 0; comp < nc_; ++comp) {
+      const JumpCoef jc(d, &t.nrm[q * d], &t.W[q * d * d], t.D[comp]);
+      double *C = &h.q_c[(size_t)comp * J * M], *G = &h.q_G[(size_t)comp * J * d * M];
+      for (int a = 0; a < d; ++a) C[a * M + q] = jc.grad(a);
+      for (int e = 0; e < nh; ++e) {
+        const int a = d == 2 ? SA2[e] : SA[e], b = d == 2 ? SB2[e] : SB[e];
+        C[(d + e) * M + q] = jc.alpha(a, b);
+        for (int f = 0; f < d; ++f) G[((d + e) * d + f) * M + q] = jc.beta(a, b, f);
+      }
     }
   }
-  // gather stencils
-  std::vector<int32_t> st_pos(M * t.S);
-  std::vector<double> st_nw(M * t.S), st_r(M * t.S * d);
+  // gather stencils: st_nw[comp][j] = n . D_comp (gradient weights of stencil node j)
+  std::vector<int32_t> st_pos(M * S);
+  h.st_nw.assign((size_t)nc_ * S * M, 0.0);
+  h.st_r.assign((size_t)M * S * d, 0.0);
   for (int64_t q = 0; q < M; ++q)
-    for (int j = 0; j < t.S; ++j) {
-      const int64_t pos = padpos(t.st_lin[q * t.S + j]);
-      st_pos[j * M + q] = t.st_chi[q * t.S + j] ? (int32_t)(-pos - 1) : (int32_t)pos;
-      double nw = 0;
-      for (int a = 0; a < d; ++a) {
-        nw += t.nrm[q * d + a] * t.st_wgrad[(q * t.S + j) * d + a];
-        st_r[(j * d + a) * M + q] = t.st_r[(q * t.S + j) * d + a];
+    for (int j = 0; j < S; ++j) {
+      const int64_t pos = padpos(t.st_lin[q * S + j]);
+      st_pos[j * M + q] = t.st_chi[q * S + j] ? (int32_t)(-pos - 1) : (int32_t)pos;
+      for (int a = 0; a < d; ++a) h.st_r[(j * d + a) * M + q] = t.st_r[(q * S + j) * d + a];
+      for (int comp = 0; comp < nc_; ++comp) {
+        double nw = 0;
+        for (int a = 0; a < d; ++a) nw += t.nrm[q * d + a] * t.D[comp][a] * t.st_wgrad[(q * S + j) * d + a];
+        h.st_nw[((size_t)comp * S + j) * M + q] = nw;
       }
-      st_nw[j * M + q] = nw;
     }
   // DST tables
   const int Mf = p.Mfft;
-  std::vector<double> tw(2 * Mf), sp(Mf / 2 + 1), lam(N);
+  h.tw.resize(2 * Mf);
+  h.sp.resize(Mf / 2 + 1);
+  std::vector<double> lam(N);
   for (int m = 0; m < Mf; ++m) {
     const double ang = -2.0 * M_PI * (double)m / (double)Mf;
-    tw[2 * m] = std::cos(ang);
-    tw[2 * m + 1] = std::sin(ang);
+    h.tw[2 * m] = std::cos(ang);
+    h.tw[2 * m + 1] = std::sin(ang);
   }
-  for (int n = 0; n <= Mf / 2; ++n) sp[n] = std::sin(M_PI * (double)n / (double)Mf);
+  for (int n = 0; n <= Mf / 2; ++n) h.sp[n] = std::sin(M_PI * (double)n / (double)Mf);
   for (int64_t k = 1; k <= N; ++k) {
-    const double s = std::sin((double)k * M_PI / (2.0 * Mf));
-    lam[k - 1] = 4.0 / (t.h * t.h) * s * s;
+    const double sn = std::sin((double)k * M_PI / (2.0 * Mf));
+    lam[k - 1] = 4.0 / (t.h * t.h) * sn * sn;
   }
   // tissue mask in the padded layout
   std::vector<int8_t> ins_pad((size_t)p.comp_stride, 0);
@@ -619,8 +651,8 @@ void upload_tables(DevProblem &p) {
   p.st_pos = dupload(st_pos);
   p.inside_pad = dupload(ins_pad);
   p.lam = dupload(lam);
-  upload_prec<double>(p, p.f64, z_w0, z_wga, z_na, z_cw, q_wg, q_n, q_wt, arm_d, arm_s, st_nw, st_r, tw, sp);
-  upload_prec<float>(p, p.f32, z_w0, z_wga, z_na, z_cw, q_wg, q_n, q_wt, arm_d, arm_s, st_nw, st_r, tw, sp);
+  upload_prec<double>(p, p.f64, h);
+  upload_prec<float>(p, p.f32, h);
   p.red = dalloc<double>(4096);
   KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,

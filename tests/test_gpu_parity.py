@@ -56,6 +56,11 @@ def problems(name):
         "ellipsoid_bido_32": (W.ellipsoid(n_nodes=512), W.box(3, 32), W.bidomain_coeffs(3, P_BIDO, 0.01)),
         "psphere_32": (W.perturbed_sphere(n_nodes=1500), W.box(3, 32), W.scalar_coeffs(3, 1.0, 400.0)),
         "ellipsoid_128": (W.ellipsoid(n_nodes=8192), W.box(3, 128), W.scalar_coeffs(3, 1.0, 400.0)),
+        # anisotropic diagonal conductivities (the paper's 30 : 5 and 20 : 10 ratios, scaled)
+        "star2d_64_aniso": (W.star2d(n_nodes=128), W.box(2, 64), W.Coeffs(1, [[3.0, 0.5]], 400.0)),
+        "ellipsoid_64_aniso": (W.ellipsoid(n_nodes=2048), W.box(3, 64), W.Coeffs(1, [[3.0, 0.5, 0.5]], 400.0)),
+        "shell_64_aniso": (W.thick_shell(n_nodes=3000), W.box(3, 64),
+                           W.Coeffs(2, [[3.0, 0.5, 0.5], [2.0, 1.0, 1.0]], 200.0)),
     }
     iface, grid, co = cases[name]
     say(f"[setup] {name}")
@@ -67,7 +72,8 @@ def problems(name):
 
 # ----------------------------------------------------------------------------- box solve (a3-a5)
 
-@pytest.mark.parametrize("name", ["circle2d_16", "star2d_128", "ellipsoid_64", "shell_64"])
+@pytest.mark.parametrize("name", ["circle2d_16", "star2d_128", "ellipsoid_64", "shell_64", "shell_64_aniso",
+                                  "star2d_64_aniso"])
 def test_box_solve_matches_oracle(name):
     g, o, iface, grid, co = problems(name)
     f = np.random.default_rng(1).normal(size=(co.ncomp, grid.n ** grid.dim))
@@ -91,7 +97,8 @@ def test_box_solve_in_place_and_ragged_tile():
 
 # ----------------------------------------------------------------------------- matvec (a1, a2, a6)
 
-@pytest.mark.parametrize("name", ["star2d_64", "star2d_128", "ellipsoid_64", "shell_64", "psphere_32"])
+@pytest.mark.parametrize("name", ["star2d_64", "star2d_128", "ellipsoid_64", "shell_64", "psphere_32",
+                                  "star2d_64_aniso", "ellipsoid_64_aniso", "shell_64_aniso"])
 def test_apply_f64_matches_oracle(name):
     g, o, iface, grid, co = problems(name)
     psi = np.random.default_rng(3).uniform(-1, 1, size=(co.ncomp, g.M))
@@ -103,7 +110,7 @@ def test_apply_f64_matches_oracle(name):
     assert e < 1e-10, e
 
 
-@pytest.mark.parametrize("name", ["star2d_128", "shell_64"])
+@pytest.mark.parametrize("name", ["star2d_128", "shell_64", "shell_64_aniso"])
 def test_apply_f32_error_is_stated_bound(name):
     g, o, iface, grid, co = problems(name)
     psi = np.random.default_rng(4).uniform(-1, 1, size=(co.ncomp, g.M))
@@ -350,3 +357,23 @@ def test_full_size_perturbed_sphere_256_mixed_precision():
     # the 128^3 ellipsoid case reaches 1e-4 at h = 0.01875; here h is half of that
     assert err < 1e-4
     g.close()
+
+
+def test_solve_neumann_anisotropic_2d_matches_oracle():
+    """Anisotropic D = diag(3, 0.5): flux data g = n.D grad u of the manufactured solution."""
+    g, o, iface, grid, co = problems("star2d_64_aniso")
+    D = np.array(co.D[0])
+    pts = ogeo.grid_points(grid)
+    ue = np.exp(pts[:, 0]) * np.sin(np.pi * pts[:, 1])
+    f = ((-D[0] + D[1] * np.pi ** 2 + 400.0) * ue)[None]
+    X, n = o.nodes.X, o.nodes.n
+    grad = np.stack([np.exp(X[:, 0]) * np.sin(np.pi * X[:, 1]), np.pi * np.exp(X[:, 0]) * np.cos(np.pi * X[:, 1])], 1)
+    gn = np.sum(n * D[None, :] * grad, 1)[None]
+    say("[solve f64] star2d_64_aniso")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-13)
+    uo, psio, infoo = o.solve_neumann(gn, f, tol=1e-13)
+    ins = o.inside
+    e = rel(u.cpu().numpy()[0][ins], uo[0][ins])
+    say(f"    iters gpu {info['iters']} oracle {infoo['iters']}; u err {e:.2e}")
+    assert e < 1e-10
+    assert rel(psi.cpu().numpy(), psio) < 1e-9

@@ -35,10 +35,11 @@ def test_error_codes_without_gpu():
     with pytest.raises(K.KfbiError) as e:
         K.Problem(W.circle2d(1.15, 64), W.box(2, 32), W.scalar_coeffs(2), host_only=True)
     assert e.value.code == K.KFBI_EGEOM
-    # anisotropic D is outside the implemented jump relations
+    # conductivities must be positive on every axis (anisotropic ones are accepted)
     with pytest.raises(K.KfbiError) as e:
-        K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.Coeffs(1, [[30.0, 5.0]], 1.0), host_only=True)
+        K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.Coeffs(1, [[30.0, -5.0]], 1.0), host_only=True)
     assert e.value.code == K.KFBI_EINVAL
+    K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.Coeffs(1, [[30.0, 5.0]], 1.0), host_only=True).close()
     # a host-only problem refuses device calls before touching the GPU
     p = K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.scalar_coeffs(2), host_only=True)
     rc = L.kfbi_apply(p.handle, ctypes.c_void_p(8), ctypes.c_void_p(8), 0, None)
