@@ -192,9 +192,14 @@ void bidomain_destroy(bidomain_ctx b);
 
 /* State, all device f64, caller-owned: V, q: [N^d] (membrane potential and gate on every
  * box node); phi: [2][N^d] output potentials (Phi_i, Phi_e) of the diffusion solve, may be
- * NULL; psi_hist: [2][2][M] densities of the last two steps (slot 0 = newest), updated. */
+ * NULL; psi_hist: [2][2][M] densities of the last two steps (slot 0 = newest), updated;
+ * I_stim: [N^d] stimulus current, constant in time (Sec. 3: only space dependent), added to
+ * the extracellular source as beta I_stim, or NULL.  A stimulus whose integral over the
+ * tissue is not zero has no solution with zero Neumann data (the coupled problem determines
+ * the potentials up to a common constant). */
 typedef struct {
   double *V, *q, *phi, *psi_hist;
+  const double *I_stim;
 } bidomain_state;
 
 /* bidomain_step: one Strang step (Sec. 3, eqs. ode1, diffusion, ode2): forward-Euler

@@ -123,7 +123,8 @@ struct Fhn {
 // f = (kappa V, -kappa V) written into the padded field.
 __global__ __launch_bounds__(kB) void k_fe_rhs(double *__restrict__ V, double *__restrict__ q,
                                                double *__restrict__ fpad, int64_t n, int64_t N, int64_t P,
-                                               int64_t cs, double dth, double kappa, Fhn m) {
+                                               int64_t cs, double dth, double kappa, Fhn m,
+                                               const double *__restrict__ stim, double beta) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   const double v = V[i], g = q[i];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kB) void k_fe_rhs(double *__restrict__ V, double *_
   q[i] = q1;
   const int64_t pos = (i % N) + P * (i / N);
   fpad[pos] = kappa * v1;
-  fpad[cs + pos] = -kappa * v1;
+  fpad[cs + pos] = -kappa * v1 + (stim ? beta * stim[i] : 0.0);
 }
 
 // Midpoint update V <- 2 (u_i - u_e) - V, then step 3 (backward Euler over dt/2, Newton on V
@@ -530,7 +531,8 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   const double dth = 0.5 * dt;
   Fhn m{params.Cm, params.H, params.theta, params.alpha, params.zeta, params.newton_tol, params.newton_maxit};
   // step 1: reaction over dt/2 and the diffusion source
-  k_fe_rhs<<<nblk(n), kB, 0, st>>>(s.V, s.q, sv.fpad, n, p.N, p.P, p.comp_stride, dth, p.kappa, m);
+  k_fe_rhs<<<nblk(n), kB, 0, st>>>(s.V, s.q, sv.fpad, n, p.N, p.P, p.comp_stride, dth, p.kappa, m, s.I_stim,
+                                   params.beta);
   KFBI_HIP(hipGetLastError());
   // step 2: diffusion, backward Euler over dt/2 for w = (V^{n+1} + V^n)/2 (Neumann BVP)
   sv.bie_rhs(p, nullptr, st);

@@ -74,7 +74,8 @@ class BidomainParamsDesc(C.Structure):
 
 
 class BidomainState(C.Structure):
-    _fields_ = [("V", C.c_void_p), ("q", C.c_void_p), ("phi", C.c_void_p), ("psi_hist", C.c_void_p)]
+    _fields_ = [("V", C.c_void_p), ("q", C.c_void_p), ("phi", C.c_void_p), ("psi_hist", C.c_void_p),
+                ("I_stim", C.c_void_p)]
 
 
 _lib = None
@@ -381,9 +382,10 @@ class Bidomain:
         except Exception:
             pass
 
-    def step(self, V, q, psi_hist, dt, phi=None, allow_noconv=False):
+    def step(self, V, q, psi_hist, dt, phi=None, allow_noconv=False, I_stim=None):
+        """One Strang step; I_stim (optional) is a stimulus current on the box nodes."""
         st = BidomainState(V.data_ptr(), q.data_ptr(), phi.data_ptr() if phi is not None else None,
-                           psi_hist.data_ptr())
+                           psi_hist.data_ptr(), I_stim.data_ptr() if I_stim is not None else None)
         info = SolveInfo()
         rc = lib().bidomain_step(self._h, C.byref(st), dt, C.byref(info), _stream())
         _check(rc, allow=(KFBI_ENOCONV,) if allow_noconv else ())

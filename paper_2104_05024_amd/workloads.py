@@ -239,6 +239,15 @@ def grid_points(grid):
     return np.stack([m.ravel() for m in reversed(mesh)], axis=1)
 
 
+def virtual_electrode(grid, anode, cathode, radius=0.25, amplitude=10.0):
+    """Stimulus current on the box nodes: +amplitude in a ball about the anode, -amplitude in a
+    ball of the same radius about the cathode (the paired electrode of the paper's examples)."""
+    pts = grid_points(grid)
+    ra = np.sum((pts - np.asarray(anode)[None, :]) ** 2, axis=1)
+    rc = np.sum((pts - np.asarray(cathode)[None, :]) ** 2, axis=1)
+    return amplitude * (np.where(ra < radius * radius, 1.0, 0.0) - np.where(rc < radius * radius, 1.0, 0.0))
+
+
 def ball_state(grid, center, radius=0.1):
     """Initial bidomain state: V = 1 inside a ball, 0 elsewhere; q = 0."""
     pts = grid_points(grid)

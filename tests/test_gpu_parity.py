@@ -377,3 +377,29 @@ def test_solve_neumann_anisotropic_2d_matches_oracle():
     say(f"    iters gpu {info['iters']} oracle {infoo['iters']}; u err {e:.2e}")
     assert e < 1e-10
     assert rel(psi.cpu().numpy(), psio) < 1e-9
+
+
+def test_bidomain_anisotropic_with_virtual_electrode_matches_oracle():
+    """The paper's stimulus form: anisotropic intra/extracellular conductivities (ratios of
+    diag(30, 5, 5) and diag(20, 10, 10), scaled) and a paired anode/cathode current in the
+    extracellular source; three steps against the oracle."""
+    iface, grid = W.ellipsoid(n_nodes=512), W.box(3, 32)
+    co = W.Coeffs(2, [[3.0, 0.5, 0.5], [2.0, 1.0, 1.0]], 200.0)
+    say("[setup] ellipsoid_32 anisotropic bidomain")
+    g = K.Problem(iface, grid, co)
+    o = ok.Problem(iface, grid, co)
+    stim = W.virtual_electrode(grid, (-0.3, 0.0, 0.0), (0.3, 0.0, 0.0), radius=0.2, amplitude=10.0)
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+    V, q = T(V0), T(q0)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    Is = T(stim)
+    Vo, qo, psi = V0.copy(), q0.copy(), None
+    for s_ in range(3):
+        info = bd.step(V, q, hist, 0.01, I_stim=Is)
+        Vo, qo, uo, psi, infoo = obd.step(o, P_BIDO, Vo, qo, 0.01, psi0=psi, tol=1e-12, I_stim=stim)
+        eV = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+        say(f"    step {s_}: V err {eV:.2e} iters {info['iters']} / {infoo['iters']}")
+        assert eV < 1e-9
+    bd.close()
+    g.close()
