@@ -282,6 +282,11 @@ int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t
  * dense pass timed at both widths on the problem's own buffers); kfbi_set_tiles overrides them.
  * Results do not depend on the widths (each pencil is transformed the same way). */
 int kfbi_get_tiles(kfbi_problem p, int32_t dtype, int32_t widths[3]);
+/* GMRES iterations of kfbi_solve_neumann / bidomain_step replay one captured Arnoldi step
+ * (a hipGraph holding the product, both Gram-Schmidt passes, the norm and the next basis
+ * vector) unless disabled here or while kfbi_profile is on; results are identical. */
+int kfbi_use_graph(kfbi_problem p, int32_t enable);
+int bidomain_use_graph(bidomain_ctx b, int32_t enable);
 int kfbi_set_tiles(kfbi_problem p, int32_t dtype, const int32_t widths[3]);
 int kfbi_profile(kfbi_problem p, int32_t enable);
 

@@ -203,6 +203,18 @@ int kfbi_get_tiles(kfbi_problem p, int32_t dtype, int32_t widths[3]) {
   return KFBI_OK;
 }
 
+int kfbi_use_graph(kfbi_problem p, int32_t enable) {
+  if (!p) return fail(KFBI_EINVAL, "argument");
+  p->solver.use_graph = enable != 0;
+  return KFBI_OK;
+}
+
+int bidomain_use_graph(bidomain_ctx b, int32_t enable) {
+  if (!b || !b->solver) return fail(KFBI_EINVAL, "argument");
+  b->solver->use_graph = enable != 0;
+  return KFBI_OK;
+}
+
 int kfbi_set_tiles(kfbi_problem p, int32_t dtype, const int32_t widths[3]) {
   if (!p || !widths || (dtype != KFBI_F64 && dtype != KFBI_F32)) return fail(KFBI_EINVAL, "argument");
   for (int k = 0; k < 3; ++k)

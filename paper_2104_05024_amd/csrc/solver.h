@@ -20,6 +20,15 @@ struct Solver {
   double *ydev = nullptr;      // least-squares coefficients uploaded for the update
   int64_t n_inside = 0;
   int8_t *inside_plain = nullptr;
+  // captured Arnoldi step (per precision of the product), replayed every GMRES iteration
+  bool use_graph = true;
+  double *vin = nullptr, *wv = nullptr;
+  int *jdev = nullptr, *jhost = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_m[2] = {0, 0};
+  void arnoldi_step(DevProblem &p, int prec, int m, hipStream_t st);
+  void run_step(DevProblem &p, int prec, int m, hipStream_t st);
 
   void init(DevProblem &p);
   void release();

@@ -23,12 +23,15 @@ T *dalloc(size_t n) {
   return p;
 }
 
-// partial dot products: block (bx, k) reduces sum_i a_k[i] b[i] over its grid-stride slice
+// partial dot products: block (bx, k) reduces sum_i a_k[i] b[i] over its grid-stride slice;
+// with jlim, only vectors k <= *jlim take part (the Arnoldi step replayed from a graph)
 __global__ __launch_bounds__(kB) void k_multidot(const double *__restrict__ A, int64_t lda,
                                                  const double *__restrict__ b, int64_t n,
-                                                 double *__restrict__ partials) {
+                                                 double *__restrict__ partials,
+                                                 const int *__restrict__ jlim = nullptr) {
   __shared__ double s[kB];
   const int k = blockIdx.y;
+  if (jlim && k > *jlim) return;
   const double *a = A + (int64_t)k * lda;
   double acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) acc += a[i] * b[i];
@@ -42,9 +45,10 @@ __global__ __launch_bounds__(kB) void k_multidot(const double *__restrict__ A, i
 }
 
 __global__ __launch_bounds__(kB) void k_finish(const double *__restrict__ partials, int nb,
-                                               double *__restrict__ out) {
+                                               double *__restrict__ out, const int *__restrict__ jlim = nullptr) {
   __shared__ double s[kB];
   const int k = blockIdx.x;
+  if (jlim && k > *jlim) return;
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += kB) acc += partials[(int64_t)k * nb + i];
   s[threadIdx.x] = acc;
@@ -64,6 +68,38 @@ __global__ __launch_bounds__(kB) void k_combine(double *__restrict__ w, const do
   double acc = 0;
   for (int k = 0; k < K; ++k) acc += h[k] * V[(int64_t)k * ldv + i];
   w[i] += sign * acc;
+}
+
+// Arnoldi step with j in device memory: w -= sum_{k <= j} h[k] V_k; V_{j+1} = w / ||w||;
+// v = V_j; j <- j + 1
+__global__ __launch_bounds__(kB) void k_combine_j(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
+                                                  const double *__restrict__ h, const int *__restrict__ jdev,
+                                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int K = *jdev + 1;
+  double acc = 0;
+  for (int k = 0; k < K; ++k) acc += h[k] * V[(int64_t)k * ldv + i];
+  w[i] -= acc;
+}
+
+__global__ __launch_bounds__(kB) void k_next_j(double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
+                                               const double *__restrict__ nrm2, const int *__restrict__ jdev,
+                                               int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const double s = *nrm2 > 0 ? 1.0 / sqrt(*nrm2) : 0.0;   // as k_scale_inv_sqrt: same rounding
+  V[(int64_t)(*jdev + 1) * ldv + i] = w[i] * s;
+}
+
+__global__ __launch_bounds__(kB) void k_take_j(const double *__restrict__ V, int64_t ldv,
+                                               const int *__restrict__ jdev, double *__restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) v[i] = V[(int64_t)(*jdev) * ldv + i];
+}
+
+__global__ void k_inc_j(int *j) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *j += 1;
 }
 
 __global__ __launch_bounds__(kB) void k_scale_inv_sqrt(double *__restrict__ y, const double *__restrict__ x,
@@ -196,6 +232,11 @@ void Solver::init(DevProblem &p) {
   hdev = dalloc<double>(3 * (kMaxRestart + 2));
   ydev = dalloc<double>(kMaxRestart + 2);
   KFBI_HIP(hipHostMalloc(&hhost, 3 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
+  vin = dalloc<double>(L);
+  wv = dalloc<double>(L);
+  jdev = dalloc<int>(1);
+  KFBI_HIP(hipHostMalloc(&jhost, sizeof(int), hipHostMallocDefault));
+  KFBI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   n_inside = 0;
   for (int8_t v : p.ht.inside) n_inside += v;
   inside_plain = dalloc<int8_t>(p.ht.inside.size());
@@ -203,7 +244,18 @@ void Solver::init(DevProblem &p) {
 }
 
 void Solver::release() {
-  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &hdev, &ydev};
+  for (int k = 0; k < 2; ++k)
+    if (graph[k]) {
+      (void)hipGraphExecDestroy(graph[k]);
+      graph[k] = nullptr;
+    }
+  if (cap) (void)hipStreamDestroy(cap);
+  cap = nullptr;
+  if (jdev) (void)hipFree(jdev);
+  if (jhost) (void)hipHostFree(jhost);
+  jdev = nullptr;
+  jhost = nullptr;
+  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &hdev, &ydev, &vin, &wv};
   for (double **q : dp) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -259,6 +311,50 @@ double Solver::dot(const double *a, const double *b, hipStream_t st) {
   return hhost[0];
 }
 
+// One Arnoldi step with j read from device memory (so one captured graph serves every j):
+// v = V_j, w = A v, two classical Gram-Schmidt passes against V_0..V_j, the norm, V_{j+1},
+// the Hessenberg column to pinned host memory, j <- j + 1.
+void Solver::arnoldi_step(DevProblem &p, int prec, int m, hipStream_t st) {
+  k_take_j<<<nblk(L), kB, 0, st>>>(V, L, jdev, vin, L);
+  apply_vec(p, prec, vin, wv, st);
+  for (int pass = 0; pass < 2; ++pass) {
+    double *h = hdev + pass * (kMaxRestart + 2);
+    k_multidot<<<dim3(nb, m), kB, 0, st>>>(V, L, wv, L, partials, jdev);
+    k_finish<<<m, kB, 0, st>>>(partials, nb, h, jdev);
+    k_combine_j<<<nblk(L), kB, 0, st>>>(wv, V, L, h, jdev, L);
+  }
+  k_multidot<<<dim3(nb, 1), kB, 0, st>>>(wv, L, wv, L, partials);
+  k_finish<<<1, kB, 0, st>>>(partials, nb, hdev + 2 * (kMaxRestart + 2));
+  k_next_j<<<nblk(L), kB, 0, st>>>(V, L, wv, hdev + 2 * (kMaxRestart + 2), jdev, L);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+  k_inc_j<<<1, 1, 0, st>>>(jdev);
+  KFBI_HIP(hipGetLastError());
+}
+
+// Replays the captured Arnoldi step (captured on first use on the solver's own stream).
+void Solver::run_step(DevProblem &p, int prec, int m, hipStream_t st) {
+  if (!graph[prec] || graph_m[prec] != m) {
+    if (graph[prec]) (void)hipGraphExecDestroy(graph[prec]);
+    graph[prec] = nullptr;
+    hipGraph_t g = nullptr;
+    KFBI_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    try {
+      arnoldi_step(p, prec, m, cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    KFBI_HIP(hipStreamEndCapture(cap, &g));
+    const hipError_t e = hipGraphInstantiate(&graph[prec], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    KFBI_HIP(e);
+    graph_m[prec] = m;
+  }
+  KFBI_HIP(hipGraphLaunch(graph[prec], st));
+}
+
 int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
                   int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
                   double *beta0, const double *r0) {
@@ -292,22 +388,31 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
     k_axpby<<<nblk(L), kB, 0, st>>>(V, 1.0 / beta, r, 0.0, nullptr, L);
     int jend = 0;
     bool breakdown = false;
+    const bool graphed = use_graph && !p.profile;
+    if (graphed) {
+      *jhost = 0;
+      KFBI_HIP(hipMemcpyAsync(jdev, jhost, sizeof(int), hipMemcpyHostToDevice, st));
+    }
     for (int j = 0; j < m; ++j) {
-      double *vj = V + (int64_t)j * L, *vn = V + (int64_t)(j + 1) * L;
-      apply_vec(p, prec, vj, vn, st);
+      if (graphed) {
+        run_step(p, prec, m, st);
+      } else {
+        double *vj = V + (int64_t)j * L, *vn = V + (int64_t)(j + 1) * L;
+        apply_vec(p, prec, vj, vn, st);
+        // classical Gram-Schmidt, twice; then the norm
+        for (int pass = 0; pass < 2; ++pass) {
+          k_multidot<<<dim3(nb, j + 1), kB, 0, st>>>(V, L, vn, L, partials);
+          k_finish<<<j + 1, kB, 0, st>>>(partials, nb, hdev + pass * (kMaxRestart + 2));
+          k_combine<<<nblk(L), kB, 0, st>>>(vn, V, L, hdev + pass * (kMaxRestart + 2), j + 1, -1.0, L);
+        }
+        k_multidot<<<dim3(nb, 1), kB, 0, st>>>(vn, L, vn, L, partials);
+        k_finish<<<1, kB, 0, st>>>(partials, nb, hdev + 2 * (kMaxRestart + 2));
+        k_scale_inv_sqrt<<<nblk(L), kB, 0, st>>>(vn, vn, hdev + 2 * (kMaxRestart + 2), L);
+        KFBI_HIP(hipGetLastError());
+        KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+      }
       ++matvecs;
       ++its;
-      // classical Gram-Schmidt, twice; then the norm
-      for (int pass = 0; pass < 2; ++pass) {
-        k_multidot<<<dim3(nb, j + 1), kB, 0, st>>>(V, L, vn, L, partials);
-        k_finish<<<j + 1, kB, 0, st>>>(partials, nb, hdev + pass * (kMaxRestart + 2));
-        k_combine<<<nblk(L), kB, 0, st>>>(vn, V, L, hdev + pass * (kMaxRestart + 2), j + 1, -1.0, L);
-      }
-      k_multidot<<<dim3(nb, 1), kB, 0, st>>>(vn, L, vn, L, partials);
-      k_finish<<<1, kB, 0, st>>>(partials, nb, hdev + 2 * (kMaxRestart + 2));
-      k_scale_inv_sqrt<<<nblk(L), kB, 0, st>>>(vn, vn, hdev + 2 * (kMaxRestart + 2), L);
-      KFBI_HIP(hipGetLastError());
-      KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
       KFBI_HIP(hipStreamSynchronize(st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + hhost[(kMaxRestart + 2) + i];
       const double hn = std::sqrt(std::max(0.0, hhost[2 * (kMaxRestart + 2)]));

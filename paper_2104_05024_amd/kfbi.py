@@ -24,7 +24,7 @@ EXPORTED = [
     "bidomain_create", "bidomain_destroy", "bidomain_step", "bidomain_mlp_init", "bidomain_train",
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
     "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
-    "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles",
+    "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles", "kfbi_use_graph", "bidomain_use_graph",
     "kfbi_profile",
 ]
 
@@ -113,6 +113,8 @@ def lib():
     L.kfbi_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dp), i64p]
     L.kfbi_profile.argtypes = [vp, i32]
     L.kfbi_get_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
+    L.kfbi_use_graph.argtypes = [vp, i32]
+    L.bidomain_use_graph.argtypes = [vp, i32]
     L.kfbi_set_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.kfbi_batch_setup.argtypes = [i32, C.POINTER(Interface), C.POINTER(GridDesc), C.POINTER(CoeffsDesc),
                                    C.POINTER(vp)]
@@ -264,6 +266,9 @@ class Problem:
     def profile(self, enable=True):
         _check(lib().kfbi_profile(self._h, 1 if enable else 0))
 
+    def use_graph(self, enable=True):
+        _check(lib().kfbi_use_graph(self._h, 1 if enable else 0))
+
     def tiles(self, dtype=KFBI_F64):
         """Autotuned DST tile widths (x, y, last-axis pass) for KFBI_F64 / KFBI_F32."""
         w = (C.c_int32 * 3)()
@@ -390,6 +395,9 @@ class Bidomain:
         rc = lib().bidomain_step(self._h, C.byref(st), dt, C.byref(info), _stream())
         _check(rc, allow=(KFBI_ENOCONV,) if allow_noconv else ())
         return info.as_dict()
+
+    def use_graph(self, enable=True):
+        _check(lib().bidomain_use_graph(self._h, 1 if enable else 0))
 
     def mlp_init(self, capacity=256, seed=3):
         _check(lib().bidomain_mlp_init(self._h, capacity, seed))

@@ -403,3 +403,34 @@ def test_bidomain_anisotropic_with_virtual_electrode_matches_oracle():
         assert eV < 1e-9
     bd.close()
     g.close()
+
+
+def test_captured_arnoldi_step_matches_direct_launches():
+    """GMRES replaying the captured Arnoldi step gives exactly the solves of direct launches, in
+    FP64 and mixed precision, and a bidomain step likewise."""
+    g, o, iface, grid, co = problems("shell_64")
+    rng = np.random.default_rng(13)
+    f = T(rng.normal(size=(2, g.N ** 3)))
+    out = {}
+    for graph in (True, False, True):
+        g.use_graph(graph)
+        r64 = g.solve_neumann(None, f, tol=1e-10)
+        r32 = g.solve_neumann(None, f, tol=1e-10, precision=1)
+        out.setdefault(graph, []).append((r64, r32))
+    g.use_graph(True)
+    for (a64, a32) in out[True] + out[False]:
+        b64, b32 = out[True][0]
+        assert torch.equal(a64[0], b64[0]) and torch.equal(a64[1], b64[1]) and a64[2]["iters"] == b64[2]["iters"]
+        assert torch.equal(a32[0], b32[0]) and a32[2]["iters"] == b32[2]["iters"]
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    res = []
+    for graph in (True, False):
+        bd = K.Bidomain(g, P_BIDO, tol=1e-10)
+        bd.use_graph(graph)
+        V, q = T(V0), T(q0)
+        hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+        for _ in range(3):
+            bd.step(V, q, hist, 0.01)
+        res.append(V.clone())
+        bd.close()
+    assert torch.equal(res[0], res[1])
