@@ -15,7 +15,7 @@ learned variant records them and trains on them) and is then timed over the same
 tissue is back at rest by about step 150, so this window holds the propagating wave; a
 later window would time a resting tissue.  Variants: plain (FP64 throughout, GMRES from psi^{n-1}), mixed (FP32
 matrix-vector products inside FP64 iterative refinement), learned (mixed + the learned warm
-start).  Every solve ends at the same FP64 relative residual bound.
+start), projected (mixed + the least-residual combination of the last 8 solutions as start).  Every solve ends at the same FP64 relative residual bound.
 
 Prints one JSON line (see the "metric" key).  --batch and --copy-calibration run the
 batched 2D workload and the counter calibration instead.
@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--cells", type=int, default=256)
     ap.add_argument("--nodes", type=int, default=40960)
-    ap.add_argument("--variants", default="plain,mixed,learned")
+    ap.add_argument("--variants", default="plain,mixed,learned,projected")
     ap.add_argument("--train-steps", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="mixed precision: relative tolerance of each FP32 inner solve")
@@ -224,6 +224,8 @@ def main():
             except K.KfbiError as e:
                 log(f"learned variant unavailable: {e}")
                 continue
+        elif name == "projected":
+            bd = K.Bidomain(prob, p, tol=1e-8, precision=1, warm_start=3, inner_tol=a.inner_tol)
         else:
             bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "mixed" else 0, warm_start=0,
                             inner_tol=a.inner_tol)

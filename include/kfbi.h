@@ -179,7 +179,9 @@ typedef struct {
                                        dq/dt = alpha V - zeta q */
   double newton_tol;                /* |F| tolerance of the backward-Euler Newton solve */
   int32_t newton_maxit;
-  int32_t warm_start;               /* 0: psi^{n-1}; 1: learned (MLP) start with fallback; 2: zero */
+  int32_t warm_start;               /* 0: psi^{n-1}; 1: learned (MLP) start with fallback; 2: zero;
+                                       3: least-residual combination of the last 8 solutions
+                                       (their images are known without a product) */
   kfbi_solve_opts solve;            /* diffusion solve options (tol, precision, ...) */
 } bidomain_params;
 

@@ -72,6 +72,14 @@ struct bidomain_s {
   double *gp_prev = nullptr;   // BIE right-hand side of the previous step
   double *d_prev = nullptr;    // final FP64 residual g'^{n-1} - A psi^{n-1} of the previous solve
   bool have_prev = false;
+  // projection start: the last kProj solutions psi_j and their images b_j = A psi_j (known
+  // without a product: g'_j minus the final residual), with Gram matrix G = B^T B
+  static constexpr int kProj = 8;
+  double *proj_psi = nullptr, *proj_b = nullptr;   // [kProj][L] rings
+  int proj_n = 0, proj_head = 0;
+  double proj_G[kProj][kProj] = {};
+  void proj_start(double *out_psi, double *out_r, hipStream_t st);
+  void proj_record(const double *psi, hipStream_t st);
   int64_t steps_done = 0;
   void init();
   void release();

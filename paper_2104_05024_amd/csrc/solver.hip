@@ -612,13 +612,81 @@ void bidomain_s::init() {
   KFBI_HIP(hipMemset(gp_prev, 0, L * sizeof(double)));
   KFBI_HIP(hipMalloc(&d_prev, L * sizeof(double)));
   KFBI_HIP(hipMemset(d_prev, 0, L * sizeof(double)));
+  if (params.warm_start == 3) {
+    KFBI_HIP(hipMalloc(&proj_psi, (size_t)kProj * L * sizeof(double)));
+    KFBI_HIP(hipMalloc(&proj_b, (size_t)kProj * L * sizeof(double)));
+  }
+}
+
+// Start of least residual over span{psi_j}: c = argmin ||g' - B c|| from the normal equations
+// (Gram matrix kept up to date as solutions are recorded, a tiny diagonal shift against
+// near-collinear columns); psi0 = sum c_j psi_j and its residual g' - sum c_j b_j follow
+// without a product.  Any c gives a consistent pair, so the shift affects only the quality.
+void bidomain_s::proj_start(double *out_psi, double *out_r, hipStream_t st) {
+  Solver &sv = *solver;
+  const int64_t L = sv.L;
+  const int k = proj_n;
+  k_multidot<<<dim3(sv.nb, k), kB, 0, st>>>(proj_b, L, sv.gp, L, sv.partials);
+  k_finish<<<k, kB, 0, st>>>(sv.partials, sv.nb, sv.hdev);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(sv.hhost, sv.hdev, k * sizeof(double), hipMemcpyDeviceToHost, st));
+  KFBI_HIP(hipStreamSynchronize(st));
+  double A[kProj][kProj + 1];
+  double dmax = 0;
+  for (int i = 0; i < k; ++i) dmax = std::max(dmax, proj_G[i][i]);
+  for (int i = 0; i < k; ++i) {
+    for (int j = 0; j < k; ++j) A[i][j] = proj_G[i][j] + (i == j ? 1e-13 * dmax : 0.0);
+    A[i][k] = sv.hhost[i];
+  }
+  for (int c = 0; c < k; ++c) {   // Gaussian elimination with partial pivoting
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    for (int j = 0; j <= k; ++j) std::swap(A[c][j], A[piv][j]);
+    if (A[c][c] == 0.0) continue;
+    for (int r = c + 1; r < k; ++r) {
+      const double f = A[r][c] / A[c][c];
+      for (int j = c; j <= k; ++j) A[r][j] -= f * A[c][j];
+    }
+  }
+  std::vector<double> cvec(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = A[i][k];
+    for (int j = i + 1; j < k; ++j) acc -= A[i][j] * cvec[j];
+    cvec[i] = A[i][i] != 0.0 ? acc / A[i][i] : 0.0;
+  }
+  KFBI_HIP(hipMemcpyAsync(sv.ydev, cvec.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+  k_axpby<<<nblk(L), kB, 0, st>>>(out_psi, 0.0, out_psi, 0.0, nullptr, L);
+  k_combine<<<nblk(L), kB, 0, st>>>(out_psi, proj_psi, L, sv.ydev, k, 1.0, L);
+  KFBI_HIP(hipMemcpyAsync(out_r, sv.gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_combine<<<nblk(L), kB, 0, st>>>(out_r, proj_b, L, sv.ydev, k, -1.0, L);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipStreamSynchronize(st));   // cvec (host) is read by the copy above
+}
+
+// Record the solution just computed: psi and b = g' - (final residual), and the new Gram row.
+void bidomain_s::proj_record(const double *psi, hipStream_t st) {
+  Solver &sv = *solver;
+  const int64_t L = sv.L;
+  const int slot = proj_head;
+  double *bs = proj_b + (int64_t)slot * L;
+  KFBI_HIP(hipMemcpyAsync(proj_psi + (int64_t)slot * L, psi, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_axpby<<<nblk(L), kB, 0, st>>>(bs, 1.0, sv.gp, -1.0, sv.last_resid, L);
+  proj_head = (proj_head + 1) % kProj;
+  proj_n = std::min(proj_n + 1, kProj);
+  k_multidot<<<dim3(sv.nb, proj_n), kB, 0, st>>>(proj_b, L, bs, L, sv.partials);
+  k_finish<<<proj_n, kB, 0, st>>>(sv.partials, sv.nb, sv.hdev);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(sv.hhost, sv.hdev, proj_n * sizeof(double), hipMemcpyDeviceToHost, st));
+  KFBI_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < proj_n; ++i) proj_G[slot][i] = proj_G[i][slot] = sv.hhost[i];
 }
 
 void bidomain_s::release() {
-  double *ps[] = {psi0, r0v, gp_prev, d_prev};
+  double *ps[] = {psi0, r0v, gp_prev, d_prev, proj_psi, proj_b};
   for (double *q : ps)
     if (q) (void)hipFree(q);
-  psi0 = r0v = gp_prev = d_prev = nullptr;
+  psi0 = r0v = gp_prev = d_prev = proj_psi = proj_b = nullptr;
   extern void mlp_release(bidomain_s *);
   mlp_release(this);
 }
@@ -659,7 +727,17 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
       k_axpby<<<nblk(L), kB, 0, st>>>(r0v, 1.0, r0v, 1.0, d_prev, L);
       have_r0 = true;
     }
-    if (params.warm_start == 1 && mlp && steps_done >= 2 && mlp_warm_start(this, hist1, hist2, sv.w, st)) {
+    if (params.warm_start == 3 && have_r0 && proj_n >= 2) {
+      // least-residual start over the recorded solutions; kept only if its (free) residual
+      // is below that of psi^{n-1}
+      proj_start(sv.w, sv.d, st);
+      const double rh = sv.dot(r0v, r0v, st), rp = sv.dot(sv.d, sv.d, st);
+      if (rp < rh) {
+        KFBI_HIP(hipMemcpyAsync(psi0, sv.w, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+        KFBI_HIP(hipMemcpyAsync(r0v, sv.d, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+        info.warm_start_used = 1;
+      }
+    } else if (params.warm_start == 1 && mlp && steps_done >= 2 && mlp_warm_start(this, hist1, hist2, sv.w, st)) {
       if (have_r0) {
         // predicted start psi^{n-1} + D: residual r0 - A D, taken only if smaller than
         // psi^{n-1}'s (checked at every use: it costs nothing more).  A D is applied in the
@@ -703,6 +781,7 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   info.matvecs_fp64 += extra64;
   KFBI_HIP(hipMemcpyAsync(d_prev, sv.last_resid, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   have_prev = true;
+  if (params.warm_start == 3) proj_record(psi0, st);
   sv.reconstruct(p, psi0, st);
   double *meanp = nullptr;
   if (s.phi) {

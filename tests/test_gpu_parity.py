@@ -434,3 +434,27 @@ def test_captured_arnoldi_step_matches_direct_launches():
         res.append(V.clone())
         bd.close()
     assert torch.equal(res[0], res[1])
+
+
+def test_projection_start_reaches_tolerance_with_fewer_iterations():
+    """Least-residual start over the recorded solutions: its residual is below psi^{n-1}'s, every
+    solve still ends at the FP64 bound, and V follows the psi^{n-1}-start run."""
+    g, o, iface, grid, co = problems("shell_64")
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    runs = {}
+    for ws in (0, 3):
+        bd = K.Bidomain(g, P_BIDO, tol=1e-10, warm_start=ws)
+        V, q = T(V0), T(q0)
+        hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+        infos = [bd.step(V, q, hist, 0.01) for _ in range(14)]
+        runs[ws] = (V.cpu().numpy(), infos)
+        bd.close()
+    i0, i3 = runs[0][1][6:], runs[3][1][6:]
+    say(f"[projection] start residual {np.mean([i['start_resid'] for i in i3]):.2e} vs "
+        f"{np.mean([i['start_resid'] for i in i0]):.2e}; iterations {[i['iters'] for i in i3]} vs "
+        f"{[i['iters'] for i in i0]}")
+    assert all(i["rel_resid"] <= 1e-10 for i in runs[3][1])
+    assert all(i["warm_start_used"] for i in i3)
+    assert np.mean([i["start_resid"] for i in i3]) < 0.5 * np.mean([i["start_resid"] for i in i0])
+    assert np.mean([i["iters"] for i in i3]) <= np.mean([i["iters"] for i in i0])
+    assert np.max(np.abs(runs[3][0] - runs[0][0])) < 1e-8
