@@ -7,9 +7,10 @@ complement ("-"), and locate every intersection of the boundary with the grid
 lines (Sec. 5.3 assumes one crossing per stencil arm, at a point z with
 x_k <= z < x_{k+1}).
 
-Shapes are star-shaped surfaces r = G(u), u = x/|x| (see the workloads
-module); the level set of one surface is  phi = orient * (|x| - G(x/|x|)),
-negative (or within 1e-12) in the tissue.
+Analytic shapes are star-shaped surfaces r = G(u), u = x/|x| (see the
+workloads module); the level set of one surface is  phi = orient * (|x| - G(x/|x|)),
+negative (or within 1e-12) in the tissue.  2D curves given by their nodes go
+through the periodic cubic spline of the ``spline`` module instead.
 """
 from __future__ import annotations
 
@@ -17,11 +18,30 @@ import math
 
 import numpy as np
 
+from .spline import SplineCurve
+
 SIDE_TOL = 1e-12          # nodes with phi <= SIDE_TOL count as tissue ("+")
 
 
 class GeometryError(ValueError):
     pass
+
+
+_CURVES = {}
+
+
+def curve_of(surf):
+    """The spline of a node-given 2D curve (built once per surface object)."""
+    key = id(surf)
+    hit = _CURVES.get(key)
+    if hit is None or hit[0] is not surf:
+        hit = (surf, SplineCurve(surf))
+        _CURVES[key] = hit
+    return hit[1]
+
+
+def is_spline(surf):
+    return getattr(surf, "kind", "analytic") == "spline"
 
 
 # ----------------------------------------------------------------------------- radial function
@@ -138,10 +158,16 @@ class Nodes:
         X, N, W, sid, par = [], [], [], [], []
         self.offsets = [0]
         for s, surf in enumerate(iface.surfaces):
-            u = node_directions(iface.dim, surf.n_nodes)
-            G, _, _ = radial(surf, u)
-            x = G[:, None] * u
-            n, w = normal_and_shape(surf, x)
+            if is_spline(surf):
+                cv = curve_of(surf)
+                t = np.arange(cv.m, dtype=np.float64)
+                x = cv.X(t)
+                n, w = cv.normal_and_shape(t)
+            else:
+                u = node_directions(iface.dim, surf.n_nodes)
+                G, _, _ = radial(surf, u)
+                x = G[:, None] * u
+                n, w = normal_and_shape(surf, x)
             X.append(x), N.append(n), W.append(w)
             sid.append(np.full(surf.n_nodes, s))
             self.offsets.append(self.offsets[-1] + surf.n_nodes)
@@ -196,7 +222,10 @@ def classify(iface, grid):
     chunk = 1 << 20
     for s, surf in enumerate(iface.surfaces):
         for i in range(0, pts.shape[0], chunk):
-            out[s, i:i + chunk] = levelset(surf, pts[i:i + chunk]) <= SIDE_TOL
+            if is_spline(surf):
+                out[s, i:i + chunk] = curve_of(surf).tissue(pts[i:i + chunk])
+            else:
+                out[s, i:i + chunk] = levelset(surf, pts[i:i + chunk]) <= SIDE_TOL
     return out
 
 
@@ -205,9 +234,12 @@ def check_box_clearance(iface, grid, margin_cells=3):
     lim = grid.hi - margin_cells * grid.h
     lim_lo = grid.lo + margin_cells * grid.h
     for surf in iface.surfaces:
-        u = node_directions(iface.dim, max(surf.n_nodes, 4096 if iface.dim == 3 else 1024))
-        G, _, _ = radial(surf, u)
-        x = G[:, None] * u
+        if is_spline(surf):
+            _, x = curve_of(surf).samples(16)
+        else:
+            u = node_directions(iface.dim, max(surf.n_nodes, 4096 if iface.dim == 3 else 1024))
+            G, _, _ = radial(surf, u)
+            x = G[:, None] * u
         if np.any(x > lim) or np.any(x < lim_lo):
             raise GeometryError("interface closer than 3h to the box boundary")
 
@@ -258,6 +290,28 @@ def _root_on_arm(surf, p, axis, h, iters=80):
     return t
 
 
+def _spline_roots_on_arms(cv, p0, axis, h, tol=1e-12):
+    """Crossing of a spline curve with each arm from p0 to p0 + h e_axis: the arm fraction
+    and the curve parameter.  Exactly one root of the curve may lie on the arm."""
+    other = 1 - axis
+    frac = np.zeros(p0.shape[0])
+    tpar = np.zeros(p0.shape[0])
+    cache = {}
+    for i in range(p0.shape[0]):
+        c = p0[i, other]
+        if c not in cache:
+            r = cv.line_roots(other, c)
+            cache[c] = (r, cv.X(r)[:, axis] if r.size else np.zeros(0))
+        r, xa = cache[c]
+        on = (xa >= p0[i, axis] - tol) & (xa <= p0[i, axis] + h + tol)
+        if np.count_nonzero(on) != 1:
+            raise GeometryError("grid arm crossed more than once")
+        k = int(np.flatnonzero(on)[0])
+        frac[i] = min(1.0, max(0.0, (xa[k] - p0[i, axis]) / h))
+        tpar[i] = r[k]
+    return frac, tpar
+
+
 class Crossings:
     """All grid-arm / boundary intersections.
 
@@ -271,7 +325,7 @@ class Crossings:
         d, N, h = grid.dim, grid.n, grid.h
         shape = (N,) * d
         inside_all = np.all(side, axis=0)
-        surf_l, axis_l, z_l, pin_l, pout_l = [], [], [], [], []
+        surf_l, axis_l, z_l, pin_l, pout_l, tparam_l = [], [], [], [], [], []
         for s, surf in enumerate(iface.surfaces):
             sd = side[s].reshape(shape)
             others = np.all(np.delete(side, s, axis=0), axis=0).reshape(shape) \
@@ -292,17 +346,23 @@ class Crossings:
                 idx1 = idx0.copy()
                 idx1[:, a] += 1
                 p0 = grid.lo + (idx0 + 1) * h
-                t = _root_on_arm(surf, p0, a, h)
+                if is_spline(surf):
+                    t, tp = _spline_roots_on_arms(curve_of(surf), p0, a, h)
+                    tparam_l.append(tp)
+                else:
+                    t = _root_on_arm(surf, p0, a, h)
+                    tparam_l.append(np.full(len(t), np.nan))
                 # reject arms that the surface crosses more than once
-                ts = np.linspace(0.0, 1.0, 9)
-                sides = []
-                for tt in ts:
-                    x = p0.copy()
-                    x[:, a] += tt * h
-                    sides.append(levelset(surf, x) <= SIDE_TOL)
-                sides = np.stack(sides, axis=1)
-                if np.any(np.sum(sides[:, 1:] != sides[:, :-1], axis=1) != 1):
-                    raise GeometryError("grid arm crossed more than once")
+                if not is_spline(surf):
+                    ts = np.linspace(0.0, 1.0, 9)
+                    sides = []
+                    for tt in ts:
+                        x = p0.copy()
+                        x[:, a] += tt * h
+                        sides.append(levelset(surf, x) <= SIDE_TOL)
+                    sides = np.stack(sides, axis=1)
+                    if np.any(np.sum(sides[:, 1:] != sides[:, :-1], axis=1) != 1):
+                        raise GeometryError("grid arm crossed more than once")
                 z = p0.copy()
                 z[:, a] += t * h
                 lin0 = linear_index(grid, idx0)
@@ -319,19 +379,24 @@ class Crossings:
             self.z = np.concatenate(z_l)
             self.p_in = np.concatenate(pin_l)
             self.p_out = np.concatenate(pout_l)
+            self.tparam = np.concatenate(tparam_l)
         else:
             self.surf = np.zeros(0, dtype=np.int64)
             self.axis = np.zeros(0, dtype=np.int64)
             self.z = np.zeros((0, d))
             self.p_in = np.zeros(0, dtype=np.int64)
             self.p_out = np.zeros(0, dtype=np.int64)
+            self.tparam = np.zeros(0)
         self.count = len(self.surf)
         self.n = np.zeros((self.count, d))
         self.W = np.zeros((self.count, d, d))
         for s, surf in enumerate(iface.surfaces):
             m = self.surf == s
             if np.any(m):
-                self.n[m], self.W[m] = normal_and_shape(surf, self.z[m])
+                if is_spline(surf):
+                    self.n[m], self.W[m] = curve_of(surf).normal_and_shape(self.tparam[m])
+                else:
+                    self.n[m], self.W[m] = normal_and_shape(surf, self.z[m])
         self.inside = inside_all
 
 

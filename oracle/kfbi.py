@@ -10,7 +10,8 @@ The pieces, in the order of Algorithm 1:
 * density transfer: psi and its surface gradient at intersection points and
   interface nodes.  The paper takes these from local coordinate systems on
   the boundary (Sec. 5.3, Fig. 1 paragraph); here a cubic Lagrange fit in the
-  curve parameter (2D) or a quadratic least-squares fit over the 10 nearest
+  curve parameter (2D: the polar angle, or the spline parameter of a curve
+  given by its nodes) or a quadratic least-squares fit over the 10 nearest
   nodes in the tangent plane (3D).
 * jump relations of the single-layer interface problem (Sec. 5.1, eq.
   single: [u] = 0, [n.D grad u] = psi, homogeneous equation on both sides).
@@ -90,6 +91,30 @@ def transfer_2d_nodes(surf, offset, m):
     idx = offset + np.mod(j[:, None] + np.arange(-2, 3)[None, :], m)
     c = np.array([1.0, -8.0, 0.0, 8.0, -1.0]) / (12.0 * dt)
     tau, speed = geometry.curve_tangent(surf, t)
+    wg = (c[None, :] / speed[:, None])[:, :, None] * tau[:, None, :]
+    return idx, wg
+
+
+def transfer_spline_points(cv, offset, tpar):
+    """Spline curves: the same cubic Lagrange fit, in the spline parameter t* of each point
+    (nodes at t = j); d psi/ds = (d psi/dt)/|X'(t*)| along the spline tangent."""
+    m = cv.m
+    j = np.floor(tpar).astype(np.int64)
+    s = tpar - j
+    w, dw = _lagrange4(s)
+    idx = offset + np.mod(j[:, None] + np.arange(-1, 3)[None, :], m)
+    tau, speed = cv.tangent(tpar)
+    wg = (dw / speed[:, None])[:, :, None] * tau[:, None, :]
+    return idx, w, wg
+
+
+def transfer_spline_nodes(cv, offset):
+    """Spline curves: 5-point central difference in t (unit node spacing) over the speed."""
+    m = cv.m
+    j = np.arange(m)
+    idx = offset + np.mod(j[:, None] + np.arange(-2, 3)[None, :], m)
+    c = np.array([1.0, -8.0, 0.0, 8.0, -1.0]) / 12.0
+    tau, speed = cv.tangent(j.astype(np.float64))
     wg = (c[None, :] / speed[:, None])[:, :, None] * tau[:, None, :]
     return idx, wg
 
@@ -229,7 +254,13 @@ class Problem:
         for s, surf in enumerate(self.iface.surfaces):
             o, m = nd.offsets[s], surf.n_nodes
             msk = cr.surf == s
-            if d == 2:
+            if geometry.is_spline(surf):
+                cv = geometry.curve_of(surf)
+                if np.any(msk):
+                    self.z_idx[msk], self.z_w0[msk], self.z_wg[msk] = \
+                        transfer_spline_points(cv, o, cr.tparam[msk])
+                self.q_idx[o:o + m], self.q_wg[o:o + m] = transfer_spline_nodes(cv, o)
+            elif d == 2:
                 if np.any(msk):
                     self.z_idx[msk], self.z_w0[msk], self.z_wg[msk] = \
                         transfer_2d_points(surf, o, m, cr.z[msk])

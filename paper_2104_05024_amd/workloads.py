@@ -5,21 +5,23 @@ physical constants, seeded random numbers).  It holds none of the method's
 arithmetic, so both the HIP path and the FP64 CPU checker take their inputs
 from here without sharing any computation.
 
-Every interface is a union of star-shaped closed surfaces (curves in 2D)
-given in polar form  r = R(u),  u = x/|x|,
+Every interface is a union of closed surfaces (curves in 2D).  A surface is
+either analytic, star-shaped in polar form  r = R(u),  u = x/|x|,
 
     R(u) = E(u) * (1 + sum_t c_t * prod_i u_i**e_ti),
     E(u) = (sum_i u_i**2 / a_i**2) ** (-1/2)          (ellipse / ellipsoid)
 
-``orient = +1`` puts the tissue (the "+" side) inside the surface, ``-1``
-outside it (the inner wall of a shell).  The tissue region is the
-intersection of the per-surface regions.
+or given only by its nodes: a closed 2D curve through ordered points (the method
+interpolates them with a periodic cubic spline), or a closed 3D triangle mesh
+(vertices and triangles).  ``orient = +1`` puts the tissue (the "+" side) inside
+the surface, ``-1`` outside it (the inner wall of a shell).  The tissue region
+is the intersection of the per-surface regions.
 """
 from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -30,6 +32,9 @@ class Surface:
     orient: int
     n_nodes: int
     terms: List[Tuple[float, Tuple[int, ...]]] = field(default_factory=list)
+    kind: str = "analytic"              # "analytic", "spline" (2D points) or "mesh" (3D triangles)
+    points: Optional[np.ndarray] = None  # (n_nodes, dim) node coordinates of a spline / mesh
+    tris: Optional[np.ndarray] = None    # (n_tris, 3) vertex indices of a mesh
 
 
 @dataclass
@@ -96,6 +101,55 @@ def star2d(R0=0.7, A=0.15, L=5, n_nodes=256) -> Interface:
 
 def circle2d(R=0.5, n_nodes=256) -> Interface:
     return Interface(2, [Surface((R, R), +1, n_nodes, [])])
+
+
+def spline_curve(points, orient=+1) -> Surface:
+    """A closed curve through the ordered points (n, 2), either direction of travel."""
+    P = np.ascontiguousarray(points, dtype=np.float64)
+    return Surface((1.0, 1.0), orient, P.shape[0], [], kind="spline", points=P)
+
+
+def _resample_closed(x, y, n, jitter, seed):
+    """n quasi-uniform points on a densely sampled closed curve: equal arc-length steps, each
+    moved by a seeded fraction (|.| <= jitter) of the step along the curve."""
+    xc, yc = np.append(x, x[0]), np.append(y, y[0])
+    s = np.concatenate([[0.0], np.cumsum(np.hypot(np.diff(xc), np.diff(yc)))])
+    u = (np.arange(n) + np.random.default_rng(seed).uniform(-jitter, jitter, size=n)) * (s[-1] / n)
+    return np.stack([np.interp(u, s, xc), np.interp(u, s, yc)], axis=1)
+
+
+def heart_points(n_nodes=256, scale=0.72, jitter=0.1, seed=3, samples=1 << 16):
+    """Quasi-uniform nodes on a smooth heart-shaped curve (counter-clockwise): the polar curve
+    r(t) = scale (1 - 0.28 g(t - pi/2, 0.45) + 0.22 g(t - 3 pi/2, 0.5)), g(s, w) = exp(-(s/w)^2)
+    (s wrapped to [-pi, pi)), a dimple at the top and a rounded tip at the bottom, shifted up
+    by 0.15.  Smallest radius of curvature 0.18."""
+    t = np.linspace(0.0, 2.0 * np.pi, samples, endpoint=False)
+
+    def g(c, w):
+        return np.exp(-((np.mod(t - c + np.pi, 2.0 * np.pi) - np.pi) / w) ** 2)
+
+    r = scale * (1.0 - 0.28 * g(0.5 * np.pi, 0.45) + 0.22 * g(1.5 * np.pi, 0.5))
+    return _resample_closed(r * np.cos(t), r * np.sin(t) + 0.15, n_nodes, jitter, seed)
+
+
+def heart2d(n_nodes=256, jitter=0.1, seed=3) -> Interface:
+    return Interface(2, [spline_curve(heart_points(n_nodes, jitter=jitter, seed=seed))])
+
+
+def spline_circle(R=0.5, n_nodes=256, clockwise=False, orient=+1) -> Interface:
+    """Circle of radius R through n equally spaced points (angle offset half a step)."""
+    t = 2.0 * np.pi * (np.arange(n_nodes) + 0.5) / n_nodes
+    if clockwise:
+        t = -t
+    return Interface(2, [spline_curve(np.stack([R * np.cos(t), R * np.sin(t)], axis=1), orient)])
+
+
+def spline_star(R0=0.7, A=0.15, L=5, n_nodes=256) -> Interface:
+    """The star r = R0 + A cos(L t) through its points at t_j = 2 pi j / n (the analytic
+    surface's own nodes), as a spline curve."""
+    t = 2.0 * np.pi * np.arange(n_nodes) / n_nodes
+    r = R0 + A * np.cos(L * t)
+    return Interface(2, [spline_curve(np.stack([r * np.cos(t), r * np.sin(t)], axis=1))])
 
 
 def ellipsoid(a=0.9, b=0.7, c=0.5, n_nodes=8192) -> Interface:
@@ -191,6 +245,8 @@ def config(name: str):
         return perturbed_sphere(n_nodes=32768), box(3, 256), scalar_coeffs(3, 1.0, 400.0)
     if name == "shell_256":
         return thick_shell(n_nodes=40960), box(3, 256), BidomainParams()
+    if name == "heart2d_128":
+        return heart2d(n_nodes=256), box(2, 128), scalar_coeffs(2, 1.0, 400.0)
     if name == "ellipsoid_bidomain_128":
         return ellipsoid(n_nodes=8192), box(3, 128), BidomainParams()
     raise KeyError(name)
