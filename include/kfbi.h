@@ -57,10 +57,21 @@ enum { KFBI_F64 = 0, KFBI_F32 = 1 };
 #define KFBI_MAX_SURFACES 2
 #define KFBI_MAX_TERMS 16
 
-/* One closed star-shaped surface (curve in 2D) in polar form r = R(u), u = x/|x|:
- *   R(u) = (sum_i u_i^2/axes_i^2)^(-1/2) * (1 + sum_t coef[t] prod_i u_i^exps[t][i]).
- * orient = +1: the tissue Omega is inside; -1: outside (inner wall of a shell).
- * n_nodes interface nodes are placed on it (Sec. 6, quasi-uniform nodes). */
+/* Kinds of surface descriptor. */
+enum { KFBI_SURF_ANALYTIC = 0, KFBI_SURF_SPLINE = 1, KFBI_SURF_MESH = 2 };
+
+/* One closed surface (curve in 2D).  orient = +1: the tissue Omega is inside it; -1: outside
+ * (the inner wall of a shell).  n_nodes interface nodes lie on it (Sec. 6, quasi-uniform nodes).
+ *
+ * kind = KFBI_SURF_ANALYTIC: star-shaped in polar form r = R(u), u = x/|x|:
+ *   R(u) = (sum_i u_i^2/axes_i^2)^(-1/2) * (1 + sum_t coef[t] prod_i u_i^exps[t][i]);
+ *   the library places the nodes (2D: equal angles; 3D: spherical Fibonacci lattice).
+ * kind = KFBI_SURF_SPLINE (2D only; Sec. 7, the 2D set-up): the boundary is given only by
+ *   its nodes, points[2*j + a] (host memory, n_nodes >= 8 points in order along the curve,
+ *   either direction); the library interpolates them with the periodic cubic spline in the
+ *   node index (C2, closed) and reads normals, curvature and grid-line crossings off it.
+ *   axes, coef and exps are ignored; the points are copied during kfbi_setup.
+ * kind = KFBI_SURF_MESH is reserved for closed triangle meshes (3D). */
 typedef struct {
   double axes[3];
   int32_t orient;
@@ -68,6 +79,11 @@ typedef struct {
   int64_t n_nodes;
   double coef[KFBI_MAX_TERMS];
   int32_t exps[KFBI_MAX_TERMS][3];
+  int32_t kind;            /* KFBI_SURF_*; 0 (analytic) when the struct is zero-initialised */
+  int32_t pad_;
+  const double *points;    /* spline / mesh: node coordinates [n_nodes][dim], host memory */
+  const int32_t *tris;     /* mesh: vertex indices [n_tris][3], host memory */
+  int64_t n_tris;
 } kfbi_surface;
 
 /* Omega = intersection of the per-surface regions (Sec. 4: Omega inside the box B). */
@@ -117,7 +133,8 @@ int kfbi_query(kfbi_problem p, int64_t *M, int64_t *N, int64_t *n_crossings, int
 /* Host copy of a setup table, for inspection and parity tests.  Names:
  * "inside"(i8,N^d) "nodes_X" "nodes_n"(f64,M*d) "nodes_W"(f64,M*d*d)
  * "cross_axis" "cross_surf"(i64) "cross_pin" "cross_pout"(i64, linear interior index)
- * "cross_z"(f64,nc*d) "z_idx"(i64,nc*K) "z_w0"(f64,nc*K) "z_wg"(f64,nc*K*d)
+ * "cross_z" "cross_n"(f64,nc*d) "cross_W"(f64,nc*d*d) "cross_t"(f64,nc: spline parameter of
+ * the crossing on a spline curve, NaN elsewhere) "z_idx"(i64,nc*K) "z_w0"(f64,nc*K) "z_wg"(f64,nc*K*d)
  * "q_idx"(i64,M*Kn) "q_wg"(f64,M*Kn*d) "st_lin"(i64,M*S) "st_r" "st_wgrad"(f64,M*S*d)
  * "irregular"(i64).  With dst == NULL only *count (elements) and *elem_bytes are set. */
 int kfbi_table(kfbi_problem p, const char *name, void *dst, int64_t *count, int32_t *elem_bytes);

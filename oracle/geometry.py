@@ -292,12 +292,22 @@ def _root_on_arm(surf, p, axis, h, iters=80):
 
 def _spline_roots_on_arms(cv, p0, axis, h, tol=1e-12):
     """Crossing of a spline curve with each arm from p0 to p0 + h e_axis: the arm fraction
-    and the curve parameter.  Exactly one root of the curve may lie on the arm."""
+    and the curve parameter.  An end point on the curve (|signed distance| <= 1e-12) is the
+    crossing itself; otherwise exactly one root of the curve may lie on the arm."""
     other = 1 - axis
     frac = np.zeros(p0.shape[0])
     tpar = np.zeros(p0.shape[0])
+    p1 = p0.copy()
+    p1[:, axis] += h
+    sd0, t0 = cv.closest(p0)
+    sd1, t1 = cv.closest(p1)
     cache = {}
     for i in range(p0.shape[0]):
+        if abs(sd0[i]) <= SIDE_TOL or abs(sd1[i]) <= SIDE_TOL:
+            end0 = abs(sd0[i]) <= SIDE_TOL
+            frac[i] = 0.0 if end0 else 1.0
+            tpar[i] = t0[i] if end0 else t1[i]
+            continue
         c = p0[i, other]
         if c not in cache:
             r = cv.line_roots(other, c)

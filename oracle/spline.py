@@ -66,6 +66,10 @@ class SplineCurve:
     # -- sides
     def signed_distance(self, pts):
         """(x - X(t*)).n(t*) at the closest point X(t*): negative in the tissue."""
+        return self.closest(pts)[0]
+
+    def closest(self, pts):
+        """Signed distance and the parameter t* of the closest point on the curve."""
         pts = np.asarray(pts, dtype=np.float64)
         ts, xs = self.samples()
         _, k = cKDTree(xs).query(pts)
@@ -80,8 +84,9 @@ class SplineCurve:
             t = t + step
             if np.all(np.abs(step) < 1e-15):
                 break
+        t = np.mod(t, self.m)
         n, _ = self.normal_and_shape(t)
-        return np.sum((pts - self.X(t)) * n, axis=1)
+        return np.sum((pts - self.X(t)) * n, axis=1), t
 
     def tissue(self, pts):
         return self.signed_distance(pts) <= SIDE_TOL

@@ -139,6 +139,9 @@ int kfbi_table(kfbi_problem p, const char *name, void *dst, int64_t *count, int3
   else if (s == "cross_pin") pick_i(t.c_pin);
   else if (s == "cross_pout") pick_i(t.c_pout);
   else if (s == "cross_z") pick_d(t.c_z);
+  else if (s == "cross_n") pick_d(t.c_n);
+  else if (s == "cross_W") pick_d(t.c_W);
+  else if (s == "cross_t") pick_d(t.c_t);
   else if (s == "z_idx") pick_i(t.z_idx);
   else if (s == "z_w0") pick_d(t.z_w0);
   else if (s == "z_wg") pick_d(t.z_wg);

@@ -8,8 +8,11 @@
 //    nodes (the paper's local coordinate systems, Sec. 5.3 Fig. 1 paragraph),
 //  * per interface node the "nearest six / ten" grid nodes of the quadratic fit and the
 //    gradient rows of the inverse h-scaled Vandermonde matrix (Sec. 5.4).
-// Shapes are star-shaped surfaces r = R(u) (see kfbi.h); their level set is
-// phi = orient (|x| - R(x/|x|)), with analytic gradient and Hessian.
+// Analytic shapes are star-shaped surfaces r = R(u) (see kfbi.h); their level set is
+// phi = orient (|x| - R(x/|x|)), with analytic gradient and Hessian.  2D curves given by their
+// nodes use the periodic cubic spline through them (host_spline.cpp): grid nodes take their
+// side from the parity of the crossings on their grid row, crossings are the spline's roots on
+// the grid lines, and the transfer runs in the spline parameter.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -400,6 +403,26 @@ void lagrange_transfer(const kfbi_surface &s, int64_t off, int64_t m, const doub
   }
 }
 
+// Spline curves: the same cubic Lagrange fit in the spline parameter t* (nodes at t = j).
+void spline_transfer(const SplineCurve2 &sc, int64_t off, double tp, int64_t *idx, double *w0, double *wg) {
+  const int64_t m = sc.m;
+  const int64_t j = (int64_t)std::floor(tp);
+  const double sl = tp - (double)j;
+  const double w[4] = {-sl * (sl - 1) * (sl - 2) / 6.0, (sl + 1) * (sl - 1) * (sl - 2) / 2.0,
+                       -(sl + 1) * sl * (sl - 2) / 2.0, (sl + 1) * sl * (sl - 1) / 6.0};
+  const double dw[4] = {-(3 * sl * sl - 6 * sl + 2) / 6.0, (3 * sl * sl - 4 * sl - 1) / 2.0,
+                        -(3 * sl * sl - 2 * sl - 2) / 2.0, (3 * sl * sl - 1) / 6.0};
+  double tau[2], speed;
+  sc.tangent(tp, tau, speed);
+  for (int i = 0; i < 4; ++i) {
+    idx[i] = off + (((j + i - 1) % m) + m) % m;
+    w0[i] = w[i];
+    const double c = dw[i] / speed;
+    wg[i * 2 + 0] = c * tau[0];
+    wg[i * 2 + 1] = c * tau[1];
+  }
+}
+
 int64_t lin_of(const int64_t *k, int d, int64_t N) {
   int64_t lin = 0;
   for (int a = d - 1; a >= 0; --a) lin = lin * N + k[a];
@@ -432,11 +455,25 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   std::memcpy(t.D, co.D, sizeof(t.D));
   t.surf.assign(iface.surf, iface.surf + iface.n_surfaces);
   t.offsets.assign(1, 0);
-  for (const auto &s : t.surf) {
-    if (s.n_nodes < 8 || s.n_terms < 0 || s.n_terms > KFBI_MAX_TERMS || (s.orient != 1 && s.orient != -1))
-      throw std::invalid_argument("surface descriptor");
-    for (int a = 0; a < d; ++a)
-      if (!(s.axes[a] > 0)) throw std::invalid_argument("surface axes");
+  std::vector<SplineCurve2> spl(t.surf.size());
+  std::vector<char> is_spl(t.surf.size(), 0);
+  for (size_t si = 0; si < t.surf.size(); ++si) {
+    const auto &s = t.surf[si];
+    if (s.n_nodes < 8 || (s.orient != 1 && s.orient != -1)) throw std::invalid_argument("surface descriptor");
+    if (s.kind == KFBI_SURF_ANALYTIC) {
+      if (s.n_terms < 0 || s.n_terms > KFBI_MAX_TERMS) throw std::invalid_argument("surface descriptor");
+      for (int a = 0; a < d; ++a)
+        if (!(s.axes[a] > 0)) throw std::invalid_argument("surface axes");
+    } else if (s.kind == KFBI_SURF_SPLINE) {
+      if (d != 2) throw std::invalid_argument("spline curves are two-dimensional");
+      if (!s.points) throw std::invalid_argument("spline curve without points");
+      for (int64_t j = 0; j < 2 * s.n_nodes; ++j)
+        if (!std::isfinite(s.points[j])) throw std::invalid_argument("spline points must be finite");
+      spl[si].build(s.points, s.n_nodes, s.orient);
+      is_spl[si] = 1;
+    } else {
+      throw std::invalid_argument("surface kind");
+    }
     t.offsets.push_back(t.offsets.back() + s.n_nodes);
   }
   t.M = t.offsets.back();
@@ -446,7 +483,17 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   for (int a = 0; a < d; ++a) total *= N;
 
   // -- clearance: the boundary stays >= 3h inside the box (stencils never reach it)
-  for (const auto &s : t.surf) {
+  for (size_t si = 0; si < t.surf.size(); ++si) {
+    const auto &s = t.surf[si];
+    if (is_spl[si]) {
+      for (int64_t q = 0; q < 16 * s.n_nodes; ++q) {
+        double x[2];
+        spl[si].eval((double)q / 16.0, x, nullptr, nullptr);
+        for (int a = 0; a < 2; ++a)
+          if (x[a] > grid.hi - 3 * h || x[a] < grid.lo + 3 * h) throw GeometryError{"interface closer than 3h to the box"};
+      }
+      continue;
+    }
     const int64_t m = std::max<int64_t>(s.n_nodes, d == 3 ? 4096 : 1024);
     for (int64_t j = 0; j < m; ++j) {
       double u[3], G, g[3], H[9];
@@ -466,6 +513,11 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   for (size_t s = 0; s < t.surf.size(); ++s)
     for (int64_t j = 0; j < t.surf[s].n_nodes; ++j) {
       const int64_t i = t.offsets[s] + j;
+      if (is_spl[s]) {
+        for (int a = 0; a < 2; ++a) t.X[i * 2 + a] = t.surf[s].points[2 * j + a];
+        spl[s].normal_shape((double)j, &t.nrm[i * 2], &t.W[i * 4]);
+        continue;
+      }
       double u[3], G, g[3], H[9];
       node_direction(d, t.surf[s].n_nodes, j, u);
       radial(t.surf[s], d, u, G, g, H);
@@ -476,7 +528,45 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   // -- sides of the grid nodes, per surface
   const int S_ = (int)t.surf.size();
   std::vector<std::vector<int8_t>> side(S_, std::vector<int8_t>(total));
+  // spline curves: crossings of every grid row (y = const) and column (x = const), sorted by
+  // the coordinate along the line; a node's side is the parity of the row crossings beyond it
+  // A node within kSideTol of a crossing on its row or column lies on the curve: it counts as
+  // tissue and is the crossing point of its arms that change side (on_t: its spline parameter).
+  std::vector<std::vector<std::vector<std::pair<double, double>>>> rows(S_), cols(S_);
+  std::vector<std::vector<double>> on_t(S_);
   for (int s = 0; s < S_; ++s) {
+    if (!is_spl[s]) continue;
+    on_t[s].assign(total, std::nan(""));
+    spl[s].grid_line_roots(1, lo, h, N, rows[s]);
+    spl[s].grid_line_roots(0, lo, h, N, cols[s]);
+    for (auto *lines : {&rows[s], &cols[s]})
+      for (auto &ln : *lines)
+        std::sort(ln.begin(), ln.end(), [](const std::pair<double, double> &A, const std::pair<double, double> &B) {
+          return A.second < B.second || (A.second == B.second && A.first < B.first);
+        });
+    for (int pass = 0; pass < 2; ++pass)           // rows (y = y_l), then columns (x = x_k)
+      for (int64_t l = 0; l < N; ++l)
+        for (const auto &r : pass == 0 ? rows[s][l] : cols[s][l]) {
+          const int64_t k = (int64_t)std::llround((r.second - lo) / h) - 1;
+          if (k < 0 || k >= N || std::fabs(r.second - (lo + h * (double)(k + 1))) > kSideTol) continue;
+          const int64_t node = pass == 0 ? l * N + k : k * N + l;
+          if (std::isnan(on_t[s][node])) on_t[s][node] = r.first;
+        }
+    for (int64_t l = 0; l < N; ++l) {
+      const auto &ln = rows[s][l];
+      for (int64_t k = 0; k < N; ++k) {
+        const double x = lo + h * (double)(k + 1);
+        size_t beyond = 0;
+        for (const auto &r : ln)
+          if (r.second > x) ++beyond;
+        const bool interior = (beyond & 1) != 0;
+        const bool on = !std::isnan(on_t[s][l * N + k]);
+        side[s][l * N + k] = (on || interior == (t.surf[s].orient == 1)) ? 1 : 0;
+      }
+    }
+  }
+  for (int s = 0; s < S_; ++s) {
+    if (is_spl[s]) continue;
 #pragma omp parallel for schedule(static)
     for (int64_t lin = 0; lin < total; ++lin) {
       int64_t r = lin;
@@ -512,6 +602,42 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
           }
         }
         const kfbi_surface &sf = t.surf[s];
+        if (is_spl[s]) {
+          // the one root of the spline on this arm: the arm's line is a row (x arms) or a column
+          const int64_t kl = (lin / stride[1 - a]) % N;     // index of the line among rows / columns
+          const auto &ln = a == 0 ? rows[s][kl] : cols[s][kl];
+          const double x0 = p[a], x1 = lo + h * (double)(ka + 2);
+          double tt, tp;
+          if (!std::isnan(on_t[s][lin])) {            // an end on the curve is the crossing
+            tt = 0.0;
+            tp = on_t[s][lin];
+          } else if (!std::isnan(on_t[s][lin1])) {
+            tt = 1.0;
+            tp = on_t[s][lin1];
+          } else {
+            int cnt = 0;
+            double along = 0.0;
+            tp = 0.0;
+            for (const auto &r : ln)
+              if (r.second >= x0 - kSideTol && r.second <= x1 + kSideTol) {
+                ++cnt;
+                along = r.second;
+                tp = r.first;
+              }
+            if (cnt != 1) throw GeometryError{"grid arm crossed more than once"};
+            tt = std::min(1.0, std::max(0.0, (along - x0) / h));
+          }
+          double z[3] = {p[0], p[1], p[2]};
+          z[a] += tt * h;
+          t.c_surf.push_back(s);
+          t.c_axis.push_back(a);
+          const bool in0 = side[s][lin] != 0;
+          t.c_pin.push_back(in0 ? lin : lin1);
+          t.c_pout.push_back(in0 ? lin1 : lin);
+          for (int b = 0; b < d; ++b) t.c_z.push_back(z[b]);
+          t.c_t.push_back(tp);
+          continue;
+        }
         auto f = [&](double tt, double &ft, double &dft) {
           double x[3] = {p[0], p[1], p[2]};
           x[a] += tt * h;
@@ -563,12 +689,17 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
         t.c_pin.push_back(in0 ? lin : lin1);
         t.c_pout.push_back(in0 ? lin1 : lin);
         for (int b = 0; b < d; ++b) t.c_z.push_back(z[b]);
+        t.c_t.push_back(std::nan(""));
       }
   t.nc = (int64_t)t.c_surf.size();
   t.c_n.resize(t.nc * d);
   t.c_W.resize(t.nc * d * d);
-  for (int64_t c = 0; c < t.nc; ++c)
-    normal_shape(t.surf[t.c_surf[c]], d, &t.c_z[c * d], &t.c_n[c * d], &t.c_W[c * d * d]);
+  for (int64_t c = 0; c < t.nc; ++c) {
+    if (is_spl[t.c_surf[c]])
+      spl[t.c_surf[c]].normal_shape(t.c_t[c], &t.c_n[c * d], &t.c_W[c * d * d]);
+    else
+      normal_shape(t.surf[t.c_surf[c]], d, &t.c_z[c * d], &t.c_n[c * d], &t.c_W[c * d * d]);
+  }
 
   // -- density transfer weights
   t.K = d == 2 ? 4 : kLsqNodes;
@@ -580,7 +711,22 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   t.q_wg.resize(M * t.Kn * d);
   for (int s = 0; s < S_; ++s) {
     const int64_t off = t.offsets[s], m = t.surf[s].n_nodes;
-    if (d == 2) {
+    if (is_spl[s]) {
+      for (int64_t c = 0; c < t.nc; ++c)
+        if (t.c_surf[c] == s) spline_transfer(spl[s], off, t.c_t[c], &t.z_idx[c * 4], &t.z_w0[c * 4], &t.z_wg[c * 8]);
+      const double cw[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+      for (int64_t j = 0; j < m; ++j) {
+        double tau[2], speed;
+        spl[s].tangent((double)j, tau, speed);
+        for (int i = 0; i < 5; ++i) {
+          const int64_t q = off + j;
+          t.q_idx[q * 5 + i] = off + (((j + i - 2) % m) + m) % m;
+          const double c = cw[i] / 12.0 / speed;
+          t.q_wg[(q * 5 + i) * 2 + 0] = c * tau[0];
+          t.q_wg[(q * 5 + i) * 2 + 1] = c * tau[1];
+        }
+      }
+    } else if (d == 2) {
       for (int64_t c = 0; c < t.nc; ++c)
         if (t.c_surf[c] == s)
           lagrange_transfer(t.surf[s], off, m, &t.c_z[c * 2], &t.z_idx[c * 4], &t.z_w0[c * 4], &t.z_wg[c * 8]);
@@ -723,6 +869,11 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   t.irregular.insert(t.irregular.end(), t.c_pout.begin(), t.c_pout.end());
   std::sort(t.irregular.begin(), t.irregular.end());
   t.irregular.erase(std::unique(t.irregular.begin(), t.irregular.end()), t.irregular.end());
+  // the caller's point / triangle arrays are only valid during setup
+  for (auto &s : t.surf) {
+    s.points = nullptr;
+    s.tris = nullptr;
+  }
 }
 
 }  // namespace kfbi

@@ -22,7 +22,7 @@ struct HostTables {
   int64_t N = 0, M = 0;
   double lo = 0, hi = 0, h = 0, kappa = 0;
   double D[2][3] = {{0}};
-  std::vector<kfbi_surface> surf;
+  std::vector<kfbi_surface> surf;          // descriptors (points / tris pointers cleared after setup)
   std::vector<int64_t> offsets;            // first node of each surface (+ total)
 
   std::vector<double> X, nrm, W;           // nodes: M*d, M*d, M*d*d
@@ -31,6 +31,7 @@ struct HostTables {
   int64_t nc = 0;                          // grid-line intersections
   std::vector<int64_t> c_surf, c_axis, c_pin, c_pout;
   std::vector<double> c_z, c_n, c_W;       // nc*d, nc*d, nc*d*d
+  std::vector<double> c_t;                 // nc: spline parameter (spline curves), NaN otherwise
 
   int K = 0, Kn = 0;                       // transfer stencil sizes (crossings / nodes)
   std::vector<int64_t> z_idx, q_idx;       // nc*K, M*Kn
@@ -42,6 +43,27 @@ struct HostTables {
   std::vector<int8_t> st_chi;              // M*S, 1 = stencil node outside the tissue
 
   std::vector<int64_t> irregular;          // sorted linear indices
+};
+
+// Closed 2D curve through m ordered nodes: the periodic cubic spline in the node index
+// (t_j = j), one cubic per piece and coordinate, a + b s + c s^2 + d s^3 for s = t - j in [0, 1].
+struct SplineCurve2 {
+  int64_t m = 0;
+  std::vector<double> co[2];   // [coord][piece][4]
+  double sigma = 1;            // n = sigma (y', -x') / |X'| points out of the tissue
+  int orient = 1;
+
+  void build(const double *pts, int64_t m, int orient);
+  // position, first and second derivatives at parameter t (taken modulo m)
+  void eval(double t, double *X, double *X1, double *X2) const;
+  void normal_shape(double t, double *n, double *W) const;
+  void tangent(double t, double *tau, double &speed) const;
+  // Crossings of the grid lines {coordinate `coord` = lo + (k+1) h}, k = 0..nl-1, as
+  // (parameter t, other coordinate) per line: one root per change of the predicate
+  // "coordinate > line value" along each monotone part of a piece, so a curve that only
+  // touches a line contributes an even number of roots.
+  void grid_line_roots(int coord, double lo, double h, int64_t nl,
+                       std::vector<std::vector<std::pair<double, double>>> &out) const;
 };
 
 // Throws GeometryError on geometric failure, std::invalid_argument on bad input.

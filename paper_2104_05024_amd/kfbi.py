@@ -37,7 +37,9 @@ class KfbiError(RuntimeError):
 
 class Surface(C.Structure):
     _fields_ = [("axes", C.c_double * 3), ("orient", C.c_int32), ("n_terms", C.c_int32), ("n_nodes", C.c_int64),
-                ("coef", C.c_double * MAX_TERMS), ("exps", (C.c_int32 * 3) * MAX_TERMS)]
+                ("coef", C.c_double * MAX_TERMS), ("exps", (C.c_int32 * 3) * MAX_TERMS),
+                ("kind", C.c_int32), ("pad_", C.c_int32), ("points", C.c_void_p), ("tris", C.c_void_p),
+                ("n_tris", C.c_int64)]
 
 
 class Interface(C.Structure):
@@ -137,12 +139,31 @@ def _check(rc, allow=()):
 
 # ----------------------------------------------------------------------------- descriptors
 
+SURF_KINDS = {"analytic": 0, "spline": 1, "mesh": 2}
+
+
 def interface_desc(iface) -> Interface:
+    """ctypes descriptor of an interface; node and triangle arrays stay referenced by the
+    descriptor (attribute ``keep``) for as long as it lives."""
     d = Interface()
     d.dim = iface.dim
     d.n_surfaces = len(iface.surfaces)
+    d.keep = []
     for s, surf in enumerate(iface.surfaces):
         cs = d.surf[s]
+        kind = getattr(surf, "kind", "analytic")
+        cs.kind = SURF_KINDS[kind]
+        if kind != "analytic":
+            pts = np.ascontiguousarray(surf.points, dtype=np.float64)
+            if pts.shape != (surf.n_nodes, iface.dim):
+                raise ValueError("points must have shape (n_nodes, dim)")
+            d.keep.append(pts)
+            cs.points = pts.ctypes.data
+            if kind == "mesh":
+                tris = np.ascontiguousarray(surf.tris, dtype=np.int32)
+                d.keep.append(tris)
+                cs.tris = tris.ctypes.data
+                cs.n_tris = tris.shape[0]
         for a in range(iface.dim):
             cs.axes[a] = surf.axes[a]
         cs.orient = surf.orient
@@ -293,7 +314,8 @@ class Batch:
         """problems: list of (interface, grid, coeffs) with dim 2 and one component."""
         n = len(problems)
         self.n = n
-        self._ifs = (Interface * n)(*[interface_desc(p[0]) for p in problems])
+        self._if_keep = [interface_desc(p[0]) for p in problems]     # owns the node arrays
+        self._ifs = (Interface * n)(*self._if_keep)
         self._grs = (GridDesc * n)(*[grid_desc(p[1]) for p in problems])
         self._cos = (CoeffsDesc * n)(*[coeffs_desc(p[2]) for p in problems])
         self._h = C.c_void_p()

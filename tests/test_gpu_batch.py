@@ -162,3 +162,24 @@ def test_batch_graph_replay_matches_direct_launches(batch):
     assert [x["iters"] for x in i1] == [x["iters"] for x in i2] == [x["iters"] for x in i3]
     assert torch.equal(u1, u2) and torch.equal(p1, p2)
     assert torch.equal(u1, u3) and torch.equal(p1, p3)
+
+
+def test_batch_with_spline_boundaries_matches_single_problems():
+    """A batch mixing analytic stars and node-given spline curves (heart, clockwise circle)
+    of three grid sizes: every problem's product equals its own single-problem product."""
+    probs = [(W.heart2d(256), W.box(2, 128), W.scalar_coeffs(2, 1.0, 300.0)),
+             (W.star2d(n_nodes=128), W.box(2, 64), W.scalar_coeffs(2, 1.0, 100.0)),
+             (W.spline_circle(0.55, 100, clockwise=True), W.box(2, 64), W.scalar_coeffs(2, 1.0, 900.0)),
+             (W.heart2d(512, seed=7), W.box(2, 256), W.scalar_coeffs(2, 1.0, 50.0))]
+    say("[batch with splines]")
+    b = K.Batch(probs)
+    psi = np.random.default_rng(9).uniform(-1, 1, size=b.L)
+    out = b.apply(T(psi)).cpu().numpy()
+    for i, (iface, grid, co) in enumerate(probs):
+        p = K.Problem(iface, grid, co)
+        ref = p.apply(T(seg(psi, b, i)[None])).cpu().numpy()
+        e = rel(seg(out, b, i), ref)
+        say(f"    problem {i}: rel diff {e:.2e}")
+        assert e < 1e-13
+        p.close()
+    b.close()

@@ -61,6 +61,11 @@ def problems(name):
         "ellipsoid_64_aniso": (W.ellipsoid(n_nodes=2048), W.box(3, 64), W.Coeffs(1, [[3.0, 0.5, 0.5]], 400.0)),
         "shell_64_aniso": (W.thick_shell(n_nodes=3000), W.box(3, 64),
                            W.Coeffs(2, [[3.0, 0.5, 0.5], [2.0, 1.0, 1.0]], 200.0)),
+        # 2D boundaries given only by their nodes (periodic cubic splines)
+        "heart_spline_128": (W.heart2d(256), W.box(2, 128), W.scalar_coeffs(2, 1.0, 400.0)),
+        "heart_spline_bido_64": (W.heart2d(128), W.box(2, 64), W.bidomain_coeffs(2, P_BIDO, 0.01)),
+        "circle_spline_cw_64": (W.spline_circle(0.55, 100, clockwise=True), W.box(2, 64),
+                                W.scalar_coeffs(2, 1.0, 400.0)),
     }
     iface, grid, co = cases[name]
     say(f"[setup] {name}")
@@ -98,7 +103,8 @@ def test_box_solve_in_place_and_ragged_tile():
 # ----------------------------------------------------------------------------- matvec (a1, a2, a6)
 
 @pytest.mark.parametrize("name", ["star2d_64", "star2d_128", "ellipsoid_64", "shell_64", "psphere_32",
-                                  "star2d_64_aniso", "ellipsoid_64_aniso", "shell_64_aniso"])
+                                  "star2d_64_aniso", "ellipsoid_64_aniso", "shell_64_aniso",
+                                  "heart_spline_128", "heart_spline_bido_64", "circle_spline_cw_64"])
 def test_apply_f64_matches_oracle(name):
     g, o, iface, grid, co = problems(name)
     psi = np.random.default_rng(3).uniform(-1, 1, size=(co.ncomp, g.M))
@@ -110,7 +116,7 @@ def test_apply_f64_matches_oracle(name):
     assert e < 1e-10, e
 
 
-@pytest.mark.parametrize("name", ["star2d_128", "shell_64", "shell_64_aniso"])
+@pytest.mark.parametrize("name", ["star2d_128", "shell_64", "shell_64_aniso", "heart_spline_128"])
 def test_apply_f32_error_is_stated_bound(name):
     g, o, iface, grid, co = problems(name)
     psi = np.random.default_rng(4).uniform(-1, 1, size=(co.ncomp, g.M))
@@ -458,3 +464,42 @@ def test_projection_start_reaches_tolerance_with_fewer_iterations():
     assert np.mean([i["start_resid"] for i in i3]) < 0.5 * np.mean([i["start_resid"] for i in i0])
     assert np.mean([i["iters"] for i in i3]) <= np.mean([i["iters"] for i in i0])
     assert np.max(np.abs(runs[3][0] - runs[0][0])) < 1e-8
+
+
+# ----------------------------------------------------------------------------- spline boundaries (f3)
+
+def test_solve_neumann_on_spline_heart_matches_oracle():
+    """A heart-shaped boundary given only by 256 quasi-uniform nodes: the GPU solve equals the
+    oracle's and is second-order accurate (max error below 0.4 h^2, as the oracle's pin)."""
+    g, o, iface, grid, co = problems("heart_spline_128")
+    f, gn, ue = _mms2d(o, grid)
+    say("[solve f64] heart_spline_128")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-13)
+    u = u.cpu().numpy()
+    uo, psio, infoo = o.solve_neumann(gn, f, tol=1e-13)
+    ins = o.inside
+    say(f"    iters gpu {info['iters']} oracle {infoo['iters']}; u err {rel(u[0][ins], uo[0][ins]):.2e}")
+    assert info["rel_resid"] <= 1e-13
+    assert rel(u[0][ins], uo[0][ins]) < 1e-10
+    assert rel(psi.cpu().numpy(), psio) < 1e-9
+    assert np.max(np.abs(u[0] - ue)[ins]) < 0.4 * grid.h ** 2
+
+
+def test_bidomain_on_spline_heart_matches_oracle():
+    """Coupled FitzHugh-Nagumo bidomain steps on the spline heart with a paired stimulus."""
+    g, o, iface, grid, co = problems("heart_spline_bido_64")
+    stim = W.virtual_electrode(grid, (-0.3, 0.0), (0.3, 0.0), radius=0.2, amplitude=10.0)
+    V0, q0 = obd.initial_state(grid, (0.0, 0.1), radius=0.3)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+    V, q = T(V0), T(q0)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    Is = T(stim)
+    Vo, qo, psi = V0.copy(), q0.copy(), None
+    for s_ in range(4):
+        say(f"[bidomain spline] step {s_}")
+        info = bd.step(V, q, hist, 0.01, I_stim=Is)
+        Vo, qo, uo, psi, infoo = obd.step(o, P_BIDO, Vo, qo, 0.01, psi0=psi, tol=1e-12, I_stim=stim)
+        eV = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+        say(f"    V err {eV:.2e} iters {info['iters']} / {infoo['iters']}")
+        assert eV < 1e-9
+    bd.close()

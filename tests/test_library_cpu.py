@@ -53,6 +53,11 @@ CASES = {
     "ellipsoid_64_tip_on_grid": (W.ellipsoid(n_nodes=2048), W.box(3, 64), W.scalar_coeffs(3)),
     "psphere_32": (W.perturbed_sphere(n_nodes=1500), W.box(3, 32), W.scalar_coeffs(3)),
     "shell_64": (W.thick_shell(n_nodes=3000), W.box(3, 64), W.Coeffs(2, [[1.0] * 3, [2.0] * 3], 200.0)),
+    "heart_spline_128": (W.heart2d(256), W.box(2, 128), W.scalar_coeffs(2)),
+    "circle_spline_cw_64": (W.spline_circle(0.55, 100, clockwise=True), W.box(2, 64), W.scalar_coeffs(2)),
+    # an interface node on a grid node: the circle's node j = 0 is the grid node (x_24, y_16)
+    "circle_spline_node_on_grid_32": (W.spline_star(-1.2 + 24 * (2.4 / 32), 0.0, 5, 64), W.box(2, 32),
+                                      W.scalar_coeffs(2)),
 }
 
 
@@ -68,7 +73,12 @@ def test_setup_tables_match_oracle(name):
     for k, v in exact.items():
         np.testing.assert_array_equal(P.table(k), np.asarray(v).ravel(), err_msg=k)
     close = {"nodes_X": O.nodes.X, "nodes_n": O.nodes.n, "nodes_W": O.nodes.W, "cross_z": O.cross.z,
+             "cross_n": O.cross.n, "cross_W": O.cross.W,
              "z_w0": O.z_w0, "z_wg": O.z_wg, "q_wg": O.q_wg, "st_r": O.st_r, "st_wgrad": O.st_wgrad}
+    if iface.surfaces[0].kind == "spline":      # the spline parameter, compared on the circle of length m
+        m = iface.surfaces[0].n_nodes
+        dt = np.mod(P.table("cross_t") - O.cross.tparam + m / 2, m) - m / 2
+        assert np.max(np.abs(dt)) < 1e-10
     for k, v in close.items():
         v = np.asarray(v).ravel()
         scale = max(1.0, np.max(np.abs(v)))
