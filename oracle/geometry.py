@@ -18,6 +18,7 @@ import math
 
 import numpy as np
 
+from .mesh import MeshError, TriMesh
 from .spline import SplineCurve
 
 SIDE_TOL = 1e-12          # nodes with phi <= SIDE_TOL count as tissue ("+")
@@ -42,6 +43,60 @@ def curve_of(surf):
 
 def is_spline(surf):
     return getattr(surf, "kind", "analytic") == "spline"
+
+
+def is_mesh(surf):
+    return getattr(surf, "kind", "analytic") == "mesh"
+
+
+_MESHES = {}
+
+
+def trimesh_of(surf):
+    """The triangle mesh of a mesh-given 3D surface (built once per surface object)."""
+    key = id(surf)
+    hit = _MESHES.get(key)
+    if hit is None or hit[0] is not surf:
+        try:
+            hit = (surf, TriMesh(surf))
+        except MeshError as e:
+            raise GeometryError(str(e))
+        _MESHES[key] = hit
+    return hit[1]
+
+
+def mesh_lines(tm, grid):
+    """Crossings of the mesh with every grid line, per axis (cached per grid on the mesh)."""
+    key = (grid.lo, grid.cells)
+    cache = getattr(tm, "_lines", None)
+    if cache is None or cache[0] != key:
+        c = grid_coords(grid)
+        tm._lines = (key, [tm.line_hits(a, c, c) for a in range(3)])
+    return tm._lines[1]
+
+
+def mesh_sides(tm, grid):
+    """Tissue flags of the grid nodes for one mesh: parity of the crossings beyond the node on
+    its x line; a node within 1e-12 of a crossing on any of its three lines is on the surface."""
+    N = grid.n
+    c = grid_coords(grid)
+    lines = mesh_lines(tm, grid)
+    interior = np.zeros((N, N, N), dtype=bool)           # [z][y][x]
+    on = np.zeros((N, N, N), dtype=bool)
+    for (iy, iz), hits in lines[0].items():
+        xs = np.array([x for x, _ in hits])
+        beyond = len(xs) - np.searchsorted(xs, c, side="right")
+        interior[iz, iy, :] = beyond % 2 == 1
+    for a in range(3):
+        for (ib, ic), hits in lines[a].items():
+            for x, _ in hits:
+                k = int(round((x - grid.lo) / grid.h)) - 1
+                if 0 <= k < N and abs(x - c[k]) <= SIDE_TOL:
+                    idx = [0, 0, 0]
+                    others = [b for b in range(3) if b != a]
+                    idx[a], idx[others[0]], idx[others[1]] = k, ib, ic
+                    on[idx[2], idx[1], idx[0]] = True
+    return on, interior
 
 
 # ----------------------------------------------------------------------------- radial function
@@ -163,6 +218,8 @@ class Nodes:
                 t = np.arange(cv.m, dtype=np.float64)
                 x = cv.X(t)
                 n, w = cv.normal_and_shape(t)
+            elif is_mesh(surf):
+                x, n, w = trimesh_of(surf).vertex_geometry()
             else:
                 u = node_directions(iface.dim, surf.n_nodes)
                 G, _, _ = radial(surf, u)
@@ -222,6 +279,11 @@ def classify(iface, grid):
     chunk = 1 << 20
     for s, surf in enumerate(iface.surfaces):
         for i in range(0, pts.shape[0], chunk):
+            if is_mesh(surf):
+                on, interior = mesh_sides(trimesh_of(surf), grid)
+                tissue = on | (interior if surf.orient == 1 else ~interior)
+                out[s] = tissue.ravel()
+                break
             if is_spline(surf):
                 out[s, i:i + chunk] = curve_of(surf).tissue(pts[i:i + chunk])
             else:
@@ -236,6 +298,8 @@ def check_box_clearance(iface, grid, margin_cells=3):
     for surf in iface.surfaces:
         if is_spline(surf):
             _, x = curve_of(surf).samples(16)
+        elif is_mesh(surf):
+            x = trimesh_of(surf).V
         else:
             u = node_directions(iface.dim, max(surf.n_nodes, 4096 if iface.dim == 3 else 1024))
             G, _, _ = radial(surf, u)
@@ -322,6 +386,40 @@ def _spline_roots_on_arms(cv, p0, axis, h, tol=1e-12):
     return frac, tpar
 
 
+def _mesh_roots_on_arms(tm, grid, idx0, p0, axis, h):
+    """Crossing of a triangle mesh with each arm from p0 to p0 + h e_axis, moved onto the local
+    quadratic patch of the triangle it passes through: arm fraction, n and W.  An end point on
+    the surface is the crossing itself; otherwise exactly one crossing may lie on the arm."""
+    lines = mesh_lines(tm, grid)[axis]
+    others = [b for b in range(3) if b != axis]
+    c = grid_coords(grid)
+    n_arm = p0.shape[0]
+    frac = np.zeros(n_arm)
+    nn = np.zeros((n_arm, 3))
+    WW = np.zeros((n_arm, 3, 3))
+    for i in range(n_arm):
+        hits = lines.get((int(idx0[i, others[0]]), int(idx0[i, others[1]])), [])
+        k0 = int(idx0[i, axis])
+        x0, x1 = c[k0], c[k0 + 1]
+        end = [(x, t) for x, t in hits if abs(x - x0) <= SIDE_TOL or abs(x - x1) <= SIDE_TOL]
+        if end:
+            x, t = min(end, key=lambda e: min(abs(e[0] - x0), abs(e[0] - x1)))
+            at0 = abs(x - x0) <= SIDE_TOL
+            z = p0[i].copy()
+            if not at0:
+                z[axis] = x1
+            frac[i] = 0.0 if at0 else 1.0
+            nn[i], WW[i] = tm.patch_geometry(t, z)
+            continue
+        inarm = [(x, t) for x, t in hits if x0 - SIDE_TOL <= x <= x1 + SIDE_TOL]
+        if len(inarm) != 1:
+            raise GeometryError("grid arm crossed more than once")
+        x, t = inarm[0]
+        z, s, nn[i], WW[i] = tm.onto_patch(t, p0[i], axis, x - x0, h)
+        frac[i] = s / h
+    return frac, nn, WW
+
+
 class Crossings:
     """All grid-arm / boundary intersections.
 
@@ -336,6 +434,7 @@ class Crossings:
         shape = (N,) * d
         inside_all = np.all(side, axis=0)
         surf_l, axis_l, z_l, pin_l, pout_l, tparam_l = [], [], [], [], [], []
+        mesh_nw = {}
         for s, surf in enumerate(iface.surfaces):
             sd = side[s].reshape(shape)
             others = np.all(np.delete(side, s, axis=0), axis=0).reshape(shape) \
@@ -359,11 +458,15 @@ class Crossings:
                 if is_spline(surf):
                     t, tp = _spline_roots_on_arms(curve_of(surf), p0, a, h)
                     tparam_l.append(tp)
+                elif is_mesh(surf):
+                    t, mn, mW = _mesh_roots_on_arms(trimesh_of(surf), grid, idx0, p0, a, h)
+                    tparam_l.append(np.full(len(t), np.nan))
+                    mesh_nw[(s, a)] = (mn, mW)
                 else:
                     t = _root_on_arm(surf, p0, a, h)
                     tparam_l.append(np.full(len(t), np.nan))
                 # reject arms that the surface crosses more than once
-                if not is_spline(surf):
+                if not is_spline(surf) and not is_mesh(surf):
                     ts = np.linspace(0.0, 1.0, 9)
                     sides = []
                     for tt in ts:
@@ -402,7 +505,12 @@ class Crossings:
         self.W = np.zeros((self.count, d, d))
         for s, surf in enumerate(iface.surfaces):
             m = self.surf == s
-            if np.any(m):
+            if np.any(m) and is_mesh(surf):
+                for a in range(d):
+                    ma = m & (self.axis == a)
+                    if np.any(ma):
+                        self.n[ma], self.W[ma] = mesh_nw[(s, a)]
+            elif np.any(m):
                 if is_spline(surf):
                     self.n[m], self.W[m] = curve_of(surf).normal_and_shape(self.tparam[m])
                 else:

@@ -208,6 +208,80 @@ def _radius(surface: Surface, u):
     return E * (1.0 + P)
 
 
+def icosphere(level: int):
+    """Unit-sphere triangulation: the icosahedron with each triangle split into 4 per level
+    (10 4^level + 2 vertices), triangles oriented with outward (counter-clockwise) normals."""
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    V = [(-1, p, 0), (1, p, 0), (-1, -p, 0), (1, -p, 0), (0, -1, p), (0, 1, p), (0, -1, -p), (0, 1, -p),
+         (p, 0, -1), (p, 0, 1), (-p, 0, -1), (-p, 0, 1)]
+    V = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                mid[key] = len(V) - 1
+            return mid[key]
+
+        G = []
+        for a, b, c in F:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            G += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = G
+    return np.array(V), np.array(F, dtype=np.int32)
+
+
+def _rotation(seed):
+    """Seeded rotation matrix (QR of a Gaussian matrix, determinant +1)."""
+    Q, R = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    Q = Q * np.sign(np.diag(R))[None, :]
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def mesh_surface(points, tris, orient=+1) -> Surface:
+    """A closed, consistently oriented triangle mesh (either orientation)."""
+    P = np.ascontiguousarray(points, dtype=np.float64)
+    Tr = np.ascontiguousarray(tris, dtype=np.int32)
+    return Surface((1.0, 1.0, 1.0), orient, P.shape[0], [], kind="mesh", points=P, tris=Tr)
+
+
+def mesh_of(surface: Surface, level: int, seed=5, flip=False) -> Surface:
+    """Triangle mesh of an analytic star-shaped surface: the icosphere's vertex directions,
+    rotated by a seeded rotation, placed at the surface's radius (triangles reversed if flip)."""
+    U, F = icosphere(level)
+    U = U @ _rotation(seed).T
+    X = np.stack([_radius(surface, u) * u for u in U])
+    if flip:
+        F = F[:, ::-1]
+    return mesh_surface(X, F, surface.orient)
+
+
+def mesh_sphere(R=0.5, level=4, seed=5) -> Interface:
+    return Interface(3, [mesh_of(Surface((R, R, R), +1, 0, []), level, seed)])
+
+
+def mesh_ellipsoid(a=0.9, b=0.7, c=0.5, level=5, seed=5, flip=False) -> Interface:
+    return Interface(3, [mesh_of(Surface((a, b, c), +1, 0, []), level, seed, flip)])
+
+
+def mesh_perturbed_sphere(R=0.8, eps=0.1, level=5, seed=5) -> Interface:
+    return Interface(3, [mesh_of(perturbed_sphere(R, eps, 1).surfaces[0], level, seed)])
+
+
+def mesh_shell(outer=(0.9, 0.7, 0.6), inner_scale=0.6, level_out=5, level_in=4, seed=1) -> Interface:
+    """The thick shell with both walls given as triangle meshes."""
+    sh = thick_shell(outer, inner_scale, 1000, seed)
+    return Interface(3, [mesh_of(sh.surfaces[0], level_out, seed + 4), mesh_of(sh.surfaces[1], level_in, seed + 5)])
+
+
 def stimulus_center(iface: Interface, seed=0):
     """Seeded centre of the initial V=1 ball: inside the tissue, mid-wall for a shell."""
     rng = np.random.default_rng(seed)
