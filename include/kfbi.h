@@ -71,7 +71,13 @@ enum { KFBI_SURF_ANALYTIC = 0, KFBI_SURF_SPLINE = 1, KFBI_SURF_MESH = 2 };
  *   either direction); the library interpolates them with the periodic cubic spline in the
  *   node index (C2, closed) and reads normals, curvature and grid-line crossings off it.
  *   axes, coef and exps are ignored; the points are copied during kfbi_setup.
- * kind = KFBI_SURF_MESH is reserved for closed triangle meshes (3D). */
+ * kind = KFBI_SURF_MESH (3D only; Sec. 6, local coordinate systems on the triangle grid): a
+ *   closed, consistently oriented triangle mesh, vertices points[3*j + a] (the n_nodes nodes)
+ *   and triangles tris[3*k + c] (n_tris >= 4, host memory, either orientation; every edge
+ *   shared by exactly two triangles).  Normals and shape operators come from quadratic height
+ *   functions fitted over each vertex's one-ring; grid-line crossings from the flat triangles,
+ *   moved onto the quadratic through each triangle's six boundary points (its vertices and
+ *   the three across its edges).  An open or inconsistently oriented mesh gives KFBI_EGEOM. */
 typedef struct {
   double axes[3];
   int32_t orient;

@@ -12,8 +12,12 @@
 // phi = orient (|x| - R(x/|x|)), with analytic gradient and Hessian.  2D curves given by their
 // nodes use the periodic cubic spline through them (host_spline.cpp): grid nodes take their
 // side from the parity of the crossings on their grid row, crossings are the spline's roots on
-// the grid lines, and the transfer runs in the spline parameter.
+// the grid lines, and the transfer runs in the spline parameter.  3D surfaces given as
+// triangle meshes (host_mesh.cpp) take their sides from crossing parity on the grid lines and
+// their crossings, normals and shape operators from the mesh's local quadratic coordinate
+// systems.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -456,7 +460,8 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   t.surf.assign(iface.surf, iface.surf + iface.n_surfaces);
   t.offsets.assign(1, 0);
   std::vector<SplineCurve2> spl(t.surf.size());
-  std::vector<char> is_spl(t.surf.size(), 0);
+  std::vector<TriMesh3> msh(t.surf.size());
+  std::vector<char> is_spl(t.surf.size(), 0), is_msh(t.surf.size(), 0);
   for (size_t si = 0; si < t.surf.size(); ++si) {
     const auto &s = t.surf[si];
     if (s.n_nodes < 8 || (s.orient != 1 && s.orient != -1)) throw std::invalid_argument("surface descriptor");
@@ -471,6 +476,13 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
         if (!std::isfinite(s.points[j])) throw std::invalid_argument("spline points must be finite");
       spl[si].build(s.points, s.n_nodes, s.orient);
       is_spl[si] = 1;
+    } else if (s.kind == KFBI_SURF_MESH) {
+      if (d != 3) throw std::invalid_argument("triangle meshes are three-dimensional");
+      if (!s.points || !s.tris || s.n_tris < 4) throw std::invalid_argument("mesh without points or triangles");
+      for (int64_t j = 0; j < 3 * s.n_nodes; ++j)
+        if (!std::isfinite(s.points[j])) throw std::invalid_argument("mesh points must be finite");
+      msh[si].build(s.points, s.n_nodes, s.tris, s.n_tris, s.orient);
+      is_msh[si] = 1;
     } else {
       throw std::invalid_argument("surface kind");
     }
@@ -492,6 +504,12 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
         for (int a = 0; a < 2; ++a)
           if (x[a] > grid.hi - 3 * h || x[a] < grid.lo + 3 * h) throw GeometryError{"interface closer than 3h to the box"};
       }
+      continue;
+    }
+    if (is_msh[si]) {
+      for (int64_t j = 0; j < 3 * s.n_nodes; ++j)
+        if (s.points[j] > grid.hi - 3 * h || s.points[j] < grid.lo + 3 * h)
+          throw GeometryError{"interface closer than 3h to the box"};
       continue;
     }
     const int64_t m = std::max<int64_t>(s.n_nodes, d == 3 ? 4096 : 1024);
@@ -516,6 +534,11 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
       if (is_spl[s]) {
         for (int a = 0; a < 2; ++a) t.X[i * 2 + a] = t.surf[s].points[2 * j + a];
         spl[s].normal_shape((double)j, &t.nrm[i * 2], &t.W[i * 4]);
+        continue;
+      }
+      if (is_msh[s]) {
+        for (int a = 0; a < 3; ++a) t.X[i * 3 + a] = t.surf[s].points[3 * j + a];
+        msh[s].vertex_geometry(j, &t.nrm[i * 3], &t.W[i * 9]);
         continue;
       }
       double u[3], G, g[3], H[9];
@@ -565,8 +588,44 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
       }
     }
   }
+  // meshes: crossings of every grid line per axis; a node's side is the parity of the x-line
+  // crossings beyond it, and a node within kSideTol of a crossing on any of its three lines
+  // lies on the surface (tissue; the crossing point of its arms that change side)
+  std::vector<std::array<std::vector<std::vector<std::pair<double, int64_t>>>, 3>> mlines(S_);
   for (int s = 0; s < S_; ++s) {
-    if (is_spl[s]) continue;
+    if (!is_msh[s]) continue;
+    for (int a = 0; a < 3; ++a) msh[s].grid_line_hits(a, lo, h, N, mlines[s][a]);
+    std::vector<char> on(total, 0);
+    for (int a = 0; a < 3; ++a) {
+      const int bx = a == 0 ? 1 : 0, cx = a == 2 ? 1 : 2;
+      for (int64_t ic = 0; ic < N; ++ic)
+        for (int64_t ib = 0; ib < N; ++ib)
+          for (const auto &hit : mlines[s][a][ic * N + ib]) {
+            const int64_t k = (int64_t)std::llround((hit.first - lo) / h) - 1;
+            if (k < 0 || k >= N || std::fabs(hit.first - (lo + h * (double)(k + 1))) > kSideTol) continue;
+            int64_t idx[3];
+            idx[a] = k;
+            idx[bx] = ib;
+            idx[cx] = ic;
+            on[(idx[2] * N + idx[1]) * N + idx[0]] = 1;
+          }
+    }
+    for (int64_t iz = 0; iz < N; ++iz)
+      for (int64_t iy = 0; iy < N; ++iy) {
+        const auto &ln = mlines[s][0][iz * N + iy];
+        for (int64_t ix = 0; ix < N; ++ix) {
+          const double x = lo + h * (double)(ix + 1);
+          size_t beyond = 0;
+          for (const auto &hit : ln)
+            if (hit.first > x) ++beyond;
+          const int64_t lin = (iz * N + iy) * N + ix;
+          const bool interior = (beyond & 1) != 0;
+          side[s][lin] = (on[lin] || interior == (t.surf[s].orient == 1)) ? 1 : 0;
+        }
+      }
+  }
+  for (int s = 0; s < S_; ++s) {
+    if (is_spl[s] || is_msh[s]) continue;
 #pragma omp parallel for schedule(static)
     for (int64_t lin = 0; lin < total; ++lin) {
       int64_t r = lin;
@@ -584,6 +643,7 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
 
   // -- grid-arm intersections, ordered by (surface, axis, lower node)
   int64_t stride[3] = {1, N, N * N};
+  std::vector<double> mesh_cn, mesh_cW;        // n, W of mesh crossings, in crossing order
   for (int s = 0; s < S_; ++s)
     for (int a = 0; a < d; ++a)
       for (int64_t lin = 0; lin < total; ++lin) {
@@ -636,6 +696,60 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
           t.c_pout.push_back(in0 ? lin1 : lin);
           for (int b = 0; b < d; ++b) t.c_z.push_back(z[b]);
           t.c_t.push_back(tp);
+          continue;
+        }
+        if (is_msh[s]) {
+          // the crossing on the flat triangle the arm passes through, moved onto that
+          // triangle's six-point patch; an end point on the surface is the crossing itself
+          const int bx = a == 0 ? 1 : 0, cx = a == 2 ? 1 : 2;
+          int64_t kk[3];
+          {
+            int64_t r = lin;
+            for (int b = 0; b < 3; ++b) {
+              kk[b] = r % N;
+              r /= N;
+            }
+          }
+          const auto &ln = mlines[s][a][kk[cx] * N + kk[bx]];
+          const double x0 = p[a], x1 = lo + h * (double)(ka + 2);
+          double best = 0.0, cn[3], cW[9];
+          int64_t tri = -1;
+          bool at_end = false, at0 = false;
+          for (const auto &hit : ln) {
+            const double dd = std::min(std::fabs(hit.first - x0), std::fabs(hit.first - x1));
+            if ((std::fabs(hit.first - x0) <= kSideTol || std::fabs(hit.first - x1) <= kSideTol) &&
+                (!at_end || dd < best)) {
+              at_end = true;
+              best = dd;
+              tri = hit.second;
+              at0 = std::fabs(hit.first - x0) <= kSideTol;
+            }
+          }
+          double z[3] = {p[0], p[1], p[2]};
+          if (at_end) {
+            if (!at0) z[a] = x1;
+            msh[s].patch_geometry(tri, z, cn, cW);
+          } else {
+            int cnt = 0;
+            double along = 0.0;
+            for (const auto &hit : ln)
+              if (hit.first >= x0 - kSideTol && hit.first <= x1 + kSideTol) {
+                ++cnt;
+                along = hit.first;
+                tri = hit.second;
+              }
+            if (cnt != 1) throw GeometryError{"grid arm crossed more than once"};
+            z[a] += msh[s].onto_patch(tri, p, a, along - x0, h, cn, cW);
+          }
+          t.c_surf.push_back(s);
+          t.c_axis.push_back(a);
+          const bool in0 = side[s][lin] != 0;
+          t.c_pin.push_back(in0 ? lin : lin1);
+          t.c_pout.push_back(in0 ? lin1 : lin);
+          for (int b = 0; b < 3; ++b) t.c_z.push_back(z[b]);
+          t.c_t.push_back(std::nan(""));
+          for (int b = 0; b < 3; ++b) mesh_cn.push_back(cn[b]);
+          for (int b = 0; b < 9; ++b) mesh_cW.push_back(cW[b]);
           continue;
         }
         auto f = [&](double tt, double &ft, double &dft) {
@@ -694,8 +808,12 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   t.nc = (int64_t)t.c_surf.size();
   t.c_n.resize(t.nc * d);
   t.c_W.resize(t.nc * d * d);
-  for (int64_t c = 0; c < t.nc; ++c) {
-    if (is_spl[t.c_surf[c]])
+  for (int64_t c = 0, mc = 0; c < t.nc; ++c) {
+    if (is_msh[t.c_surf[c]]) {
+      std::copy(&mesh_cn[3 * mc], &mesh_cn[3 * mc] + 3, &t.c_n[c * 3]);
+      std::copy(&mesh_cW[9 * mc], &mesh_cW[9 * mc] + 9, &t.c_W[c * 9]);
+      ++mc;
+    } else if (is_spl[t.c_surf[c]])
       spl[t.c_surf[c]].normal_shape(t.c_t[c], &t.c_n[c * d], &t.c_W[c * d * d]);
     else
       normal_shape(t.surf[t.c_surf[c]], d, &t.c_z[c * d], &t.c_n[c * d], &t.c_W[c * d * d]);

@@ -66,6 +66,36 @@ struct SplineCurve2 {
                        std::vector<std::vector<std::pair<double, double>>> &out) const;
 };
 
+// Closed, consistently oriented triangle mesh in 3D with the local coordinate systems of the
+// method: a quadratic height function fitted over each vertex's one-ring (normals and shape
+// operators at the nodes) and, per triangle, the quadratic height function through its six
+// boundary points (its vertices and the three vertices across its edges) over its plane.
+struct TriMesh3 {
+  int64_t m = 0, nt = 0;
+  std::vector<double> V;             // m*3
+  std::vector<int64_t> F, opp;       // nt*3 vertices; vertex across edge e = (F[e], F[e+1])
+  std::vector<double> cr;            // nt*3 area-weighted normals out of the tissue
+  std::vector<double> vacc;          // m*3 sum of cr over each vertex's triangles
+  std::vector<int64_t> nbr_ptr, nbr; // one-ring of each vertex (CSR, ascending)
+  double sigma = 1;                  // orient * sign(enclosed volume)
+  struct Patch {
+    double o[3], R[9], c[6];         // origin, frame columns (t1, t2, n), height coefficients
+  };
+  std::vector<Patch> patch;
+
+  // Throws GeometryError for an open, inconsistently oriented or degenerate mesh.
+  void build(const double *pts, int64_t m, const int32_t *tris, int64_t nt, int orient);
+  void vertex_geometry(int64_t i, double *n, double *W) const;
+  void patch_geometry(int64_t t, const double *z, double *n, double *W) const;
+  // Crossing of the line p + s e_axis with triangle t (flat crossing at s_flat) moved onto the
+  // triangle's patch, s clamped to [0, h]; returns s and n, W there.
+  double onto_patch(int64_t t, const double *p, int axis, double s_flat, double h, double *n, double *W) const;
+  // Crossings of the grid lines parallel to `axis` as (coordinate along the axis, triangle),
+  // per line (ic * N + ib over the other two axes b < c), sorted by coordinate.
+  void grid_line_hits(int axis, double lo, double h, int64_t N,
+                      std::vector<std::vector<std::pair<double, int64_t>>> &out) const;
+};
+
 // Throws GeometryError on geometric failure, std::invalid_argument on bad input.
 void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const kfbi_coeffs &co,
                        HostTables &t);

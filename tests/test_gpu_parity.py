@@ -66,6 +66,11 @@ def problems(name):
         "heart_spline_bido_64": (W.heart2d(128), W.box(2, 64), W.bidomain_coeffs(2, P_BIDO, 0.01)),
         "circle_spline_cw_64": (W.spline_circle(0.55, 100, clockwise=True), W.box(2, 64),
                                 W.scalar_coeffs(2, 1.0, 400.0)),
+        # 3D boundaries given only as closed triangle meshes
+        "mesh_ellipsoid_64": (W.mesh_ellipsoid(level=4), W.box(3, 64), W.scalar_coeffs(3, 1.0, 400.0)),
+        "mesh_shell_64": (W.mesh_shell(level_out=4, level_in=3), W.box(3, 64), W.bidomain_coeffs(3, P_BIDO, 0.01)),
+        "mesh_psphere_bido_32": (W.mesh_perturbed_sphere(level=3), W.box(3, 32),
+                                 W.Coeffs(2, [[3.0, 0.5, 0.5], [2.0, 1.0, 1.0]], 200.0)),
     }
     iface, grid, co = cases[name]
     say(f"[setup] {name}")
@@ -104,7 +109,8 @@ def test_box_solve_in_place_and_ragged_tile():
 
 @pytest.mark.parametrize("name", ["star2d_64", "star2d_128", "ellipsoid_64", "shell_64", "psphere_32",
                                   "star2d_64_aniso", "ellipsoid_64_aniso", "shell_64_aniso",
-                                  "heart_spline_128", "heart_spline_bido_64", "circle_spline_cw_64"])
+                                  "heart_spline_128", "heart_spline_bido_64", "circle_spline_cw_64",
+                                  "mesh_ellipsoid_64", "mesh_shell_64", "mesh_psphere_bido_32"])
 def test_apply_f64_matches_oracle(name):
     g, o, iface, grid, co = problems(name)
     psi = np.random.default_rng(3).uniform(-1, 1, size=(co.ncomp, g.M))
@@ -116,7 +122,7 @@ def test_apply_f64_matches_oracle(name):
     assert e < 1e-10, e
 
 
-@pytest.mark.parametrize("name", ["star2d_128", "shell_64", "shell_64_aniso", "heart_spline_128"])
+@pytest.mark.parametrize("name", ["star2d_128", "shell_64", "shell_64_aniso", "heart_spline_128", "mesh_shell_64"])
 def test_apply_f32_error_is_stated_bound(name):
     g, o, iface, grid, co = problems(name)
     psi = np.random.default_rng(4).uniform(-1, 1, size=(co.ncomp, g.M))
@@ -497,6 +503,56 @@ def test_bidomain_on_spline_heart_matches_oracle():
     Vo, qo, psi = V0.copy(), q0.copy(), None
     for s_ in range(4):
         say(f"[bidomain spline] step {s_}")
+        info = bd.step(V, q, hist, 0.01, I_stim=Is)
+        Vo, qo, uo, psi, infoo = obd.step(o, P_BIDO, Vo, qo, 0.01, psi0=psi, tol=1e-12, I_stim=stim)
+        eV = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+        say(f"    V err {eV:.2e} iters {info['iters']} / {infoo['iters']}")
+        assert eV < 1e-9
+    bd.close()
+
+
+# ----------------------------------------------------------------------------- triangle-mesh boundaries (f3)
+
+def _mms3(o, grid, kappa):
+    """u = e^x sin(pi y) cos z: source on the grid and Neumann data at the oracle's nodes."""
+    pts = ogeo.grid_points(grid)
+    ue = np.exp(pts[:, 0]) * np.sin(np.pi * pts[:, 1]) * np.cos(pts[:, 2])
+    X, n = o.nodes.X, o.nodes.n
+    g = np.stack([np.exp(X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.cos(X[:, 2]),
+                  np.pi * np.exp(X[:, 0]) * np.cos(np.pi * X[:, 1]) * np.cos(X[:, 2]),
+                  -np.exp(X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(X[:, 2])], 1)
+    return ((np.pi ** 2 + kappa) * ue)[None], np.sum(n * g, 1)[None], ue
+
+
+def test_solve_neumann_on_mesh_ellipsoid_matches_oracle():
+    """An ellipsoid given only as a 2562-vertex triangle mesh: the GPU solve equals the oracle's
+    and keeps the oracle's pinned accuracy (max error below 0.3 h^2)."""
+    g, o, iface, grid, co = problems("mesh_ellipsoid_64")
+    f, gn, ue = _mms3(o, grid, co.kappa)
+    say("[solve f64] mesh_ellipsoid_64")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-12)
+    u = u.cpu().numpy()
+    uo, psio, infoo = o.solve_neumann(gn, f, tol=1e-12)
+    ins = o.inside
+    say(f"    iters gpu {info['iters']} oracle {infoo['iters']}; u err {rel(u[0][ins], uo[0][ins]):.2e}")
+    assert info["rel_resid"] <= 1e-12
+    assert rel(u[0][ins], uo[0][ins]) < 1e-9
+    assert np.max(np.abs(u[0] - ue)[ins]) < 0.3 * grid.h ** 2
+
+
+def test_bidomain_on_mesh_perturbed_sphere_matches_oracle():
+    """Anisotropic coupled bidomain steps with a paired stimulus on a perturbed sphere given as a
+    triangle mesh."""
+    g, o, iface, grid, co = problems("mesh_psphere_bido_32")
+    stim = W.virtual_electrode(grid, (-0.3, 0.0, 0.0), (0.3, 0.0, 0.0), radius=0.25, amplitude=10.0)
+    V0, q0 = obd.initial_state(grid, (0.0, 0.2, 0.1), radius=0.3)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+    V, q = T(V0), T(q0)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    Is = T(stim)
+    Vo, qo, psi = V0.copy(), q0.copy(), None
+    for s_ in range(3):
+        say(f"[bidomain mesh] step {s_}")
         info = bd.step(V, q, hist, 0.01, I_stim=Is)
         Vo, qo, uo, psi, infoo = obd.step(o, P_BIDO, Vo, qo, 0.01, psi0=psi, tol=1e-12, I_stim=stim)
         eV = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))

@@ -40,6 +40,14 @@ def test_error_codes_without_gpu():
         K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.Coeffs(1, [[30.0, -5.0]], 1.0), host_only=True)
     assert e.value.code == K.KFBI_EINVAL
     K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.Coeffs(1, [[30.0, 5.0]], 1.0), host_only=True).close()
+    # node-given boundaries: a mesh with a hole, a spline in 3D
+    V, F = W.icosphere(2)
+    with pytest.raises(K.KfbiError) as e:
+        K.Problem(W.Interface(3, [W.mesh_surface(0.5 * V, F[:-1])]), W.box(3, 32), W.scalar_coeffs(3), host_only=True)
+    assert e.value.code == K.KFBI_EGEOM
+    with pytest.raises(K.KfbiError) as e:
+        K.Problem(W.Interface(3, [W.mesh_surface(0.5 * V, F)]), W.box(2, 32), W.scalar_coeffs(2), host_only=True)
+    assert e.value.code == K.KFBI_EINVAL
     # a host-only problem refuses device calls before touching the GPU
     p = K.Problem(W.star2d(n_nodes=64), W.box(2, 32), W.scalar_coeffs(2), host_only=True)
     rc = L.kfbi_apply(p.handle, ctypes.c_void_p(8), ctypes.c_void_p(8), 0, None)
@@ -58,12 +66,30 @@ CASES = {
     # an interface node on a grid node: the circle's node j = 0 is the grid node (x_24, y_16)
     "circle_spline_node_on_grid_32": (W.spline_star(-1.2 + 24 * (2.4 / 32), 0.0, 5, 64), W.box(2, 32),
                                       W.scalar_coeffs(2)),
+    "mesh_sphere_32": (W.mesh_sphere(0.5, 3), W.box(3, 32), W.scalar_coeffs(3)),
+    "mesh_ellipsoid_flipped_32": (W.mesh_ellipsoid(level=3, flip=True), W.box(3, 32), W.scalar_coeffs(3)),
+    "mesh_shell_64": (W.mesh_shell(level_out=4, level_in=3), W.box(3, 64),
+                      W.Coeffs(2, [[1.0] * 3, [2.0] * 3], 200.0)),
+    "mesh_vertex_on_grid_32": (None, W.box(3, 32), W.scalar_coeffs(3)),
 }
+
+
+def _vertex_on_grid(grid):
+    """The level-3 mesh sphere with the vertex nearest a grid node moved onto that node."""
+    s = W.mesh_sphere(0.5, 3).surfaces[0]
+    P = s.points.copy()
+    c = grid.lo + grid.h * np.arange(1, grid.cells)
+    node = c[np.argmin(np.abs(c[:, None, None] - P[None]), axis=0)]     # nearest grid coordinates
+    j = int(np.argmin(np.sum((node - P) ** 2, axis=1)))
+    P[j] = node[j]
+    return W.Interface(3, [W.mesh_surface(P, s.tris)])
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_setup_tables_match_oracle(name):
     iface, grid, co = CASES[name]
+    if iface is None:
+        iface = _vertex_on_grid(grid)
     P = K.Problem(iface, grid, co, host_only=True)
     O = ok.Problem(iface, grid, co)
     assert (P.M, P.n_crossings, P.n_irregular) == (O.M, O.cross.count, len(O.irregular))
