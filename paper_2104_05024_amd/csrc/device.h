@@ -119,7 +119,7 @@ struct DevProblem {
   int tile_w[2][3] = {{1, 1, 1}, {1, 1, 1}};
 
   bool profile = false;
-  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse;
+  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse, t_dst_last_sparse;
   hipStream_t stream = nullptr;
 
   template <typename T>

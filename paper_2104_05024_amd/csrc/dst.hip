@@ -566,13 +566,18 @@ struct ModeHook {
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
 // In 2D, blockIdx.y may index the problems of a batch of equal-size fields at stride pstride,
 // each with its own mode parameters msv[problem] (msv = nullptr: one problem, parameters ms).
-template <typename T, int M, int NC, int DIM, int W = 1>
+// In 3D, zin / zout (optional, [z] bytes) name the planes that may be nonzero on input (the
+// others are not read) and the planes needed on output (the others are not written).
+// ZM: the plane-masked form (a kernel of its own, so that traces tell the two apart).
+template <typename T, int M, int NC, int DIM, int W = 1, bool ZM = false>
 __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__restrict__ ain, T *__restrict__ a,
                                                                      int64_t P, int64_t comp_stride,
                                                                   ModeScale ms0, const C2<T> *__restrict__ tw,
                                                                   const T *__restrict__ sp,
                                                                   const ModeScale *__restrict__ msv = nullptr,
-                                                                  int64_t pstride = 0) {
+                                                                  int64_t pstride = 0,
+                                                                  const uint8_t *__restrict__ zin = nullptr,
+                                                                  const uint8_t *__restrict__ zout = nullptr) {
   using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
@@ -593,7 +598,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   T *base = a + boff;
   const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
-  Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid);
+  Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid, ZM ? zin : nullptr);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
   C2<T> *mine = sbuf + pr * PADM;
@@ -623,7 +628,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
   dst_pair<T, M>(mine, lane, tw, sp, mh);
-  Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
+  Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, ZM ? zout : nullptr);
 }
 
 // DST along contiguous rows listed in `rows` (indices into the flattened [comp][..] row list),
@@ -714,13 +719,20 @@ void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8
 // fused last-axis pass; nprob > 1 only in 2D (batched groups with per-problem msv)
 template <typename T, int M, int W>
 void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms,
-                 const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st) {
+                 const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
+                 const uint8_t *zin = nullptr, const uint8_t *zout = nullptr) {
   using Sh = Shape<T, M, W>;
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
   if (dim == 3) {
-    if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
-    else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+    if (zin || zout) {
+      if (!zin || !zout) throw std::invalid_argument("plane masks come in pairs");
+      if (ncomp == 2) k_dst_last<T, M, 2, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, zin, zout);
+      else k_dst_last<T, M, 1, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, zin, zout);
+    } else {
+      if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+      else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+    }
   } else {
     if (ncomp == 2) k_dst_last<T, M, 2, 2, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, msv, pstride);
     else k_dst_last<T, M, 1, 2, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, msv, pstride);
@@ -743,10 +755,10 @@ void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const 
 template <typename T, int M>
 void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
                const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-               const T *in = nullptr) {
+               const T *in = nullptr, const uint8_t *zin = nullptr, const uint8_t *zout = nullptr) {
   if (!in) in = a;
-  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
-  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st);
+  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout);
+  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout);
 }
 
 template <typename T>
@@ -825,9 +837,11 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   tic(p.t_dst_y_sparse);
   pass_y<T, M>(w[1], X, Y, P, cs, p.ncomp, p.mask_in, nullptr, tw, sp, st, p.planes_in);
   toc(p.t_dst_y_sparse);
-  tic(p.t_dst_last);
-  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, Y);
-  toc(p.t_dst_last);
+  tic(p.t_dst_last_sparse);
+  // planes without rhs rows are zero in Y (not read); only planes with stencil rows are used
+  // by the inverse passes (only those are written)
+  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, Y, p.planes_in, p.planes_out);
+  toc(p.t_dst_last_sparse);
   tic(p.t_dst_y_sparse);
   pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st, p.planes_out);
   toc(p.t_dst_y_sparse);
