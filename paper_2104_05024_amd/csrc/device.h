@@ -83,6 +83,12 @@ struct Timer {
   }
 };
 
+// A set of z planes as bits (plane z = bit z % 64 of word z / 64; up to 1024 planes), passed to
+// kernels by value so that testing a plane needs no memory access.
+struct PlaneBits {
+  uint64_t w[16] = {};
+};
+
 struct DevProblem {
   HostTables ht;
   bool on_device = false;
@@ -104,8 +110,9 @@ struct DevProblem {
   bool sparse = true;
   int32_t *rows_in = nullptr, *rows_out = nullptr;
   int64_t n_rows_in = 0, n_rows_out = 0;
-  uint8_t *mask_in = nullptr, *mask_out = nullptr;
+  uint64_t *mask_in = nullptr, *mask_out = nullptr;     // [z][16] bit rows: y rows with rhs / stencil nodes
   uint8_t *planes_in = nullptr, *planes_out = nullptr;   // [z]: plane holds any rhs / stencil row
+  PlaneBits planes_in_bits, planes_out_bits;             // the same sets as bits
   double *lam = nullptr;       // (4/h^2) sin^2(k pi / 2M), k = 1..N
 
   PrecTables<double> f64;

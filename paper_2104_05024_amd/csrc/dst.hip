@@ -385,6 +385,37 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restr
   }
 }
 
+// Row predicates of the strided tile mover: every row; rows in a bit set read once from memory
+// (a uniform address: scalar loads; null means every row); rows in a bit set passed as a
+// kernel argument.  Bits avoid a memory load per row ahead of the tile's data loads.
+struct AllRows {
+  __device__ bool operator()(int) const { return true; }
+};
+template <int NW>
+struct BitRowsMem {
+  uint64_t w[NW];
+  __device__ explicit BitRowsMem(const uint64_t *__restrict__ p) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = p ? p[i] : ~uint64_t(0);
+  }
+  __device__ bool operator()(int r) const {
+    uint64_t x = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) x = (r >> 6) == i ? w[i] : x;
+    return (x >> (r & 63)) & 1;
+  }
+};
+template <int NW>
+struct BitRows {
+  const PlaneBits &b;
+  __device__ bool operator()(int r) const {
+    uint64_t x = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) x = (r >> 6) == i ? b.w[i] : x;
+    return (x >> (r & 63)) & 1;
+  }
+};
+
 // Tile mover for the strided passes: a tile is NR rows (stride RS elements) of TX consecutive
 // columns starting at column x0, for NC components (stride CS); element (row r, column xo,
 // component c) lives at LDS pair PAIR(xo, c), lane LANE(xo, c), position r + 1.
@@ -398,11 +429,12 @@ struct StridedTile {
   __device__ static int pair_of(int xo, int c) { return NC == 2 ? xo : (xo >> 1); }
   __device__ static int lane_sel(int xo, int c) { return NC == 2 ? c : (xo & 1); }
 
-  // rmask (optional): rows r with rmask[r] == 0 are known to be zero and are not read.
+  // rows: rows r with rows(r) false are known to be zero and are not read.
   // Vector path: NC = 1 pairs adjacent columns, so the elements of a 16-byte vector form whole
   // complex LDS words; NC = 2 loads both components of the same columns in one thread.
+  template <typename R = AllRows>
   __device__ static void load(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
-                              const uint8_t *__restrict__ rmask = nullptr) {
+                              const R &rows = R()) {
     if constexpr (VEC) {
       constexpr int VPR = TX / VW, NU = N * VPR, PU = (NU + NT - 1) / NT;
       V16<T> reg[PU][NC];
@@ -410,7 +442,7 @@ struct StridedTile {
       for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
         const int s = e % VPR, r = e / VPR;
-        const bool ok = e < NU && (!rmask || rmask[r]);
+        const bool ok = e < NU && rows(r);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           if (ok)
@@ -441,7 +473,7 @@ struct StridedTile {
       for (int i = 0; i < PER; ++i) {
         const int e = tid + i * NT;
         const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
-        reg[i] = (e < NE && x0 + xo < N && (!rmask || rmask[r])) ? base[c * CS + (int64_t)r * RS + x0 + xo] : T(0);
+        reg[i] = (e < NE && x0 + xo < N && rows(r)) ? base[c * CS + (int64_t)r * RS + x0 + xo] : T(0);
       }
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
@@ -454,9 +486,10 @@ struct StridedTile {
     }
   }
 
-  // rmask (optional): only rows r with rmask[r] != 0 are written
+  // rows: only rows r with rows(r) true are written
+  template <typename R = AllRows>
   __device__ static void store(T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
-                               const uint8_t *__restrict__ rmask = nullptr) {
+                               const R &rows = R()) {
     if constexpr (VEC) {
       constexpr int VPR = TX / VW, NU = N * VPR, PU = (NU + NT - 1) / NT;
       V16<T> reg[PU][NC];
@@ -487,7 +520,7 @@ struct StridedTile {
       for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
         const int s = e % VPR, r = e / VPR;
-        if (e < NU && (!rmask || rmask[r]))
+        if (e < NU && rows(r))
 #pragma unroll
           for (int c = 0; c < NC; ++c)
             *reinterpret_cast<V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW) = reg[i][c];
@@ -504,21 +537,21 @@ struct StridedTile {
       for (int i = 0; i < PER; ++i) {
         const int e = tid + i * NT;
         const int xo = e % TX, rc = e / TX, c = rc % NC, r = rc / NC;
-        if (e < NE && x0 + xo < N && (!rmask || rmask[r])) base[c * CS + (int64_t)r * RS + x0 + xo] = reg[i];
+        if (e < NE && x0 + xo < N && rows(r)) base[c * CS + (int64_t)r * RS + x0 + xo] = reg[i];
       }
     }
   }
 };
 
 // DST along y (3D): tile = 2 NP consecutive x columns of one (comp, z) plane.  in and out
-// may alias.  mask_in / mask_out (optional, [z][y] bytes): rows known to be zero on input are
-// not read; only rows flagged on output are written.  planes (optional, [z] bytes): planes
+// may alias.  mask_in / mask_out (optional, [z][16] bit rows, bit y of plane z): rows known to
+// be zero on input are not read; only rows flagged on output are written.  planes (optional, [z] bytes): planes
 // flagged 0 are skipped altogether (no reads, no writes).
 template <typename T, int M, int W = 1>
 __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restrict__ in, T *__restrict__ out,
                                                                int64_t P, int64_t comp_stride,
-                                                               const uint8_t *__restrict__ mask_in,
-                                                               const uint8_t *__restrict__ mask_out,
+                                                               const uint64_t *__restrict__ mask_in,
+                                                               const uint64_t *__restrict__ mask_out,
                                                                const uint8_t *__restrict__ planes,
                                                                const C2<T> *__restrict__ tw, const T *__restrict__ sp) {
   using Sh = Shape<T, M, W>;
@@ -528,10 +561,11 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restr
   const int x0 = blockIdx.x * 2 * Sh::NP, z = blockIdx.y, c = blockIdx.z;
   const int64_t off = c * comp_stride + (int64_t)z * Sh::N * P;
   if (planes && !planes[z]) return;   // nothing to read or write in this plane (whole workgroup)
-  Tl::load(in + off, P, 0, x0, sbuf, tid, mask_in ? mask_in + (int64_t)z * Sh::N : nullptr);
+  constexpr int NW = (Sh::N + 63) / 64;
+  Tl::load(in + off, P, 0, x0, sbuf, tid, BitRowsMem<NW>(mask_in ? mask_in + (int64_t)z * 16 : nullptr));
   __syncthreads();
   dst_pair<T, M>(sbuf + (tid / Sh::TPP) * Sh::PADM, tid % Sh::TPP, tw, sp);
-  Tl::store(out + off, P, 0, x0, sbuf, tid, mask_out ? mask_out + (int64_t)z * Sh::N : nullptr);
+  Tl::store(out + off, P, 0, x0, sbuf, tid, BitRowsMem<NW>(mask_out ? mask_out + (int64_t)z * 16 : nullptr));
 }
 
 using ModeScale = ModeParams;
@@ -566,18 +600,17 @@ struct ModeHook {
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
 // In 2D, blockIdx.y may index the problems of a batch of equal-size fields at stride pstride,
 // each with its own mode parameters msv[problem] (msv = nullptr: one problem, parameters ms).
-// In 3D, zin / zout (optional, [z] bytes) name the planes that may be nonzero on input (the
-// others are not read) and the planes needed on output (the others are not written).
-// ZM: the plane-masked form (a kernel of its own, so that traces tell the two apart).
+// ZM (3D): the plane-masked form, a kernel of its own so that traces tell the two apart; the
+// bit sets zin / zout name the planes that may be nonzero on input (the others are not read)
+// and the planes needed on output (the others are not written).
 template <typename T, int M, int NC, int DIM, int W = 1, bool ZM = false>
 __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__restrict__ ain, T *__restrict__ a,
                                                                      int64_t P, int64_t comp_stride,
                                                                   ModeScale ms0, const C2<T> *__restrict__ tw,
                                                                   const T *__restrict__ sp,
                                                                   const ModeScale *__restrict__ msv = nullptr,
-                                                                  int64_t pstride = 0,
-                                                                  const uint8_t *__restrict__ zin = nullptr,
-                                                                  const uint8_t *__restrict__ zout = nullptr) {
+                                                                  int64_t pstride = 0, PlaneBits zin = {},
+                                                                  PlaneBits zout = {}) {
   using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
@@ -598,7 +631,9 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   T *base = a + boff;
   const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
-  Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid, ZM ? zin : nullptr);
+  constexpr int NW = (N + 63) / 64;
+  if constexpr (ZM) Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zin});
+  else Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
   C2<T> *mine = sbuf + pr * PADM;
@@ -628,7 +663,8 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
   dst_pair<T, M>(mine, lane, tw, sp, mh);
-  Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, ZM ? zout : nullptr);
+  if constexpr (ZM) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
+  else Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
 
 // DST along contiguous rows listed in `rows` (indices into the flattened [comp][..] row list),
@@ -708,8 +744,8 @@ void launch_x(const T *in, bool in_plain, T *out, bool out_plain, int64_t rows, 
 }
 
 template <typename T, int M, int W>
-void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8_t *mask_in,
-              const uint8_t *mask_out, const uint8_t *planes, const C2<T> *tw, const T *sp, hipStream_t st) {
+void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint64_t *mask_in,
+              const uint64_t *mask_out, const uint8_t *planes, const C2<T> *tw, const T *sp, hipStream_t st) {
   using Sh = Shape<T, M, W>;
   const dim3 g((Sh::N + 2 * Sh::NP - 1) / (2 * Sh::NP), Sh::N, ncomp);
   k_dst_y<T, M, W><<<g, Sh::NT, 0, st>>>(in, out, P, cs, mask_in, mask_out, planes, tw, sp);
@@ -720,15 +756,15 @@ void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8
 template <typename T, int M, int W>
 void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms,
                  const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-                 const uint8_t *zin = nullptr, const uint8_t *zout = nullptr) {
+                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr) {
   using Sh = Shape<T, M, W>;
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
   if (dim == 3) {
     if (zin || zout) {
       if (!zin || !zout) throw std::invalid_argument("plane masks come in pairs");
-      if (ncomp == 2) k_dst_last<T, M, 2, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, zin, zout);
-      else k_dst_last<T, M, 1, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, zin, zout);
+      if (ncomp == 2) k_dst_last<T, M, 2, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
+      else k_dst_last<T, M, 1, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
     } else {
       if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
       else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
@@ -747,7 +783,7 @@ void pass_x(int w, const T *in, bool in_plain, T *out, bool out_plain, int64_t r
   else launch_x<T, M, 1>(in, in_plain, out, out_plain, rows, tw, sp, st);
 }
 template <typename T, int M>
-void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint8_t *mi, const uint8_t *mo,
+void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint64_t *mi, const uint64_t *mo,
             const C2<T> *tw, const T *sp, hipStream_t st, const uint8_t *planes = nullptr) {
   if (w == 2) launch_y<T, M, 2>(in, out, P, cs, ncomp, mi, mo, planes, tw, sp, st);
   else launch_y<T, M, 1>(in, out, P, cs, ncomp, mi, mo, planes, tw, sp, st);
@@ -755,7 +791,7 @@ void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const 
 template <typename T, int M>
 void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
                const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-               const T *in = nullptr, const uint8_t *zin = nullptr, const uint8_t *zout = nullptr) {
+               const T *in = nullptr, const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr) {
   if (!in) in = a;
   if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout);
   else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout);
@@ -840,7 +876,7 @@ void run_box_sparse(DevProblem &p, hipStream_t st) {
   tic(p.t_dst_last_sparse);
   // planes without rhs rows are zero in Y (not read); only planes with stencil rows are used
   // by the inverse passes (only those are written)
-  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, Y, p.planes_in, p.planes_out);
+  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, Y, &p.planes_in_bits, &p.planes_out_bits);
   toc(p.t_dst_last_sparse);
   tic(p.t_dst_y_sparse);
   pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st, p.planes_out);

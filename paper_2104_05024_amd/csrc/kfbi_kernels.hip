@@ -632,8 +632,14 @@ void upload_tables(DevProblem &p) {
     p.n_rows_out = (int64_t)rout.size();
     p.rows_in = dupload(rin);
     p.rows_out = dupload(rout);
-    p.mask_in = dupload(min_);
-    p.mask_out = dupload(mout);
+    std::vector<uint64_t> bin((size_t)N * 16, 0), bout((size_t)N * 16, 0);
+    for (int64_t r = 0; r < N * N; ++r) {
+      const int64_t z = r / N, y = r % N;
+      if (min_[r]) bin[(size_t)z * 16 + (y >> 6)] |= uint64_t(1) << (y & 63);
+      if (mout[r]) bout[(size_t)z * 16 + (y >> 6)] |= uint64_t(1) << (y & 63);
+    }
+    p.mask_in = dupload(bin);
+    p.mask_out = dupload(bout);
     std::vector<uint8_t> pin(N, 0), pout(N, 0);
     for (int64_t r = 0; r < N * N; ++r) {
       if (min_[r]) pin[r / N] = 1;
@@ -641,6 +647,12 @@ void upload_tables(DevProblem &p) {
     }
     p.planes_in = dupload(pin);
     p.planes_out = dupload(pout);
+    p.planes_in_bits = PlaneBits{};
+    p.planes_out_bits = PlaneBits{};
+    for (int64_t z = 0; z < N; ++z) {
+      if (pin[z]) p.planes_in_bits.w[z >> 6] |= uint64_t(1) << (z & 63);
+      if (pout[z]) p.planes_out_bits.w[z >> 6] |= uint64_t(1) << (z & 63);
+    }
   }
   p.z_idx = dupload(z_idx);
   p.z_axis = dupload(z_axis);
@@ -663,8 +675,13 @@ void upload_tables(DevProblem &p) {
 void free_tables(DevProblem &p) {
   int32_t **ip[] = {&p.z_idx, &p.z_axis, &p.q_idx, &p.irr_pos, &p.irr_ptr, &p.arm_cross, &p.st_pos,
                     &p.rows_in, &p.rows_out};
-  uint8_t **up[] = {&p.mask_in, &p.mask_out, &p.planes_in, &p.planes_out};
+  uint8_t **up[] = {&p.planes_in, &p.planes_out};
   for (uint8_t **q : up) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  uint64_t **bp[] = {&p.mask_in, &p.mask_out};
+  for (uint64_t **q : bp) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
