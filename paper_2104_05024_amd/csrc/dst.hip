@@ -680,13 +680,24 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
   __shared__ C2<T> sbuf[NP * PADM];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  // the tile's row indices through uniform (scalar) loads, then picked per thread from
+  // registers: no data load waits on a per-thread index load
+  int32_t ri[ROWS];
+#pragma unroll
+  for (int k = 0; k < ROWS; ++k) ri[k] = r0 + k < nlist ? rows[r0 + k] : 0;
+  auto row_of = [&](int rr) {
+    int32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) v = rr == k ? ri[k] : v;
+    return v;
+  };
   V16<T> reg[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = tid + i * NT;
     const int rr = e / VPR, s = e - rr * VPR;
     if (e < NV && r0 + rr < nlist)
-      reg[i] = *reinterpret_cast<const V16<T> *>(in + (int64_t)rows[r0 + rr] * M + s * VW);
+      reg[i] = *reinterpret_cast<const V16<T> *>(in + (int64_t)row_of(rr) * M + s * VW);
     else
 #pragma unroll
       for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
@@ -719,7 +730,7 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
   for (int i = 0; i < PER; ++i) {
     const int e = tid + i * NT;
     const int rr = e / VPR, s = e - rr * VPR;
-    if (e < NV && r0 + rr < nlist) *reinterpret_cast<V16<T> *>(out + (int64_t)rows[r0 + rr] * M + s * VW) = reg[i];
+    if (e < NV && r0 + rr < nlist) *reinterpret_cast<V16<T> *>(out + (int64_t)row_of(rr) * M + s * VW) = reg[i];
   }
 }
 
