@@ -253,7 +253,7 @@ def main():
             bd.step(V, q, hist, dt)
         torch.cuda.synchronize()
         kt[name] = {k: prob.kernel_time(k) for k in ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse",
-                                                     "dst_last_sparse",
+                                                     "dst_last_sparse", "dst_last_out",
                                                      "jumps", "correct", "gather")}
         prob.profile(False)
         worst = max(i["rel_resid"] for i in infos)
@@ -276,14 +276,17 @@ def main():
     # dense passes (dst_x, dst_y, dst_last) each read and write the whole coupled field.  The
     # z pass of the matrix-vector product (dst_last_sparse) reads only the z planes that hold
     # irregular nodes (the others are zero) and writes only those that hold extrapolation
-    # stencil nodes; the row-masked x and y passes (dst_x_rows, dst_y_sparse) are not priced.
+    # stencil nodes; the z pass of the BIE right-hand side's volume solve (dst_last_out) reads
+    # every plane and writes only the stencil planes.  The row-masked x and y passes
+    # (dst_x_rows, dst_y_sparse) are not priced.
     ref = "plain" if "plain" in kt else head
     N = grid.n
     field_bytes = co.ncomp * N ** 3 * 8
     planes_in = len(np.unique(prob.table("irregular") // (N * N)))
     planes_out = len(np.unique(prob.table("st_lin") // (N * N)))
     algo_of = {"dst_x": 2.0 * field_bytes, "dst_y": 2.0 * field_bytes, "dst_last": 2.0 * field_bytes,
-               "dst_last_sparse": float(co.ncomp * N * N * 8 * (planes_in + planes_out))}
+               "dst_last_sparse": float(co.ncomp * N * N * 8 * (planes_in + planes_out)),
+               "dst_last_out": float(field_bytes + co.ncomp * N * N * 8 * planes_out)}
     tot = {k: us * n for k, (us, n) in kt[ref].items()}
     priced = [k for k in algo_of if kt[ref][k][1] > 0]
     dom = max(priced, key=tot.get)

@@ -303,7 +303,8 @@ int kfbi_profile(kfbi_problem p, int32_t enable) {
     if (!p->p.on_device) return fail(KFBI_ENODEV, "problem set up host-only");
     p->p.profile = enable != 0;
     Timer *ts[] = {&p->p.t_dst_x, &p->p.t_dst_y, &p->p.t_dst_last, &p->p.t_correct, &p->p.t_gather,
-                   &p->p.t_jumps, &p->p.t_dst_x_rows, &p->p.t_dst_y_sparse, &p->p.t_dst_last_sparse};
+                   &p->p.t_jumps, &p->p.t_dst_x_rows, &p->p.t_dst_y_sparse, &p->p.t_dst_last_sparse,
+                   &p->p.t_dst_last_out};
     for (Timer *t : ts) t->reset();
     return KFBI_OK;
   });
@@ -322,6 +323,7 @@ int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t
   else if (s == "dst_x_rows") t = &p->p.t_dst_x_rows;
   else if (s == "dst_y_sparse") t = &p->p.t_dst_y_sparse;
   else if (s == "dst_last_sparse") t = &p->p.t_dst_last_sparse;
+  else if (s == "dst_last_out") t = &p->p.t_dst_last_out;
   else return fail(KFBI_EINVAL, "unknown kernel class");
   return guard([&]() -> int {
     if (p->p.on_device) t->harvest();

@@ -126,7 +126,8 @@ struct DevProblem {
   int tile_w[2][3] = {{1, 1, 1}, {1, 1, 1}};
 
   bool profile = false;
-  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse, t_dst_last_sparse;
+  Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse, t_dst_last_sparse,
+      t_dst_last_out;
   hipStream_t stream = nullptr;
 
   template <typename T>
@@ -181,6 +182,11 @@ void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_pla
 // extrapolation-stencil values of work are meaningful afterwards.
 template <typename T>
 void box_solve_matvec(DevProblem &p, hipStream_t st);
+
+// Box solve of src (padded) into work when only the extrapolation-stencil values of the result
+// are read afterwards (identical there to box_solve).
+template <typename T>
+void box_solve_stencils(DevProblem &p, const T *src, hipStream_t st);
 
 template <typename T>
 void launch_jumps(DevProblem &p, const T *psi, hipStream_t st);

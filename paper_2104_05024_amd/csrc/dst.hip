@@ -600,10 +600,11 @@ struct ModeHook {
 // ncomp = 2: a pencil pair is (comp 0, comp 1) of one column; ncomp = 1: two adjacent columns.
 // In 2D, blockIdx.y may index the problems of a batch of equal-size fields at stride pstride,
 // each with its own mode parameters msv[problem] (msv = nullptr: one problem, parameters ms).
-// ZM (3D): the plane-masked form, a kernel of its own so that traces tell the two apart; the
-// bit sets zin / zout name the planes that may be nonzero on input (the others are not read)
-// and the planes needed on output (the others are not written).
-template <typename T, int M, int NC, int DIM, int W = 1, bool ZM = false>
+// ZM (3D): plane-masked forms, kernels of their own so that traces tell them apart.  ZM = 1:
+// the bit sets zin / zout name the planes that may be nonzero on input (the others are not
+// read) and the planes needed on output (the others are not written); ZM = 2: every plane is
+// read, only the planes in zout are written.
+template <typename T, int M, int NC, int DIM, int W = 1, int ZM = 0>
 __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__restrict__ ain, T *__restrict__ a,
                                                                      int64_t P, int64_t comp_stride,
                                                                   ModeScale ms0, const C2<T> *__restrict__ tw,
@@ -632,7 +633,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   constexpr int NW = (N + 63) / 64;
-  if constexpr (ZM) Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zin});
+  if constexpr (ZM == 1) Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zin});
   else Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
@@ -663,7 +664,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
   dst_pair<T, M>(mine, lane, tw, sp, mh);
-  if constexpr (ZM) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
+  if constexpr (ZM != 0) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
   else Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
 
@@ -772,11 +773,14 @@ void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, c
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
   if (dim == 3) {
-    if (zin || zout) {
-      if (!zin || !zout) throw std::invalid_argument("plane masks come in pairs");
-      if (ncomp == 2) k_dst_last<T, M, 2, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
-      else k_dst_last<T, M, 1, 3, W, true><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
+    if (zin && zout) {
+      if (ncomp == 2) k_dst_last<T, M, 2, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
+      else k_dst_last<T, M, 1, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
+    } else if (zout) {
+      if (ncomp == 2) k_dst_last<T, M, 2, 3, W, 2><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, {}, *zout);
+      else k_dst_last<T, M, 1, 3, W, 2><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, {}, *zout);
     } else {
+      if (zin) throw std::invalid_argument("an input plane mask needs an output plane mask");
       if (ncomp == 2) k_dst_last<T, M, 2, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
       else k_dst_last<T, M, 1, 3, W><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
     }
@@ -853,6 +857,43 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
   tic(p.t_dst_x);
   pass_x<T, M>(w[0], A, false, dst, dst_plain, rows, tw, sp, st);
   toc(p.t_dst_x);
+}
+
+// Box solve whose result is read only at extrapolation-stencil nodes (the volume part of the
+// BIE right-hand side): dense forward passes, then the z pass writes and the inverse y and x
+// passes transform only the planes and rows that hold stencil nodes.  Result in work; the
+// values at every stencil node are identical to the full solve.
+template <typename T, int M>
+void run_box_stencils(DevProblem &p, const T *src, hipStream_t st) {
+  constexpr int N = M - 1;
+  using Sh = Shape<T, M>;
+  PrecTables<T> &tb = p.tab<T>();
+  T *A = tb.work;
+  const C2<T> *tw = reinterpret_cast<const C2<T> *>(tb.tw);
+  const T *sp = tb.sp;
+  const int64_t P = p.P, cs = p.comp_stride;
+  const int64_t rows = (int64_t)p.ncomp * N * N;
+  const int *w = p.tile_w[prec_index<T>()];
+  const ModeScale ms = mode_of<T>(p);
+  auto tic = [&](Timer &t) { t.tic(p.profile, st); };
+  auto toc = [&](Timer &t) { t.toc(p.profile, st); };
+  tic(p.t_dst_x);
+  pass_x<T, M>(w[0], src, false, A, false, rows, tw, sp, st);
+  toc(p.t_dst_x);
+  tic(p.t_dst_y);
+  pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
+  toc(p.t_dst_y);
+  tic(p.t_dst_last_out);
+  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, nullptr, nullptr, &p.planes_out_bits);
+  toc(p.t_dst_last_out);
+  tic(p.t_dst_y_sparse);
+  pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st, p.planes_out);
+  toc(p.t_dst_y_sparse);
+  const unsigned gout = (unsigned)((p.n_rows_out + 2 * Sh::NP - 1) / (2 * Sh::NP));
+  tic(p.t_dst_x_rows);
+  if (gout) k_dst_x_rows<T, M><<<gout, Sh::NT, 0, st>>>(A, A, p.rows_out, p.n_rows_out, tw, sp);
+  KFBI_HIP(hipGetLastError());
+  toc(p.t_dst_x_rows);
 }
 
 // Box solve inside the matrix-vector product: the right-hand side is zero outside the rows
@@ -1069,6 +1110,25 @@ void box_solve(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_pla
 
 template void box_solve<double>(DevProblem &, const double *, bool, double *, bool, hipStream_t);
 template void box_solve<float>(DevProblem &, const float *, bool, float *, bool, hipStream_t);
+
+template <typename T>
+void box_solve_stencils(DevProblem &p, const T *src, hipStream_t st) {
+  if (p.dim != 3 || !p.sparse) {
+    box_solve<T>(p, src, false, p.tab<T>().work, false, st);
+    return;
+  }
+  switch (p.Mfft) {
+    case 16: run_box_stencils<T, 16>(p, src, st); break;
+    case 32: run_box_stencils<T, 32>(p, src, st); break;
+    case 64: run_box_stencils<T, 64>(p, src, st); break;
+    case 128: run_box_stencils<T, 128>(p, src, st); break;
+    case 256: run_box_stencils<T, 256>(p, src, st); break;
+    case 512: run_box_stencils<T, 512>(p, src, st); break;
+    case 1024: run_box_stencils<T, 1024>(p, src, st); break;
+    default: throw std::invalid_argument("unsupported grid size");
+  }
+}
+template void box_solve_stencils<double>(DevProblem &, const double *, hipStream_t);
 
 template <typename T>
 void box_solve_matvec(DevProblem &p, hipStream_t st) {

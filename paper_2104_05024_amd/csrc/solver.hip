@@ -489,7 +489,8 @@ int Solver::richardson(DevProblem &p, const double *b, double bnorm, double *x, 
 }
 
 void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st) {
-  box_solve<double>(p, fpad, false, p.f64.work, false, st);
+  // u_V is needed only at the extrapolation stencils of the interface nodes
+  box_solve_stencils<double>(p, fpad, st);
   launch_gather<double>(p, p.f64.work, false, t, st);
   if (g)
     k_axpby<<<nblk(L), kB, 0, st>>>(gp, 1.0, g, -1.0, t, L);
