@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--cells", type=int, default=256)
     ap.add_argument("--nodes", type=int, default=40960)
-    ap.add_argument("--variants", default="plain,mixed,learned,projected")
+    ap.add_argument("--variants", default="plain,mixed,learned,projected,projected_mixed")
     ap.add_argument("--train-steps", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="mixed precision: relative tolerance of each FP32 inner solve")
@@ -224,8 +224,9 @@ def main():
             except K.KfbiError as e:
                 log(f"learned variant unavailable: {e}")
                 continue
-        elif name == "projected":
-            bd = K.Bidomain(prob, p, tol=1e-8, precision=1, warm_start=3, inner_tol=a.inner_tol)
+        elif name in ("projected", "projected_mixed"):
+            bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "projected_mixed" else 0, warm_start=3,
+                            inner_tol=a.inner_tol)
         else:
             bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "mixed" else 0, warm_start=0,
                             inner_tol=a.inner_tol)
