@@ -108,7 +108,8 @@ typedef struct {
 } kfbi_grid;
 
 /* ncomp = 1: -div(D[0] grad u) + kappa u;  ncomp = 2: the coupled pair of eq. bvp.
- * D[c][axis] must be isotropic per component (D[c][0] = D[c][1] = D[c][2]). */
+ * D[c][axis] is the diagonal conductivity of component c along each axis (anisotropic
+ * allowed; every entry positive and finite, else KFBI_EINVAL). */
 typedef struct {
   int32_t ncomp;
   int32_t pad_;
@@ -210,8 +211,9 @@ typedef struct {
 
 typedef struct bidomain_s *bidomain_ctx;
 
-/* The coupled problem passed here must have ncomp = 2, isotropic sigma_i, sigma_e and
- * kappa = 2 Cm beta / dt for the dt later given to bidomain_step. */
+/* The coupled problem passed here must have ncomp = 2 (D[0] intracellular, D[1]
+ * extracellular, diagonal) and kappa = 2 Cm beta / dt for the dt later given to
+ * bidomain_step. */
 int bidomain_create(kfbi_problem p, const bidomain_params *params, bidomain_ctx *out);
 void bidomain_destroy(bidomain_ctx b);
 
