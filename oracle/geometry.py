@@ -395,6 +395,7 @@ def _mesh_roots_on_arms(tm, grid, idx0, p0, axis, h):
     c = grid_coords(grid)
     n_arm = p0.shape[0]
     frac = np.zeros(n_arm)
+    tri = np.zeros(n_arm, dtype=np.int64)
     nn = np.zeros((n_arm, 3))
     WW = np.zeros((n_arm, 3, 3))
     for i in range(n_arm):
@@ -409,6 +410,7 @@ def _mesh_roots_on_arms(tm, grid, idx0, p0, axis, h):
             if not at0:
                 z[axis] = x1
             frac[i] = 0.0 if at0 else 1.0
+            tri[i] = t
             nn[i], WW[i] = tm.patch_geometry(t, z)
             continue
         inarm = [(x, t) for x, t in hits if x0 - SIDE_TOL <= x <= x1 + SIDE_TOL]
@@ -417,7 +419,8 @@ def _mesh_roots_on_arms(tm, grid, idx0, p0, axis, h):
         x, t = inarm[0]
         z, s, nn[i], WW[i] = tm.onto_patch(t, p0[i], axis, x - x0, h)
         frac[i] = s / h
-    return frac, nn, WW
+        tri[i] = t
+    return frac, nn, WW, tri
 
 
 class Crossings:
@@ -426,7 +429,9 @@ class Crossings:
     For every arm between interior nodes p and p + e_axis whose end points lie
     on different sides of one surface: the surface id, the axis, the
     intersection z, the linear indices of its tissue-side ("plus") and
-    complement-side ("minus") end points, and n, W at z.
+    complement-side ("minus") end points, and n, W at z.  ``tparam`` holds the spline
+    parameter of the crossing on a spline curve, the index of the triangle it lies in on a
+    mesh, NaN on an analytic surface.
     """
 
     def __init__(self, iface, grid, side):
@@ -459,8 +464,8 @@ class Crossings:
                     t, tp = _spline_roots_on_arms(curve_of(surf), p0, a, h)
                     tparam_l.append(tp)
                 elif is_mesh(surf):
-                    t, mn, mW = _mesh_roots_on_arms(trimesh_of(surf), grid, idx0, p0, a, h)
-                    tparam_l.append(np.full(len(t), np.nan))
+                    t, mn, mW, mt = _mesh_roots_on_arms(trimesh_of(surf), grid, idx0, p0, a, h)
+                    tparam_l.append(mt.astype(np.float64))
                     mesh_nw[(s, a)] = (mn, mW)
                 else:
                     t = _root_on_arm(surf, p0, a, h)

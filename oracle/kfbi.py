@@ -254,7 +254,9 @@ class Problem:
         for s, surf in enumerate(self.iface.surfaces):
             o, m = nd.offsets[s], surf.n_nodes
             msk = cr.surf == s
-            if geometry.is_spline(surf):
+            if geometry.is_mesh(surf):
+                self._transfer_mesh(geometry.trimesh_of(surf), o, m, msk, K, Kn)
+            elif geometry.is_spline(surf):
                 cv = geometry.curve_of(surf)
                 if np.any(msk):
                     self.z_idx[msk], self.z_w0[msk], self.z_wg[msk] = \
@@ -272,6 +274,26 @@ class Problem:
                         transfer_3d(xs, o, cr.z[msk], cr.n[msk], self.grid.h)
                 idx, _, wg = transfer_3d(xs, o, xs, nd.n[o:o + m], self.grid.h)
                 self.q_idx[o:o + m], self.q_wg[o:o + m] = idx, wg
+
+    def _transfer_mesh(self, tm, o, m, msk, K, Kn):
+        """Triangle meshes: the six-point system of the crossing's triangle (slots beyond six
+        carry zero weight), and the one-ring fit at each vertex."""
+        cr = self.cross
+        for c in np.flatnonzero(msk):
+            idx, w0, wg = tm.crossing_transfer(int(cr.tparam[c]), cr.z[c])
+            self.z_idx[c] = o + idx[0]
+            self.z_idx[c, :6] = o + idx
+            self.z_w0[c] = 0.0
+            self.z_w0[c, :6] = w0
+            self.z_wg[c] = 0.0
+            self.z_wg[c, :6] = wg
+        for j in range(m):
+            idx, wg = tm.vertex_transfer(j, Kn)
+            k = len(idx)
+            self.q_idx[o + j] = o + idx[0]
+            self.q_idx[o + j, :k] = o + idx
+            self.q_wg[o + j] = 0.0
+            self.q_wg[o + j, :k] = wg
 
     # -- extrapolation stencils
     def _stencils(self):

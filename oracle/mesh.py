@@ -17,7 +17,12 @@ the jumps in 3D, Fig. "six boundary points"; Sec. 7, Example 4).  Here:
   grid lines lies on the surface and counts as tissue;
 * the crossing of a grid arm is found on the flat triangle it passes through and moved
   onto that triangle's quadratic patch (a quadratic equation along the arm), clamped to
-  the arm; n and W at the crossing are the patch's.
+  the arm; n and W at the crossing are the patch's;
+* psi and its surface gradient at a crossing come from the same six-point system: the
+  quadratic in (xi, eta) through the six values, differentiated along the patch's tangents
+  X_xi = t1 + w_xi n0, X_eta = t2 + w_eta n0 (grad_G psi = [X_xi X_eta] g^-1 (psi_xi, psi_eta),
+  g the metric); at a vertex, a least-squares quadratic in the vertex frame over the vertex
+  and its one-ring (at most 10 points: the nearest neighbours) gives the gradient the same way.
 
 For the graph zeta = w over a frame (t1, t2, n0) with the tissue below it the level set
 phi = zeta - w gives n = (-w_xi, -w_eta, 1)/q, q = |grad phi|, and
@@ -93,6 +98,7 @@ class TriMesh:
             nbr[c] |= {a, b}
         self.nbr = [sorted(s) for s in nbr]
         self._patch = {}
+        self._pts = {}
 
     # -- vertices
     def vertex_geometry(self):
@@ -156,6 +162,76 @@ class TriMesh:
         qz = R.T @ (z - o)
         n, W = _graph_geometry(R, c, qz[0], qz[1])
         return z, s, n, W
+
+    def _patch_points(self, t):
+        """Indices and the inverse of the scaled six-point Vandermonde matrix of triangle t."""
+        hit = self._pts.get(t)
+        if hit is None:
+            o, R, c = self.patch(t)
+            idx = np.array(list(self.F[t]) + list(self.opp[t]), dtype=np.int64)
+            d = self.V[idx] - o
+            L = np.max(np.linalg.norm(d[:3], axis=1))
+            xi, eta = d @ R[:, 0] / L, d @ R[:, 1] / L
+            A = np.stack([np.ones(6), xi, eta, xi * xi, xi * eta, eta * eta], axis=1)
+            hit = (idx, np.linalg.inv(A), L)
+            self._pts[t] = hit
+        return hit
+
+    def crossing_transfer(self, t, z):
+        """Weights carrying the six nodal values of triangle t's local system to psi(z) and
+        grad_Gamma psi(z) on its patch: (indices, w0 (6), wg (6, 3))."""
+        o, R, c = self.patch(t)
+        idx, Ainv, L = self._patch_points(t)
+        q = R.T @ (z - o)
+        x, y = q[0] / L, q[1] / L
+        b = np.array([1.0, x, y, x * x, x * y, y * y])
+        bx = np.array([0.0, 1.0, 0.0, 2 * x, y, 0.0]) / L
+        by = np.array([0.0, 0.0, 1.0, 0.0, x, 2 * y]) / L
+        # psi(q) = b^T a, a = Ainv psi_nodes  ->  weights Ainv^T b
+        w0, wx, wy = Ainv.T @ b, Ainv.T @ bx, Ainv.T @ by
+        return idx, w0, self._grad_weights(R, c, q[0], q[1], wx, wy)
+
+    @staticmethod
+    def _grad_weights(R, c, xi, eta, wx, wy):
+        t1, t2, n0 = R[:, 0], R[:, 1], R[:, 2]
+        Xx = t1 + (c[1] + 2 * c[3] * xi + c[4] * eta) * n0
+        Xy = t2 + (c[2] + c[4] * xi + 2 * c[5] * eta) * n0
+        g = np.array([[Xx @ Xx, Xx @ Xy], [Xx @ Xy, Xy @ Xy]])
+        gi = np.linalg.inv(g)
+        ax = gi[0, 0] * wx + gi[0, 1] * wy
+        ay = gi[1, 0] * wx + gi[1, 1] * wy
+        return ax[:, None] * Xx[None, :] + ay[:, None] * Xy[None, :]
+
+    def vertex_transfer(self, i, kmax=10):
+        """Weights of grad_Gamma psi at vertex i over the vertex and its one-ring (nearest
+        kmax - 1 neighbours, ties by index): (indices, wg (k, 3))."""
+        acc = self._vacc()[i]
+        n0 = acc / np.linalg.norm(acc)
+        t1, t2 = _frame(n0)
+        R = np.stack([t1, t2, n0], axis=1)
+        nb = np.array(self.nbr[i], dtype=np.int64)
+        dn = self.V[nb] - self.V[i]
+        d2 = np.sum(dn * dn, axis=1)
+        nb = nb[np.lexsort((nb, d2))][:kmax - 1]
+        d = self.V[nb] - self.V[i]
+        xi, eta, zeta = d @ t1, d @ t2, d @ n0
+        G = np.stack([xi, eta, xi * xi, xi * eta, eta * eta], axis=1)
+        c = np.concatenate([[0.0], np.linalg.lstsq(G, zeta, rcond=None)[0]])
+        idx = np.concatenate([[i], nb])
+        dd = self.V[idx] - self.V[i]
+        L = np.max(np.linalg.norm(dd, axis=1))
+        x, y = dd @ t1 / L, dd @ t2 / L
+        A = np.stack([np.ones(len(idx)), x, y, x * x, x * y, y * y], axis=1)
+        P = np.linalg.pinv(A)
+        return idx, self._grad_weights(R, c, 0.0, 0.0, P[1] / L, P[2] / L)
+
+    def _vacc(self):
+        if getattr(self, "_acc", None) is None:
+            acc = np.zeros((self.m, 3))
+            for k in range(3):
+                np.add.at(acc, self.F[:, k], self.cross)
+            self._acc = acc
+        return self._acc
 
     def patch_geometry(self, t, z):
         """n and W of triangle t's patch over the point z (projected onto its plane)."""

@@ -114,3 +114,26 @@ def test_manufactured_solution_on_a_mesh_ellipsoid():
         assert res[0] < 1.1 * res[1]
         assert res[0] < 0.3 * grid.h ** 2
     assert np.log2(errs[0] / errs[1]) > 1.5
+
+
+def test_six_point_transfer_of_a_linear_function():
+    """psi = x on a sphere mesh: on the six-point patches x is itself the quadratic interpolant,
+    so psi at the crossings is exact; the surface gradient P_n e_x converges at about third
+    order at crossings and vertices; unused slots carry no weight."""
+    errs_c, errs_q = [], []
+    for L, cells in ((3, 32), (4, 64)):
+        o = ok.Problem(W.mesh_sphere(0.5, L), W.box(3, cells), W.scalar_coeffs(3))
+        psi = o.nodes.X[:, 0]
+        p0 = np.sum(o.z_w0 * psi[o.z_idx], axis=1)
+        assert np.max(np.abs(p0 - o.cross.z[:, 0])) < 1e-13
+        assert np.all(o.z_w0[:, 6:] == 0) and np.all(o.z_wg[:, 6:] == 0)
+        u = o.cross.z / np.linalg.norm(o.cross.z, axis=1)[:, None]
+        g = np.einsum("nk,nkd->nd", psi[o.z_idx], o.z_wg)
+        errs_c.append(np.max(np.abs(g - (np.array([1.0, 0, 0])[None] - u * u[:, :1]))))
+        un = o.nodes.X / np.linalg.norm(o.nodes.X, axis=1)[:, None]
+        gq = np.einsum("nk,nkd->nd", psi[o.q_idx], o.q_wg)
+        errs_q.append(np.max(np.abs(gq - (np.array([1.0, 0, 0])[None] - un * un[:, :1]))))
+        # the gradient is tangent to the patch: orthogonal to the patch normal at the crossing
+        assert np.max(np.abs(np.sum(g * o.cross.n, axis=1))) < 1e-12
+    assert errs_c[1] < 1e-4 and errs_c[0] / errs_c[1] > 5
+    assert errs_q[1] < 1.5e-5 and errs_q[0] / errs_q[1] > 5
