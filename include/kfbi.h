@@ -77,7 +77,9 @@ enum { KFBI_SURF_ANALYTIC = 0, KFBI_SURF_SPLINE = 1, KFBI_SURF_MESH = 2 };
  *   shared by exactly two triangles).  Normals and shape operators come from quadratic height
  *   functions fitted over each vertex's one-ring; grid-line crossings from the flat triangles,
  *   moved onto the quadratic through each triangle's six boundary points (its vertices and
- *   the three across its edges).  An open or inconsistently oriented mesh gives KFBI_EGEOM. */
+ *   the three across its edges), which also carries psi and its surface gradient to the
+ *   crossing (the one-ring fit does at the vertices).  An open or inconsistently oriented
+ *   mesh gives KFBI_EGEOM. */
 typedef struct {
   double axes[3];
   int32_t orient;
@@ -141,7 +143,7 @@ int kfbi_query(kfbi_problem p, int64_t *M, int64_t *N, int64_t *n_crossings, int
  * "inside"(i8,N^d) "nodes_X" "nodes_n"(f64,M*d) "nodes_W"(f64,M*d*d)
  * "cross_axis" "cross_surf"(i64) "cross_pin" "cross_pout"(i64, linear interior index)
  * "cross_z" "cross_n"(f64,nc*d) "cross_W"(f64,nc*d*d) "cross_t"(f64,nc: spline parameter of
- * the crossing on a spline curve, NaN elsewhere) "z_idx"(i64,nc*K) "z_w0"(f64,nc*K) "z_wg"(f64,nc*K*d)
+ * the crossing on a spline curve, index of its triangle on a mesh, NaN elsewhere) "z_idx"(i64,nc*K) "z_w0"(f64,nc*K) "z_wg"(f64,nc*K*d)
  * "q_idx"(i64,M*Kn) "q_wg"(f64,M*Kn*d) "st_lin"(i64,M*S) "st_r" "st_wgrad"(f64,M*S*d)
  * "irregular"(i64).  With dst == NULL only *count (elements) and *elem_bytes are set. */
 int kfbi_table(kfbi_problem p, const char *name, void *dst, int64_t *count, int32_t *elem_bytes);

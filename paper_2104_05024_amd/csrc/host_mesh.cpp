@@ -103,7 +103,135 @@ bool lsq(std::vector<double> A, int rows, int cols, std::vector<double> b, doubl
   return true;
 }
 
+// Weights of grad_Gamma psi on the graph zeta = w(xi, eta) (frame R, coefficients c) at
+// (xi, eta) from the weights wx, wy of psi_xi, psi_eta: [X_xi X_eta] g^-1 (psi_xi, psi_eta)
+// with the tangents X_xi = t1 + w_xi n0, X_eta = t2 + w_eta n0 and their metric g.
+void grad_weights(const double *R, const double *c, double xi, double eta, const double *wx, const double *wy,
+                  int k, double *wg) {
+  const double wxi = c[1] + 2 * c[3] * xi + c[4] * eta, weta = c[2] + c[4] * xi + 2 * c[5] * eta;
+  double Xx[3], Xy[3];
+  for (int a = 0; a < 3; ++a) {
+    Xx[a] = R[a * 3 + 0] + wxi * R[a * 3 + 2];
+    Xy[a] = R[a * 3 + 1] + weta * R[a * 3 + 2];
+  }
+  const double g00 = Xx[0] * Xx[0] + Xx[1] * Xx[1] + Xx[2] * Xx[2];
+  const double g01 = Xx[0] * Xy[0] + Xx[1] * Xy[1] + Xx[2] * Xy[2];
+  const double g11 = Xy[0] * Xy[0] + Xy[1] * Xy[1] + Xy[2] * Xy[2];
+  const double det = g00 * g11 - g01 * g01;
+  const double i00 = g11 / det, i01 = -g01 / det, i11 = g00 / det;
+  for (int j = 0; j < k; ++j) {
+    const double ax = i00 * wx[j] + i01 * wy[j], ay = i01 * wx[j] + i11 * wy[j];
+    for (int a = 0; a < 3; ++a) wg[j * 3 + a] = ax * Xx[a] + ay * Xy[a];
+  }
+}
+
 }  // namespace
+
+void TriMesh3::crossing_transfer(int64_t t, const double *z, int64_t *idx, double *w0, double *wg) const {
+  const Patch &P = patch[t];
+  const int64_t id[6] = {F[3 * t], F[3 * t + 1], F[3 * t + 2], opp[3 * t], opp[3 * t + 1], opp[3 * t + 2]};
+  double L = 0.0, d[6][3];
+  for (int k = 0; k < 6; ++k)
+    for (int a = 0; a < 3; ++a) d[k][a] = V[3 * id[k] + a] - P.o[a];
+  for (int k = 0; k < 3; ++k) L = std::max(L, norm3(d[k]));
+  // A (rows: [1, x, y, x^2, xy, y^2] at the six points, scaled coordinates); the weights of
+  // psi and its derivatives at z solve A^T w = basis(z)
+  std::vector<double> At(36);
+  for (int k = 0; k < 6; ++k) {
+    const double x = (d[k][0] * P.R[0] + d[k][1] * P.R[3] + d[k][2] * P.R[6]) / L;
+    const double y = (d[k][0] * P.R[1] + d[k][1] * P.R[4] + d[k][2] * P.R[7]) / L;
+    const double row[6] = {1.0, x, y, x * x, x * y, y * y};
+    for (int j = 0; j < 6; ++j) At[j * 6 + k] = row[j];
+  }
+  double q[3];
+  for (int k = 0; k < 3; ++k) {
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a) acc += P.R[a * 3 + k] * (z[a] - P.o[a]);
+    q[k] = acc;
+  }
+  const double x = q[0] / L, y = q[1] / L;
+  const std::vector<double> b = {1.0, x, y, x * x, x * y, y * y};
+  const std::vector<double> bx = {0.0, 1.0 / L, 0.0, 2 * x / L, y / L, 0.0};
+  const std::vector<double> by = {0.0, 0.0, 1.0 / L, 0.0, x / L, 2 * y / L};
+  double wx[6], wy[6];
+  if (!lsq(At, 6, 6, b, w0) || !lsq(At, 6, 6, bx, wx) || !lsq(At, 6, 6, by, wy))
+    throw GeometryError{"degenerate six-point local coordinate system"};
+  grad_weights(P.R, P.c, q[0], q[1], wx, wy, 6, wg);
+  for (int k = 0; k < 6; ++k) idx[k] = id[k];
+}
+
+int TriMesh3::vertex_transfer(int64_t i, int kmax, int64_t *idx, double *wg) const {
+  const double *acc = &vacc[3 * i];
+  const double an = norm3(acc);
+  const double n0[3] = {acc[0] / an, acc[1] / an, acc[2] / an};
+  int mi = 0;
+  for (int a = 1; a < 3; ++a)
+    if (std::fabs(n0[a]) < std::fabs(n0[mi])) mi = a;
+  double e[3] = {0, 0, 0}, t1[3], t2[3];
+  e[mi] = 1.0;
+  cross3(e, n0, t1);
+  const double l1 = norm3(t1);
+  for (double &v : t1) v /= l1;
+  cross3(n0, t1, t2);
+  double R[9];
+  for (int a = 0; a < 3; ++a) {
+    R[a * 3 + 0] = t1[a];
+    R[a * 3 + 1] = t2[a];
+    R[a * 3 + 2] = n0[a];
+  }
+  // nearest one-ring neighbours (squared distance, then index)
+  std::vector<std::pair<double, int64_t>> nb;
+  for (int64_t s = nbr_ptr[i]; s < nbr_ptr[i + 1]; ++s) {
+    const int64_t j = nbr[s];
+    const double dx = V[3 * j] - V[3 * i], dy = V[3 * j + 1] - V[3 * i + 1], dz = V[3 * j + 2] - V[3 * i + 2];
+    nb.push_back({(dx * dx + dy * dy) + dz * dz, j});
+  }
+  std::sort(nb.begin(), nb.end());
+  if ((int)nb.size() > kmax - 1) nb.resize(kmax - 1);
+  const int kn = (int)nb.size(), k = kn + 1;
+  // graph coefficients over the selected neighbours
+  std::vector<double> G((size_t)kn * 5), zeta(kn);
+  for (int r = 0; r < kn; ++r) {
+    const int64_t j = nb[r].second;
+    const double d[3] = {V[3 * j] - V[3 * i], V[3 * j + 1] - V[3 * i + 1], V[3 * j + 2] - V[3 * i + 2]};
+    const double xi = d[0] * t1[0] + d[1] * t1[1] + d[2] * t1[2];
+    const double eta = d[0] * t2[0] + d[1] * t2[1] + d[2] * t2[2];
+    zeta[r] = d[0] * n0[0] + d[1] * n0[1] + d[2] * n0[2];
+    const double row[5] = {xi, eta, xi * xi, xi * eta, eta * eta};
+    for (int c5 = 0; c5 < 5; ++c5) G[(size_t)r * 5 + c5] = row[c5];
+  }
+  double c[6] = {0, 0, 0, 0, 0, 0};
+  if (!lsq(G, kn, 5, zeta, c + 1)) throw GeometryError{"degenerate vertex neighbourhood in the mesh"};
+  // psi fit [1, x, y, x^2, xy, y^2] over the vertex and the neighbours (scaled coordinates);
+  // column j of pinv(A) is the least-squares solution for the unit vector e_j
+  idx[0] = i;
+  for (int r = 0; r < kn; ++r) idx[r + 1] = nb[r].second;
+  double L = 0.0, xy[10][2];
+  for (int r = 0; r < k; ++r) {
+    const int64_t j = idx[r];
+    const double d[3] = {V[3 * j] - V[3 * i], V[3 * j + 1] - V[3 * i + 1], V[3 * j + 2] - V[3 * i + 2]};
+    L = std::max(L, norm3(d));
+    xy[r][0] = d[0] * t1[0] + d[1] * t1[1] + d[2] * t1[2];
+    xy[r][1] = d[0] * t2[0] + d[1] * t2[1] + d[2] * t2[2];
+  }
+  std::vector<double> A((size_t)k * 6);
+  for (int r = 0; r < k; ++r) {
+    const double x = xy[r][0] / L, y = xy[r][1] / L;
+    const double row[6] = {1.0, x, y, x * x, x * y, y * y};
+    for (int j = 0; j < 6; ++j) A[(size_t)r * 6 + j] = row[j];
+  }
+  double wx[10], wy[10];
+  for (int r = 0; r < k; ++r) {
+    std::vector<double> ej(k, 0.0);
+    ej[r] = 1.0;
+    double col[6];
+    if (!lsq(A, k, 6, ej, col)) throw GeometryError{"degenerate vertex neighbourhood in the mesh"};
+    wx[r] = col[1] / L;
+    wy[r] = col[2] / L;
+  }
+  grad_weights(R, c, 0.0, 0.0, wx, wy, k, wg);
+  return k;
+}
 
 void TriMesh3::build(const double *pts, int64_t m_, const int32_t *tris, int64_t nt_, int orient) {
   m = m_;

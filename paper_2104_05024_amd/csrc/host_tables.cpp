@@ -747,7 +747,7 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
           t.c_pin.push_back(in0 ? lin : lin1);
           t.c_pout.push_back(in0 ? lin1 : lin);
           for (int b = 0; b < 3; ++b) t.c_z.push_back(z[b]);
-          t.c_t.push_back(std::nan(""));
+          t.c_t.push_back((double)tri);                 // meshes: the triangle of the crossing
           for (int b = 0; b < 3; ++b) mesh_cn.push_back(cn[b]);
           for (int b = 0; b < 9; ++b) mesh_cW.push_back(cW[b]);
           continue;
@@ -829,7 +829,31 @@ void build_host_tables(const kfbi_interface &iface, const kfbi_grid &grid, const
   t.q_wg.resize(M * t.Kn * d);
   for (int s = 0; s < S_; ++s) {
     const int64_t off = t.offsets[s], m = t.surf[s].n_nodes;
-    if (is_spl[s]) {
+    if (is_msh[s]) {
+      // the six-point system of the crossing's triangle (slots beyond six carry zero weight)
+      // and the one-ring fit at each vertex
+      for (int64_t c = 0; c < t.nc; ++c) {
+        if (t.c_surf[c] != s) continue;
+        int64_t idx[6];
+        double w0[6], wg[18];
+        msh[s].crossing_transfer((int64_t)t.c_t[c], &t.c_z[c * 3], idx, w0, wg);
+        for (int k = 0; k < t.K; ++k) {
+          t.z_idx[c * t.K + k] = off + (k < 6 ? idx[k] : idx[0]);
+          t.z_w0[c * t.K + k] = k < 6 ? w0[k] : 0.0;
+          for (int a = 0; a < 3; ++a) t.z_wg[(c * t.K + k) * 3 + a] = k < 6 ? wg[k * 3 + a] : 0.0;
+        }
+      }
+      for (int64_t j = 0; j < m; ++j) {
+        int64_t idx[10];
+        double wg[30];
+        const int k = msh[s].vertex_transfer(j, t.Kn, idx, wg);
+        const int64_t q = off + j;
+        for (int r = 0; r < t.Kn; ++r) {
+          t.q_idx[q * t.Kn + r] = off + (r < k ? idx[r] : idx[0]);
+          for (int a = 0; a < 3; ++a) t.q_wg[(q * t.Kn + r) * 3 + a] = r < k ? wg[r * 3 + a] : 0.0;
+        }
+      }
+    } else if (is_spl[s]) {
       for (int64_t c = 0; c < t.nc; ++c)
         if (t.c_surf[c] == s) spline_transfer(spl[s], off, t.c_t[c], &t.z_idx[c * 4], &t.z_w0[c * 4], &t.z_wg[c * 8]);
       const double cw[5] = {1.0, -8.0, 0.0, 8.0, -1.0};

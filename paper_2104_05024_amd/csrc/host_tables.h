@@ -90,6 +90,12 @@ struct TriMesh3 {
   // Crossing of the line p + s e_axis with triangle t (flat crossing at s_flat) moved onto the
   // triangle's patch, s clamped to [0, h]; returns s and n, W there.
   double onto_patch(int64_t t, const double *p, int axis, double s_flat, double h, double *n, double *W) const;
+  // psi and grad_Gamma psi at z on triangle t's patch from its six nodal values: indices (6),
+  // value weights w0 (6), gradient weights wg (6 x 3).
+  void crossing_transfer(int64_t t, const double *z, int64_t *idx, double *w0, double *wg) const;
+  // grad_Gamma psi at vertex i from a least-squares quadratic over the vertex and its nearest
+  // kmax - 1 one-ring neighbours: indices and weights (3 per index); returns the count.
+  int vertex_transfer(int64_t i, int kmax, int64_t *idx, double *wg) const;
   // Crossings of the grid lines parallel to `axis` as (coordinate along the axis, triangle),
   // per line (ic * N + ib over the other two axes b < c), sorted by coordinate.
   void grid_line_hits(int axis, double lo, double h, int64_t N,

@@ -101,6 +101,8 @@ def test_setup_tables_match_oracle(name):
     close = {"nodes_X": O.nodes.X, "nodes_n": O.nodes.n, "nodes_W": O.nodes.W, "cross_z": O.cross.z,
              "cross_n": O.cross.n, "cross_W": O.cross.W,
              "z_w0": O.z_w0, "z_wg": O.z_wg, "q_wg": O.q_wg, "st_r": O.st_r, "st_wgrad": O.st_wgrad}
+    if iface.surfaces[0].kind == "mesh":        # the triangle of each crossing
+        np.testing.assert_array_equal(P.table("cross_t"), O.cross.tparam)
     if iface.surfaces[0].kind == "spline":      # the spline parameter, compared on the circle of length m
         m = iface.surfaces[0].n_nodes
         dt = np.mod(P.table("cross_t") - O.cross.tparam + m / 2, m) - m / 2
