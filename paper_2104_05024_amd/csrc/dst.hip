@@ -207,20 +207,18 @@ __device__ __forceinline__ T shfl_up_w(T v, int d, int w) { return __shfl_up(v, 
 template <typename T>
 __device__ __forceinline__ T shfl_w(T v, int s, int w) { return __shfl(v, s, w); }
 
-// DST-I (unnormalised: y_k = sum_n x_n sin(pi n k / M)) of one pencil pair held in LDS as
-// complex values at positions 1..N; result at the same positions.  All threads of the
-// workgroup must call it (it contains barriers).
+// Mode hook that leaves the values alone.
 template <typename T>
 struct NoHook {
   __device__ __forceinline__ void operator()(int, C2<T> &) const {}
 };
 
-template <typename T, int M, typename Hook = NoHook<T>>
-__device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__restrict__ tw,
-                                         const T *__restrict__ sp, const Hook &hook = Hook()) {
+// Pre-processing t_n = s_n (x_n + x_{M-n}) + (x_n - x_{M-n})/2: (n, M-n) pairs are owned by one
+// thread, so no barrier inside; the hook sees every input value (position m = 1..N) as it is
+// read.
+template <typename T, int M, typename Hook>
+__device__ __forceinline__ void dst_pre(C2<T> *buf, int lane, const T *__restrict__ sp, const Hook &hook) {
   constexpr int TPP = M / 16;
-  // pre-processing: (n, M-n) pairs are owned by one thread, so no barrier inside; the hook
-  // sees every input value (position m = 1..N) as it is read
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int n = 1 + lane + TPP * i;
@@ -233,7 +231,13 @@ __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__re
     buf[pad(M - n)] = sum - dif;
   }
   if (lane == 0) buf[pad(0)] = {0, 0};
-  __syncthreads();
+}
+
+// The FFT of the pre-processed pencil pair and the post-processing (prefix scan over the odd
+// outputs); result at positions 1..N.  All threads of the workgroup must call it.
+template <typename T, int M>
+__device__ __forceinline__ void dst_rest(C2<T> *buf, int lane, const C2<T> *__restrict__ tw) {
+  constexpr int TPP = M / 16;
   fft_stages<T, M, 1>(buf, lane, tw);
   // post-processing: lane owns k in [8 lane, 8 lane + 8)
   C2<T> ev[8], od[8];
@@ -267,6 +271,17 @@ __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__re
     buf[pad(2 * k + 1)] = od[i];
   }
   __syncthreads();
+}
+
+// DST-I (unnormalised: y_k = sum_n x_n sin(pi n k / M)) of one pencil pair held in LDS as
+// complex values at positions 1..N; result at the same positions.  All threads of the
+// workgroup must call it (it contains barriers).
+template <typename T, int M, typename Hook = NoHook<T>>
+__device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__restrict__ tw,
+                                         const T *__restrict__ sp, const Hook &hook = Hook()) {
+  dst_pre<T, M>(buf, lane, sp, hook);
+  __syncthreads();
+  dst_rest<T, M>(buf, lane, tw);
 }
 
 template <typename T>
@@ -486,6 +501,66 @@ struct StridedTile {
     }
   }
 
+  // load() followed by the DST pre-processing of every pencil pair of the tile (dst_pre), the
+  // two fused: a thread loads rows r and N-1-r (positions n and M-n) of its columns and writes
+  // t_n and t_{M-n} straight into LDS, which saves one LDS round trip of the tile.  The same
+  // arithmetic as load(), barrier, dst_pre.  A barrier must follow before the transform.
+  template <typename R = AllRows>
+  __device__ static void load_pre(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
+                                  const T *__restrict__ sp, const R &rows = R()) {
+    if constexpr (!VEC) {
+      load(base, RS, CS, x0, sbuf, tid, rows);
+      __syncthreads();
+      dst_pre<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, sp, NoHook<T>());
+    } else {
+      constexpr int VPR = TX / VW, NPR = M / 2, NU = NPR * VPR, PU = (NU + NT - 1) / NT;
+      V16<T> ra[PU][NC], rb[PU][NC];
+#pragma unroll
+      for (int i = 0; i < PU; ++i) {
+        const int e = tid + i * NT;
+        const int s = e % VPR, p = e / VPR, r0 = p, r1 = N - 1 - p;
+        const bool ok0 = e < NU && rows(r0), ok1 = e < NU && rows(r1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const T *q = base + c * CS + x0 + s * VW;
+          if (ok0) ra[i][c] = *reinterpret_cast<const V16<T> *>(q + (int64_t)r0 * RS);
+          else
+#pragma unroll
+            for (int j = 0; j < VW; ++j) ra[i][c].v[j] = T(0);
+          if (ok1) rb[i][c] = *reinterpret_cast<const V16<T> *>(q + (int64_t)r1 * RS);
+          else
+#pragma unroll
+            for (int j = 0; j < VW; ++j) rb[i][c].v[j] = T(0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PU; ++i) {
+        const int e = tid + i * NT;
+        if (e < NU) {
+          const int s = e % VPR, p = e / VPR, n = p + 1;
+          const T sn = sp[n];
+          constexpr int NW = NC == 2 ? VW : VW / 2;     // complex LDS words per 16-byte vector
+#pragma unroll
+          for (int j = 0; j < NW; ++j) {
+            C2<T> a, b;
+            if constexpr (NC == 2) {
+              a = {ra[i][0].v[j], ra[i][1].v[j]};
+              b = {rb[i][0].v[j], rb[i][1].v[j]};
+            } else {
+              a = {ra[i][0].v[2 * j], ra[i][0].v[2 * j + 1]};
+              b = {rb[i][0].v[2 * j], rb[i][0].v[2 * j + 1]};
+            }
+            const C2<T> sum = sn * (a + b), dif = (T)0.5 * (a - b);
+            C2<T> *col = sbuf + (s * NW + j) * PADM;
+            col[pad(n)] = sum + dif;
+            col[pad(M - n)] = sum - dif;
+            if (p == 0) col[pad(0)] = {0, 0};
+          }
+        }
+      }
+    }
+  }
+
   // rows: only rows r with rows(r) true are written
   template <typename R = AllRows>
   __device__ static void store(T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
@@ -633,12 +708,12 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   constexpr int NW = (N + 63) / 64;
-  if constexpr (ZM == 1) Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zin});
-  else Tl::load(ain + boff, LS * P, comp_stride, x0, sbuf, tid);
+  if constexpr (ZM == 1) Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp, BitRows<NW>{zin});
+  else Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
   C2<T> *mine = sbuf + pr * PADM;
-  dst_pair<T, M>(mine, lane, tw, sp);
+  dst_rest<T, M>(mine, lane, tw);
   // inverse transform with the mode solve applied as it reads the spectrum
   ModeHook<T, NC> mh;
   mh.slam = slam;
