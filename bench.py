@@ -254,7 +254,7 @@ def main():
             bd.step(V, q, hist, dt)
         torch.cuda.synchronize()
         kt[name] = {k: prob.kernel_time(k) for k in ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse",
-                                                     "dst_last_sparse", "dst_last_out",
+                                                     "dst_last_sparse", "dst_last_out", "dst_x_fhn",
                                                      "jumps", "correct", "gather")}
         prob.profile(False)
         worst = max(i["rel_resid"] for i in infos)

@@ -305,7 +305,8 @@ const char *kfbi_last_error(void);
  * kernel class ("dst_x", "dst_y", "dst_last" (dense passes), "dst_x_rows", "dst_y_sparse",
  * "dst_last_sparse" (row- and plane-masked passes of the matrix-vector product), "dst_last_out"
  * (the z pass of the volume solve whose result is read only at the interface stencils: every
- * plane read, stencil planes written), "correct", "gather", "jumps").
+ * plane read, stencil planes written), "dst_x_fhn" (the x passes of a bidomain step's box solves
+ * that also carry its reaction half steps), "correct", "gather", "jumps").
  * Returns KFBI_EINVAL if the name is unknown. */
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
 /* DST tile widths (1 or 2: multiples of the base pencil pairs per workgroup) of the x, y and

@@ -127,7 +127,7 @@ struct DevProblem {
 
   bool profile = false;
   Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse, t_dst_last_sparse,
-      t_dst_last_out;
+      t_dst_last_out, t_dst_x_fhn;
   hipStream_t stream = nullptr;
 
   template <typename T>
@@ -187,6 +187,63 @@ void box_solve_matvec(DevProblem &p, hipStream_t st);
 // are read afterwards (identical there to box_solve).
 template <typename T>
 void box_solve_stencils(DevProblem &p, const T *src, hipStream_t st);
+
+// FitzHugh-Nagumo reaction (Sec. 7) and its two half steps in the Strang splitting (Sec. 3):
+// forward Euler, and backward Euler with q eliminated and Newton on V.
+struct FhnCoef {
+  double Cm, H, theta, alpha, zeta, tol;
+  int maxit;
+};
+
+// Forward Euler over dth: (v, g) <- (v - dth I_ion(v, g) / C_m, g + dth (alpha v - zeta g)).
+__device__ __forceinline__ void fhn_fe(double &v, double &g, double dth, const FhnCoef &m) {
+  const double I = m.H * (g - v * (v - m.theta) * (1.0 - v));
+  const double v1 = v + dth * (-I / m.Cm);
+  const double q1 = g + dth * (m.alpha * v - m.zeta * g);
+  v = v1;
+  g = q1;
+}
+
+// Backward Euler over dth from (vb, g): q' = (g + dth alpha V') / (1 + dth zeta) is eliminated
+// and Newton solves for V'; it stops once |F| <= tol and takes one more step.
+__device__ __forceinline__ void fhn_be(double vb, double g, double dth, const FhnCoef &m, double &V, double &q) {
+  const double a = dth * m.alpha / (1.0 + dth * m.zeta);
+  const double qb = g / (1.0 + dth * m.zeta);
+  const double c = dth * m.H / m.Cm;
+  double x = vb;
+  for (int it = 0; it < m.maxit; ++it) {
+    const double cub = x * (x - m.theta) * (1.0 - x);
+    const double F = x - vb + c * (qb + a * x - cub);
+    const double dcub = -3.0 * x * x + 2.0 * (1.0 + m.theta) * x - m.theta;
+    const double dF = 1.0 + c * (a - dcub);
+    const bool ok = fabs(F) <= m.tol;
+    x = x - F / dF;
+    if (ok) break;
+  }
+  V = x;
+  q = qb + a * x;
+}
+
+// Pointwise state of a coupled bidomain step (caller layout, pitch N) handed to the box
+// solves that carry the reaction half steps in their x passes.
+struct FhnArgs {
+  double *V, *q;
+  const double *stim;         // I_stim or null
+  double dth, kappa, beta;
+  FhnCoef m;
+};
+
+// Box solves of a coupled (two-component, FP64) bidomain step whose x passes pair row r of
+// component 0 with row r of component 1, so that both potentials of a node share one complex
+// value and the pointwise work of the splitting rides in those passes:
+//   bidomain_volume_solve: forward Euler half step of (V, q) in place, then S f for
+//     f = (kappa V, -kappa V + beta I) into work (extrapolation-stencil values, as
+//     box_solve_stencils);
+//   bidomain_final_solve: S(f + C psi) with C psi taken from rhs (launch_correct), into work;
+//     with fuse_be the inverse x pass instead finishes the step: V <- 2 (u_i - u_e) - V and the
+//     backward Euler half step of (V, q), and work is left holding the y-inverse output.
+void bidomain_volume_solve(DevProblem &p, const FhnArgs &a, hipStream_t st);
+void bidomain_final_solve(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st);
 
 template <typename T>
 void launch_jumps(DevProblem &p, const T *psi, hipStream_t st);

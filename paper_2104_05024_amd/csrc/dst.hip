@@ -810,6 +810,159 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
   }
 }
 
+// ---------------------------------------------------------------- bidomain x passes
+//
+// The x passes of a coupled bidomain step pair row r of component 0 with row r of component 1
+// (instead of two rows of one component), so that the two potentials of a node share one
+// complex value in LDS.  The reaction half steps of the splitting are pointwise, so they ride
+// in these passes instead of separate sweeps over the box:
+//   FHN_FE   forward Euler half step of (V, q) in place, source f = (kappa V, -kappa V + beta I),
+//            forward DST into work;
+//   FHN_SRC  source f(V) plus the irregular-node correction C psi (rhs, read only on rows flagged
+//            in mask, every row when mask is null), forward DST into work;
+//   FHN_BE   inverse DST of work, then V <- 2 (u_i - u_e) - V and the backward Euler half step.
+// A thread handles whole nodes, so its LDS accesses are unit-stride 16-byte values.  The
+// arithmetic per node is that of the separate sweeps (same expressions, same order).
+enum { FHN_FE = 0, FHN_SRC = 1, FHN_BE = 2 };
+
+template <int M, int MODE>
+__global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a, double *__restrict__ work,
+                                                                    const double *__restrict__ rhs,
+                                                                    const uint64_t *__restrict__ mask, int64_t rows,
+                                                                    int64_t cs, const C2<double> *__restrict__ tw,
+                                                                    const double *__restrict__ sp) {
+  using Sh = Shape<double, M>;
+  using C = C2<double>;
+  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
+  constexpr int NE = NP * N, PER = (NE + NT - 1) / NT;
+  __shared__ C sbuf[NP * PADM];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * NP;
+  double *__restrict__ V = a.V;
+  double *__restrict__ q = a.q;
+  const double *__restrict__ stim = a.stim;
+  double va[PER], qa[PER];
+  if constexpr (MODE == FHN_BE) {
+    C u[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      const bool ok = e < NE && row < rows;
+      u[i] = ok ? C{work[row * M + n], work[cs + row * M + n]} : C{0.0, 0.0};
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      if (e < NE) sbuf[rr * PADM + pad(n + 1)] = u[i];
+    }
+  } else {
+    // rows of the tile holding irregular nodes, from uniform loads of the bit rows [z][16]
+    uint64_t rb = ~uint64_t(0);
+    if constexpr (MODE == FHN_SRC && NP <= 64) {
+      if (mask) {
+        rb = 0;
+        for (int k = 0; k < NP; ++k) {
+          const int64_t row = r0 + k;
+          if (row < rows) {
+            const int64_t z = row / N, y = row - z * N;
+            rb |= ((mask[z * 16 + (y >> 6)] >> (y & 63)) & uint64_t(1)) << k;
+          }
+        }
+      }
+    }
+    auto flagged = [&](int rr) -> bool {
+      if constexpr (NP > 64) return true;
+      else return (rb >> rr) & 1;
+    };
+    double sa[PER], c0[PER], c1[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      const bool ok = e < NE && row < rows;
+      va[i] = ok ? V[row * N + n] : 0.0;
+      if constexpr (MODE == FHN_FE) qa[i] = ok ? q[row * N + n] : 0.0;
+      sa[i] = ok && stim ? stim[row * N + n] : 0.0;
+      if constexpr (MODE == FHN_SRC) {
+        const bool has = ok && flagged(rr);
+        c0[i] = has ? rhs[row * M + n] : 0.0;
+        c1[i] = has ? rhs[cs + row * M + n] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      if (e < NE) {
+        double v = va[i];
+        if constexpr (MODE == FHN_FE) {
+          if (row < rows) {
+            double g = qa[i];
+            fhn_fe(v, g, a.dth, a.m);
+            V[row * N + n] = v;
+            q[row * N + n] = g;
+          }
+        }
+        C f = {a.kappa * v, -a.kappa * v + (stim ? a.beta * sa[i] : 0.0)};
+        if constexpr (MODE == FHN_SRC) {
+          if (row < rows && flagged(rr)) {
+            f.x = f.x + c0[i];
+            f.y = f.y + c1[i];
+          }
+        }
+        sbuf[rr * PADM + pad(n + 1)] = f;
+      }
+    }
+  }
+  __syncthreads();
+  dst_pair<double, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
+  if constexpr (MODE == FHN_BE) {
+    // V and q after the transform: fetched ahead of it they would be held across it in
+    // registers (a second wave per SIMD would no longer fit)
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      const bool ok = e < NE && row < rows;
+      va[i] = ok ? V[row * N + n] : 0.0;
+      qa[i] = ok ? q[row * N + n] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      if (e < NE && row < rows) {
+        const C u = sbuf[rr * PADM + pad(n + 1)];
+        double vn, qn;
+        fhn_be(2.0 * (u.x - u.y) - va[i], qa[i], a.dth, a.m, vn, qn);
+        V[row * N + n] = vn;
+        q[row * N + n] = qn;
+      }
+    }
+  } else {
+    // whole padded rows of both components; the pad column (x = N) is written as zero
+    constexpr int NO = NP * M, PO = (NO + NT - 1) / NT;
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / M, x = e - rr * M;
+      const int64_t row = r0 + rr;
+      if (e < NO && row < rows) {
+        const C v = x < N ? sbuf[rr * PADM + pad(x + 1)] : C{0.0, 0.0};
+        work[row * M + x] = v.x;
+        work[cs + row * M + x] = v.y;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 //
 // Every dense pass exists at two tile widths (W = 1, 2: pencil pairs per workgroup); the
@@ -900,8 +1053,10 @@ ModeScale mode_of(const DevProblem &p) {
   return m;
 }
 
+// skip & 1: work already holds the forward x pass of the source (src unused); skip & 2: stop
+// after the inverse y (3D) / last-axis (2D) pass, leaving its output in work.
 template <typename T, int M>
-void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st) {
+void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain, hipStream_t st, int skip = 0) {
   constexpr int N = M - 1;
   PrecTables<T> &tb = p.tab<T>();
   T *A = tb.work;
@@ -913,9 +1068,11 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
   const ModeScale ms = mode_of<T>(p);
   auto tic = [&](Timer &t) { t.tic(p.profile, st); };
   auto toc = [&](Timer &t) { t.toc(p.profile, st); };
-  tic(p.t_dst_x);
-  pass_x<T, M>(w[0], src, src_plain, A, false, rows, tw, sp, st);
-  toc(p.t_dst_x);
+  if (!(skip & 1)) {
+    tic(p.t_dst_x);
+    pass_x<T, M>(w[0], src, src_plain, A, false, rows, tw, sp, st);
+    toc(p.t_dst_x);
+  }
   if (p.dim == 3) {
     tic(p.t_dst_y);
     pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
@@ -929,17 +1086,20 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
     pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
     toc(p.t_dst_y);
   }
-  tic(p.t_dst_x);
-  pass_x<T, M>(w[0], A, false, dst, dst_plain, rows, tw, sp, st);
-  toc(p.t_dst_x);
+  if (!(skip & 2)) {
+    tic(p.t_dst_x);
+    pass_x<T, M>(w[0], A, false, dst, dst_plain, rows, tw, sp, st);
+    toc(p.t_dst_x);
+  }
 }
 
 // Box solve whose result is read only at extrapolation-stencil nodes (the volume part of the
 // BIE right-hand side): dense forward passes, then the z pass writes and the inverse y and x
 // passes transform only the planes and rows that hold stencil nodes.  Result in work; the
 // values at every stencil node are identical to the full solve.
+// skip_x: work already holds the forward x pass of the source (src unused).
 template <typename T, int M>
-void run_box_stencils(DevProblem &p, const T *src, hipStream_t st) {
+void run_box_stencils(DevProblem &p, const T *src, hipStream_t st, bool skip_x = false) {
   constexpr int N = M - 1;
   using Sh = Shape<T, M>;
   PrecTables<T> &tb = p.tab<T>();
@@ -952,9 +1112,11 @@ void run_box_stencils(DevProblem &p, const T *src, hipStream_t st) {
   const ModeScale ms = mode_of<T>(p);
   auto tic = [&](Timer &t) { t.tic(p.profile, st); };
   auto toc = [&](Timer &t) { t.toc(p.profile, st); };
-  tic(p.t_dst_x);
-  pass_x<T, M>(w[0], src, false, A, false, rows, tw, sp, st);
-  toc(p.t_dst_x);
+  if (!skip_x) {
+    tic(p.t_dst_x);
+    pass_x<T, M>(w[0], src, false, A, false, rows, tw, sp, st);
+    toc(p.t_dst_x);
+  }
   tic(p.t_dst_y);
   pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
   toc(p.t_dst_y);
@@ -969,6 +1131,35 @@ void run_box_stencils(DevProblem &p, const T *src, hipStream_t st) {
   if (gout) k_dst_x_rows<T, M><<<gout, Sh::NT, 0, st>>>(A, A, p.rows_out, p.n_rows_out, tw, sp);
   KFBI_HIP(hipGetLastError());
   toc(p.t_dst_x_rows);
+}
+
+template <int M, int MODE>
+void launch_x_fhn(DevProblem &p, const FhnArgs &a, hipStream_t st) {
+  using Sh = Shape<double, M>;
+  if (p.ncomp != 2 || p.P != M) throw std::invalid_argument("bidomain x pass: coupled pair in the padded layout");
+  const int64_t rows = p.dim == 3 ? p.N * p.N : p.N;
+  const unsigned g = (unsigned)((rows + Sh::NP - 1) / Sh::NP);
+  const uint64_t *mask = MODE == FHN_SRC && p.dim == 3 && p.sparse ? p.mask_in : nullptr;
+  PrecTables<double> &tb = p.f64;
+  p.t_dst_x_fhn.tic(p.profile, st);
+  k_dst_x_fhn<M, MODE><<<g, Sh::NT, 0, st>>>(a, tb.work, tb.rhs, mask, rows, p.comp_stride,
+                                             reinterpret_cast<const C2<double> *>(tb.tw), tb.sp);
+  KFBI_HIP(hipGetLastError());
+  p.t_dst_x_fhn.toc(p.profile, st);
+}
+
+template <int M>
+void run_bidomain_volume(DevProblem &p, const FhnArgs &a, hipStream_t st) {
+  launch_x_fhn<M, FHN_FE>(p, a, st);
+  if (p.dim == 3 && p.sparse) run_box_stencils<double, M>(p, nullptr, st, true);
+  else run_box<double, M>(p, nullptr, false, p.f64.work, false, st, 1);
+}
+
+template <int M>
+void run_bidomain_final(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st) {
+  launch_x_fhn<M, FHN_SRC>(p, a, st);
+  run_box<double, M>(p, nullptr, false, p.f64.work, false, st, fuse_be ? 3 : 1);
+  if (fuse_be) launch_x_fhn<M, FHN_BE>(p, a, st);
 }
 
 // Box solve inside the matrix-vector product: the right-hand side is zero outside the rows
@@ -1204,6 +1395,32 @@ void box_solve_stencils(DevProblem &p, const T *src, hipStream_t st) {
   }
 }
 template void box_solve_stencils<double>(DevProblem &, const double *, hipStream_t);
+
+void bidomain_volume_solve(DevProblem &p, const FhnArgs &a, hipStream_t st) {
+  switch (p.Mfft) {
+    case 16: run_bidomain_volume<16>(p, a, st); break;
+    case 32: run_bidomain_volume<32>(p, a, st); break;
+    case 64: run_bidomain_volume<64>(p, a, st); break;
+    case 128: run_bidomain_volume<128>(p, a, st); break;
+    case 256: run_bidomain_volume<256>(p, a, st); break;
+    case 512: run_bidomain_volume<512>(p, a, st); break;
+    case 1024: run_bidomain_volume<1024>(p, a, st); break;
+    default: throw std::invalid_argument("unsupported grid size");
+  }
+}
+
+void bidomain_final_solve(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st) {
+  switch (p.Mfft) {
+    case 16: run_bidomain_final<16>(p, a, fuse_be, st); break;
+    case 32: run_bidomain_final<32>(p, a, fuse_be, st); break;
+    case 64: run_bidomain_final<64>(p, a, fuse_be, st); break;
+    case 128: run_bidomain_final<128>(p, a, fuse_be, st); break;
+    case 256: run_bidomain_final<256>(p, a, fuse_be, st); break;
+    case 512: run_bidomain_final<512>(p, a, fuse_be, st); break;
+    case 1024: run_bidomain_final<1024>(p, a, fuse_be, st); break;
+    default: throw std::invalid_argument("unsupported grid size");
+  }
+}
 
 template <typename T>
 void box_solve_matvec(DevProblem &p, hipStream_t st) {

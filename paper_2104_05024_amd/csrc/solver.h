@@ -47,14 +47,18 @@ struct Solver {
   int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
                  int &its, int &matvecs, double &resid, hipStream_t st, double *r0 = nullptr);
   // g' = g - n.D grad (S f)+, with f already in fpad (padded). g may be null.
-  void bie_rhs(DevProblem &p, const double *g, hipStream_t st);
+  // fa: bidomain step (source from V after the forward Euler half step it performs; fpad unused)
+  void bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnArgs *fa = nullptr);
   // psi solve of A psi = gp with the options; psi holds the start if x0 = 1; r0 (optional) is
   // its residual gp - A psi if already known.  Afterwards last_resid holds gp - A64 psi.
   int solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
                     hipStream_t st, const double *r0 = nullptr);
   const double *last_resid = nullptr;
   // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added)
-  void reconstruct(DevProblem &p, const double *psi, hipStream_t st);
+  // fa: bidomain step (source from V); fuse_be: the inverse x pass also finishes the step
+  // (midpoint update and backward Euler half step), leaving no potentials in work
+  void reconstruct(DevProblem &p, const double *psi, hipStream_t st, const FhnArgs *fa = nullptr,
+                   bool fuse_be = false);
   double gauge_mean(DevProblem &p, hipStream_t st);   // mean over tissue nodes of comp 1 of work
   int solve_neumann(DevProblem &p, const double *g, const double *f, double *u, double *psi,
                     const kfbi_solve_opts &o, kfbi_solve_info &info, hipStream_t st);

@@ -150,62 +150,21 @@ __global__ __launch_bounds__(kB) void k_masked_sum(const double *__restrict__ u,
 
 // ---------------------------------------------------------------- FitzHugh-Nagumo kernels
 
-struct Fhn {
-  double Cm, H, theta, alpha, zeta, tol;
-  int maxit;
-};
-
-// Step 1 of the splitting (forward Euler over dt/2) fused with the diffusion source
-// f = (kappa V, -kappa V) written into the padded field.
-__global__ __launch_bounds__(kB) void k_fe_rhs(double *__restrict__ V, double *__restrict__ q,
-                                               double *__restrict__ fpad, int64_t n, int64_t N, int64_t P,
-                                               int64_t cs, double dth, double kappa, Fhn m,
-                                               const double *__restrict__ stim, double beta) {
-  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
-  const double v = V[i], g = q[i];
-  const double I = m.H * (g - v * (v - m.theta) * (1.0 - v));
-  const double v1 = v + dth * (-I / m.Cm);
-  const double q1 = g + dth * (m.alpha * v - m.zeta * g);
-  V[i] = v1;
-  q[i] = q1;
-  const int64_t pos = (i % N) + P * (i / N);
-  fpad[pos] = kappa * v1;
-  fpad[cs + pos] = -kappa * v1 + (stim ? beta * stim[i] : 0.0);
-}
-
-// Midpoint update V <- 2 (u_i - u_e) - V, then step 3 (backward Euler over dt/2, Newton on V
-// with q eliminated: q' = (q + dt/2 alpha V') / (1 + dt/2 zeta)); Newton stops once
-// |F| <= tol and takes one more step.  Optionally writes the gauged potentials.
+// Midpoint update V <- 2 (u_i - u_e) - V and step 3 (backward Euler over dt/2) when the
+// potentials are also returned: writes them in the gauge of the given mean.  (Without them the
+// inverse x pass of the final box solve does this work.)
 __global__ __launch_bounds__(kB) void k_mid_be(const double *__restrict__ u, double *__restrict__ V,
                                                double *__restrict__ q, double *__restrict__ phi,
                                                const double *__restrict__ mean, int64_t n, int64_t N, int64_t P,
-                                               int64_t cs, double dth, Fhn m) {
+                                               int64_t cs, double dth, FhnCoef m) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   const int64_t pos = (i % N) + P * (i / N);
   const double ui = u[pos], ue = u[cs + pos];
-  const double vb = 2.0 * (ui - ue) - V[i];
-  const double a = dth * m.alpha / (1.0 + dth * m.zeta);
-  const double qb = q[i] / (1.0 + dth * m.zeta);
-  const double c = dth * m.H / m.Cm;
-  double x = vb;
-  bool conv = false;
-  for (int it = 0; it < m.maxit; ++it) {
-    const double cub = x * (x - m.theta) * (1.0 - x);
-    const double F = x - vb + c * (qb + a * x - cub);
-    const double dcub = -3.0 * x * x + 2.0 * (1.0 + m.theta) * x - m.theta;
-    const double dF = 1.0 + c * (a - dcub);
-    const bool ok = fabs(F) <= m.tol;
-    x = x - F / dF;
-    if (ok) {
-      conv = true;
-      break;
-    }
-  }
-  (void)conv;
-  V[i] = x;
-  q[i] = qb + a * x;
+  double vn, qn;
+  fhn_be(2.0 * (ui - ue) - V[i], q[i], dth, m, vn, qn);
+  V[i] = vn;
+  q[i] = qn;
   if (phi) {
     const double s = mean ? mean[0] : 0.0;
     phi[i] = ui - s;
@@ -488,9 +447,10 @@ int Solver::richardson(DevProblem &p, const double *b, double bnorm, double *x, 
   return resid <= tol_abs ? KFBI_OK : KFBI_ENOCONV;
 }
 
-void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st) {
+void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnArgs *fa) {
   // u_V is needed only at the extrapolation stencils of the interface nodes
-  box_solve_stencils<double>(p, fpad, st);
+  if (fa) bidomain_volume_solve(p, *fa, st);
+  else box_solve_stencils<double>(p, fpad, st);
   launch_gather<double>(p, p.f64.work, false, t, st);
   if (g)
     k_axpby<<<nblk(L), kB, 0, st>>>(gp, 1.0, g, -1.0, t, L);
@@ -557,8 +517,13 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
   return rc;
 }
 
-void Solver::reconstruct(DevProblem &p, const double *psi, hipStream_t st) {
+void Solver::reconstruct(DevProblem &p, const double *psi, hipStream_t st, const FhnArgs *fa, bool fuse_be) {
   launch_jumps<double>(p, psi, st);
+  if (fa) {
+    launch_correct<double>(p, st);
+    bidomain_final_solve(p, *fa, fuse_be, st);
+    return;
+  }
   launch_add_correction<double>(p, fpad, st);
   box_solve<double>(p, fpad, false, p.f64.work, false, st);
 }
@@ -703,13 +668,12 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   Solver &sv = *solver;
   const int64_t n = (int64_t)p.ht.inside.size(), L = sv.L;
   const double dth = 0.5 * dt;
-  Fhn m{params.Cm, params.H, params.theta, params.alpha, params.zeta, params.newton_tol, params.newton_maxit};
-  // step 1: reaction over dt/2 and the diffusion source
-  k_fe_rhs<<<nblk(n), kB, 0, st>>>(s.V, s.q, sv.fpad, n, p.N, p.P, p.comp_stride, dth, p.kappa, m, s.I_stim,
-                                   params.beta);
-  KFBI_HIP(hipGetLastError());
+  const FhnCoef m{params.Cm, params.H, params.theta, params.alpha, params.zeta, params.newton_tol,
+                  params.newton_maxit};
+  const FhnArgs fa{s.V, s.q, s.I_stim, dth, p.kappa, params.beta, m};
+  // step 1 (reaction over dt/2, forward Euler) rides in the first x pass of the volume solve of
   // step 2: diffusion, backward Euler over dt/2 for w = (V^{n+1} + V^n)/2 (Neumann BVP)
-  sv.bie_rhs(p, nullptr, st);
+  sv.bie_rhs(p, nullptr, st, &fa);
   double *hist1 = s.psi_hist, *hist2 = s.psi_hist + L;
   kfbi_solve_opts o = params.solve;
   bool x0 = true;
@@ -783,17 +747,16 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   KFBI_HIP(hipMemcpyAsync(d_prev, sv.last_resid, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   have_prev = true;
   if (params.warm_start == 3) proj_record(psi0, st);
-  sv.reconstruct(p, psi0, st);
-  double *meanp = nullptr;
+  // u = S(f + C psi); the midpoint update and step 3 (reaction over dt/2, backward Euler) ride
+  // in its inverse x pass unless the potentials are returned as well
+  sv.reconstruct(p, psi0, st, &fa, s.phi == nullptr);
   if (s.phi) {
     const double mu = sv.gauge_mean(p, st);
     sv.hhost[0] = mu;
     KFBI_HIP(hipMemcpyAsync(sv.ydev, sv.hhost, sizeof(double), hipMemcpyHostToDevice, st));
-    meanp = sv.ydev;
+    k_mid_be<<<nblk(n), kB, 0, st>>>(p.f64.work, s.V, s.q, s.phi, sv.ydev, n, p.N, p.P, p.comp_stride, dth, m);
+    KFBI_HIP(hipGetLastError());
   }
-  // midpoint update and step 3: reaction over dt/2 (backward Euler)
-  k_mid_be<<<nblk(n), kB, 0, st>>>(p.f64.work, s.V, s.q, s.phi, meanp, n, p.N, p.P, p.comp_stride, dth, m);
-  KFBI_HIP(hipGetLastError());
   // record (features, target) once two earlier densities and g'^{n-1} exist
   if (mlp && steps_done >= 2) {
     mlp_record(this, hist1, hist2, psi0, st);

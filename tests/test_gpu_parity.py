@@ -264,6 +264,28 @@ def test_bidomain_mixed_precision_step():
     bd.close()
 
 
+def test_bidomain_state_does_not_depend_on_returning_potentials():
+    """Without phi the midpoint update and the backward Euler half step ride in the inverse x
+    pass of the final box solve; with phi they run as a separate sweep after the gauge.  Both
+    give the same V and q."""
+    g, o, iface, grid, co = problems("ellipsoid_bido_32")
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    out = []
+    for with_phi in (False, True):
+        say(f"[bidomain] phi returned: {with_phi}")
+        bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+        V, q = T(V0), T(q0)
+        hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+        phi = torch.zeros(2, V0.size, dtype=torch.float64, device=DEV) if with_phi else None
+        for _ in range(3):
+            bd.step(V, q, hist, 0.01, phi=phi)
+        out.append((V.cpu().numpy(), q.cpu().numpy()))
+        bd.close()
+    (Va, qa), (Vb, qb) = out
+    assert np.max(np.abs(Va - Vb)) <= 1e-10 * np.max(np.abs(Vb))
+    assert np.max(np.abs(qa - qb)) <= 1e-10 * max(np.max(np.abs(qb)), 1e-30)
+
+
 # ----------------------------------------------------------------------------- 128^3 full parity
 
 def test_apply_and_solve_full_size_ellipsoid_128():
