@@ -78,19 +78,7 @@ inline uint16_t f2bf_host(float x) {
 
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
 
-// |x| maxima: per-block partials then one block finishes (fixed order)
-__global__ __launch_bounds__(kB) void k_absmax(const double *__restrict__ x, int64_t n, double *__restrict__ part) {
-  __shared__ double s[kB];
-  double m = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) m = fmax(m, fabs(x[i]));
-  s[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
-}
+// |x| maxima: one block finishes the per-block partials (fixed order)
 __global__ __launch_bounds__(kB) void k_absmax_finish(const double *__restrict__ part, int nb, double *__restrict__ out) {
   __shared__ double s[kB];
   double m = 0;
@@ -376,11 +364,6 @@ __global__ __launch_bounds__(kB) void k_adam(float *__restrict__ p, float *__res
   p[i] = x;
   if (pb) pb[i] = f2bf(x);
   g[i] = 0.f;
-}
-
-__global__ __launch_bounds__(kB) void k_tobf16(const float *__restrict__ p, uint16_t *__restrict__ pb, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i < n) pb[i] = f2bf(p[i]);
 }
 
 template <typename T>

@@ -70,44 +70,65 @@ __global__ __launch_bounds__(kB) void k_combine(double *__restrict__ w, const do
   w[i] += sign * acc;
 }
 
-// Arnoldi step with j in device memory: w -= sum_{k <= j} h[k] V_k; V_{j+1} = w / ||w||;
-// v = V_j; j <- j + 1
-__global__ __launch_bounds__(kB) void k_combine_j(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
-                                                  const double *__restrict__ h, const int *__restrict__ jdev,
-                                                  int64_t n) {
+// Sum of the nb block partials of row k by one wave: lane-strided sums, then a butterfly (every
+// lane ends with the same value).
+__device__ __forceinline__ double wave_sum_partials(const double *__restrict__ partials, int nb, int k) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0;
+  for (int i = lane; i < nb; i += 64) acc += partials[(int64_t)k * nb + i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  return acc;
+}
+
+// One classical Gram-Schmidt pass after k_multidot: every block sums the partials into
+// h_k (k < K; the sums are identical in every block), then w -= sum_k h_k V_k; block 0 stores h
+// for the Hessenberg column.  K = *jdev + 1 when jdev is given (the captured step).
+__global__ __launch_bounds__(kB) void k_cgs_combine(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
+                                                    const double *__restrict__ partials, int nb,
+                                                    double *__restrict__ hout, const int *__restrict__ jdev, int K,
+                                                    int64_t n) {
+  __shared__ double hs[Solver::kMaxRestart + 1];
+  if (jdev) K = *jdev + 1;
+  for (int k = threadIdx.x >> 6; k < K; k += kB / 64) {
+    const double s = wave_sum_partials(partials, nb, k);
+    if ((threadIdx.x & 63) == 0) hs[k] = s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < K; k += kB) hout[k] = hs[k];
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
-  const int K = *jdev + 1;
   double acc = 0;
-  for (int k = 0; k < K; ++k) acc += h[k] * V[(int64_t)k * ldv + i];
+  for (int k = 0; k < K; ++k) acc += hs[k] * V[(int64_t)k * ldv + i];
   w[i] -= acc;
 }
 
-__global__ __launch_bounds__(kB) void k_next_j(double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
-                                               const double *__restrict__ nrm2, const int *__restrict__ jdev,
-                                               int64_t n) {
+// The norm after k_multidot of w with itself: V_{j+1} = w / ||w|| (j = *jdev when given, else
+// jh), also into vnext when given (the next step's input); block 0 stores ||w||^2.  w may be
+// V_{j+1} itself.
+__global__ __launch_bounds__(kB) void k_normalize(double *V, int64_t ldv, const double *w,
+                                                  const double *__restrict__ partials, int nb,
+                                                  double *__restrict__ hout, const int *__restrict__ jdev, int jh,
+                                                  double *__restrict__ vnext, int64_t n) {
+  __shared__ double s0;
+  if (threadIdx.x < 64) {
+    const double s = wave_sum_partials(partials, nb, 0);
+    if (threadIdx.x == 0) s0 = s;
+  }
+  __syncthreads();
+  const double nrm2 = s0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm2;
+  const int j = jdev ? *jdev : jh;
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
-  const double s = *nrm2 > 0 ? 1.0 / sqrt(*nrm2) : 0.0;   // as k_scale_inv_sqrt: same rounding
-  V[(int64_t)(*jdev + 1) * ldv + i] = w[i] * s;
-}
-
-__global__ __launch_bounds__(kB) void k_take_j(const double *__restrict__ V, int64_t ldv,
-                                               const int *__restrict__ jdev, double *__restrict__ v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i < n) v[i] = V[(int64_t)(*jdev) * ldv + i];
+  const double sc = nrm2 > 0 ? 1.0 / sqrt(nrm2) : 0.0;
+  const double v = w[i] * sc;
+  V[(int64_t)(j + 1) * ldv + i] = v;
+  if (vnext) vnext[i] = v;
 }
 
 __global__ void k_inc_j(int *j) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *j += 1;
-}
-
-__global__ __launch_bounds__(kB) void k_scale_inv_sqrt(double *__restrict__ y, const double *__restrict__ x,
-                                                       const double *__restrict__ nrm2, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
-  const double s = nrm2[0] > 0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
-  y[i] = x[i] * s;
 }
 
 __global__ __launch_bounds__(kB) void k_axpby(double *__restrict__ z, double a, const double *__restrict__ x,
@@ -271,20 +292,16 @@ double Solver::dot(const double *a, const double *b, hipStream_t st) {
 }
 
 // One Arnoldi step with j read from device memory (so one captured graph serves every j):
-// v = V_j, w = A v, two classical Gram-Schmidt passes against V_0..V_j, the norm, V_{j+1},
-// the Hessenberg column to pinned host memory, j <- j + 1.
+// w = A v for v = V_j (held in vin), two classical Gram-Schmidt passes against V_0..V_j, the
+// norm, V_{j+1} (also into vin), the Hessenberg column to pinned host memory, j <- j + 1.
 void Solver::arnoldi_step(DevProblem &p, int prec, int m, hipStream_t st) {
-  k_take_j<<<nblk(L), kB, 0, st>>>(V, L, jdev, vin, L);
   apply_vec(p, prec, vin, wv, st);
   for (int pass = 0; pass < 2; ++pass) {
-    double *h = hdev + pass * (kMaxRestart + 2);
     k_multidot<<<dim3(nb, m), kB, 0, st>>>(V, L, wv, L, partials, jdev);
-    k_finish<<<m, kB, 0, st>>>(partials, nb, h, jdev);
-    k_combine_j<<<nblk(L), kB, 0, st>>>(wv, V, L, h, jdev, L);
+    k_cgs_combine<<<nblk(L), kB, 0, st>>>(wv, V, L, partials, nb, hdev + pass * (kMaxRestart + 2), jdev, 0, L);
   }
   k_multidot<<<dim3(nb, 1), kB, 0, st>>>(wv, L, wv, L, partials);
-  k_finish<<<1, kB, 0, st>>>(partials, nb, hdev + 2 * (kMaxRestart + 2));
-  k_next_j<<<nblk(L), kB, 0, st>>>(V, L, wv, hdev + 2 * (kMaxRestart + 2), jdev, L);
+  k_normalize<<<nblk(L), kB, 0, st>>>(V, L, wv, partials, nb, hdev + 2 * (kMaxRestart + 2), jdev, 0, vin, L);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
   k_inc_j<<<1, 1, 0, st>>>(jdev);
@@ -351,6 +368,7 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
     if (graphed) {
       *jhost = 0;
       KFBI_HIP(hipMemcpyAsync(jdev, jhost, sizeof(int), hipMemcpyHostToDevice, st));
+      k_axpby<<<nblk(L), kB, 0, st>>>(vin, 1.0 / beta, r, 0.0, nullptr, L);   // the first step's input V_0
     }
     for (int j = 0; j < m; ++j) {
       if (graphed) {
@@ -361,12 +379,12 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
         // classical Gram-Schmidt, twice; then the norm
         for (int pass = 0; pass < 2; ++pass) {
           k_multidot<<<dim3(nb, j + 1), kB, 0, st>>>(V, L, vn, L, partials);
-          k_finish<<<j + 1, kB, 0, st>>>(partials, nb, hdev + pass * (kMaxRestart + 2));
-          k_combine<<<nblk(L), kB, 0, st>>>(vn, V, L, hdev + pass * (kMaxRestart + 2), j + 1, -1.0, L);
+          k_cgs_combine<<<nblk(L), kB, 0, st>>>(vn, V, L, partials, nb, hdev + pass * (kMaxRestart + 2), nullptr,
+                                                j + 1, L);
         }
         k_multidot<<<dim3(nb, 1), kB, 0, st>>>(vn, L, vn, L, partials);
-        k_finish<<<1, kB, 0, st>>>(partials, nb, hdev + 2 * (kMaxRestart + 2));
-        k_scale_inv_sqrt<<<nblk(L), kB, 0, st>>>(vn, vn, hdev + 2 * (kMaxRestart + 2), L);
+        k_normalize<<<nblk(L), kB, 0, st>>>(V, L, vn, partials, nb, hdev + 2 * (kMaxRestart + 2), nullptr, j, nullptr,
+                                            L);
         KFBI_HIP(hipGetLastError());
         KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
       }
