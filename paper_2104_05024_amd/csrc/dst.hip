@@ -213,11 +213,25 @@ struct NoHook {
   __device__ __forceinline__ void operator()(int, C2<T> &) const {}
 };
 
+// s_n = sin(pi n / M) at the positions n = 1 + lane + (M/16) i, i < 8, that one thread's
+// pre-processing combines, from a table in global memory or LDS.  Kernels load them from
+// memory with their tile, so that the pre-processing, which follows a barrier, does not wait
+// on memory (the last-axis pass reads them from an LDS copy instead, to hold no registers
+// across its forward transform).
+template <typename T, int M>
+struct Sines {
+  T s[8];
+  __device__ __forceinline__ Sines(const T *sp, int lane) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] = sp[1 + lane + (M / 16) * i];
+  }
+};
+
 // Pre-processing t_n = s_n (x_n + x_{M-n}) + (x_n - x_{M-n})/2: (n, M-n) pairs are owned by one
 // thread, so no barrier inside; the hook sees every input value (position m = 1..N) as it is
 // read.
 template <typename T, int M, typename Hook>
-__device__ __forceinline__ void dst_pre(C2<T> *buf, int lane, const T *__restrict__ sp, const Hook &hook) {
+__device__ __forceinline__ void dst_pre(C2<T> *buf, int lane, const Sines<T, M> &sn, const Hook &hook) {
   constexpr int TPP = M / 16;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -225,7 +239,7 @@ __device__ __forceinline__ void dst_pre(C2<T> *buf, int lane, const T *__restric
     C2<T> a = buf[pad(n)], b = buf[pad(M - n)];
     hook(n, a);
     hook(M - n, b);
-    const T s = sp[n];
+    const T s = sn.s[i];
     const C2<T> sum = s * (a + b), dif = (T)0.5 * (a - b);
     buf[pad(n)] = sum + dif;
     buf[pad(M - n)] = sum - dif;
@@ -278,8 +292,8 @@ __device__ __forceinline__ void dst_rest(C2<T> *buf, int lane, const C2<T> *__re
 // workgroup must call it (it contains barriers).
 template <typename T, int M, typename Hook = NoHook<T>>
 __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__restrict__ tw,
-                                         const T *__restrict__ sp, const Hook &hook = Hook()) {
-  dst_pre<T, M>(buf, lane, sp, hook);
+                                         const Sines<T, M> &sn, const Hook &hook = Hook()) {
+  dst_pre<T, M>(buf, lane, sn, hook);
   __syncthreads();
   dst_rest<T, M>(buf, lane, tw);
 }
@@ -314,6 +328,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restr
   __shared__ C2<T> sbuf[NP * PADM];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  const Sines<T, M> sn(sp, tid % Sh::TPP);
   if constexpr (PIN) {
     constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
     V16<T> reg[PER];
@@ -360,7 +375,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restr
     }
   }
   __syncthreads();
-  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
+  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
   if constexpr (POUT) {
     constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
     V16<T> reg[PER];
@@ -511,7 +526,7 @@ struct StridedTile {
     if constexpr (!VEC) {
       load(base, RS, CS, x0, sbuf, tid, rows);
       __syncthreads();
-      dst_pre<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, sp, NoHook<T>());
+      dst_pre<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, Sines<T, M>(sp, tid % Sh::TPP), NoHook<T>());
     } else {
       constexpr int VPR = TX / VW, NPR = M / 2, NU = NPR * VPR, PU = (NU + NT - 1) / NT;
       V16<T> ra[PU][NC], rb[PU][NC];
@@ -637,9 +652,10 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_y(const T *__restr
   const int64_t off = c * comp_stride + (int64_t)z * Sh::N * P;
   if (planes && !planes[z]) return;   // nothing to read or write in this plane (whole workgroup)
   constexpr int NW = (Sh::N + 63) / 64;
+  const Sines<T, M> sn(sp, tid % Sh::TPP);
   Tl::load(in + off, P, 0, x0, sbuf, tid, BitRowsMem<NW>(mask_in ? mask_in + (int64_t)z * 16 : nullptr));
   __syncthreads();
-  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * Sh::PADM, tid % Sh::TPP, tw, sp);
+  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * Sh::PADM, tid % Sh::TPP, tw, sn);
   Tl::store(out + off, P, 0, x0, sbuf, tid, BitRowsMem<NW>(mask_out ? mask_out + (int64_t)z * 16 : nullptr));
 }
 
@@ -694,6 +710,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   using Tl = StridedTile<T, M, TX, NC, W>;
   __shared__ C2<T> sbuf[NP * PADM];
   __shared__ T slam[M];
+  __shared__ T ssin[M / 2 + 1];
   const int tid = threadIdx.x;
   // At W = 1 a tile row of TX columns is half of a 128-byte line; the tile sharing the line is
   // given to the workgroup dispatched 8 later, i.e. on the same XCD (round-robin dispatch), so
@@ -707,6 +724,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   T *base = a + boff;
   const ModeScale ms = (DIM == 2 && msv) ? msv[by] : ms0;
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
+  for (int i = tid; i <= M / 2; i += NT) ssin[i] = sp[i];
   constexpr int NW = (N + 63) / 64;
   if constexpr (ZM == 1) Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp, BitRows<NW>{zin});
   else Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
@@ -738,7 +756,7 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   }
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
-  dst_pair<T, M>(mine, lane, tw, sp, mh);
+  dst_pair<T, M>(mine, lane, tw, Sines<T, M>(ssin, lane), mh);
   if constexpr (ZM != 0) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
   else Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
@@ -767,6 +785,7 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
     for (int k = 0; k < ROWS; ++k) v = rr == k ? ri[k] : v;
     return v;
   };
+  const Sines<T, M> sn(sp, tid % Sh::TPP);
   V16<T> reg[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
@@ -791,7 +810,7 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
     }
   }
   __syncthreads();
-  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
+  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = tid + i * NT;
@@ -841,6 +860,7 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
   double *__restrict__ V = a.V;
   double *__restrict__ q = a.q;
   const double *__restrict__ stim = a.stim;
+  const Sines<double, M> sn(sp, tid % Sh::TPP);
   double va[PER], qa[PER];
   if constexpr (MODE == FHN_BE) {
     C u[PER];
@@ -859,24 +879,6 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
       if (e < NE) sbuf[rr * PADM + pad(n + 1)] = u[i];
     }
   } else {
-    // rows of the tile holding irregular nodes, from uniform loads of the bit rows [z][16]
-    uint64_t rb = ~uint64_t(0);
-    if constexpr (MODE == FHN_SRC && NP <= 64) {
-      if (mask) {
-        rb = 0;
-        for (int k = 0; k < NP; ++k) {
-          const int64_t row = r0 + k;
-          if (row < rows) {
-            const int64_t z = row / N, y = row - z * N;
-            rb |= ((mask[z * 16 + (y >> 6)] >> (y & 63)) & uint64_t(1)) << k;
-          }
-        }
-      }
-    }
-    auto flagged = [&](int rr) -> bool {
-      if constexpr (NP > 64) return true;
-      else return (rb >> rr) & 1;
-    };
     double sa[PER], c0[PER], c1[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -887,8 +889,42 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
       va[i] = ok ? V[row * N + n] : 0.0;
       if constexpr (MODE == FHN_FE) qa[i] = ok ? q[row * N + n] : 0.0;
       sa[i] = ok && stim ? stim[row * N + n] : 0.0;
-      if constexpr (MODE == FHN_SRC) {
-        const bool has = ok && flagged(rr);
+    }
+    // rows of the tile holding irregular nodes, from uniform loads of the bit rows [z][16]
+    // (all issued before the first is used: the correction loads wait on them)
+    uint64_t rb = ~uint64_t(0);
+    if constexpr (MODE == FHN_SRC && NP <= 64) {
+      if (mask) {
+        constexpr int NB = NP < 16 ? NP : 16;
+        rb = 0;
+#pragma unroll 1
+        for (int k0 = 0; k0 < NP; k0 += NB) {
+          uint64_t wd[NB];
+          int sh[NB];
+#pragma unroll
+          for (int k = 0; k < NB; ++k) {
+            const int64_t row = r0 + k0 + k < rows ? r0 + k0 + k : rows - 1;
+            const int64_t z = row / N, y = row - z * N;
+            wd[k] = mask[z * 16 + (y >> 6)];
+            sh[k] = (int)(y & 63);
+          }
+#pragma unroll
+          for (int k = 0; k < NB; ++k)
+            rb |= ((wd[k] >> sh[k]) & uint64_t(r0 + k0 + k < rows)) << (k0 + k);
+        }
+      }
+    }
+    auto flagged = [&](int rr) -> bool {
+      if constexpr (NP > 64) return true;
+      else return (rb >> rr) & 1;
+    };
+    if constexpr (MODE == FHN_SRC) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / N, n = e - rr * N;
+        const int64_t row = r0 + rr;
+        const bool has = e < NE && row < rows && flagged(rr);
         c0[i] = has ? rhs[row * M + n] : 0.0;
         c1[i] = has ? rhs[cs + row * M + n] : 0.0;
       }
@@ -920,7 +956,7 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
     }
   }
   __syncthreads();
-  dst_pair<double, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sp);
+  dst_pair<double, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
   if constexpr (MODE == FHN_BE) {
     // V and q after the transform: fetched ahead of it they would be held across it in
     // registers (a second wave per SIMD would no longer fit)

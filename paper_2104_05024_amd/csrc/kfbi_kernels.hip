@@ -1,9 +1,9 @@
 // Interface-side kernels of the KFBI matrix-vector product and the table upload.
 //
-//  k_jumps_cross : density -> jumps [u_a], [u_aa] at every grid-line intersection
+//  k_jumps       : density -> jumps [u_a], [u_aa] at every grid-line intersection
 //                  (single-layer interface problem, Sec. 5.1 eq. single; jump relations
-//                  from [u] = 0 and [n.D grad u] = psi for diagonal D_c).
-//  k_jumps_nodes : density -> [grad u] and [Hess u] at every interface node.
+//                  from [u] = 0 and [n.D grad u] = psi for diagonal D_c), and
+//                  [grad u], [Hess u] at every interface node, in one launch.
 //  k_correct     : right-hand-side correction at irregular grid nodes (Sec. 5.3, eq.
 //                  correct): rhs_p = sum_arms s_p D_{c,a}/h^2 ([u_a] d + [u_aa] d^2 / 2).
 //                  One thread owns one irregular node, so no atomics are needed.
@@ -48,14 +48,6 @@ __device__ __forceinline__ void jumps_cross_at(int64_t c, const T *__restrict__ 
     jz[(2 * comp) * nc + c] = ju;
     jz[(2 * comp + 1) * nc + c] = juu;
   }
-}
-
-template <typename T, int K>
-__global__ __launch_bounds__(kBlock) void k_jumps_cross(const T *__restrict__ psi, int64_t M, int64_t nc,
-                                                        const int32_t *__restrict__ z_idx, const T *__restrict__ zA,
-                                                        const T *__restrict__ zB, int ncomp, T *__restrict__ jz) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < nc) jumps_cross_at<T, K>(c, psi, M, nc, z_idx, zA, zB, ncomp, jz);
 }
 
 // One thread per irregular node; at most 2D arms, loaded predicated and all at once.
@@ -162,13 +154,22 @@ __device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ 
   }
 }
 
-template <typename T, int D, int KN>
-__global__ __launch_bounds__(kBlock) void k_jumps_nodes(const T *__restrict__ psi, int64_t M,
-                                                        const int32_t *__restrict__ q_idx,
-                                                        const T *__restrict__ q_wg, const T *__restrict__ q_c,
-                                                        const T *__restrict__ q_G, int ncomp, T *__restrict__ jq) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < M) jumps_nodes_at<T, D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, ncomp, jq);
+// Both jump sets in one launch (they are independent): blocks [0, nbc) take the crossings,
+// the others the interface nodes.
+template <typename T, int D, int K, int KN>
+__global__ __launch_bounds__(kBlock) void k_jumps(const T *__restrict__ psi, int64_t M, int64_t nc, int64_t nbc,
+                                                  const int32_t *__restrict__ z_idx, const T *__restrict__ zA,
+                                                  const T *__restrict__ zB, const int32_t *__restrict__ q_idx,
+                                                  const T *__restrict__ q_wg, const T *__restrict__ q_c,
+                                                  const T *__restrict__ q_G, int ncomp, T *__restrict__ jz,
+                                                  T *__restrict__ jq) {
+  if ((int64_t)blockIdx.x < nbc) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc) jumps_cross_at<T, K>(c, psi, M, nc, z_idx, zA, zB, ncomp, jz);
+  } else {
+    const int64_t q = ((int64_t)blockIdx.x - nbc) * blockDim.x + threadIdx.x;
+    if (q < M) jumps_nodes_at<T, D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, ncomp, jq);
+  }
 }
 
 // n.D_c grad u+ at one node: st_nw[comp][j] = sum_a n_a D_{c,a} (gradient weight of node j)_a.
@@ -352,19 +353,15 @@ void free_prec(PrecTables<T> &tb) {
 template <typename T>
 void launch_jumps(DevProblem &p, const T *psi, hipStream_t st) {
   PrecTables<T> &tb = p.tab<T>();
-  if (p.nc > 0) {
-    if (p.dim == 2)
-      k_jumps_cross<T, 4><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_A, tb.z_B, p.ncomp, tb.jz);
-    else
-      k_jumps_cross<T, kLsqNodes><<<nblk(p.nc), kBlock, 0, st>>>(psi, p.M, p.nc, p.z_idx, tb.z_A, tb.z_B, p.ncomp,
-                                                                 tb.jz);
-    KFBI_HIP(hipGetLastError());
-  }
+  const int64_t nbc = p.nc > 0 ? nblk(p.nc) : 0;
+  const unsigned g = (unsigned)(nbc + nblk(p.M));
   if (p.dim == 2)
-    k_jumps_nodes<T, 2, 5><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_c, tb.q_G, p.ncomp, tb.jq);
+    k_jumps<T, 2, 4, 5><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B, p.q_idx, tb.q_wg,
+                                              tb.q_c, tb.q_G, p.ncomp, tb.jz, tb.jq);
   else
-    k_jumps_nodes<T, 3, kLsqNodes><<<nblk(p.M), kBlock, 0, st>>>(psi, p.M, p.q_idx, tb.q_wg, tb.q_c, tb.q_G,
-                                                                p.ncomp, tb.jq);
+    k_jumps<T, 3, kLsqNodes, kLsqNodes><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B,
+                                                              p.q_idx, tb.q_wg, tb.q_c, tb.q_G, p.ncomp, tb.jz,
+                                                              tb.jq);
   KFBI_HIP(hipGetLastError());
 }
 
