@@ -786,46 +786,88 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
     return v;
   };
   const Sines<T, M> sn(sp, tid % Sh::TPP);
-  V16<T> reg[PER];
+  if constexpr (M >= 64) {
+    // one pencil pair per wave at a time (pair index uniform in the wave, so its two rows are
+    // picked by scalar selects); a lane moves whole complex values: two 8-byte row elements
+    // per 16-byte LDS word, unit stride, no bank conflicts
+    constexpr int NWV = NT / 64, PPW = NP / NWV, KS = M / 64;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+    C2<T> v[PPW][KS];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
-    const int rr = e / VPR, s = e - rr * VPR;
-    if (e < NV && r0 + rr < nlist)
-      reg[i] = *reinterpret_cast<const V16<T> *>(in + (int64_t)row_of(rr) * M + s * VW);
-    else
+    for (int pp = 0; pp < PPW; ++pp) {
+      const int rr = wv + NWV * pp;
+      const bool oka = r0 + 2 * rr < nlist, okb = r0 + 2 * rr + 1 < nlist;
+      const T *ra = in + (int64_t)row_of(2 * rr) * M, *rb = in + (int64_t)row_of(2 * rr + 1) * M;
 #pragma unroll
-      for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
-  }
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        v[pp][k] = {oka && n < N ? ra[n] : T(0), okb && n < N ? rb[n] : T(0)};
+      }
+    }
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
-    if (e < NV) {
+    for (int pp = 0; pp < PPW; ++pp)
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        if (n < N) sbuf[(wv + NWV * pp) * PADM + pad(n + 1)] = v[pp][k];
+      }
+    __syncthreads();
+    dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp) {
+      const int rr = wv + NWV * pp;
+      const bool oka = r0 + 2 * rr < nlist, okb = r0 + 2 * rr + 1 < nlist;
+      T *ra = out + (int64_t)row_of(2 * rr) * M, *rb = out + (int64_t)row_of(2 * rr + 1) * M;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;   // n = N is the pad column: written as zero
+        const C2<T> c = n < N ? sbuf[rr * PADM + pad(n + 1)] : C2<T>{T(0), T(0)};
+        if (oka) ra[n] = c.x;
+        if (okb) rb[n] = c.y;
+      }
+    }
+  } else {
+    V16<T> reg[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / VPR, s = e - rr * VPR;
+      if (e < NV && r0 + rr < nlist)
+        reg[i] = *reinterpret_cast<const V16<T> *>(in + (int64_t)row_of(rr) * M + s * VW);
+      else
+#pragma unroll
+        for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < NV) {
+        const int rr = e / VPR, s = e - rr * VPR;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          const int n = s * VW + j;
+          if (n < N) lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i].v[j];
+        }
+      }
+    }
+    __syncthreads();
+    dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
       const int rr = e / VPR, s = e - rr * VPR;
 #pragma unroll
       for (int j = 0; j < VW; ++j) {
         const int n = s * VW + j;
-        if (n < N) lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i].v[j];
+        reg[i].v[j] = (e < NV && n < N) ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
       }
     }
-  }
-  __syncthreads();
-  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
-    const int rr = e / VPR, s = e - rr * VPR;
-#pragma unroll
-    for (int j = 0; j < VW; ++j) {
-      const int n = s * VW + j;
-      reg[i].v[j] = (e < NV && n < N) ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / VPR, s = e - rr * VPR;
+      if (e < NV && r0 + rr < nlist) *reinterpret_cast<V16<T> *>(out + (int64_t)row_of(rr) * M + s * VW) = reg[i];
     }
-  }
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
-    const int rr = e / VPR, s = e - rr * VPR;
-    if (e < NV && r0 + rr < nlist) *reinterpret_cast<V16<T> *>(out + (int64_t)row_of(rr) * M + s * VW) = reg[i];
   }
 }
 
