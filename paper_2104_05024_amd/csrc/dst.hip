@@ -329,88 +329,133 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restr
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * ROWS;
   const Sines<T, M> sn(sp, tid % Sh::TPP);
-  if constexpr (PIN) {
-    constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
-    V16<T> reg[PER];
+  if constexpr (M >= 64) {
+    // one pencil pair per wave at a time; a lane moves whole complex values (two 8-byte row
+    // elements per 16-byte LDS word, unit stride: no LDS bank conflicts)
+    constexpr int NWV = NT / 64, PPW = NP / NWV, KS = M / 64;
+    constexpr int64_t PI = PIN ? M : N, PO = POUT ? M : N;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+    C2<T> v[PPW][KS];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / VPR, s = e - rr * VPR;
-      const int64_t row = r0 + rr;
-      if (e < NV && row < nrows)
-        reg[i] = *reinterpret_cast<const V16<T> *>(in + row * M + s * VW);
-      else
+    for (int pp = 0; pp < PPW; ++pp) {
+      const int64_t rowa = r0 + 2 * (wv + NWV * pp);
+      const bool oka = rowa < nrows, okb = rowa + 1 < nrows;
+      const T *ra = in + rowa * PI, *rb = ra + PI;
 #pragma unroll
-        for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        v[pp][k] = {oka && n < N ? ra[n] : T(0), okb && n < N ? rb[n] : T(0)};
+      }
     }
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      if (e < NV) {
-        const int rr = e / VPR, s = e - rr * VPR;
+    for (int pp = 0; pp < PPW; ++pp)
 #pragma unroll
-        for (int j = 0; j < VW; ++j) {
-          const int n = s * VW + j;
-          if (n < N) lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i].v[j];
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        if (n < N) sbuf[(wv + NWV * pp) * PADM + pad(n + 1)] = v[pp][k];
+      }
+    __syncthreads();
+    dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp) {
+      const int rr = wv + NWV * pp;
+      const int64_t rowa = r0 + 2 * rr;
+      const bool oka = rowa < nrows, okb = rowa + 1 < nrows;
+      T *oa = out + rowa * PO, *ob = oa + PO;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;   // n = N: the pad column of the padded layout, zero
+        if (POUT || n < N) {
+          const C2<T> c = n < N ? sbuf[rr * PADM + pad(n + 1)] : C2<T>{T(0), T(0)};
+          if (oka) oa[n] = c.x;
+          if (okb) ob[n] = c.y;
         }
       }
     }
   } else {
-    constexpr int NE = ROWS * N, PER = (NE + NT - 1) / NT;
-    T reg[PER];
+    if constexpr (PIN) {
+      constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
+      V16<T> reg[PER];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / N, n = e - rr * N;
-      const int64_t row = r0 + rr;
-      reg[i] = (e < NE && row < nrows) ? in[row * N + n] : T(0);
-    }
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / VPR, s = e - rr * VPR;
+        const int64_t row = r0 + rr;
+        if (e < NV && row < nrows)
+          reg[i] = *reinterpret_cast<const V16<T> *>(in + row * M + s * VW);
+        else
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      if (e < NE) {
+          for (int j = 0; j < VW; ++j) reg[i].v[j] = T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        if (e < NV) {
+          const int rr = e / VPR, s = e - rr * VPR;
+#pragma unroll
+          for (int j = 0; j < VW; ++j) {
+            const int n = s * VW + j;
+            if (n < N) lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i].v[j];
+          }
+        }
+      }
+    } else {
+      constexpr int NE = ROWS * N, PER = (NE + NT - 1) / NT;
+      T reg[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
         const int rr = e / N, n = e - rr * N;
-        lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i];
+        const int64_t row = r0 + rr;
+        reg[i] = (e < NE && row < nrows) ? in[row * N + n] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        if (e < NE) {
+          const int rr = e / N, n = e - rr * N;
+          lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) = reg[i];
+        }
       }
     }
-  }
-  __syncthreads();
-  dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
-  if constexpr (POUT) {
-    constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
-    V16<T> reg[PER];
+    __syncthreads();
+    dst_pair<T, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
+    if constexpr (POUT) {
+      constexpr int VPR = M / VW, NV = ROWS * VPR, PER = (NV + NT - 1) / NT;
+      V16<T> reg[PER];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / VPR, s = e - rr * VPR;
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / VPR, s = e - rr * VPR;
 #pragma unroll
-      for (int j = 0; j < VW; ++j) {
-        const int n = s * VW + j;
-        reg[i].v[j] = (e < NV && n < N) ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+        for (int j = 0; j < VW; ++j) {
+          const int n = s * VW + j;
+          reg[i].v[j] = (e < NV && n < N) ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+        }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / VPR, s = e - rr * VPR;
-      const int64_t row = r0 + rr;
-      if (e < NV && row < nrows) *reinterpret_cast<V16<T> *>(out + row * M + s * VW) = reg[i];
-    }
-  } else {
-    constexpr int NE = ROWS * N, PER = (NE + NT - 1) / NT;
-    T reg[PER];
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / VPR, s = e - rr * VPR;
+        const int64_t row = r0 + rr;
+        if (e < NV && row < nrows) *reinterpret_cast<V16<T> *>(out + row * M + s * VW) = reg[i];
+      }
+    } else {
+      constexpr int NE = ROWS * N, PER = (NE + NT - 1) / NT;
+      T reg[PER];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / N, n = e - rr * N;
-      reg[i] = e < NE ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
-    }
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / N, n = e - rr * N;
+        reg[i] = e < NE ? lane_of(sbuf[(rr >> 1) * PADM + pad(n + 1)], rr & 1) : T(0);
+      }
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / N, n = e - rr * N;
-      const int64_t row = r0 + rr;
-      if (e < NE && row < nrows) out[row * N + n] = reg[i];
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / N, n = e - rr * N;
+        const int64_t row = r0 + rr;
+        if (e < NE && row < nrows) out[row * N + n] = reg[i];
+      }
     }
   }
 }
