@@ -15,6 +15,7 @@ struct Solver {
   float *v32 = nullptr, *w32 = nullptr;
   double *fpad = nullptr;      // padded FP64 field: source + correction of the final solve
   double *partials = nullptr;  // [vector][block] partial sums
+  double *npart = nullptr;     // [block] partials of ||w||^2 from the last Gram-Schmidt pass
   double *hdev = nullptr;      // device dot results (3 * (kMaxRestart + 2))
   double *hhost = nullptr;     // pinned host mirror
   double *ydev = nullptr;      // least-squares coefficients uploaded for the update

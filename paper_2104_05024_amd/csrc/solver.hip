@@ -82,12 +82,16 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
 
 // One classical Gram-Schmidt pass after k_multidot: every block sums the partials into
 // h_k (k < K; the sums are identical in every block), then w -= sum_k h_k V_k; block 0 stores h
-// for the Hessenberg column.  K = *jdev + 1 when jdev is given (the captured step).
+// for the Hessenberg column.  K = *jdev + 1 when jdev is given (the captured step).  With
+// npart (the last pass), each block also stores the sum of its updated w_i^2 in npart[block]:
+// the partials of ||w||^2, one element per thread as k_multidot has them when its grid covers
+// the vector.
 __global__ __launch_bounds__(kB) void k_cgs_combine(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
                                                     const double *__restrict__ partials, int nb,
                                                     double *__restrict__ hout, const int *__restrict__ jdev, int K,
-                                                    int64_t n) {
+                                                    int64_t n, double *__restrict__ npart) {
   __shared__ double hs[Solver::kMaxRestart + 1];
+  __shared__ double sq[kB];
   if (jdev) K = *jdev + 1;
   for (int k = threadIdx.x >> 6; k < K; k += kB / 64) {
     const double s = wave_sum_partials(partials, nb, k);
@@ -97,10 +101,21 @@ __global__ __launch_bounds__(kB) void k_cgs_combine(double *__restrict__ w, cons
   if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < K; k += kB) hout[k] = hs[k];
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
-  double acc = 0;
-  for (int k = 0; k < K; ++k) acc += hs[k] * V[(int64_t)k * ldv + i];
-  w[i] -= acc;
+  double wi = 0;
+  if (i < n) {
+    double acc = 0;
+    for (int k = 0; k < K; ++k) acc += hs[k] * V[(int64_t)k * ldv + i];
+    wi = w[i] - acc;
+    w[i] = wi;
+  }
+  if (!npart) return;
+  sq[threadIdx.x] = wi * wi;
+  __syncthreads();
+  for (int off = kB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sq[threadIdx.x] += sq[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) npart[blockIdx.x] = sq[0];
 }
 
 // The norm after k_multidot of w with itself: V_{j+1} = w / ||w|| (j = *jdev when given, else
@@ -136,6 +151,25 @@ __global__ __launch_bounds__(kB) void k_axpby(double *__restrict__ z, double a, 
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   z[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+// Starting residual of psi^{n-1} without a product: (g'^n - g'^{n-1}) + (g'^{n-1} - A psi^{n-1}).
+__global__ __launch_bounds__(kB) void k_recycled_resid(double *__restrict__ r, const double *__restrict__ gp,
+                                                       const double *__restrict__ gp_prev,
+                                                       const double *__restrict__ d_prev, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) r[i] = (gp[i] - gp_prev[i]) + d_prev[i];
+}
+
+// End of a bidomain step: g'^{n-1} <- g'^n and the density history shifts by one step.
+__global__ __launch_bounds__(kB) void k_end_step(double *__restrict__ gp_prev, const double *__restrict__ gp,
+                                                 double *__restrict__ hist2, double *__restrict__ hist1,
+                                                 const double *__restrict__ psi, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  gp_prev[i] = gp[i];
+  hist2[i] = hist1[i];
+  hist1[i] = psi[i];
 }
 
 template <typename A, typename B>
@@ -209,6 +243,7 @@ void Solver::init(DevProblem &p) {
   fpad = dalloc<double>((size_t)p.ncomp * p.comp_stride);
   KFBI_HIP(hipMemset(fpad, 0, (size_t)p.ncomp * p.comp_stride * sizeof(double)));
   partials = dalloc<double>((size_t)(kMaxRestart + 2) * 512);
+  npart = dalloc<double>((size_t)nblk(L));
   hdev = dalloc<double>(3 * (kMaxRestart + 2));
   ydev = dalloc<double>(kMaxRestart + 2);
   KFBI_HIP(hipHostMalloc(&hhost, 3 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
@@ -235,7 +270,7 @@ void Solver::release() {
   if (jhost) (void)hipHostFree(jhost);
   jdev = nullptr;
   jhost = nullptr;
-  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &hdev, &ydev, &vin, &wv};
+  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &npart, &hdev, &ydev, &vin, &wv};
   for (double **q : dp) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -298,10 +333,11 @@ void Solver::arnoldi_step(DevProblem &p, int prec, int m, hipStream_t st) {
   apply_vec(p, prec, vin, wv, st);
   for (int pass = 0; pass < 2; ++pass) {
     k_multidot<<<dim3(nb, m), kB, 0, st>>>(V, L, wv, L, partials, jdev);
-    k_cgs_combine<<<nblk(L), kB, 0, st>>>(wv, V, L, partials, nb, hdev + pass * (kMaxRestart + 2), jdev, 0, L);
+    k_cgs_combine<<<nblk(L), kB, 0, st>>>(wv, V, L, partials, nb, hdev + pass * (kMaxRestart + 2), jdev, 0, L,
+                                          pass == 1 ? npart : nullptr);
   }
-  k_multidot<<<dim3(nb, 1), kB, 0, st>>>(wv, L, wv, L, partials);
-  k_normalize<<<nblk(L), kB, 0, st>>>(V, L, wv, partials, nb, hdev + 2 * (kMaxRestart + 2), jdev, 0, vin, L);
+  k_normalize<<<nblk(L), kB, 0, st>>>(V, L, wv, npart, (int)nblk(L), hdev + 2 * (kMaxRestart + 2), jdev, 0, vin,
+                                      L);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
   k_inc_j<<<1, 1, 0, st>>>(jdev);
@@ -380,11 +416,10 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
         for (int pass = 0; pass < 2; ++pass) {
           k_multidot<<<dim3(nb, j + 1), kB, 0, st>>>(V, L, vn, L, partials);
           k_cgs_combine<<<nblk(L), kB, 0, st>>>(vn, V, L, partials, nb, hdev + pass * (kMaxRestart + 2), nullptr,
-                                                j + 1, L);
+                                                j + 1, L, pass == 1 ? npart : nullptr);
         }
-        k_multidot<<<dim3(nb, 1), kB, 0, st>>>(vn, L, vn, L, partials);
-        k_normalize<<<nblk(L), kB, 0, st>>>(V, L, vn, partials, nb, hdev + 2 * (kMaxRestart + 2), nullptr, j, nullptr,
-                                            L);
+        k_normalize<<<nblk(L), kB, 0, st>>>(V, L, vn, npart, (int)nblk(L), hdev + 2 * (kMaxRestart + 2), nullptr, j,
+                                            nullptr, L);
         KFBI_HIP(hipGetLastError());
         KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
       }
@@ -706,8 +741,7 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
     // the last term being the final FP64 residual of the previous solve
     KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (have_prev) {
-      k_axpby<<<nblk(L), kB, 0, st>>>(r0v, 1.0, sv.gp, -1.0, gp_prev, L);
-      k_axpby<<<nblk(L), kB, 0, st>>>(r0v, 1.0, r0v, 1.0, d_prev, L);
+      k_recycled_resid<<<nblk(L), kB, 0, st>>>(r0v, sv.gp, gp_prev, d_prev, L);
       have_r0 = true;
     }
     if (params.warm_start == 3 && have_r0 && proj_n >= 2) {
@@ -780,10 +814,9 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
     mlp_record(this, hist1, hist2, psi0, st);
     if (params.warm_start == 1) mlp_note_cost(this, info.matvecs_fp64 + 0.5 * info.matvecs_fp32, info.warm_start_used);
   }
-  KFBI_HIP(hipMemcpyAsync(gp_prev, sv.gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   ++steps_done;
-  KFBI_HIP(hipMemcpyAsync(hist2, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-  KFBI_HIP(hipMemcpyAsync(hist1, psi0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_end_step<<<nblk(L), kB, 0, st>>>(gp_prev, sv.gp, hist2, hist1, psi0, L);
+  KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipStreamSynchronize(st));
   return rc;
 }
