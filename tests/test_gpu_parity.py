@@ -360,6 +360,33 @@ def test_full_size_shell_256_apply_matches_oracle():
     g.close()
 
 
+def test_full_size_shell_256_bidomain_step_matches_oracle():
+    """One bidomain step of the bench workload (thick shell, 256^3, the bench's stimulus ball)
+    in the launch configuration the bench times (fused reaction x passes, sparse matvec box
+    solves, captured Arnoldi step) against the oracle's step: V and q at every node."""
+    iface, grid = W.thick_shell(n_nodes=40960), W.box(3, 256)
+    co = W.bidomain_coeffs(3, P_BIDO, 0.01)
+    say("[setup] shell_256 (GPU)")
+    g = K.Problem(iface, grid, co)
+    say("[setup] shell_256 (oracle)")
+    o = ok.Problem(iface, grid, co)
+    V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.25)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+    V, q = T(V0), T(q0)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    say("[bidomain step] shell_256 (GPU)")
+    info = bd.step(V, q, hist, 0.01)
+    say("[bidomain step] shell_256 (oracle)")
+    Vo, qo, _, _, infoo = obd.step(o, P_BIDO, V0, q0, 0.01, tol=1e-12)
+    eV = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+    eq = np.max(np.abs(q.cpu().numpy() - qo)) / np.max(np.abs(qo))
+    say(f"    V err {eV:.2e} q err {eq:.2e} iters {info['iters']} / {infoo['iters']}")
+    assert info["rel_resid"] <= 1e-12
+    assert eV < 1e-9 and eq < 1e-9
+    bd.close()
+    g.close()
+
+
 def test_full_size_perturbed_sphere_256_mixed_precision():
     """C3 at full size: FP32 products inside FP64 refinement reach the FP64 relative residual
     1e-10, agree with the FP64 solve, and solve the manufactured problem to second order."""
