@@ -199,27 +199,33 @@ def _cost(i):
 
 def test_trained_start_gain_fp64():
     """What the trained network gains with FP64 GMRES: a start whose residual is several times
-    smaller than that of psi^{n-1}, the same final residual bound and the same solution.  GMRES
-    contracts about tenfold per iteration on this operator, so a 4x better start is worth less
-    than one iteration; the count stays within one of the psi^{n-1} start (training sums its
-    gradients with atomics, so the last digits of the network vary from run to run).  The
-    prediction's residual costs one FP64 product that the recycled residual of psi^{n-1} does
-    not, so the cost check may switch the learned start off after its first 8 uses."""
+    smaller than that of psi^{n-1}, the same final residual bound and the same solution.  The
+    iteration count is not guaranteed to follow: GMRES contracts about tenfold per iteration
+    on this operator, so a 4x better start is worth less than one iteration, and some trained
+    networks give starts that take more iterations than psi^{n-1} despite their smaller
+    residual (training sums its gradients with atomics, so the network varies from run to
+    run).  The prediction's residual also costs one FP64 product that the recycled residual
+    of psi^{n-1} does not.  The cost check bounds both: when the first 8 learned starts cost
+    more than the 8 psi^{n-1} starts before them, the learned start is switched off."""
     say("[mlp gain fp64] shell 64")
-    _, li, losses, Vl = _shell_run(0, 1, True)
+    pre, li, losses, Vl = _shell_run(0, 1, True)
     _, ci, _, Vc = _shell_run(0, 0, False)
     say(f"    loss after 1 epoch {losses[0]:.3e}, after 151 {losses[1]:.3e}")
     assert losses[1] < 0.1 * losses[0]
     used = [k for k, i in enumerate(li) if i["warm_start_used"]]
     rl = [li[k]["start_resid"] for k in used]
     rc = [ci[k]["start_resid"] for k in used]
+    cl = [_cost(i) for i in li[:8]]
+    cp = [_cost(i) for i in pre[-8:]]
     say(f"    learned start used in steps {used}")
     say(f"    start residual learned {np.mean(rl):.2e} vs psi^(n-1) {np.mean(rc):.2e} (same steps)")
     say(f"    iterations learned {[i['iters'] for i in li]} vs psi^(n-1) {[i['iters'] for i in ci]}")
+    say(f"    cost of the first 8 learned starts {cl}, of the 8 psi^(n-1) starts before {cp}")
     assert used[:8] == list(range(8))
     assert all(i["rel_resid"] <= 1e-10 for i in li + ci)
     assert np.mean(rl) < 0.5 * np.mean(rc)
-    assert np.mean([i["iters"] for i in li]) <= np.mean([i["iters"] for i in ci]) + 1.0
+    if np.mean(cl) >= np.mean(cp):
+        assert used == list(range(8))
     assert np.max(np.abs(Vl - Vc)) < 1e-8
 
 
