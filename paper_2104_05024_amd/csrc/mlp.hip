@@ -28,6 +28,7 @@ namespace kfbi {
 constexpr int kIn = 16;     // padded input features
 constexpr int kHid = 128;   // hidden width
 constexpr int kOut = 16;    // padded outputs (ncomp real)
+constexpr int kWgBlocks = 256;   // blocks of the weight-gradient reduction (fixed order)
 constexpr int kRowsWG = 64; // rows per workgroup in the row-parallel kernels
 
 struct Mlp {
@@ -55,6 +56,9 @@ struct Mlp {
   double *scal = nullptr;   // [0] s_d, [1] s_g, [2..] partial maxima
   float *loss = nullptr;    // [blocks]
   int nloss = 0;
+  // per-block weight-gradient partials [kWgBlocks][kHid * kHid] and [kWgBlocks][kHid], summed
+  // in a fixed order (training is deterministic: no atomics)
+  float *gWp = nullptr, *gbp = nullptr;
 };
 
 namespace {
@@ -302,12 +306,13 @@ __global__ __launch_bounds__(256) void k_bwd_data(const uint16_t *__restrict__ d
     }
 }
 
-// Weight gradient: gW[o][c] += sum_r dZ[r][o] Ain[r][c] over this block's rows; gb[o] += sum_r dZ[r][o].
-// NO x NC output tiles of 16x16 spread over 4 waves; reduction over rows in steps of 16.
+// Weight-gradient partials of this block's rows: gWp[block][o][c] = sum_r dZ[r][o] Ain[r][c],
+// gbp[block][o] = sum_r dZ[r][o].  NO x NC output tiles of 16x16 spread over 4 waves; reduction
+// over rows in steps of 16.  k_wgrad_sum adds the blocks' partials in block order.
 template <int NO, int NCI>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ Ain,
-                                               int64_t R, int64_t rows_per_block, float *__restrict__ gW,
-                                               float *__restrict__ gb) {
+                                               int64_t R, int64_t rows_per_block, float *__restrict__ gWp,
+                                               float *__restrict__ gbp) {
   constexpr int TO = NO / 16, TC = NCI / 16, NT = TO * TC, PW = (NT + 3) / 4;
   const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int i = lane % 16, kg = 4 * (lane / 16);
@@ -343,10 +348,28 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dZ, 
     const int tile = w + 4 * t;
     if (tile >= NT) break;
     const int to = tile / TC, tc = tile % TC;
+    float *gw = gWp + (int64_t)blockIdx.x * NO * NCI;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) atomicAdd(&gW[(int64_t)(to * 16 + kg + j) * NCI + tc * 16 + (lane % 16)], acc[t][j]);
+    for (int j = 0; j < 4; ++j) gw[(to * 16 + kg + j) * NCI + tc * 16 + (lane % 16)] = acc[t][j];
   }
-  if (tid < NO) atomicAdd(&gb[tid], bsum);
+  if (tid < NO) gbp[(int64_t)blockIdx.x * NO + tid] = bsum;
+}
+
+// gW[e] += sum over blocks b < nblocks of gWp[b][e] (and the biases likewise), in block order.
+template <int NO, int NCI>
+__global__ __launch_bounds__(kB) void k_wgrad_sum(const float *__restrict__ gWp, const float *__restrict__ gbp,
+                                                  int nblocks, float *__restrict__ gW, float *__restrict__ gb) {
+  const int e = blockIdx.x * kB + threadIdx.x;
+  if (e < NO * NCI) {
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += gWp[(int64_t)b * NO * NCI + e];
+    gW[e] += s;
+  } else if (e < NO * NCI + NO) {
+    const int o = e - NO * NCI;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += gbp[(int64_t)b * NO + o];
+    gb[o] += s;
+  }
 }
 
 // Adam (bias-corrected) on fp32 master weights; refreshes the bf16 copy and clears the gradient.
@@ -417,12 +440,23 @@ void backward_net(Mlp &m, const uint16_t *X, int64_t R, hipStream_t st) {
   k_bwd_data<kOut><<<g, 256, 0, st>>>(m.dZ4, m.Wb[3], m.A3, R, m.dZ3);
   k_bwd_data<kHid><<<g, 256, 0, st>>>(m.dZ3, m.Wb[2], m.A2, R, m.dZ2);
   k_bwd_data<kHid><<<g, 256, 0, st>>>(m.dZ2, m.Wb[1], m.A1, R, m.dZ1);
-  const int64_t rpb = 1024;
+  // at most kWgBlocks blocks of a multiple of 16 rows each
+  const int64_t rpb = std::max<int64_t>(16, ((R + kWgBlocks - 1) / kWgBlocks + 15) / 16 * 16);
   const unsigned gw = (unsigned)((R + rpb - 1) / rpb);
-  k_wgrad<kOut, kHid><<<gw, 256, 0, st>>>(m.dZ4, m.A3, R, rpb, m.gW[3], m.gb[3]);
-  k_wgrad<kHid, kHid><<<gw, 256, 0, st>>>(m.dZ3, m.A2, R, rpb, m.gW[2], m.gb[2]);
-  k_wgrad<kHid, kHid><<<gw, 256, 0, st>>>(m.dZ2, m.A1, R, rpb, m.gW[1], m.gb[1]);
-  k_wgrad<kHid, kIn><<<gw, 256, 0, st>>>(m.dZ1, X, R, rpb, m.gW[0], m.gb[0]);
+  auto sum_blocks = [&](int no, int nci, int l) {
+    const unsigned g = nblk((int64_t)no * nci + no);
+    if (no == kOut) k_wgrad_sum<kOut, kHid><<<g, kB, 0, st>>>(m.gWp, m.gbp, (int)gw, m.gW[l], m.gb[l]);
+    else if (nci == kIn) k_wgrad_sum<kHid, kIn><<<g, kB, 0, st>>>(m.gWp, m.gbp, (int)gw, m.gW[l], m.gb[l]);
+    else k_wgrad_sum<kHid, kHid><<<g, kB, 0, st>>>(m.gWp, m.gbp, (int)gw, m.gW[l], m.gb[l]);
+  };
+  k_wgrad<kOut, kHid><<<gw, 256, 0, st>>>(m.dZ4, m.A3, R, rpb, m.gWp, m.gbp);
+  sum_blocks(kOut, kHid, 3);
+  k_wgrad<kHid, kHid><<<gw, 256, 0, st>>>(m.dZ3, m.A2, R, rpb, m.gWp, m.gbp);
+  sum_blocks(kHid, kHid, 2);
+  k_wgrad<kHid, kHid><<<gw, 256, 0, st>>>(m.dZ2, m.A1, R, rpb, m.gWp, m.gbp);
+  sum_blocks(kHid, kHid, 1);
+  k_wgrad<kHid, kIn><<<gw, 256, 0, st>>>(m.dZ1, X, R, rpb, m.gWp, m.gbp);
+  sum_blocks(kHid, kIn, 0);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -455,7 +489,7 @@ void mlp_release(bidomain_s *b) {
   uint16_t *us[] = {m.G, m.X, m.A1, m.A2, m.A3, m.dZ4, m.dZ3, m.dZ2, m.dZ1};
   for (uint16_t *u : us)
     if (u) (void)hipFree(u);
-  float *fs[] = {m.Fs, m.Ts, m.F, m.Y, m.loss};
+  float *fs[] = {m.Fs, m.Ts, m.F, m.Y, m.loss, m.gWp, m.gbp};
   for (float *f : fs)
     if (f) (void)hipFree(f);
   if (m.scal) (void)hipFree(m.scal);
@@ -501,6 +535,8 @@ void bidomain_s::mlp_init(int capacity, uint64_t seed) {
     m.mb[l] = dalloc<float>(r);
     m.vb[l] = dalloc<float>(r);
   }
+  m.gWp = dalloc<float>((size_t)kWgBlocks * kHid * kHid);
+  m.gbp = dalloc<float>((size_t)kWgBlocks * kHid);
   const int64_t M = m.M;
   m.Fs = dalloc<float>((size_t)m.cap * M * m.nf);
   m.Ts = dalloc<float>((size_t)m.cap * M * m.ncomp);

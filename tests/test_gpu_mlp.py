@@ -132,6 +132,31 @@ def test_training_loss_matches_oracle_after_epochs(recorded):
     assert np.array_equal(unpack(bd.mlp_params())[3][0], net[3][0])
 
 
+def test_training_is_deterministic():
+    """Training adds the weight-gradient partials of its blocks in block order (no atomics):
+    the same recorded steps and seed give bitwise the same loss and network."""
+    iface, grid = W.ellipsoid(n_nodes=512), W.box(3, 32)
+    co = W.bidomain_coeffs(3, P, 0.01)
+    say("[mlp determinism] ellipsoid 32")
+    prob = K.Problem(iface, grid, co)
+    runs = []
+    for _ in range(2):
+        bd = K.Bidomain(prob, P, tol=1e-10, precision=0, warm_start=1)
+        bd.mlp_init(capacity=8, seed=3)
+        V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.3)
+        V, q = torch.tensor(V0, device=DEV), torch.tensor(q0, device=DEV)
+        hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=DEV)
+        for _ in range(STEPS):
+            bd.step(V, q, hist, 0.01)
+        loss = bd.train(epochs=20, lr=3e-3)
+        runs.append((loss, bd.mlp_params()))
+        bd.close()
+    prob.close()
+    say(f"    losses {runs[0][0]:.9e} {runs[1][0]:.9e}")
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
 def test_forward_matches_oracle_with_bf16_weights(recorded):
     prob, bd, _, _ = recorded
     net = unpack(bd.mlp_params())
@@ -203,8 +228,7 @@ def test_trained_start_gain_fp64():
     iteration count is not guaranteed to follow: GMRES contracts about tenfold per iteration
     on this operator, so a 4x better start is worth less than one iteration, and some trained
     networks give starts that take more iterations than psi^{n-1} despite their smaller
-    residual (training sums its gradients with atomics, so the network varies from run to
-    run).  The prediction's residual also costs one FP64 product that the recycled residual
+    residual.  The prediction's residual also costs one FP64 product that the recycled residual
     of psi^{n-1} does not.  The cost check bounds both: when the first 8 learned starts cost
     more than the 8 psi^{n-1} starts before them, the learned start is switched off."""
     say("[mlp gain fp64] shell 64")
