@@ -17,8 +17,7 @@ HIP_SOURCES = ["dst.hip", "kfbi_kernels.hip", "solver.hip", "api.hip", "mlp.hip"
 HOST_SOURCES = ["host_tables.cpp", "host_spline.cpp", "host_mesh.cpp"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
-DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def _run(cmd):
