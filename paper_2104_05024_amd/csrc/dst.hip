@@ -928,7 +928,8 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
 //            in mask, every row when mask is null), forward DST into work;
 //   FHN_BE   inverse DST of work, then V <- 2 (u_i - u_e) - V and the backward Euler half step.
 // A thread handles whole nodes, so its LDS accesses are unit-stride 16-byte values.  The
-// arithmetic per node is that of the separate sweeps (same expressions, same order).
+// pointwise arithmetic is fhn_fe / fhn_be, which the separate midpoint sweep (k_mid_be, used
+// when the potentials are returned) shares.
 enum { FHN_FE = 0, FHN_SRC = 1, FHN_BE = 2 };
 
 template <int M, int MODE>
