@@ -280,8 +280,8 @@ def main():
     # stencil nodes; the z pass of the BIE right-hand side's volume solve (dst_last_out) reads
     # every plane and writes only the stencil planes.  The row-masked x and y passes
     # (dst_x_rows, dst_y_sparse) are not priced.  The three x passes of a step that carry the
-    # reaction (dst_x_fhn) are priced per launch as the mean of: forward Euler + source (V, q read
-    # and written, the transformed pair written), source + correction (V and the correction rows
+    # reaction (dst_x_fhn) are priced per launch as the mean of: forward Euler + source (V, q
+    # read, the transformed pair written), source + correction (V, q and the correction rows
     # read, the pair written) and inverse + backward Euler (the pair, V and q read, V, q written).
     ref = "plain" if "plain" in kt else head
     N = grid.n
@@ -292,7 +292,7 @@ def main():
     algo_of = {"dst_x": 2.0 * field_bytes, "dst_y": 2.0 * field_bytes, "dst_last": 2.0 * field_bytes,
                "dst_last_sparse": float(co.ncomp * N * N * 8 * (planes_in + planes_out)),
                "dst_last_out": float(field_bytes + co.ncomp * N * N * 8 * planes_out),
-               "dst_x_fhn": (3.0 * field_bytes + (1.5 * field_bytes + co.ncomp * rows_in * N * 8)
+               "dst_x_fhn": (2.0 * field_bytes + (2.0 * field_bytes + co.ncomp * rows_in * N * 8)
                              + 3.0 * field_bytes) / 3.0}
     tot = {k: us * n for k, (us, n) in kt[ref].items()}
     priced = [k for k in algo_of if kt[ref][k][1] > 0]

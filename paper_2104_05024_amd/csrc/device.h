@@ -188,17 +188,32 @@ void box_solve_matvec(DevProblem &p, hipStream_t st);
 template <typename T>
 void box_solve_stencils(DevProblem &p, const T *src, hipStream_t st);
 
+// 1/x from the hardware reciprocal estimate refined by Newton steps (two in FP64, one in FP32):
+// within an ulp or two of the IEEE quotient at a fraction of the cost of a full division.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // FitzHugh-Nagumo reaction (Sec. 7) and its two half steps in the Strang splitting (Sec. 3):
-// forward Euler, and backward Euler with q eliminated and Newton on V.
+// forward Euler, and backward Euler with q eliminated and Newton on V.  inv_cm = 1 / C_m and
+// inv_den = 1 / (1 + dth zeta) for the half step dth, so that no node divides by constants.
 struct FhnCoef {
   double Cm, H, theta, alpha, zeta, tol;
   int maxit;
+  double inv_cm, inv_den;
 };
 
 // Forward Euler over dth: (v, g) <- (v - dth I_ion(v, g) / C_m, g + dth (alpha v - zeta g)).
 __device__ __forceinline__ void fhn_fe(double &v, double &g, double dth, const FhnCoef &m) {
   const double I = m.H * (g - v * (v - m.theta) * (1.0 - v));
-  const double v1 = v + dth * (-I / m.Cm);
+  const double v1 = v + dth * (-I * m.inv_cm);
   const double q1 = g + dth * (m.alpha * v - m.zeta * g);
   v = v1;
   g = q1;
@@ -207,9 +222,9 @@ __device__ __forceinline__ void fhn_fe(double &v, double &g, double dth, const F
 // Backward Euler over dth from (vb, g): q' = (g + dth alpha V') / (1 + dth zeta) is eliminated
 // and Newton solves for V'; it stops once |F| <= tol and takes one more step.
 __device__ __forceinline__ void fhn_be(double vb, double g, double dth, const FhnCoef &m, double &V, double &q) {
-  const double a = dth * m.alpha / (1.0 + dth * m.zeta);
-  const double qb = g / (1.0 + dth * m.zeta);
-  const double c = dth * m.H / m.Cm;
+  const double a = dth * m.alpha * m.inv_den;
+  const double qb = g * m.inv_den;
+  const double c = dth * m.H * m.inv_cm;
   double x = vb;
   for (int it = 0; it < m.maxit; ++it) {
     const double cub = x * (x - m.theta) * (1.0 - x);
@@ -217,7 +232,7 @@ __device__ __forceinline__ void fhn_be(double vb, double g, double dth, const Fh
     const double dcub = -3.0 * x * x + 2.0 * (1.0 + m.theta) * x - m.theta;
     const double dF = 1.0 + c * (a - dcub);
     const bool ok = fabs(F) <= m.tol;
-    x = x - F / dF;
+    x = x - F * recip(dF);
     if (ok) break;
   }
   V = x;
@@ -236,12 +251,13 @@ struct FhnArgs {
 // Box solves of a coupled (two-component, FP64) bidomain step whose x passes pair row r of
 // component 0 with row r of component 1, so that both potentials of a node share one complex
 // value and the pointwise work of the splitting rides in those passes:
-//   bidomain_volume_solve: forward Euler half step of (V, q) in place, then S f for
-//     f = (kappa V, -kappa V + beta I) into work (extrapolation-stencil values, as
-//     box_solve_stencils);
+//   bidomain_volume_solve: S f for f = (kappa V1, -kappa V1 + beta I), (V1, q1) the forward
+//     Euler half step of (V, q), into work (extrapolation-stencil values, as
+//     box_solve_stencils); V and q are left unchanged;
 //   bidomain_final_solve: S(f + C psi) with C psi taken from rhs (launch_correct), into work;
-//     with fuse_be the inverse x pass instead finishes the step: V <- 2 (u_i - u_e) - V and the
-//     backward Euler half step of (V, q), and work is left holding the y-inverse output.
+//     with fuse_be the inverse x pass instead finishes the step: V <- 2 (u_i - u_e) - V1 and the
+//     backward Euler half step from q1 into V and q, and work is left holding the y-inverse
+//     output.  Each pass recomputes (V1, q1) from the unchanged (V, q).
 void bidomain_volume_solve(DevProblem &p, const FhnArgs &a, hipStream_t st);
 void bidomain_final_solve(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st);
 

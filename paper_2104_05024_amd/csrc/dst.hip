@@ -138,18 +138,6 @@ __device__ __forceinline__ void dft(C2<T> *v) {
 #endif
 __device__ __forceinline__ int pad(int i) { return i + (i >> KFBI_LDS_PAD_SHIFT); }
 
-// 1/x from the hardware reciprocal estimate refined by Newton steps (two in FP64, one in FP32):
-// within an ulp or two of the IEEE quotient at a fraction of the cost of a full division.
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-__device__ __forceinline__ float recip(float x) {
-  float r = __builtin_amdgcn_rcpf(x);
-  return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
 
 // W: tile-width multiplier picked by the autotuner (1 or 2 times the base pairs per workgroup)
 template <typename T, int M, int W = 1>
@@ -922,11 +910,15 @@ __global__ __launch_bounds__((Shape<T, M>::NT)) void k_dst_x_rows(const T *__res
 // (instead of two rows of one component), so that the two potentials of a node share one
 // complex value in LDS.  The reaction half steps of the splitting are pointwise, so they ride
 // in these passes instead of separate sweeps over the box:
-//   FHN_FE   forward Euler half step of (V, q) in place, source f = (kappa V, -kappa V + beta I),
-//            forward DST into work;
-//   FHN_SRC  source f(V) plus the irregular-node correction C psi (rhs, read only on rows flagged
-//            in mask, every row when mask is null), forward DST into work;
-//   FHN_BE   inverse DST of work, then V <- 2 (u_i - u_e) - V and the backward Euler half step.
+//   FHN_FE   source f = (kappa V1, -kappa V1 + beta I) of the forward Euler half step
+//            (V1, q1) = FE(V, q), forward DST into work;
+//   FHN_SRC  the same source plus the irregular-node correction C psi (rhs, read only on rows
+//            flagged in mask, every row when mask is null), forward DST into work;
+//   FHN_BE   inverse DST of work, then V <- 2 (u_i - u_e) - V1 and the backward Euler half step
+//            from q1, written to V and q.
+// V and q keep the step's starting state until FHN_BE: each pass recomputes (V1, q1) from
+// them (the same arithmetic, so the same values), which costs less than writing and reading
+// back the intermediate state.
 // A thread handles whole nodes, so its LDS accesses are unit-stride 16-byte values.  The
 // pointwise arithmetic is fhn_fe / fhn_be, which the separate midpoint sweep (k_mid_be, used
 // when the potentials are returned) shares.
@@ -975,7 +967,7 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
       const int64_t row = r0 + rr;
       const bool ok = e < NE && row < rows;
       va[i] = ok ? V[row * N + n] : 0.0;
-      if constexpr (MODE == FHN_FE) qa[i] = ok ? q[row * N + n] : 0.0;
+      qa[i] = ok ? q[row * N + n] : 0.0;
       sa[i] = ok && stim ? stim[row * N + n] : 0.0;
     }
     // rows of the tile holding irregular nodes, from uniform loads of the bit rows [z][16]
@@ -1023,15 +1015,8 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
       const int rr = e / N, n = e - rr * N;
       const int64_t row = r0 + rr;
       if (e < NE) {
-        double v = va[i];
-        if constexpr (MODE == FHN_FE) {
-          if (row < rows) {
-            double g = qa[i];
-            fhn_fe(v, g, a.dth, a.m);
-            V[row * N + n] = v;
-            q[row * N + n] = g;
-          }
-        }
+        double v = va[i], g = qa[i];
+        fhn_fe(v, g, a.dth, a.m);
         C f = {a.kappa * v, -a.kappa * v + (stim ? a.beta * sa[i] : 0.0)};
         if constexpr (MODE == FHN_SRC) {
           if (row < rows && flagged(rr)) {
@@ -1064,8 +1049,9 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
       const int64_t row = r0 + rr;
       if (e < NE && row < rows) {
         const C u = sbuf[rr * PADM + pad(n + 1)];
-        double vn, qn;
-        fhn_be(2.0 * (u.x - u.y) - va[i], qa[i], a.dth, a.m, vn, qn);
+        double v1 = va[i], q1 = qa[i], vn, qn;
+        fhn_fe(v1, q1, a.dth, a.m);
+        fhn_be(2.0 * (u.x - u.y) - v1, q1, a.dth, a.m, vn, qn);
         V[row * N + n] = vn;
         q[row * N + n] = qn;
       }

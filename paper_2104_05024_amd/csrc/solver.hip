@@ -205,9 +205,10 @@ __global__ __launch_bounds__(kB) void k_masked_sum(const double *__restrict__ u,
 
 // ---------------------------------------------------------------- FitzHugh-Nagumo kernels
 
-// Midpoint update V <- 2 (u_i - u_e) - V and step 3 (backward Euler over dt/2) when the
+// Midpoint update V <- 2 (u_i - u_e) - V1 and step 3 (backward Euler over dt/2) when the
 // potentials are also returned: writes them in the gauge of the given mean.  (Without them the
-// inverse x pass of the final box solve does this work.)
+// inverse x pass of the final box solve does this work.)  V and q still hold the step's
+// starting state; (V1, q1) is their forward Euler half step, recomputed as the x passes do.
 __global__ __launch_bounds__(kB) void k_mid_be(const double *__restrict__ u, double *__restrict__ V,
                                                double *__restrict__ q, double *__restrict__ phi,
                                                const double *__restrict__ mean, int64_t n, int64_t N, int64_t P,
@@ -216,8 +217,9 @@ __global__ __launch_bounds__(kB) void k_mid_be(const double *__restrict__ u, dou
   if (i >= n) return;
   const int64_t pos = (i % N) + P * (i / N);
   const double ui = u[pos], ue = u[cs + pos];
-  double vn, qn;
-  fhn_be(2.0 * (ui - ue) - V[i], q[i], dth, m, vn, qn);
+  double v1 = V[i], q1 = q[i], vn, qn;
+  fhn_fe(v1, q1, dth, m);   // V and q hold the step's starting state (see the x passes)
+  fhn_be(2.0 * (ui - ue) - v1, q1, dth, m, vn, qn);
   V[i] = vn;
   q[i] = qn;
   if (phi) {
@@ -721,11 +723,13 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   Solver &sv = *solver;
   const int64_t n = (int64_t)p.ht.inside.size(), L = sv.L;
   const double dth = 0.5 * dt;
-  const FhnCoef m{params.Cm, params.H, params.theta, params.alpha, params.zeta, params.newton_tol,
-                  params.newton_maxit};
+  const FhnCoef m{params.Cm,  params.H,           params.theta,       params.alpha,
+                  params.zeta, params.newton_tol, params.newton_maxit, 1.0 / params.Cm,
+                  1.0 / (1.0 + dth * params.zeta)};
   const FhnArgs fa{s.V, s.q, s.I_stim, dth, p.kappa, params.beta, m};
-  // step 1 (reaction over dt/2, forward Euler) rides in the first x pass of the volume solve of
-  // step 2: diffusion, backward Euler over dt/2 for w = (V^{n+1} + V^n)/2 (Neumann BVP)
+  // step 1 (reaction over dt/2, forward Euler) is computed where its result is used: in the x
+  // passes of the box solves of step 2 (diffusion, backward Euler over dt/2 for
+  // w = (V^{n+1} + V^n)/2, a Neumann BVP); V and q change only at the end of the step
   sv.bie_rhs(p, nullptr, st, &fa);
   double *hist1 = s.psi_hist, *hist2 = s.psi_hist + L;
   kfbi_solve_opts o = params.solve;
