@@ -998,7 +998,19 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
       if constexpr (NP > 64) return true;
       else return (rb >> rr) & 1;
     };
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      const int rr = e / N, n = e - rr * N;
+      if (e < NE) {
+        double v = va[i], g = qa[i];
+        fhn_fe(v, g, a.dth, a.m);
+        sbuf[rr * PADM + pad(n + 1)] = C{a.kappa * v, -a.kappa * v + (stim ? a.beta * sa[i] : 0.0)};
+      }
+    }
     if constexpr (MODE == FHN_SRC) {
+      // the correction, added to the source words this thread wrote (loaded after the source
+      // is in LDS, so that both sets of loads are not held in registers at once)
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int e = tid + i * NT;
@@ -1008,23 +1020,15 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
         c0[i] = has ? rhs[row * M + n] : 0.0;
         c1[i] = has ? rhs[cs + row * M + n] : 0.0;
       }
-    }
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      const int rr = e / N, n = e - rr * N;
-      const int64_t row = r0 + rr;
-      if (e < NE) {
-        double v = va[i], g = qa[i];
-        fhn_fe(v, g, a.dth, a.m);
-        C f = {a.kappa * v, -a.kappa * v + (stim ? a.beta * sa[i] : 0.0)};
-        if constexpr (MODE == FHN_SRC) {
-          if (row < rows && flagged(rr)) {
-            f.x = f.x + c0[i];
-            f.y = f.y + c1[i];
-          }
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        const int rr = e / N, n = e - rr * N;
+        if (e < NE && r0 + rr < rows && flagged(rr)) {
+          C &w = sbuf[rr * PADM + pad(n + 1)];
+          w.x = w.x + c0[i];
+          w.y = w.y + c1[i];
         }
-        sbuf[rr * PADM + pad(n + 1)] = f;
       }
     }
   }
