@@ -185,7 +185,7 @@ def copy_calibration(a, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs the workload on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
