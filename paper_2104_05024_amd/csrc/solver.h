@@ -25,6 +25,11 @@ struct Solver {
   bool use_graph = true;
   double *vin = nullptr, *wv = nullptr;
   int *jdev = nullptr, *jhost = nullptr;
+  // step counter: each replayed step ends by storing its number in pinned host memory, which
+  // the host polls instead of sleeping in a stream synchronisation between steps
+  int *seqdev = nullptr, *seqhost = nullptr;
+  int seq_next = 0;
+  void wait_step(hipStream_t st);
   hipStream_t cap = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graph_m[2] = {0, 0};

@@ -3,6 +3,7 @@
 // with one re-orthogonalisation), Givens rotations and the least-squares update are FP64;
 // only the matrix-vector product may run in FP32 (inner solve of the refinement scheme).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -142,8 +143,15 @@ __global__ __launch_bounds__(kB) void k_normalize(double *V, int64_t ldv, const 
   if (vnext) vnext[i] = v;
 }
 
-__global__ void k_inc_j(int *j) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *j += 1;
+// j <- j + 1, and the step counter: seq <- seq + 1, also stored to the host's copy
+__global__ void k_inc_j(int *j, int *seq, int *seq_host) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *j += 1;
+    const int s = *seq + 1;
+    *seq = s;
+    __threadfence_system();
+    __hip_atomic_store(seq_host, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 __global__ __launch_bounds__(kB) void k_axpby(double *__restrict__ z, double a, const double *__restrict__ x,
@@ -253,6 +261,11 @@ void Solver::init(DevProblem &p) {
   wv = dalloc<double>(L);
   jdev = dalloc<int>(1);
   KFBI_HIP(hipHostMalloc(&jhost, sizeof(int), hipHostMallocDefault));
+  seqdev = dalloc<int>(1);
+  KFBI_HIP(hipMemset(seqdev, 0, sizeof(int)));
+  KFBI_HIP(hipHostMalloc(&seqhost, sizeof(int), hipHostMallocDefault));
+  *seqhost = 0;
+  seq_next = 0;
   KFBI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   n_inside = 0;
   for (int8_t v : p.ht.inside) n_inside += v;
@@ -272,6 +285,10 @@ void Solver::release() {
   if (jhost) (void)hipHostFree(jhost);
   jdev = nullptr;
   jhost = nullptr;
+  if (seqdev) (void)hipFree(seqdev);
+  if (seqhost) (void)hipHostFree(seqhost);
+  seqdev = nullptr;
+  seqhost = nullptr;
   double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &npart, &hdev, &ydev, &vin, &wv};
   for (double **q : dp) {
     if (*q) (void)hipFree(*q);
@@ -342,8 +359,22 @@ void Solver::arnoldi_step(DevProblem &p, int prec, int m, hipStream_t st) {
                                       L);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
-  k_inc_j<<<1, 1, 0, st>>>(jdev);
+  k_inc_j<<<1, 1, 0, st>>>(jdev, seqdev, seqhost);
   KFBI_HIP(hipGetLastError());
+}
+
+// Waits for the step just replayed: polls the step counter in pinned memory (the step's
+// Hessenberg column copy precedes the counter store), falling back to a stream
+// synchronisation after 20 ms or if anything is off, which also reports errors.
+void Solver::wait_step(hipStream_t st) {
+  ++seq_next;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int spins = 0;; ++spins) {
+    if (__atomic_load_n(seqhost, __ATOMIC_ACQUIRE) == seq_next) return;
+    if ((spins & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
+  }
+  KFBI_HIP(hipStreamSynchronize(st));
+  seq_next = __atomic_load_n(seqhost, __ATOMIC_ACQUIRE);
 }
 
 // Replays the captured Arnoldi step (captured on first use on the solver's own stream).
@@ -427,7 +458,8 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       }
       ++matvecs;
       ++its;
-      KFBI_HIP(hipStreamSynchronize(st));
+      if (graphed) wait_step(st);
+      else KFBI_HIP(hipStreamSynchronize(st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + hhost[(kMaxRestart + 2) + i];
       const double hn = std::sqrt(std::max(0.0, hhost[2 * (kMaxRestart + 2)]));
       H[(size_t)(j + 1) * m + j] = hn;
