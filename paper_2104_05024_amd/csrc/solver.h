@@ -30,6 +30,9 @@ struct Solver {
   int *seqdev = nullptr, *seqhost = nullptr;
   int seq_next = 0;
   void wait_step(hipStream_t st);
+  // waits until the stream has run all work enqueued so far (a step counter stored by a tiny
+  // kernel, polled; errors are reported through the stream synchronisation it falls back to)
+  void host_wait(hipStream_t st);
   hipStream_t cap = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graph_m[2] = {0, 0};

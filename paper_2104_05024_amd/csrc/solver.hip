@@ -143,10 +143,10 @@ __global__ __launch_bounds__(kB) void k_normalize(double *V, int64_t ldv, const 
   if (vnext) vnext[i] = v;
 }
 
-// j <- j + 1, and the step counter: seq <- seq + 1, also stored to the host's copy
+// j <- j + 1 (when given), and the step counter: seq <- seq + 1, also stored to the host's copy
 __global__ void k_inc_j(int *j, int *seq, int *seq_host) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *j += 1;
+    if (j) *j += 1;
     const int s = *seq + 1;
     *seq = s;
     __threadfence_system();
@@ -341,7 +341,7 @@ double Solver::dot(const double *a, const double *b, hipStream_t st) {
   k_multidot<<<dim3(nb, 1), kB, 0, st>>>(a, L, b, L, partials);
   k_finish<<<1, kB, 0, st>>>(partials, nb, hdev);
   KFBI_HIP(hipMemcpyAsync(hhost, hdev, sizeof(double), hipMemcpyDeviceToHost, st));
-  KFBI_HIP(hipStreamSynchronize(st));
+  host_wait(st);
   return hhost[0];
 }
 
@@ -361,6 +361,12 @@ void Solver::arnoldi_step(DevProblem &p, int prec, int m, hipStream_t st) {
   KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
   k_inc_j<<<1, 1, 0, st>>>(jdev, seqdev, seqhost);
   KFBI_HIP(hipGetLastError());
+}
+
+void Solver::host_wait(hipStream_t st) {
+  k_inc_j<<<1, 1, 0, st>>>(nullptr, seqdev, seqhost);
+  KFBI_HIP(hipGetLastError());
+  wait_step(st);
 }
 
 // Waits for the step just replayed: polls the step counter in pinned memory (the step's
@@ -505,7 +511,7 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       k_combine<<<nblk(L), kB, 0, st>>>(r, V, L, ydev, jend + 1, 1.0, L);
       KFBI_HIP(hipGetLastError());
       beta = std::fabs(g[jend]);
-      KFBI_HIP(hipStreamSynchronize(st));
+      host_wait(st);
       break;
     }
     apply_vec(p, prec, x, t, st);
@@ -621,7 +627,7 @@ double Solver::gauge_mean(DevProblem &p, hipStream_t st) {
   k_finish<<<1, kB, 0, st>>>(partials, nb, hdev);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hhost, hdev, sizeof(double), hipMemcpyDeviceToHost, st));
-  KFBI_HIP(hipStreamSynchronize(st));
+  host_wait(st);
   return n_inside > 0 ? hhost[0] / (double)n_inside : 0.0;
 }
 
@@ -683,7 +689,7 @@ void bidomain_s::proj_start(double *out_psi, double *out_r, hipStream_t st) {
   k_finish<<<k, kB, 0, st>>>(sv.partials, sv.nb, sv.hdev);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(sv.hhost, sv.hdev, k * sizeof(double), hipMemcpyDeviceToHost, st));
-  KFBI_HIP(hipStreamSynchronize(st));
+  sv.host_wait(st);
   double A[kProj][kProj + 1];
   double dmax = 0;
   for (int i = 0; i < k; ++i) dmax = std::max(dmax, proj_G[i][i]);
@@ -731,7 +737,7 @@ void bidomain_s::proj_record(const double *psi, hipStream_t st) {
   k_finish<<<proj_n, kB, 0, st>>>(sv.partials, sv.nb, sv.hdev);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(sv.hhost, sv.hdev, proj_n * sizeof(double), hipMemcpyDeviceToHost, st));
-  KFBI_HIP(hipStreamSynchronize(st));
+  sv.host_wait(st);
   for (int i = 0; i < proj_n; ++i) proj_G[slot][i] = proj_G[i][slot] = sv.hhost[i];
 }
 
@@ -853,6 +859,6 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   ++steps_done;
   k_end_step<<<nblk(L), kB, 0, st>>>(gp_prev, sv.gp, hist2, hist1, psi0, L);
   KFBI_HIP(hipGetLastError());
-  KFBI_HIP(hipStreamSynchronize(st));
+  sv.host_wait(st);
   return rc;
 }
