@@ -55,6 +55,9 @@ struct Batch {
   float *v32 = nullptr, *w32 = nullptr;
   double *hcols = nullptr, *hhost = nullptr, *ydev = nullptr, *sdev = nullptr, *nrm = nullptr;
   int *jdev = nullptr, *jhost = nullptr;
+  int *seqdev = nullptr, *seqhost = nullptr;   // step counter polled by the host (as the solver's)
+  int seq_next = 0;
+  void host_wait(hipStream_t st);
   bool use_graph = true;
   hipStream_t cap = nullptr;           // capture stream (the caller's stream may be the null stream)
   hipGraphExec_t graph[2] = {nullptr, nullptr};

@@ -86,8 +86,15 @@ __global__ __launch_bounds__(kB) void k_take(const double *__restrict__ V, int64
   if (e < L) v[e] = V[(int64_t)(*jdev) * L + e];
 }
 
-__global__ void k_inc(int *j) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *j += 1;
+// j <- j + 1 (when given), and the step counter: seq <- seq + 1, also stored to the host's copy
+__global__ void k_inc(int *j, int *seq, int *seq_host) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (j) *j += 1;
+    const int s = *seq + 1;
+    *seq = s;
+    __threadfence_system();
+    __hip_atomic_store(seq_host, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // V_0 = r * s[pid] (s = 1/beta, or 0 for problems that are done)
@@ -306,10 +313,15 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
   hcols = balloc<double>((size_t)3 * (kMaxRestart + 1) * n);
   KFBI_HIP(hipHostMalloc(&hhost, (size_t)3 * (kMaxRestart + 1) * n * sizeof(double), hipHostMallocDefault));
   KFBI_HIP(hipHostMalloc(&jhost, sizeof(int), hipHostMallocDefault));
+  KFBI_HIP(hipHostMalloc(&seqhost, sizeof(int), hipHostMallocDefault));
+  *seqhost = 0;
+  seq_next = 0;
   ydev = balloc<double>((size_t)kMaxRestart * n);
   sdev = balloc<double>(n);
   nrm = balloc<double>(n);
   jdev = balloc<int>(1);
+  seqdev = balloc<int>(1);
+  KFBI_HIP(hipMemset(seqdev, 0, sizeof(int)));
   KFBI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   // tile widths of every size group, timed on the group's own buffers
   for (Group &g : groups) {
@@ -333,13 +345,15 @@ void Batch::release() {
   }
   groups.clear();
   void *ps[] = {pid, off_dev, goff_dev, cum_nc, cum_irr, items64, items32, packs, V, vin, w, r, d, t, gp, x, dx,
-                v32, w32, hcols, ydev, sdev, nrm, jdev};
+                v32, w32, hcols, ydev, sdev, nrm, jdev, seqdev};
   for (void *q : ps)
     if (q) (void)hipFree(q);
   if (cap) (void)hipStreamDestroy(cap);
   cap = nullptr;
   if (hhost) (void)hipHostFree(hhost);
   if (jhost) (void)hipHostFree(jhost);
+  if (seqhost) (void)hipHostFree(seqhost);
+  seqhost = nullptr;
   hhost = nullptr;
   jhost = nullptr;
   for (auto &p : probs)
@@ -378,7 +392,7 @@ void Batch::seg_norms(const double *v, std::vector<double> &out, hipStream_t st)
   k_seg_dot<<<dim3(np, 1), kB, 0, st>>>(v, 0, nullptr, v, off_dev, np, nrm);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hhost, nrm, np * sizeof(double), hipMemcpyDeviceToHost, st));
-  KFBI_HIP(hipStreamSynchronize(st));
+  host_wait(st);
   out.resize(np);
   for (int p = 0; p < np; ++p) out[p] = std::sqrt(std::max(0.0, hhost[p]));
 }
@@ -397,8 +411,14 @@ void Batch::arnoldi_step(int prec, int m, hipStream_t st) {
   k_seg_next<<<nb(L), kB, 0, st>>>(w, hn, pid, V, L, jdev);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hhost, hcols, (size_t)3 * ld * np * sizeof(double), hipMemcpyDeviceToHost, st));
-  k_inc<<<1, 1, 0, st>>>(jdev);
+  k_inc<<<1, 1, 0, st>>>(jdev, seqdev, seqhost);
   KFBI_HIP(hipGetLastError());
+}
+
+void Batch::host_wait(hipStream_t st) {
+  k_inc<<<1, 1, 0, st>>>(nullptr, seqdev, seqhost);
+  KFBI_HIP(hipGetLastError());
+  seq_next = poll_step_counter(seqhost, seq_next + 1, st);
 }
 
 void Batch::run_step(int prec, int m, hipStream_t st) {
@@ -467,7 +487,7 @@ void Batch::gmres(int prec, const double *b, double *xv, bool x_zero, const std:
       run_step(prec, m, st);
       ++matvecs;
       ++total;
-      KFBI_HIP(hipStreamSynchronize(st));
+      seq_next = poll_step_counter(seqhost, seq_next + 1, st);   // the step ends with the counter
       bool all = true;
       for (int p = 0; p < np; ++p) {
         if (done[p]) continue;

@@ -201,6 +201,11 @@ __device__ __forceinline__ float recip(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
+// Waits until the step counter *seq_host (pinned host memory, stored by a one-thread kernel with
+// a system-scope release after the work it follows) reaches expect: polls it for up to 20 ms,
+// then synchronises the stream, which also reports any error.  Returns the counter's value.
+int poll_step_counter(const int *seq_host, int expect, hipStream_t st);
+
 // FitzHugh-Nagumo reaction (Sec. 7) and its two half steps in the Strang splitting (Sec. 3):
 // forward Euler, and backward Euler with q eliminated and Newton on V.  inv_cm = 1 / C_m and
 // inv_den = 1 / (1 + dth zeta) for the half step dth, so that no node divides by constants.

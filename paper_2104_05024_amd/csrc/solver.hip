@@ -369,19 +369,18 @@ void Solver::host_wait(hipStream_t st) {
   wait_step(st);
 }
 
-// Waits for the step just replayed: polls the step counter in pinned memory (the step's
-// Hessenberg column copy precedes the counter store), falling back to a stream
-// synchronisation after 20 ms or if anything is off, which also reports errors.
-void Solver::wait_step(hipStream_t st) {
-  ++seq_next;
+int poll_step_counter(const int *seq_host, int expect, hipStream_t st) {
   const auto t0 = std::chrono::steady_clock::now();
   for (int spins = 0;; ++spins) {
-    if (__atomic_load_n(seqhost, __ATOMIC_ACQUIRE) == seq_next) return;
+    if (__atomic_load_n(seq_host, __ATOMIC_ACQUIRE) == expect) return expect;
     if ((spins & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
   }
   KFBI_HIP(hipStreamSynchronize(st));
-  seq_next = __atomic_load_n(seqhost, __ATOMIC_ACQUIRE);
+  return __atomic_load_n(seq_host, __ATOMIC_ACQUIRE);
 }
+
+// Waits for the step just replayed (its Hessenberg column copy precedes the counter store).
+void Solver::wait_step(hipStream_t st) { seq_next = poll_step_counter(seqhost, seq_next + 1, st); }
 
 // Replays the captured Arnoldi step (captured on first use on the solver's own stream).
 void Solver::run_step(DevProblem &p, int prec, int m, hipStream_t st) {
