@@ -19,6 +19,7 @@ struct Solver {
   double *hdev = nullptr;      // device dot results (3 * (kMaxRestart + 2))
   double *hhost = nullptr;     // pinned host mirror
   double *ydev = nullptr;      // least-squares coefficients uploaded for the update
+  double *ypin = nullptr;      // pinned staging of those coefficients [2][kMaxRestart + 2]
   int64_t n_inside = 0;
   int8_t *inside_plain = nullptr;
   // captured Arnoldi step (per precision of the product), replayed every GMRES iteration

@@ -257,6 +257,7 @@ void Solver::init(DevProblem &p) {
   hdev = dalloc<double>(3 * (kMaxRestart + 2));
   ydev = dalloc<double>(kMaxRestart + 2);
   KFBI_HIP(hipHostMalloc(&hhost, 3 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
+  KFBI_HIP(hipHostMalloc(&ypin, 2 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
   vin = dalloc<double>(L);
   wv = dalloc<double>(L);
   jdev = dalloc<int>(1);
@@ -298,6 +299,8 @@ void Solver::release() {
   if (w32) (void)hipFree(w32);
   if (inside_plain) (void)hipFree(inside_plain);
   if (hhost) (void)hipHostFree(hhost);
+  if (ypin) (void)hipHostFree(ypin);
+  ypin = nullptr;
   v32 = w32 = nullptr;
   inside_plain = nullptr;
   hhost = nullptr;
@@ -494,7 +497,8 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
       y[i] = acc / H[(size_t)i * m + i];
     }
-    KFBI_HIP(hipMemcpyAsync(ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, st));
+    std::copy(y.begin(), y.begin() + jend, ypin);
+    KFBI_HIP(hipMemcpyAsync(ydev, ypin, jend * sizeof(double), hipMemcpyHostToDevice, st));
     k_combine<<<nblk(L), kB, 0, st>>>(x, V, L, ydev, jend, 1.0, L);
     KFBI_HIP(hipGetLastError());
     if (std::fabs(g[jend]) <= tol_abs && !breakdown) {
@@ -505,7 +509,9 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
         for (int k = 0; k < jend; ++k) acc -= Hc[(size_t)i * m + k] * y[k];
         z[i] = acc;
       }
-      KFBI_HIP(hipMemcpyAsync(ydev, z.data(), (jend + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+      std::copy(z.begin(), z.begin() + jend + 1, ypin + (kMaxRestart + 2));
+      KFBI_HIP(hipMemcpyAsync(ydev, ypin + (kMaxRestart + 2), (jend + 1) * sizeof(double), hipMemcpyHostToDevice,
+                              st));
       k_axpby<<<nblk(L), kB, 0, st>>>(r, 0.0, r, 0.0, nullptr, L);
       k_combine<<<nblk(L), kB, 0, st>>>(r, V, L, ydev, jend + 1, 1.0, L);
       KFBI_HIP(hipGetLastError());
@@ -713,13 +719,13 @@ void bidomain_s::proj_start(double *out_psi, double *out_r, hipStream_t st) {
     for (int j = i + 1; j < k; ++j) acc -= A[i][j] * cvec[j];
     cvec[i] = A[i][i] != 0.0 ? acc / A[i][i] : 0.0;
   }
-  KFBI_HIP(hipMemcpyAsync(sv.ydev, cvec.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+  std::copy(cvec.begin(), cvec.begin() + k, sv.ypin);
+  KFBI_HIP(hipMemcpyAsync(sv.ydev, sv.ypin, k * sizeof(double), hipMemcpyHostToDevice, st));
   k_axpby<<<nblk(L), kB, 0, st>>>(out_psi, 0.0, out_psi, 0.0, nullptr, L);
   k_combine<<<nblk(L), kB, 0, st>>>(out_psi, proj_psi, L, sv.ydev, k, 1.0, L);
   KFBI_HIP(hipMemcpyAsync(out_r, sv.gp, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   k_combine<<<nblk(L), kB, 0, st>>>(out_r, proj_b, L, sv.ydev, k, -1.0, L);
   KFBI_HIP(hipGetLastError());
-  KFBI_HIP(hipStreamSynchronize(st));   // cvec (host) is read by the copy above
 }
 
 // Record the solution just computed: psi and b = g' - (final residual), and the new Gram row.
