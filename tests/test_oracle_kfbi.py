@@ -303,6 +303,33 @@ def test_neumann_mms_second_order_2d_and_flat_iterations():
         assert r[2]["rel_resid"] <= 1e-10
 
 
+def _psi_boundary_data_only(I):
+    """The C1 star with f = 0 and the manufactured Neumann data: the density carries the whole
+    solution (|psi| about 11), so the jump terms are large."""
+    P = kfbi.Problem(W.star2d(n_nodes=2 * I), W.box(2, I), W.scalar_coeffs(2, 1.0, 400.0))
+    X, n = P.nodes.X, P.nodes.n
+    g = n[:, 0] * np.exp(X[:, 0]) * np.sin(math.pi * X[:, 1]) \
+        + n[:, 1] * math.pi * np.exp(X[:, 0]) * np.cos(math.pi * X[:, 1])
+    _, psi, info = P.solve_neumann(g[None], np.zeros((1, P.grid.n ** 2)), tol=1e-12)
+    assert info["rel_resid"] <= 1e-12
+    return psi[0]
+
+
+@pytest.mark.parametrize("case", ["mms", "boundary_data_only"])
+def test_density_self_convergence_second_order_2d(case):
+    """The density psi of the BIE (Sec. 4, eq. bie; the strength of the single layer, Sec. 5.1)
+    converges at second order: node j of M = 2I nodes sits at the same point as node 2j of
+    M = 4I nodes, so successive solutions compare at nested nodes (C1 star, 64^2..256^2).
+    With f = 0 the density is large; a dropped Hessian jump in the extrapolation, a dropped
+    second-derivative term in the correction or a sign error in the surface gradient of psi
+    at the crossings each bring this order below 1.65."""
+    get = (lambda I: _mms_2d(I)[3][0]) if case == "mms" else _psi_boundary_data_only
+    ps = {I: get(I) for I in (64, 128, 256)}
+    e1 = np.max(np.abs(ps[64] - ps[128][::2]))
+    e2 = np.max(np.abs(ps[128] - ps[256][::2]))
+    assert math.log2(e1 / e2) >= (1.7 if case == "mms" else 1.8), (e1, e2)
+
+
 def test_neumann_mms_3d_ellipsoid():
     ue = lambda x: np.sin(x[:, 0]) * np.cos(x[:, 1]) * np.exp(x[:, 2])
 

@@ -104,7 +104,7 @@ def test_diffusion_step_conserves_tissue_integral_of_V():
     assert np.max(V2) < np.max(V)                 # diffusion smooths the peak
 
 
-def test_bidomain_step_gauge_and_midpoint_update():
+def test_bidomain_step_gauge_and_reconstruct():
     prob, iface, grid = _small_bidomain()
     V, q = bidomain.initial_state(grid, W.stimulus_center(iface), radius=0.3)
     V1, q1, u, psi, info = bidomain.step(prob, P, V, q, 0.01, tol=1e-10)
@@ -115,6 +115,93 @@ def test_bidomain_step_gauge_and_midpoint_update():
     Vh, qh = bidomain.reaction_forward_euler(V, q, 0.005, P)
     u2 = prob.reconstruct(bidomain.diffusion_rhs(Vh, kap), psi.ravel())
     np.testing.assert_allclose(u2, u, atol=1e-13)
+
+
+def _fhn_flow(v0, q0, T, p):
+    """Exact FitzHugh-Nagumo flow over T (reaction only), by an 8th-order adaptive integrator."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(t, y):
+        return [-p.H * (y[1] - y[0] * (y[0] - p.theta) * (1.0 - y[0])) / p.Cm, p.alpha * y[0] - p.zeta * y[1]]
+    s = solve_ivp(rhs, (0.0, T), [v0, q0], method="DOP853", rtol=1e-13, atol=1e-15)
+    return s.y[0, -1], s.y[1, -1]
+
+
+def test_reaction_half_steps_against_exact_flow():
+    """Forward Euler over h has local error O(h^2) against the exact reaction flow; the
+    symmetric pair 'forward Euler over h, then backward Euler over h' (the reaction part of one
+    Strang step of length 2h, Sec. 3) has local error O(h^3).  Halving h divides the errors by
+    about 4 and 8; the reversed pair is also O(h^3) but differs from it at O(h^2)."""
+    v0, q0 = 0.6, 0.02
+    e_fe, e_pair = [], []
+    for h in (0.002, 0.001, 0.0005):
+        Ve, qe = _fhn_flow(v0, q0, h, P)
+        V1, q1 = bidomain.reaction_forward_euler(np.array([v0]), np.array([q0]), h, P)
+        e_fe.append(abs(V1[0] - Ve) + abs(q1[0] - qe))
+        V2e, q2e = _fhn_flow(v0, q0, 2 * h, P)
+        V2, q2 = bidomain.reaction_backward_euler(V1, q1, h, P)
+        e_pair.append(abs(V2[0] - V2e) + abs(q2[0] - q2e))
+    r_fe = [e_fe[i] / e_fe[i + 1] for i in range(2)]
+    r_pair = [e_pair[i] / e_pair[i + 1] for i in range(2)]
+    assert all(3.6 < r < 4.4 for r in r_fe), r_fe
+    assert all(7.0 < r < 9.0 for r in r_pair), r_pair
+
+
+def test_step_with_identity_diffusion_is_forward_then_backward_euler():
+    """Pins the composition of bidomain.step (Sec. 3, eqs. ode1, diffusion, ode2).
+
+    With a spatially uniform state and conductivities so small that the screening length
+    sqrt(sigma/kappa) (about 2e-3) is far below the distance from the interface to the box
+    (0.7), the coupled solve returns Phi_i - Phi_e = V1 on the tissue to rounding (g' vanishes),
+    so the midpoint update gives back V1 and the step must equal backward Euler over dt/2
+    applied to forward Euler over dt/2 of the reaction, node by node.  A step that swapped the
+    order of the half steps, used V instead of V1 in the midpoint update (2w - V, off by
+    V1 - V = 4.6e-2 here) or dropped a half step fails by far more than the tolerance."""
+    p = W.BidomainParams(sigma_i=1e-3, sigma_e=2e-3)
+    v0, q0, dt = 0.6, 0.02, 0.01
+    grid = W.box(3, 32)
+    prob = kfbi.Problem(W.sphere(R=0.5, n_nodes=512), grid, W.bidomain_coeffs(3, p, dt))
+    n = grid.n ** 3
+    V3, q3, u, psi, info = bidomain.step(prob, p, np.full(n, v0), np.full(n, q0), dt, tol=1e-8)
+    V1, q1 = bidomain.reaction_forward_euler(np.array([v0]), np.array([q0]), dt / 2, p)
+    Vb, qb = bidomain.reaction_backward_euler(V1, q1, dt / 2, p)
+    ins = prob.inside
+    assert np.max(np.abs(V3[ins] - Vb[0])) <= 1e-10
+    assert np.max(np.abs(q3[ins] - qb[0])) <= 1e-12
+    # the alternatives this excludes are far from it
+    Vr1, qr1 = bidomain.reaction_backward_euler(np.array([v0]), np.array([q0]), dt / 2, p)
+    Vr, _ = bidomain.reaction_forward_euler(Vr1, qr1, dt / 2, p)
+    assert abs(Vr[0] - Vb[0]) > 1e-3 and abs(V1[0] - v0) > 1e-2
+
+
+def test_midpoint_rule_maps_a_checkerboard_by_its_amplification_factor():
+    """Pins the diffusion substep of bidomain.step as the implicit midpoint rule (Sec. 3: backward
+    Euler over dt/2 for w, then V <- 2w - V1) with kappa = 2 C_m beta / dt.
+
+    With the reaction switched off, a grid-scale checkerboard V = (-1)^(i+j+k) on a block in the
+    middle of the tissue is an eigenvector of the discrete coupled operator away from the block's
+    edges: with sigma_i grad Phi_i + sigma_e grad Phi_e divergence-free, V obeys
+    C_m beta dV/dt = sigma_m Lap V, sigma_m = sigma_i sigma_e / (sigma_i + sigma_e), and the
+    7-point Laplacian has eigenvalue -12/h^2 on the checkerboard.  One midpoint step multiplies
+    it by (1 - a) / (1 + a), a = (dt/2) sigma_m 12 / (h^2 C_m beta) (= -0.7534 here), where a
+    backward-Euler step would give 1 / (1 + a) (= +0.123) and kappa = C_m beta / dt would give
+    (1 - 2a) / (1 + 2a) (= -0.868)."""
+    p = W.BidomainParams(H=0.0, alpha=0.0, zeta=0.0)
+    dt = 0.01
+    grid = W.box(3, 32)
+    prob = kfbi.Problem(W.ellipsoid(n_nodes=1024), grid, W.bidomain_coeffs(3, p, dt))
+    k = np.arange(grid.n)
+    Kz, Jy, Ix = np.meshgrid(k, k, k, indexing="ij")
+    pts = geometry.grid_points(grid)
+    blk = np.all(np.abs(pts) <= 0.3 + 1e-9, axis=1)
+    V = np.where(blk, ((-1.0) ** (Ix + Jy + Kz)).ravel(), 0.0)
+    V1, q1, u, psi, info = bidomain.step(prob, p, V, np.zeros_like(V), dt, tol=1e-12)
+    sig_m = p.sigma_i * p.sigma_e / (p.sigma_i + p.sigma_e)
+    a = 0.5 * dt * sig_m * 12.0 / (grid.h ** 2 * p.Cm * p.beta)
+    core = np.all(np.abs(pts) <= 0.3 - 3 * grid.h + 1e-9, axis=1)
+    assert np.count_nonzero(core) >= 27
+    np.testing.assert_allclose(V1[core] / V[core], (1 - a) / (1 + a), atol=2e-4)
+    assert np.all(q1 == 0)
 
 
 # ----------------------------------------------------------------------------- MLP
