@@ -153,7 +153,10 @@ int kfbi_table(kfbi_problem p, const char *name, void *dst, int64_t *count, int3
  * problem from psi (Sec. 5.1 eq. single), right-hand-side correction at irregular
  * nodes (Sec. 5.3 eq. correct), DST-I box solve, and n.D grad u+ at the nodes by
  * jump-corrected quadratic extrapolation (Sec. 5.4).  psi, out: device [ncomp][M]
- * in `dtype` (KFBI_F64 or KFBI_F32: the whole product then runs in that precision). */
+ * in `dtype`.  KFBI_F64: the whole product in FP64.  KFBI_F32 (the reduced-precision product of
+ * the mixed-precision solves): the correction and the box solve run in FP32, while the jumps and
+ * the extrapolation fits keep FP64 weights and FP64 sums (psi is widened to FP64 on entry, the
+ * result rounded to FP32 on exit). */
 int kfbi_apply(kfbi_problem p, const void *psi, void *out, int32_t dtype, void *stream);
 
 /* kfbi_box_solve: u = S f, the fast box solve alone (Sec. 5.2 eq. FDE with u = 0 on the box
@@ -172,6 +175,9 @@ typedef struct {
   int32_t max_outer;    /* precision = 1: maximum FP64 refinement steps */
   int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4) */
   double gamma;         /* Richardson parameter, gamma in (0,1) */
+  int32_t true_resid;   /* 1: after the solve form g' - A64 psi with an explicit FP64 product and
+                           report its relative norm in info.true_resid (a check: one product more) */
+  int32_t pad_;
 } kfbi_solve_opts;
 
 typedef struct {
@@ -184,6 +190,8 @@ typedef struct {
   int32_t warm_start_used;  /* bidomain_step: 1 if the learned start was taken */
   int32_t pad_;
   double start_resid;       /* ||g' - A64 psi0|| / ||g'|| of the start density (1 for a zero start) */
+  double true_resid;        /* opts.true_resid = 1: ||g' - A64 psi|| / ||g'|| by an explicit product,
+                               else -1 */
 } kfbi_solve_info;
 
 /* kfbi_solve_neumann: solve the Neumann problem above (Algorithm 1 with GMRES):
@@ -233,9 +241,18 @@ typedef struct {
 
 /* bidomain_step: one Strang step (Sec. 3, eqs. ode1, diffusion, ode2): forward-Euler
  * reaction over dt/2, implicit-midpoint diffusion over dt (backward Euler over dt/2 for
- * w, then V <- 2 w_V - V), backward-Euler reaction over dt/2 solved by Newton. */
+ * w, then V <- 2 w_V - V), backward-Euler reaction over dt/2 solved by Newton.
+ * Starting from psi^{n-1} = psi_hist slot 0, the solve takes that density's residual from the
+ * previous step of this context without a product (g'^n - g'^{n-1} plus the previous final
+ * residual) only while psi_hist is the same array as in that step and its slot 0 still holds,
+ * at every node, the density that step returned; otherwise the residual is computed with an
+ * FP64 product.  So a caller may reset or rewrite psi_hist, V and q between steps at any time. */
 int bidomain_step(bidomain_ctx b, bidomain_state *state, double dt, kfbi_solve_info *info,
                   void *stream);
+/* bidomain_reset: start a new simulation on the same context: forgets the recycled residual, the
+ * solutions recorded for the projection start (warm_start = 3) and the step count that the
+ * learned start waits on (its network is kept). */
+int bidomain_reset(bidomain_ctx b);
 
 /* Learned warm start (not in the paper, which starts GMRES from zero).  The change of the
  * density between steps solves A (psi^n - psi^{n-1}) = g'^n - g'^{n-1}; the start is
@@ -284,7 +301,8 @@ void kfbi_batch_destroy(kfbi_batch b);
  * grid arrays; i = -1 returns the totals in iface_offset / grid_offset. */
 int kfbi_batch_query(kfbi_batch b, int32_t i, int64_t *M, int64_t *N, int64_t *iface_offset,
                      int64_t *grid_offset);
-/* A psi for every problem (device, concatenated, KFBI_F64 or KFBI_F32). */
+/* A psi for every problem (device, concatenated, KFBI_F64 or KFBI_F32 with the same split of
+ * precisions as kfbi_apply). */
 int kfbi_batch_apply(kfbi_batch b, const void *psi, void *out, int32_t dtype, void *stream);
 /* Every problem's Neumann solve (FP64 device arrays, concatenated; g may be NULL for zero
  * Neumann data); opts as for kfbi_solve_neumann (method 0 only), the tolerance relative to

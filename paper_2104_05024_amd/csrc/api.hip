@@ -166,7 +166,7 @@ int kfbi_apply(kfbi_problem p, const void *psi, void *out, int32_t dtype, void *
     if (dtype == KFBI_F64)
       p->solver.apply<double>(p->p, (const double *)psi, (double *)out, st);
     else if (dtype == KFBI_F32)
-      p->solver.apply<float>(p->p, (const float *)psi, (float *)out, st);
+      p->solver.apply_f32(p->p, (const float *)psi, (float *)out, st);
     else
       return fail(KFBI_EINVAL, "dtype");
     return KFBI_OK;
@@ -215,6 +215,12 @@ int kfbi_use_graph(kfbi_problem p, int32_t enable) {
 int bidomain_use_graph(bidomain_ctx b, int32_t enable) {
   if (!b || !b->solver) return fail(KFBI_EINVAL, "argument");
   b->solver->use_graph = enable != 0;
+  return KFBI_OK;
+}
+
+int bidomain_reset(bidomain_ctx b) {
+  if (!b || !b->solver) return fail(KFBI_EINVAL, "argument");
+  b->reset();
   return KFBI_OK;
 }
 
@@ -271,7 +277,7 @@ int kfbi_batch_apply(kfbi_batch b, const void *psi, void *out, int32_t dtype, vo
     if (!b || !psi || !out) return fail(KFBI_EINVAL, "argument");
     const hipStream_t st = (hipStream_t)stream;
     if (dtype == KFBI_F64) b->b.matvec<double>((const double *)psi, (double *)out, st);
-    else if (dtype == KFBI_F32) b->b.matvec<float>((const float *)psi, (float *)out, st);
+    else if (dtype == KFBI_F32) b->b.apply_f32((const float *)psi, (float *)out, st);
     else return fail(KFBI_EINVAL, "dtype");
     KFBI_HIP(hipStreamSynchronize(st));
     return KFBI_OK;

@@ -52,7 +52,6 @@ struct Batch {
   PackItem *packs = nullptr;
   double *V = nullptr, *vin = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *gp = nullptr;
   double *x = nullptr, *dx = nullptr;
-  float *v32 = nullptr, *w32 = nullptr;
   double *hcols = nullptr, *hhost = nullptr, *ydev = nullptr, *sdev = nullptr, *nrm = nullptr;
   int *jdev = nullptr, *jhost = nullptr;
   int *seqdev = nullptr, *seqhost = nullptr;   // step counter polled by the host (as the solver's)
@@ -67,9 +66,13 @@ struct Batch {
   void release();
   template <typename T>
   BatchItem<T> *items() const;
+  // A psi for every problem with the grid side (correction, box solve) in T; the density side
+  // (jumps, extrapolation fits) is FP64 in both, and so are the vectors
   template <typename T>
-  void matvec(const T *in, T *out, hipStream_t st);
+  void matvec(const double *in, double *out, hipStream_t st);
   void apply_vec(int prec, const double *in, double *out, hipStream_t st);
+  // FP32 vectors at the boundary (converted to and from FP64 around the FP32 product)
+  void apply_f32(const float *in, float *out, hipStream_t st);
   void seg_norms(const double *v, std::vector<double> &out, hipStream_t st);
   void arnoldi_step(int prec, int m, hipStream_t st);
   void run_step(int prec, int m, hipStream_t st);

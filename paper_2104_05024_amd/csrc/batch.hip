@@ -257,10 +257,12 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
   std::vector<BatchItem<double>> i64(n);
   std::vector<BatchItem<float>> i32(n);
   std::vector<PackItem> pk(n);
+  // fits (transfer, jump and extrapolation weights, node jumps) from the FP64 tables in both precisions
   auto fill = [&](auto &it, auto &tb, auto *rhs, auto *fpad, auto *work, const DevProblem &p, int i) {
+    const PrecTables<double> &t64 = p.f64;
     it.z_idx = p.z_idx;
-    it.z_A = tb.z_A;
-    it.z_B = tb.z_B;
+    it.z_A = t64.z_A;
+    it.z_B = t64.z_B;
     it.irr_pos = p.irr_pos;
     it.irr_ptr = p.irr_ptr;
     it.arm_cross = p.arm_cross;
@@ -268,14 +270,14 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
     it.arm_s = tb.arm_s;
     it.narm = p.narm;
     it.q_idx = p.q_idx;
-    it.q_wg = tb.q_wg;
-    it.q_c = tb.q_c;
-    it.q_G = tb.q_G;
+    it.q_wg = t64.q_wg;
+    it.q_c = t64.q_c;
+    it.q_G = t64.q_G;
     it.st_pos = p.st_pos;
-    it.st_nw = tb.st_nw;
-    it.st_r = tb.st_r;
+    it.st_nw = t64.st_nw;
+    it.st_r = t64.st_r;
     it.jz = tb.jz;
-    it.jq = tb.jq;
+    it.jq = t64.jq;
     it.rhs = rhs;
     it.fpad = fpad;
     it.work = work;
@@ -308,8 +310,6 @@ void Batch::init(int n, const kfbi_interface *ifaces, const kfbi_grid *grids, co
   gp = balloc<double>(L);
   x = balloc<double>(L);
   dx = balloc<double>(L);
-  v32 = balloc<float>(L);
-  w32 = balloc<float>(L);
   hcols = balloc<double>((size_t)3 * (kMaxRestart + 1) * n);
   KFBI_HIP(hipHostMalloc(&hhost, (size_t)3 * (kMaxRestart + 1) * n * sizeof(double), hipHostMallocDefault));
   KFBI_HIP(hipHostMalloc(&jhost, sizeof(int), hipHostMallocDefault));
@@ -345,7 +345,7 @@ void Batch::release() {
   }
   groups.clear();
   void *ps[] = {pid, off_dev, goff_dev, cum_nc, cum_irr, items64, items32, packs, V, vin, w, r, d, t, gp, x, dx,
-                v32, w32, hcols, ydev, sdev, nrm, jdev, seqdev};
+                hcols, ydev, sdev, nrm, jdev, seqdev};
   for (void *q : ps)
     if (q) (void)hipFree(q);
   if (cap) (void)hipStreamDestroy(cap);
@@ -362,7 +362,7 @@ void Batch::release() {
 }
 
 template <typename T>
-void Batch::matvec(const T *in, T *out, hipStream_t st) {
+void Batch::matvec(const double *in, double *out, hipStream_t st) {
   launch_batch_jumps<T>(items<T>(), counts, in, st);
   launch_batch_correct<T>(items<T>(), counts, 0, st);
   for (const Group &g : groups) {
@@ -374,16 +374,17 @@ void Batch::matvec(const T *in, T *out, hipStream_t st) {
   launch_batch_gather<T>(items<T>(), counts, true, out, st);
 }
 template void Batch::matvec<double>(const double *, double *, hipStream_t);
-template void Batch::matvec<float>(const float *, float *, hipStream_t);
+template void Batch::matvec<float>(const double *, double *, hipStream_t);
 
 void Batch::apply_vec(int prec, const double *in, double *out, hipStream_t st) {
-  if (prec == 0) {
-    matvec<double>(in, out, st);
-  } else {
-    k_cast<double, float><<<nb(L), kB, 0, st>>>(in, v32, L);
-    matvec<float>(v32, w32, st);
-    k_cast<float, double><<<nb(L), kB, 0, st>>>(w32, out, L);
-  }
+  if (prec == 0) matvec<double>(in, out, st);
+  else matvec<float>(in, out, st);
+}
+
+void Batch::apply_f32(const float *in, float *out, hipStream_t st) {
+  k_cast<float, double><<<nb(L), kB, 0, st>>>(in, t, L);
+  matvec<float>(t, w, st);
+  k_cast<double, float><<<nb(L), kB, 0, st>>>(w, out, L);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -647,6 +648,7 @@ int Batch::solve(const double *g, const double *f, double *u, double *psi, const
       in.rel_resid = gn[p] > 0 ? res[p] / gn[p] : 0.0;
       in.gp_norm = gn[p];
       in.start_resid = gn[p] > 0 ? res0[p] / gn[p] : 0.0;
+      in.true_resid = -1.0;
     }
   }
   return ok ? KFBI_OK : KFBI_ENOCONV;

@@ -27,16 +27,20 @@ struct HipError {
 
 template <typename T>
 struct PrecTables {          // per-precision device copies of the numeric tables
+  // density-side tables, FP64 only (null in the FP32 set): every product takes its jumps and its
+  // extrapolation fits in FP64
   T *z_A = nullptr, *z_B = nullptr;      // crossing jumps [comp][K][nc]: [u_a] = sum A psi, [u_aa] = sum B psi
   T *q_wg = nullptr;                     // node surface-gradient weights [Kn][d][M]
   T *q_c = nullptr, *q_G = nullptr;      // node jumps [comp][d + NH][M] on psi_q, [comp][d + NH][d][M] on g
-  T *arm_d = nullptr, *arm_s = nullptr;  // arm offsets [narm]; s D_{c,a} / h^2 [comp][narm]
   T *st_nw = nullptr, *st_r = nullptr;   // gather weights n.D_c grad [comp][S][M]; offsets [S][d][M]
+  // grid-side tables, one copy per precision
+  T *arm_d = nullptr, *arm_s = nullptr;  // arm offsets [narm]; s D_{c,a} / h^2 [comp][narm]
   T *tw = nullptr, *sp = nullptr;        // DST twiddles exp(-2 pi i m/M) (complex) and sin(pi n/M)
   T *rhs = nullptr, *work = nullptr;     // matvec right-hand side (zero off irregular nodes), work field
   T *xbuf = nullptr;                     // sparse matvec: x-forward output, zero outside the rhs rows
   T *ybuf = nullptr;                     // sparse matvec: y-forward output, zero in planes without rhs rows
-  T *jz = nullptr, *jq = nullptr;        // jumps at crossings [comp][2][nc], at nodes [comp][d+nh][M]
+  T *jz = nullptr;                       // jumps at crossings [comp][2][nc] (written in this precision)
+  T *jq = nullptr;                       // jumps at nodes [comp][d+nh][M] (FP64 set only)
 };
 
 // Per-kernel-class launch timer: HIP events recorded around each launch on the launch
@@ -150,18 +154,20 @@ struct ModeParams {
 // One two-dimensional, one-component problem of a batch as the batched interface kernels see
 // it: its tables, its fields inside the size-group buffers, and its offset in the
 // concatenated interface vectors.
+// The density-side tables and node jumps are FP64 for both precisions (as in PrecTables).
 template <typename T>
 struct BatchItem {
   const int32_t *z_idx;
-  const T *z_A, *z_B;
+  const double *z_A, *z_B;
   const int32_t *irr_pos, *irr_ptr, *arm_cross;
   const T *arm_d, *arm_s;
   int64_t narm;
   const int32_t *q_idx;
-  const T *q_wg, *q_c, *q_G;
+  const double *q_wg, *q_c, *q_G;
   const int32_t *st_pos;
-  const T *st_nw, *st_r;
-  T *jz, *jq;
+  const double *st_nw, *st_r;
+  T *jz;
+  double *jq;
   T *rhs, *fpad, *work;        // padded fields inside the group buffers
   int64_t M, nc, nirr, ioff;
 };
@@ -266,23 +272,27 @@ struct FhnArgs {
 void bidomain_volume_solve(DevProblem &p, const FhnArgs &a, hipStream_t st);
 void bidomain_final_solve(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st);
 
+// Jumps from the FP64 density (FP64 weights and arithmetic); the crossing jumps are stored in T
+// for the correction of a T product, the node jumps in FP64.
 template <typename T>
-void launch_jumps(DevProblem &p, const T *psi, hipStream_t st);
+void launch_jumps(DevProblem &p, const double *psi, hipStream_t st);
 template <typename T>
 void launch_correct(DevProblem &p, hipStream_t st);
+// n.D grad u+ at the nodes from the T grid values u: FP64 fit weights, jumps and sums, FP64 out.
 template <typename T>
-void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream_t st);
+void launch_gather(DevProblem &p, const T *u, bool with_jumps, double *out, hipStream_t st);
 template <typename T>
 void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st);
 
 // Batched 2D launches: jumps of every problem (crossings and nodes) in one launch; the
 // correction into rhs (overwrite, target 0) or fpad (accumulate, target 1); the gather from work.
 template <typename T>
-void launch_batch_jumps(const BatchItem<T> *items, const BatchCounts &c, const T *psi, hipStream_t st);
+void launch_batch_jumps(const BatchItem<T> *items, const BatchCounts &c, const double *psi, hipStream_t st);
 template <typename T>
 void launch_batch_correct(const BatchItem<T> *items, const BatchCounts &c, int target, hipStream_t st);
 template <typename T>
-void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, T *out, hipStream_t st);
+void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, double *out,
+                         hipStream_t st);
 // Grouped 2D box solve of G equal-size problems (padded layout, stride cs, msv on the device).
 // w: tile widths of the x and last-axis passes (w[0], w[2]).
 template <typename T>

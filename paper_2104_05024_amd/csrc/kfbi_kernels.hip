@@ -10,6 +10,11 @@
 //  k_gather      : n.D grad u+ at every interface node from its 6/10-node quadratic fit,
 //                  adding the Taylor-expanded jump to values on the "-" side
 //                  (Sec. 5.4, eqs. taylor-i-po, taylor-i-co, ji).
+//
+// Precision: the density, the transfer and jump weights, the node jumps and the extrapolation
+// fits are FP64 in every product.  Only the grid side follows the product's precision T: the
+// crossing jumps are stored in T for the correction, which writes the T right-hand side that
+// the T box solve transforms, and the gather reads the T grid values into its FP64 fit.
 #include <cmath>
 #include <stdexcept>
 
@@ -26,27 +31,27 @@ constexpr int kBlock = 256;
 // values of the transfer stencil), so these kernels hold no geometry and serve any diagonal D.
 
 // [u_a], [u_aa] at one crossing for every component: two weighted sums of the density values.
-template <typename T, int K>
-__device__ __forceinline__ void jumps_cross_at(int64_t c, const T *__restrict__ psi, int64_t M, int64_t nc,
-                                               const int32_t *__restrict__ z_idx, const T *__restrict__ zA,
-                                               const T *__restrict__ zB, int ncomp, T *__restrict__ jz) {
+template <typename TZ, int K>
+__device__ __forceinline__ void jumps_cross_at(int64_t c, const double *__restrict__ psi, int64_t M, int64_t nc,
+                                               const int32_t *__restrict__ z_idx, const double *__restrict__ zA,
+                                               const double *__restrict__ zB, int ncomp, TZ *__restrict__ jz) {
   int32_t j[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) j[k] = z_idx[k * nc + c];
   for (int comp = 0; comp < ncomp; ++comp) {
-    const T *ps = psi + comp * M;
-    const T *A = zA + (int64_t)comp * K * nc, *B = zB + (int64_t)comp * K * nc;
-    T v[K];
+    const double *ps = psi + comp * M;
+    const double *A = zA + (int64_t)comp * K * nc, *B = zB + (int64_t)comp * K * nc;
+    double v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = ps[j[k]];
-    T ju = 0, juu = 0;
+    double ju = 0, juu = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       ju += A[k * nc + c] * v[k];
       juu += B[k * nc + c] * v[k];
     }
-    jz[(2 * comp) * nc + c] = ju;
-    jz[(2 * comp + 1) * nc + c] = juu;
+    jz[(2 * comp) * nc + c] = (TZ)ju;
+    jz[(2 * comp + 1) * nc + c] = (TZ)juu;
   }
 }
 
@@ -120,33 +125,33 @@ __device__ __forceinline__ void sym_index(int e, int &a, int &b) {
 
 // [grad u] (D entries) and [Hess u] (NH entries) at one node for every component:
 // out_j = psi_q qc[j] + sum_f g_f qG[j][f], g = surface gradient of psi from the transfer fit.
-template <typename T, int D, int KN>
-__device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ psi, int64_t M,
-                                               const int32_t *__restrict__ q_idx, const T *__restrict__ q_wg,
-                                               const T *__restrict__ q_c, const T *__restrict__ q_G, int ncomp,
-                                               T *__restrict__ jq) {
+template <int D, int KN>
+__device__ __forceinline__ void jumps_nodes_at(int64_t q, const double *__restrict__ psi, int64_t M,
+                                               const int32_t *__restrict__ q_idx, const double *__restrict__ q_wg,
+                                               const double *__restrict__ q_c, const double *__restrict__ q_G,
+                                               int ncomp, double *__restrict__ jq) {
   constexpr int J = D + NH<D>::v;
   int32_t j[KN];
 #pragma unroll
   for (int k = 0; k < KN; ++k) j[k] = q_idx[k * M + q];
   for (int comp = 0; comp < ncomp; ++comp) {
-    const T *ps = psi + comp * M;
-    T v[KN];
+    const double *ps = psi + comp * M;
+    double v[KN];
 #pragma unroll
     for (int k = 0; k < KN; ++k) v[k] = ps[j[k]];
-    T g[D];
+    double g[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       g[a] = 0;
 #pragma unroll
       for (int k = 0; k < KN; ++k) g[a] += q_wg[(k * D + a) * M + q] * v[k];
     }
-    const T pq = ps[q];
-    const T *C = q_c + (int64_t)comp * J * M, *G = q_G + (int64_t)comp * J * D * M;
-    T *o = jq + (int64_t)comp * J * M;
+    const double pq = ps[q];
+    const double *C = q_c + (int64_t)comp * J * M, *G = q_G + (int64_t)comp * J * D * M;
+    double *o = jq + (int64_t)comp * J * M;
 #pragma unroll
     for (int e = 0; e < J; ++e) {
-      T acc = pq * C[e * M + q];
+      double acc = pq * C[e * M + q];
 #pragma unroll
       for (int f = 0; f < D; ++f) acc += g[f] * G[(e * D + f) * M + q];
       o[e * M + q] = acc;
@@ -156,40 +161,40 @@ __device__ __forceinline__ void jumps_nodes_at(int64_t q, const T *__restrict__ 
 
 // Both jump sets in one launch (they are independent): blocks [0, nbc) take the crossings,
 // the others the interface nodes.
-template <typename T, int D, int K, int KN>
-__global__ __launch_bounds__(kBlock) void k_jumps(const T *__restrict__ psi, int64_t M, int64_t nc, int64_t nbc,
-                                                  const int32_t *__restrict__ z_idx, const T *__restrict__ zA,
-                                                  const T *__restrict__ zB, const int32_t *__restrict__ q_idx,
-                                                  const T *__restrict__ q_wg, const T *__restrict__ q_c,
-                                                  const T *__restrict__ q_G, int ncomp, T *__restrict__ jz,
-                                                  T *__restrict__ jq) {
+template <typename TZ, int D, int K, int KN>
+__global__ __launch_bounds__(kBlock) void k_jumps(const double *__restrict__ psi, int64_t M, int64_t nc,
+                                                  int64_t nbc, const int32_t *__restrict__ z_idx,
+                                                  const double *__restrict__ zA, const double *__restrict__ zB,
+                                                  const int32_t *__restrict__ q_idx, const double *__restrict__ q_wg,
+                                                  const double *__restrict__ q_c, const double *__restrict__ q_G,
+                                                  int ncomp, TZ *__restrict__ jz, double *__restrict__ jq) {
   if ((int64_t)blockIdx.x < nbc) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nc) jumps_cross_at<T, K>(c, psi, M, nc, z_idx, zA, zB, ncomp, jz);
+    if (c < nc) jumps_cross_at<TZ, K>(c, psi, M, nc, z_idx, zA, zB, ncomp, jz);
   } else {
     const int64_t q = ((int64_t)blockIdx.x - nbc) * blockDim.x + threadIdx.x;
-    if (q < M) jumps_nodes_at<T, D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, ncomp, jq);
+    if (q < M) jumps_nodes_at<D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, ncomp, jq);
   }
 }
 
 // n.D_c grad u+ at one node: st_nw[comp][j] = sum_a n_a D_{c,a} (gradient weight of node j)_a.
-template <typename T, int D, int S>
-__device__ __forceinline__ void gather_at(int64_t q, const T *__restrict__ u, int64_t comp_stride, int64_t M,
-                                          const int32_t *__restrict__ st_pos, const T *__restrict__ st_nw,
-                                          const T *__restrict__ st_r, const T *__restrict__ jq, int ncomp,
-                                          int with_jumps, T *__restrict__ out) {
+template <typename TU, int D, int S>
+__device__ __forceinline__ void gather_at(int64_t q, const TU *__restrict__ u, int64_t comp_stride, int64_t M,
+                                          const int32_t *__restrict__ st_pos, const double *__restrict__ st_nw,
+                                          const double *__restrict__ st_r, const double *__restrict__ jq, int ncomp,
+                                          int with_jumps, double *__restrict__ out) {
   constexpr int NHv = NH<D>::v, STR = D + NHv;
   int32_t pe[S];
 #pragma unroll
   for (int j = 0; j < S; ++j) pe[j] = st_pos[j * M + q];
   for (int comp = 0; comp < ncomp; ++comp) {
-    const T *uc = u + comp * comp_stride;
-    T val[S];
+    const TU *uc = u + comp * comp_stride;
+    double val[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) val[j] = uc[pe[j] < 0 ? -pe[j] - 1 : pe[j]];
+    for (int j = 0; j < S; ++j) val[j] = (double)uc[pe[j] < 0 ? -pe[j] - 1 : pe[j]];
     if (with_jumps) {
-      const T *o = jq + (int64_t)comp * STR * M;
-      T du[D], H[D][D];
+      const double *o = jq + (int64_t)comp * STR * M;
+      double du[D], H[D][D];
 #pragma unroll
       for (int a = 0; a < D; ++a) du[a] = o[a * M + q];
 #pragma unroll
@@ -201,36 +206,36 @@ __device__ __forceinline__ void gather_at(int64_t q, const T *__restrict__ u, in
 #pragma unroll
       for (int j = 0; j < S; ++j) {
         if (pe[j] >= 0) continue;
-        T r[D];
+        double r[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) r[a] = st_r[(j * D + a) * M + q];
-        T Jv = 0;
+        double Jv = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          T hr = 0;
+          double hr = 0;
 #pragma unroll
           for (int b = 0; b < D; ++b) hr += H[a][b] * r[b];
-          Jv += r[a] * (du[a] + (T)0.5 * hr);
+          Jv += r[a] * (du[a] + 0.5 * hr);
         }
         val[j] += Jv;
       }
     }
-    const T *nw = st_nw + (int64_t)comp * S * M;
-    T acc = 0;
+    const double *nw = st_nw + (int64_t)comp * S * M;
+    double acc = 0;
 #pragma unroll
     for (int j = 0; j < S; ++j) acc += nw[j * M + q] * val[j];
     out[comp * M + q] = acc;
   }
 }
 
-template <typename T, int D, int S>
-__global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ u, int64_t comp_stride, int64_t M,
+template <typename TU, int D, int S>
+__global__ __launch_bounds__(kBlock) void k_gather(const TU *__restrict__ u, int64_t comp_stride, int64_t M,
                                                    const int32_t *__restrict__ st_pos,
-                                                   const T *__restrict__ st_nw, const T *__restrict__ st_r,
-                                                   const T *__restrict__ jq, int ncomp, int with_jumps,
-                                                   T *__restrict__ out) {
+                                                   const double *__restrict__ st_nw, const double *__restrict__ st_r,
+                                                   const double *__restrict__ jq, int ncomp, int with_jumps,
+                                                   double *__restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < M) gather_at<T, D, S>(q, u, comp_stride, M, st_pos, st_nw, st_r, jq, ncomp, with_jumps, out);
+  if (q < M) gather_at<TU, D, S>(q, u, comp_stride, M, st_pos, st_nw, st_r, jq, ncomp, with_jumps, out);
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -249,7 +254,7 @@ __device__ __forceinline__ int batch_problem(const int64_t *__restrict__ cum, in
 // Work list of one launch: all crossings of all problems, then all their nodes.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_batch_jumps(const BatchItem<T> *__restrict__ items, BatchCounts c,
-                                                        const T *__restrict__ psi) {
+                                                        const double *__restrict__ psi) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < c.tot_nc) {
     const int p = batch_problem(c.cum_nc, c.n, i);
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_jumps(const BatchItem<T> *__re
   if (i >= c.tot_M) return;
   const int p = batch_problem(c.cum_M, c.n, i);
   const BatchItem<T> &it = items[p];
-  jumps_nodes_at<T, 2, 5>(i - c.cum_M[p], psi + it.ioff, it.M, it.q_idx, it.q_wg, it.q_c, it.q_G, 1, it.jq);
+  jumps_nodes_at<2, 5>(i - c.cum_M[p], psi + it.ioff, it.M, it.q_idx, it.q_wg, it.q_c, it.q_G, 1, it.jq);
 }
 
 template <typename T>
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_correct(const BatchItem<T> *__
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchItem<T> *__restrict__ items, BatchCounts c,
-                                                         int with_jumps, T *__restrict__ out) {
+                                                         int with_jumps, double *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.tot_M) return;
   const int p = batch_problem(c.cum_M, c.n, i);
@@ -309,17 +314,23 @@ struct NumTables {
   std::vector<double> z_A, z_B, q_wg, q_c, q_G, arm_d, arm_s, st_nw, st_r, tw, sp;
 };
 
+// The density-side tables (transfer and jump weights, extrapolation fits) and the node jumps
+// exist in FP64 only; every precision keeps its correction weights, DST tables, fields and
+// crossing jumps.
 template <typename T>
 void upload_prec(DevProblem &p, PrecTables<T> &tb, const NumTables &h) {
-  tb.z_A = dupload(cast_vec<T>(h.z_A));
-  tb.z_B = dupload(cast_vec<T>(h.z_B));
-  tb.q_wg = dupload(cast_vec<T>(h.q_wg));
-  tb.q_c = dupload(cast_vec<T>(h.q_c));
-  tb.q_G = dupload(cast_vec<T>(h.q_G));
+  const bool fits = sizeof(T) == sizeof(double);
+  if (fits) {
+    tb.z_A = dupload(cast_vec<T>(h.z_A));
+    tb.z_B = dupload(cast_vec<T>(h.z_B));
+    tb.q_wg = dupload(cast_vec<T>(h.q_wg));
+    tb.q_c = dupload(cast_vec<T>(h.q_c));
+    tb.q_G = dupload(cast_vec<T>(h.q_G));
+    tb.st_nw = dupload(cast_vec<T>(h.st_nw));
+    tb.st_r = dupload(cast_vec<T>(h.st_r));
+  }
   tb.arm_d = dupload(cast_vec<T>(h.arm_d));
   tb.arm_s = dupload(cast_vec<T>(h.arm_s));
-  tb.st_nw = dupload(cast_vec<T>(h.st_nw));
-  tb.st_r = dupload(cast_vec<T>(h.st_r));
   tb.tw = dupload(cast_vec<T>(h.tw));
   tb.sp = dupload(cast_vec<T>(h.sp));
   const size_t field = (size_t)p.ncomp * p.comp_stride;
@@ -335,7 +346,7 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const NumTables &h) {
   }
   const int nh = p.dim == 2 ? 3 : 6;
   tb.jz = dalloc<T>((size_t)p.ncomp * 2 * std::max<int64_t>(p.nc, 1));
-  tb.jq = dalloc<T>((size_t)p.ncomp * (p.dim + nh) * p.M);
+  if (fits) tb.jq = dalloc<T>((size_t)p.ncomp * (p.dim + nh) * p.M);
 }
 
 template <typename T>
@@ -351,16 +362,17 @@ void free_prec(PrecTables<T> &tb) {
 }  // namespace
 
 template <typename T>
-void launch_jumps(DevProblem &p, const T *psi, hipStream_t st) {
-  PrecTables<T> &tb = p.tab<T>();
+void launch_jumps(DevProblem &p, const double *psi, hipStream_t st) {
+  const PrecTables<double> &tb = p.f64;
+  T *jz = p.tab<T>().jz;
   const int64_t nbc = p.nc > 0 ? nblk(p.nc) : 0;
   const unsigned g = (unsigned)(nbc + nblk(p.M));
   if (p.dim == 2)
     k_jumps<T, 2, 4, 5><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B, p.q_idx, tb.q_wg,
-                                              tb.q_c, tb.q_G, p.ncomp, tb.jz, tb.jq);
+                                              tb.q_c, tb.q_G, p.ncomp, jz, tb.jq);
   else
     k_jumps<T, 3, kLsqNodes, kLsqNodes><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B,
-                                                              p.q_idx, tb.q_wg, tb.q_c, tb.q_G, p.ncomp, tb.jz,
+                                                              p.q_idx, tb.q_wg, tb.q_c, tb.q_G, p.ncomp, jz,
                                                               tb.jq);
   KFBI_HIP(hipGetLastError());
 }
@@ -389,8 +401,8 @@ void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st) {
 }
 
 template <typename T>
-void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream_t st) {
-  PrecTables<T> &tb = p.tab<T>();
+void launch_gather(DevProblem &p, const T *u, bool with_jumps, double *out, hipStream_t st) {
+  const PrecTables<double> &tb = p.f64;
   if (p.dim == 2)
     k_gather<T, 2, 6><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
                                                    p.ncomp, with_jumps ? 1 : 0, out);
@@ -401,7 +413,7 @@ void launch_gather(DevProblem &p, const T *u, bool with_jumps, T *out, hipStream
 }
 
 template <typename T>
-void launch_batch_jumps(const BatchItem<T> *items, const BatchCounts &c, const T *psi, hipStream_t st) {
+void launch_batch_jumps(const BatchItem<T> *items, const BatchCounts &c, const double *psi, hipStream_t st) {
   const int64_t n = c.tot_nc + c.tot_M;
   if (n == 0) return;
   k_batch_jumps<T><<<nblk(n), kBlock, 0, st>>>(items, c, psi);
@@ -414,27 +426,28 @@ void launch_batch_correct(const BatchItem<T> *items, const BatchCounts &c, int t
   KFBI_HIP(hipGetLastError());
 }
 template <typename T>
-void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, T *out, hipStream_t st) {
+void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool with_jumps, double *out,
+                         hipStream_t st) {
   if (c.tot_M == 0) return;
   k_batch_gather<T><<<nblk(c.tot_M), kBlock, 0, st>>>(items, c, with_jumps ? 1 : 0, out);
   KFBI_HIP(hipGetLastError());
 }
 template void launch_batch_jumps<double>(const BatchItem<double> *, const BatchCounts &, const double *, hipStream_t);
-template void launch_batch_jumps<float>(const BatchItem<float> *, const BatchCounts &, const float *, hipStream_t);
+template void launch_batch_jumps<float>(const BatchItem<float> *, const BatchCounts &, const double *, hipStream_t);
 template void launch_batch_correct<double>(const BatchItem<double> *, const BatchCounts &, int, hipStream_t);
 template void launch_batch_correct<float>(const BatchItem<float> *, const BatchCounts &, int, hipStream_t);
 template void launch_batch_gather<double>(const BatchItem<double> *, const BatchCounts &, bool, double *,
                                           hipStream_t);
-template void launch_batch_gather<float>(const BatchItem<float> *, const BatchCounts &, bool, float *, hipStream_t);
+template void launch_batch_gather<float>(const BatchItem<float> *, const BatchCounts &, bool, double *, hipStream_t);
 
 template void launch_jumps<double>(DevProblem &, const double *, hipStream_t);
-template void launch_jumps<float>(DevProblem &, const float *, hipStream_t);
+template void launch_jumps<float>(DevProblem &, const double *, hipStream_t);
 template void launch_correct<double>(DevProblem &, hipStream_t);
 template void launch_correct<float>(DevProblem &, hipStream_t);
 template void launch_add_correction<double>(DevProblem &, double *, hipStream_t);
 template void launch_add_correction<float>(DevProblem &, float *, hipStream_t);
 template void launch_gather<double>(DevProblem &, const double *, bool, double *, hipStream_t);
-template void launch_gather<float>(DevProblem &, const float *, bool, float *, hipStream_t);
+template void launch_gather<float>(DevProblem &, const float *, bool, double *, hipStream_t);
 
 // Jump-relation coefficients of one component at a point with normal n and shape operator W
 // (diagonal conductivity Dv): with a = psi / (n.D n),

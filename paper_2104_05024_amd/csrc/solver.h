@@ -12,7 +12,6 @@ struct Solver {
   int nb = 0;                  // reduction blocks per dot product
   double *V = nullptr;         // (kMaxRestart + 1) * L Krylov basis
   double *r = nullptr, *w = nullptr, *t = nullptr, *gp = nullptr, *d = nullptr;
-  float *v32 = nullptr, *w32 = nullptr;
   double *fpad = nullptr;      // padded FP64 field: source + correction of the final solve
   double *partials = nullptr;  // [vector][block] partial sums
   double *npart = nullptr;     // [block] partials of ||w||^2 from the last Gram-Schmidt pass
@@ -43,10 +42,14 @@ struct Solver {
   void init(DevProblem &p);
   void release();
 
+  // out = A psi with FP64 vectors; T is the precision of the grid side (correction and box solve),
+  // the density side (jumps, extrapolation fits) is FP64 in both
   template <typename T>
-  void apply(DevProblem &p, const T *psi, T *out, hipStream_t st);
-  // y = A x with FP64 vectors; prec 1 runs the product in FP32
+  void apply(DevProblem &p, const double *psi, double *out, hipStream_t st);
+  // y = A x; prec 1 runs the grid side in FP32
   void apply_vec(DevProblem &p, int prec, const double *x, double *y, hipStream_t st);
+  // FP32 vectors at the boundary, converted to and from FP64 around the FP32 product
+  void apply_f32(DevProblem &p, const float *psi, float *out, hipStream_t st);
 
   double dot(const double *a, const double *b, hipStream_t st);
   double residual_norm(const double *b, const double *Ax, hipStream_t st);   // ||b - Ax||_2 (uses d)
@@ -60,9 +63,11 @@ struct Solver {
   // fa: bidomain step (source from V after the forward Euler half step it performs; fpad unused)
   void bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnArgs *fa = nullptr);
   // psi solve of A psi = gp with the options; psi holds the start if x0 = 1; r0 (optional) is
-  // its residual gp - A psi if already known.  Afterwards last_resid holds gp - A64 psi.
+  // its residual gp - A psi if already known, unless *r0_bad (pinned host memory, valid after the
+  // first wait of the solve) is set, when the residual is computed with an FP64 product.
+  // Afterwards last_resid holds gp - A64 psi.
   int solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                    hipStream_t st, const double *r0 = nullptr);
+                    hipStream_t st, const double *r0 = nullptr, const int *r0_bad = nullptr);
   const double *last_resid = nullptr;
   // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added)
   // fa: bidomain step (source from V); fuse_be: the inverse x pass also finishes the step
@@ -85,7 +90,15 @@ struct bidomain_s {
   double *r0v = nullptr;       // its residual, recycled from the previous solve
   double *gp_prev = nullptr;   // BIE right-hand side of the previous step
   double *d_prev = nullptr;    // final FP64 residual g'^{n-1} - A psi^{n-1} of the previous solve
+  // the recycled residual belongs to the density of the previous solve: the context keeps its own
+  // copy (psi_last) and the history array it was given (hist_last); a step whose psi^{n-1}
+  // differs from it at any node (flag set on the device, read by the host) takes the starting
+  // residual with an FP64 product instead
+  double *psi_last = nullptr;
+  const double *hist_last = nullptr;
+  int *r0_bad_dev = nullptr, *r0_bad_host = nullptr;
   bool have_prev = false;
+  void reset();                // forget the recycled residual, the projection history and the counts
   // projection start: the last kProj solutions psi_j and their images b_j = A psi_j (known
   // without a product: g'_j minus the final residual), with Gram matrix G = B^T B
   static constexpr int kProj = 8;

@@ -162,22 +162,38 @@ __global__ __launch_bounds__(kB) void k_axpby(double *__restrict__ z, double a, 
 }
 
 // Starting residual of psi^{n-1} without a product: (g'^n - g'^{n-1}) + (g'^{n-1} - A psi^{n-1}).
+// It holds only if the caller's psi^{n-1} (hist1) is still the density the previous solve
+// returned (psi_last, the context's own copy): any node that differs sets *bad.
 __global__ __launch_bounds__(kB) void k_recycled_resid(double *__restrict__ r, const double *__restrict__ gp,
                                                        const double *__restrict__ gp_prev,
-                                                       const double *__restrict__ d_prev, int64_t n) {
+                                                       const double *__restrict__ d_prev,
+                                                       const double *__restrict__ hist1,
+                                                       const double *__restrict__ psi_last, int *__restrict__ bad,
+                                                       int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i < n) r[i] = (gp[i] - gp_prev[i]) + d_prev[i];
+  bool differs = false;
+  if (i < n) {
+    r[i] = (gp[i] - gp_prev[i]) + d_prev[i];
+    differs = hist1[i] != psi_last[i];
+  }
+  if (__any(differs) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
-// End of a bidomain step: g'^{n-1} <- g'^n and the density history shifts by one step.
+// End of a bidomain step: g'^{n-1} <- g'^n, the density history shifts by one step, the context
+// keeps its own copy of the new density, and the mismatch flag of the next recycled residual is
+// cleared.
 __global__ __launch_bounds__(kB) void k_end_step(double *__restrict__ gp_prev, const double *__restrict__ gp,
                                                  double *__restrict__ hist2, double *__restrict__ hist1,
-                                                 const double *__restrict__ psi, int64_t n) {
+                                                 double *__restrict__ psi_last, const double *__restrict__ psi,
+                                                 int *__restrict__ bad, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i == 0) *bad = 0;
   if (i >= n) return;
+  const double v = psi[i];
   gp_prev[i] = gp[i];
   hist2[i] = hist1[i];
-  hist1[i] = psi[i];
+  hist1[i] = v;
+  psi_last[i] = v;
 }
 
 template <typename A, typename B>
@@ -248,8 +264,6 @@ void Solver::init(DevProblem &p) {
   t = dalloc<double>(L);
   gp = dalloc<double>(L);
   d = dalloc<double>(L);
-  v32 = dalloc<float>(L);
-  w32 = dalloc<float>(L);
   fpad = dalloc<double>((size_t)p.ncomp * p.comp_stride);
   KFBI_HIP(hipMemset(fpad, 0, (size_t)p.ncomp * p.comp_stride * sizeof(double)));
   partials = dalloc<double>((size_t)(kMaxRestart + 2) * 512);
@@ -295,19 +309,16 @@ void Solver::release() {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
-  if (v32) (void)hipFree(v32);
-  if (w32) (void)hipFree(w32);
   if (inside_plain) (void)hipFree(inside_plain);
   if (hhost) (void)hipHostFree(hhost);
   if (ypin) (void)hipHostFree(ypin);
   ypin = nullptr;
-  v32 = w32 = nullptr;
   inside_plain = nullptr;
   hhost = nullptr;
 }
 
 template <typename T>
-void Solver::apply(DevProblem &p, const T *psi, T *out, hipStream_t st) {
+void Solver::apply(DevProblem &p, const double *psi, double *out, hipStream_t st) {
   PrecTables<T> &tb = p.tab<T>();
   p.t_jumps.tic(p.profile, st);
   launch_jumps<T>(p, psi, st);
@@ -321,16 +332,17 @@ void Solver::apply(DevProblem &p, const T *psi, T *out, hipStream_t st) {
   p.t_gather.toc(p.profile, st);
 }
 template void Solver::apply<double>(DevProblem &, const double *, double *, hipStream_t);
-template void Solver::apply<float>(DevProblem &, const float *, float *, hipStream_t);
+template void Solver::apply<float>(DevProblem &, const double *, double *, hipStream_t);
 
 void Solver::apply_vec(DevProblem &p, int prec, const double *x, double *y, hipStream_t st) {
-  if (prec == 0) {
-    apply<double>(p, x, y, st);
-    return;
-  }
-  k_cast<double, float><<<nblk(L), kB, 0, st>>>(x, v32, L);
-  apply<float>(p, v32, w32, st);
-  k_cast<float, double><<<nblk(L), kB, 0, st>>>(w32, y, L);
+  if (prec == 0) apply<double>(p, x, y, st);
+  else apply<float>(p, x, y, st);
+}
+
+void Solver::apply_f32(DevProblem &p, const float *psi, float *out, hipStream_t st) {
+  k_cast<float, double><<<nblk(L), kB, 0, st>>>(psi, t, L);
+  apply<float>(p, t, w, st);
+  k_cast<double, float><<<nblk(L), kB, 0, st>>>(w, out, L);
   KFBI_HIP(hipGetLastError());
 }
 
@@ -414,7 +426,10 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
   const int m = std::max(1, std::min(restart, kMaxRestart));
   its = 0;
   if (bnorm == 0.0) {
-    KFBI_HIP(hipMemsetAsync(x, 0, L * sizeof(double), st));
+    // b = 0: the solution is 0 and so is its residual, which callers read from r
+    k_axpby<<<nblk(L), kB, 0, st>>>(x, 0.0, b, 0.0, nullptr, L);
+    k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, 0.0, nullptr, L);
+    KFBI_HIP(hipGetLastError());
     resid = 0;
     if (beta0) *beta0 = 0;
     return KFBI_OK;
@@ -558,8 +573,9 @@ void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnAr
 }
 
 int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                          hipStream_t st, const double *r0) {
+                          hipStream_t st, const double *r0, const int *r0_bad) {
   const double gn = std::sqrt(dot(gp, gp, st));
+  if (r0 && r0_bad && *r0_bad) r0 = nullptr;   // read after the wait above: r0 does not belong to psi
   info.gp_norm = gn;
   const double tol_abs = o.tol * gn;
   int its = 0, mv = 0, rc = KFBI_OK;
@@ -612,6 +628,14 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
   }
   info.rel_resid = gn > 0 ? res / gn : 0.0;
   info.start_resid = gn > 0 ? res0 / gn : 0.0;
+  info.true_resid = -1.0;
+  if (o.true_resid) {
+    // a check: the FP64 residual of the returned density by an explicit product (not counted);
+    // d may be last_resid, which it then overwrites with the same vector
+    apply_vec(p, 0, psi, t, st);
+    const double tr = residual_norm(gp, t, st);
+    info.true_resid = gn > 0 ? tr / gn : 0.0;
+  }
   return rc;
 }
 
@@ -676,6 +700,12 @@ void bidomain_s::init() {
   KFBI_HIP(hipMemset(gp_prev, 0, L * sizeof(double)));
   KFBI_HIP(hipMalloc(&d_prev, L * sizeof(double)));
   KFBI_HIP(hipMemset(d_prev, 0, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&psi_last, L * sizeof(double)));
+  KFBI_HIP(hipMemset(psi_last, 0, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&r0_bad_dev, sizeof(int)));
+  KFBI_HIP(hipMemset(r0_bad_dev, 0, sizeof(int)));
+  KFBI_HIP(hipHostMalloc(&r0_bad_host, sizeof(int), hipHostMallocDefault));
+  *r0_bad_host = 0;
   if (params.warm_start == 3) {
     KFBI_HIP(hipMalloc(&proj_psi, (size_t)kProj * L * sizeof(double)));
     KFBI_HIP(hipMalloc(&proj_b, (size_t)kProj * L * sizeof(double)));
@@ -746,11 +776,23 @@ void bidomain_s::proj_record(const double *psi, hipStream_t st) {
   for (int i = 0; i < proj_n; ++i) proj_G[slot][i] = proj_G[i][slot] = sv.hhost[i];
 }
 
+void bidomain_s::reset() {
+  have_prev = false;
+  hist_last = nullptr;
+  proj_n = 0;
+  proj_head = 0;
+  steps_done = 0;
+}
+
 void bidomain_s::release() {
-  double *ps[] = {psi0, r0v, gp_prev, d_prev, proj_psi, proj_b};
+  double *ps[] = {psi0, r0v, gp_prev, d_prev, psi_last, proj_psi, proj_b};
   for (double *q : ps)
     if (q) (void)hipFree(q);
-  psi0 = r0v = gp_prev = d_prev = proj_psi = proj_b = nullptr;
+  psi0 = r0v = gp_prev = d_prev = psi_last = proj_psi = proj_b = nullptr;
+  if (r0_bad_dev) (void)hipFree(r0_bad_dev);
+  if (r0_bad_host) (void)hipHostFree(r0_bad_host);
+  r0_bad_dev = nullptr;
+  r0_bad_host = nullptr;
   extern void mlp_release(bidomain_s *);
   mlp_release(this);
 }
@@ -773,11 +815,16 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   // step 1 (reaction over dt/2, forward Euler) is computed where its result is used: in the x
   // passes of the box solves of step 2 (diffusion, backward Euler over dt/2 for
   // w = (V^{n+1} + V^n)/2, a Neumann BVP); V and q change only at the end of the step
+  // the recycled residual is usable only on the history array of the previous step (and, checked
+  // on the device, only if its newest density is still the one that step returned)
+  const bool prev_ok = have_prev && s.psi_hist == hist_last;
+  have_prev = false;   // set again when this step completes
   sv.bie_rhs(p, nullptr, st, &fa);
   double *hist1 = s.psi_hist, *hist2 = s.psi_hist + L;
   kfbi_solve_opts o = params.solve;
   bool x0 = true;
   bool have_r0 = false;
+  const int *r0_flag = nullptr;   // set while r0v holds the recycled residual, not yet validated
   info.warm_start_used = 0;
   int extra32 = 0, extra64 = 0;
   if (params.warm_start == 2) {
@@ -787,20 +834,28 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
     //   g'^n - A psi^{n-1} = g'^n - g'^{n-1} + (g'^{n-1} - A psi^{n-1}),
     // the last term being the final FP64 residual of the previous solve
     KFBI_HIP(hipMemcpyAsync(psi0, hist1, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (have_prev) {
-      k_recycled_resid<<<nblk(L), kB, 0, st>>>(r0v, sv.gp, gp_prev, d_prev, L);
+    if (prev_ok) {
+      k_recycled_resid<<<nblk(L), kB, 0, st>>>(r0v, sv.gp, gp_prev, d_prev, hist1, psi_last, r0_bad_dev, L);
+      KFBI_HIP(hipGetLastError());
+      KFBI_HIP(hipMemcpyAsync(r0_bad_host, r0_bad_dev, sizeof(int), hipMemcpyDeviceToHost, st));
       have_r0 = true;
+      r0_flag = r0_bad_host;
     }
-    if (params.warm_start == 3 && have_r0 && proj_n >= 2) {
-      // least-residual start over the recorded solutions; kept only if its (free) residual
-      // is below that of psi^{n-1}
+    if (params.warm_start == 3 && proj_n >= 2) {
+      // least-residual start over the recorded solutions (its residual is exact whatever the
+      // caller's history holds); kept only if that residual is below psi^{n-1}'s, or taken
+      // when psi^{n-1}'s residual is unknown or invalid
       proj_start(sv.w, sv.d, st);
-      const double rh = sv.dot(r0v, r0v, st), rp = sv.dot(sv.d, sv.d, st);
-      if (rp < rh) {
+      const double rp = sv.dot(sv.d, sv.d, st);
+      const bool r0_valid = have_r0 && !*r0_bad_host;   // read after the waits above
+      const double rh = r0_valid ? sv.dot(r0v, r0v, st) : 0.0;
+      if (!r0_valid || rp < rh) {
         KFBI_HIP(hipMemcpyAsync(psi0, sv.w, L * sizeof(double), hipMemcpyDeviceToDevice, st));
         KFBI_HIP(hipMemcpyAsync(r0v, sv.d, L * sizeof(double), hipMemcpyDeviceToDevice, st));
         info.warm_start_used = 1;
+        have_r0 = true;
       }
+      r0_flag = nullptr;   // r0v now holds a validated or an exact residual
     } else if (params.warm_start == 1 && mlp && steps_done >= 2 && mlp_warm_start(this, hist1, hist2, sv.w, st)) {
       if (have_r0) {
         // predicted start psi^{n-1} + D: residual r0 - A D, taken only if smaller than
@@ -814,13 +869,16 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
         else extra64 = 1;
         k_axpby<<<nblk(L), kB, 0, st>>>(sv.d, 1.0, r0v, -1.0, sv.t, L);
         const double rh = sv.dot(r0v, r0v, st), rp = sv.dot(sv.d, sv.d, st);
-        if (rp < rh) {
+        if (*r0_bad_host) {
+          have_r0 = false;   // psi^{n-1} is not the previous solution: no recycled residual
+        } else if (rp < rh) {
           k_axpby<<<nblk(L), kB, 0, st>>>(psi0, 1.0, hist1, 1.0, sv.w, L);
           KFBI_HIP(hipMemcpyAsync(r0v, sv.d, L * sizeof(double), hipMemcpyDeviceToDevice, st));
           info.warm_start_used = 1;
         } else {
           mlp_disable(this);
         }
+        r0_flag = nullptr;
       } else if (mlp_should_check(this)) {
         // no recycled residual (first steps): compare FP32 residuals of both starts
         sv.apply_vec(p, 1, sv.w, sv.t, st);
@@ -840,11 +898,10 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
       }
     }
   }
-  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr);
+  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr, r0_flag);
   info.matvecs_fp32 += extra32;
   info.matvecs_fp64 += extra64;
   KFBI_HIP(hipMemcpyAsync(d_prev, sv.last_resid, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-  have_prev = true;
   if (params.warm_start == 3) proj_record(psi0, st);
   // u = S(f + C psi); the midpoint update and step 3 (reaction over dt/2, backward Euler) ride
   // in its inverse x pass unless the potentials are returned as well
@@ -862,8 +919,10 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
     if (params.warm_start == 1) mlp_note_cost(this, info.matvecs_fp64 + 0.5 * info.matvecs_fp32, info.warm_start_used);
   }
   ++steps_done;
-  k_end_step<<<nblk(L), kB, 0, st>>>(gp_prev, sv.gp, hist2, hist1, psi0, L);
+  k_end_step<<<nblk(L), kB, 0, st>>>(gp_prev, sv.gp, hist2, hist1, psi_last, psi0, r0_bad_dev, L);
   KFBI_HIP(hipGetLastError());
   sv.host_wait(st);
+  have_prev = true;
+  hist_last = s.psi_hist;
   return rc;
 }

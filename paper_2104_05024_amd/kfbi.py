@@ -25,7 +25,7 @@ EXPORTED = [
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
     "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
     "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles", "kfbi_use_graph", "bidomain_use_graph",
-    "kfbi_profile",
+    "kfbi_profile", "bidomain_reset",
 ]
 
 
@@ -57,13 +57,14 @@ class CoeffsDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32), ("precision", C.c_int32),
                 ("x0", C.c_int32), ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("method", C.c_int32),
-                ("gamma", C.c_double)]
+                ("gamma", C.c_double), ("true_resid", C.c_int32), ("pad_", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("matvecs_fp64", C.c_int32),
                 ("matvecs_fp32", C.c_int32), ("rel_resid", C.c_double), ("gp_norm", C.c_double),
-                ("warm_start_used", C.c_int32), ("pad_", C.c_int32), ("start_resid", C.c_double)]
+                ("warm_start_used", C.c_int32), ("pad_", C.c_int32), ("start_resid", C.c_double),
+                ("true_resid", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
@@ -117,6 +118,7 @@ def lib():
     L.kfbi_get_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.kfbi_use_graph.argtypes = [vp, i32]
     L.bidomain_use_graph.argtypes = [vp, i32]
+    L.bidomain_reset.argtypes = [vp]
     L.kfbi_set_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.kfbi_batch_setup.argtypes = [i32, C.POINTER(Interface), C.POINTER(GridDesc), C.POINTER(CoeffsDesc),
                                    C.POINTER(vp)]
@@ -195,8 +197,9 @@ def coeffs_desc(co) -> CoeffsDesc:
 
 
 def solve_opts(tol=1e-10, restart=50, max_iters=500, precision=0, x0=0, inner_tol=1e-4, max_outer=20,
-               method=0, gamma=0.8) -> SolveOpts:
-    return SolveOpts(tol, restart, max_iters, precision, x0, inner_tol, max_outer, method, gamma)
+               method=0, gamma=0.8, true_resid=0) -> SolveOpts:
+    return SolveOpts(tol, restart, max_iters, precision, x0, inner_tol, max_outer, method, gamma,
+                     1 if true_resid else 0, 0)
 
 
 def _stream():
@@ -379,13 +382,14 @@ _INT_TABLES = {"cross_axis", "cross_surf", "cross_pin", "cross_pout", "z_idx", "
 
 
 def bidomain_params(p, tol=1e-8, precision=0, warm_start=0, restart=50, max_iters=500, inner_tol=1e-4,
-                    max_outer=20):
+                    max_outer=20, method=0, gamma=0.8, true_resid=0):
     d = BidomainParamsDesc()
     d.Cm, d.beta, d.H, d.theta, d.alpha, d.zeta = p.Cm, p.beta, p.H, p.theta, p.alpha, p.zeta
     d.newton_tol, d.newton_maxit = p.newton_tol, p.newton_maxit
     d.warm_start = warm_start
     d.solve = solve_opts(tol=tol, restart=restart, max_iters=max_iters, precision=precision, x0=1,
-                         inner_tol=inner_tol, max_outer=max_outer)
+                         inner_tol=inner_tol, max_outer=max_outer, method=method, gamma=gamma,
+                         true_resid=true_resid)
     return d
 
 
@@ -420,6 +424,9 @@ class Bidomain:
 
     def use_graph(self, enable=True):
         _check(lib().bidomain_use_graph(self._h, 1 if enable else 0))
+
+    def reset(self):
+        _check(lib().bidomain_reset(self._h))
 
     def mlp_init(self, capacity=256, seed=3):
         _check(lib().bidomain_mlp_init(self._h, capacity, seed))

@@ -1,8 +1,8 @@
 """Batched 2D Neumann problems on the GPU: 64 seeded problems of grid sizes 64..1024 and
-star shapes with 3-8 lobes, one batch.  Parity against the FP64 oracle on the small problems,
-against the single-problem GPU path on all, manufactured-solution accuracy on all, the
-mixed-precision batch against the FP64 batch, and the captured Arnoldi step against direct
-launches."""
+star shapes with 3-8 lobes, one batch.  Parity against the FP64 oracle (element by element) on
+small problems and on a 512^2 and a 1024^2 member, against the single-problem GPU path on all,
+manufactured-solution accuracy on all, the mixed-precision batch against the FP64 batch, and the
+captured Arnoldi step against direct launches."""
 import sys
 import time
 
@@ -28,8 +28,10 @@ def say(m):
     sys.stdout.flush()
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+def err(a, b):
+    """Largest element-wise difference relative to the largest reference magnitude."""
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
 def T(x):
@@ -72,18 +74,40 @@ def gseg(v, b, i):
     return v[b.goff[i]:b.goff[i] + b.N[i] ** 2]
 
 
-def test_batch_apply_matches_oracle_on_small_problems(batch):
+def _members(probs):
+    """Indices compared with the oracle: up to four small problems and the first problem of the
+    512^2 and of the 1024^2 size groups."""
+    small = [i for i, (_, g, _) in enumerate(probs) if g.cells <= 128][:4]
+    big = [next(i for i, (_, g, _) in enumerate(probs) if g.cells == c) for c in (512, 1024)]
+    return small + big
+
+
+_ORACLE = {}
+
+
+def oracle_problem(probs, i):
+    if i not in _ORACLE:
+        iface, grid, co = probs[i]
+        say(f"    [oracle setup] problem {i} (cells {grid.cells})")
+        _ORACLE[i] = ok.Problem(iface, grid, co)
+    return _ORACLE[i]
+
+
+def test_batch_apply_matches_oracle(batch):
+    """The batched product against the oracle's, element by element, on small problems and on a
+    512^2 and a 1024^2 member (whose DST passes are their own size groups' launches)."""
     b, probs, _, _, _ = batch
     psi = np.random.default_rng(4).uniform(-1, 1, size=b.L)
     say("[batch apply f64]")
     out = b.apply(T(psi)).cpu().numpy()
-    small = [i for i, (_, g, _) in enumerate(probs) if g.cells <= 128][:8]
-    for i in small:
-        iface, grid, co = probs[i]
-        o = ok.Problem(iface, grid, co)
-        e = rel(seg(out, b, i), o.apply(seg(psi, b, i)[None])[0])
-        say(f"    problem {i} (cells {grid.cells}): rel err {e:.2e}")
-        assert e < 1e-10
+    out32 = b.apply(T(psi).float()).double().cpu().numpy()
+    for i in _members(probs):
+        o = oracle_problem(probs, i)
+        ref = o.apply(seg(psi, b, i)[None])[0]
+        e, e32 = err(seg(out, b, i), ref), err(seg(out32, b, i), ref)
+        say(f"    problem {i} (cells {probs[i][1].cells}): FP64 err {e:.2e}, FP32 err {e32:.2e}")
+        assert e < 1e-12
+        assert e32 < 1e-5
 
 
 def test_batch_apply_matches_single_problem_path(batch):
@@ -97,14 +121,17 @@ def test_batch_apply_matches_single_problem_path(batch):
     for i, (iface, grid, co) in enumerate(probs):
         p = K.Problem(iface, grid, co)
         s = T(seg(psi, b, i)[None])
-        worst64 = max(worst64, rel(seg(out64, b, i), p.apply(s).cpu().numpy()))
-        worst32 = max(worst32, rel(seg(out32, b, i), p.apply(s).cpu().numpy()))
+        worst64 = max(worst64, err(seg(out64, b, i), p.apply(s).cpu().numpy()))
+        worst32 = max(worst32, err(seg(out32, b, i), p.apply(s).cpu().numpy()))
         p.close()
     say(f"    batch vs single: FP64 worst {worst64:.2e}, FP32 batch vs FP64 single worst {worst32:.2e}")
-    assert worst64 < 1e-13
-    assert worst32 < 1e-5
+    # element-wise: the FP32 grid side loses about u32 = 6e-8 per DST stage, and the extrapolated
+    # gradient (differences of grid values over h) magnifies it at the finest grids (1024^2)
+    assert worst64 < 1e-12
+    assert worst32 < 5e-5
 
 
+@pytest.mark.timeout(900)
 def test_batch_solve_f64_parity_and_accuracy(batch):
     b, probs, f, g, ue = batch
     say("[batch solve f64]")
@@ -118,21 +145,22 @@ def test_batch_solve_f64_parity_and_accuracy(batch):
     worst = 0.0
     for i, (iface, grid, co) in enumerate(probs):
         o_inside = ogeo.classify(iface, grid).all(axis=0)
-        err = np.max(np.abs(gseg(u, b, i) - ue[i])[o_inside])
+        e_exact = np.max(np.abs(gseg(u, b, i) - ue[i])[o_inside])
         # second order: the 128^2 star of the 2D parity case has max error 0.57 h^2; allow 10x
-        worst = max(worst, err / grid.h ** 2)
-        assert err < 6.0 * grid.h ** 2, (i, grid.cells, err)
+        worst = max(worst, e_exact / grid.h ** 2)
+        assert e_exact < 6.0 * grid.h ** 2, (i, grid.cells, e_exact)
     say(f"    worst max-norm error / h^2 = {worst:.2f}")
-    small = [i for i, (_, gr, _) in enumerate(probs) if gr.cells <= 128][:4]
-    for i in small:
+    for i in _members(probs):
         iface, grid, co = probs[i]
-        o = ok.Problem(iface, grid, co)
+        o = oracle_problem(probs, i)
         fi, gi, _ = mms(iface, grid, co.kappa)
         uo, psio, infoo = o.solve_neumann(gi[None], fi[None], tol=1e-13)
-        e = rel(gseg(u, b, i)[o.inside], uo[0][o.inside])
-        say(f"    problem {i}: u err vs oracle {e:.2e}, iters {infos[i]['iters']} / {infoo['iters']}")
+        e = err(gseg(u, b, i)[o.inside], uo[0][o.inside])
+        ep = err(seg(psi, b, i), psio[0])
+        say(f"    problem {i} (cells {grid.cells}): u err vs oracle {e:.2e}, psi err {ep:.2e}, "
+            f"iters {infos[i]['iters']} / {infoo['iters']}")
         assert e < 1e-10
-        assert rel(seg(psi, b, i), psio[0]) < 1e-9
+        assert ep < 1e-9
 
 
 def test_batch_solve_mixed_precision(batch):
@@ -144,7 +172,7 @@ def test_batch_solve_mixed_precision(batch):
     say(f"    outer {[i['outer'] for i in infos]}")
     assert all(i["rel_resid"] <= 1e-10 for i in infos)
     assert all(i["matvecs_fp32"] > 0 for i in infos)
-    worst = max(rel(gseg(u32, b, i), gseg(u64, b, i)) for i in range(b.n))
+    worst = max(err(gseg(u32, b, i), gseg(u64, b, i)) for i in range(b.n))
     say(f"    worst u difference mixed vs FP64 {worst:.2e}")
     assert worst < 1e-8
 
@@ -178,7 +206,7 @@ def test_batch_with_spline_boundaries_matches_single_problems():
     for i, (iface, grid, co) in enumerate(probs):
         p = K.Problem(iface, grid, co)
         ref = p.apply(T(seg(psi, b, i)[None])).cpu().numpy()
-        e = rel(seg(out, b, i), ref)
+        e = err(seg(out, b, i), ref)
         say(f"    problem {i}: rel diff {e:.2e}")
         assert e < 1e-13
         p.close()
