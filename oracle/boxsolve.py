@@ -15,9 +15,15 @@ coupled pair) and an inverse DST-I (end of Sec. 5.3).
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import scipy.fft
 import scipy.sparse as sp
+
+# the FFTs use every host core the process may run on (independent 1D transforms: the result does
+# not depend on the count)
+WORKERS = len(os.sched_getaffinity(0))
 
 
 def eigenvalues(N, h):
@@ -39,7 +45,7 @@ def box_solve(rhs, grid, coeffs):
     d, N, h = grid.dim, grid.n, grid.h
     shape = (N,) * d
     f = rhs.reshape((coeffs.ncomp,) + shape)
-    fh = np.stack([scipy.fft.dstn(f[c], type=1) for c in range(coeffs.ncomp)])
+    fh = np.stack([scipy.fft.dstn(f[c], type=1, workers=WORKERS) for c in range(coeffs.ncomp)])
     kap = coeffs.kappa
     if coeffs.ncomp == 1:
         uh = fh / (_mode_sums(d, N, h, coeffs.D[0]) + kap)[None]
@@ -50,7 +56,7 @@ def box_solve(rhs, grid, coeffs):
         ui = ((ae + kap) * fh[0] + kap * fh[1]) / det
         ue = (kap * fh[0] + (ai + kap) * fh[1]) / det
         uh = np.stack([ui, ue])
-    u = np.stack([scipy.fft.idstn(uh[c], type=1) for c in range(coeffs.ncomp)])
+    u = np.stack([scipy.fft.idstn(uh[c], type=1, workers=WORKERS) for c in range(coeffs.ncomp)])
     return u.reshape(coeffs.ncomp, -1)
 
 
