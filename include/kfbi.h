@@ -205,6 +205,21 @@ int kfbi_solve_neumann(kfbi_problem p, const double *g, const double *f, double 
                        double *psi_inout, const kfbi_solve_opts *opts, kfbi_solve_info *info,
                        void *stream);
 
+/* kfbi_box_solve_noalloc: the box solve of kfbi_box_solve without a problem handle and without
+ * allocating, for callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid it).  grid and coeffs as for kfbi_setup (every D[c][a] of
+ * the used components and axes finite and > 0, kappa finite and >= 0); f, u: device
+ * [ncomp][N^d] in `dtype` (caller layout, may alias).  Its padded work field and its tables
+ * (twiddles, DST sines, mode eigenvalues, computed on the device each call) live in a static
+ * device array of 36 MiB per GPU, held until the process ends: grids whose padded field
+ * ncomp (cells-1)^(d-1) cells entries plus tables exceed it give KFBI_EINVAL (FP64: a coupled
+ * 128^3 or 1024^2 field fits, 256^3 does not).  No hipMalloc/hipFree, no host-to-device copy, no
+ * memset; errors set a literal message for kfbi_last_error.  Every call on a GPU shares that
+ * GPU's array and leaves its last contents there: calls that overlap on one GPU (two streams or
+ * threads at once) race. */
+int kfbi_box_solve_noalloc(const kfbi_grid *grid, const kfbi_coeffs *coeffs, const void *f, void *u,
+                           int32_t dtype, void *stream);
+
 /* ----------------------------------------------------------------- bidomain */
 
 typedef struct {

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HIP_SOURCES = ["dst.hip", "kfbi_kernels.hip", "solver.hip", "api.hip", "mlp.hip", "batch.hip"]
+HIP_SOURCES = ["dst.hip", "kfbi_kernels.hip", "solver.hip", "api.hip", "mlp.hip", "batch.hip", "noalloc.hip"]
 HOST_SOURCES = ["host_tables.cpp", "host_spline.cpp", "host_mesh.cpp"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]

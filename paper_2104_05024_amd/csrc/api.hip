@@ -15,6 +15,9 @@
 
 namespace kfbi {
 thread_local std::string g_last_error;
+// message of the last error of kfbi_box_solve_noalloc: a string literal (that entry point never
+// touches the host heap); null once any other call has failed
+thread_local const char *g_last_static = nullptr;
 }
 
 using namespace kfbi;
@@ -35,6 +38,7 @@ namespace {
 
 int fail(int code, const std::string &msg) {
   g_last_error = msg;
+  g_last_static = nullptr;
   return code;
 }
 
@@ -72,7 +76,7 @@ const char *kfbi_strerror(int code) {
   }
 }
 
-const char *kfbi_last_error(void) { return g_last_error.c_str(); }
+const char *kfbi_last_error(void) { return g_last_static ? g_last_static : g_last_error.c_str(); }
 
 int kfbi_setup(const kfbi_interface *iface, const kfbi_grid *grid, const kfbi_coeffs *coeffs, uint32_t flags,
                kfbi_problem *out) {

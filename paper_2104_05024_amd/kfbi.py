@@ -25,7 +25,7 @@ EXPORTED = [
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
     "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
     "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles", "kfbi_use_graph", "bidomain_use_graph",
-    "kfbi_profile", "bidomain_reset",
+    "kfbi_profile", "bidomain_reset", "kfbi_box_solve_noalloc",
 ]
 
 
@@ -119,6 +119,7 @@ def lib():
     L.kfbi_use_graph.argtypes = [vp, i32]
     L.bidomain_use_graph.argtypes = [vp, i32]
     L.bidomain_reset.argtypes = [vp]
+    L.kfbi_box_solve_noalloc.argtypes = [C.POINTER(GridDesc), C.POINTER(CoeffsDesc), vp, vp, i32, vp]
     L.kfbi_set_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.kfbi_batch_setup.argtypes = [i32, C.POINTER(Interface), C.POINTER(GridDesc), C.POINTER(CoeffsDesc),
                                    C.POINTER(vp)]
@@ -194,6 +195,19 @@ def coeffs_desc(co) -> CoeffsDesc:
             d.D[c][a] = co.D[c][0]
     d.kappa = co.kappa
     return d
+
+
+def box_solve_noalloc(grid, coeffs, f, out=None):
+    """kfbi_box_solve_noalloc: u = S f for a grid and coefficients without a problem handle and
+    without any allocation in the library (its work field lives in a static device array)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(f)
+    dt = {torch.float64: KFBI_F64, torch.float32: KFBI_F32}[f.dtype]
+    assert f.is_contiguous() and out.is_contiguous() and f.numel() == coeffs.ncomp * grid.n ** grid.dim
+    g, c = grid_desc(grid), coeffs_desc(coeffs)
+    _check(lib().kfbi_box_solve_noalloc(C.byref(g), C.byref(c), _ptr(f), _ptr(out), dt, _stream()))
+    return out
 
 
 def solve_opts(tol=1e-10, restart=50, max_iters=500, precision=0, x0=0, inner_tol=1e-4, max_outer=20,
