@@ -6,19 +6,26 @@ component, coupled intra/extracellular pair); a closed thick shell (outer ellips
 0.9/0.7/0.6, inner wall 0.6 x ellipsoid with seeded smooth radial noise) carrying 40,960
 interface nodes; sigma_i = 1, sigma_e = 2, Cm = beta = 1, dt = 0.01 (kappa = 200);
 FHN theta = 0.13, H = 100, alpha = 0.25, zeta = 1; V = 1 in a ball of radius 0.25 at a
-seeded mid-wall point; GMRES(50) relative tolerance 1e-8 on ||g'||.
+seeded mid-wall point, the same ball set to V = 1 again at step 300 (a second beat: the tissue
+is excitable again about 300 steps after a beat); GMRES(50) relative tolerance 1e-8 on ||g'||.
 
-A step is one whole Strang step (reaction, coupled KFBI Neumann solve, reaction) with all
-inputs resident in HBM.  Every variant runs the same untimed steps first (default 40; the
-learned variant records them and trains on them) and is then timed over the same window
-(default steps 40-140).  The stimulus excites the whole shell by about step 60 and the
-tissue is back at rest by about step 150, so this window holds the propagating wave; a
-later window would time a resting tissue.  Variants: plain (FP64 throughout, GMRES from psi^{n-1}), mixed (FP32
-matrix-vector products inside FP64 iterative refinement), learned (mixed + the learned warm
-start), projected (mixed + the least-residual combination of the last 8 solutions as start).  Every solve ends at the same FP64 relative residual bound.
+Schedule (the same for every variant, from the same initial state): the first 200 steps
+(the learned variant records them and trains its network on them afterwards), then --warmup
+untimed steps, then --steps timed steps (by default 295, so the run is the 500 steps of the
+workload), then steps after the window for per-kernel HIP-event timing and for the FP64
+residual check by explicit products.  A step is one whole Strang step (reaction, coupled KFBI
+Neumann solve, reaction) with all inputs resident in HBM.
 
-Prints one JSON line (see the "metric" key).  --batch and --copy-calibration run the
-batched 2D workload and the counter calibration instead.
+Variants: plain (FP64, GMRES from psi^{n-1}); mixed (one GMRES whose products turn FP32 once
+the residual allows, with an FP64 product certifying the result); learned (the value: start
+from the least-residual combination of the last 8 solutions, the trained network's prediction
+as the first search direction, mixed precision as in mixed); projected and projected_mixed (the
+learned variant without the network, in FP64 and mixed precision); mixed_ir (FP32 inner GMRES
+with FP64 iterative refinement); richardson (the simple iteration, gamma = 0.8, FP64).  Every
+solve ends at the same FP64 relative residual bound.
+
+Prints one JSON line (see the "metric" key).  --batch and --copy-calibration run the batched
+2D workload and the counter calibration alone.
 """
 from __future__ import annotations
 
@@ -34,6 +41,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bidomain steps/s at 256^3 (GMRES tol 1e-8), learned+mixed vs plain; HBM % peak"
 HBM_PEAK_GBS = 8000.0
+PREFIX = 200          # the first steps of the workload: the learned variant trains on them
+PACE_AT = 300         # second stimulus of the seeded ball
 
 
 def log(msg):
@@ -43,17 +52,22 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=500 - PREFIX - 5)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cells", type=int, default=256)
     ap.add_argument("--nodes", type=int, default=40960)
-    ap.add_argument("--variants", default="plain,mixed,learned,projected,projected_mixed")
-    ap.add_argument("--train-steps", type=int, default=40)
+    ap.add_argument("--variants", default="plain,mixed,learned,projected,projected_mixed,mixed_ir,richardson")
     ap.add_argument("--epochs", type=int, default=150)
-    ap.add_argument("--inner-tol", type=float, default=1e-4, help="mixed precision: relative tolerance of each FP32 inner solve")
+    ap.add_argument("--switch", type=float, default=2e-3,
+                    help="mixed precision: relative residual below which the products run in FP32")
+    ap.add_argument("--inner-tol", type=float, default=1e-4, help="mixed_ir: relative tolerance of each FP32 inner solve")
     ap.add_argument("--kernel-steps", type=int, default=10, help="steps after the timed window timed per kernel")
+    ap.add_argument("--check-steps", type=int, default=10,
+                    help="steps after those whose FP64 residual is checked by an explicit product")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (first listed variant only, no CPU baseline)")
+    ap.add_argument("--no-batch", action="store_true", help="leave the batched 2D workload out of the line")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for rocprofv3 (first listed variant only, no CPU baseline, no batch)")
     ap.add_argument("--batch", action="store_true",
                     help="only the batched 2D workload: 64 seeded Neumann problems of sizes 64..1024, "
                          "solved as one batch and one by one (problems/s)")
@@ -63,27 +77,38 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(grid, co, box_solves_per_step):
-    """Oracle (FP64 NumPy/SciPy, single-threaded FFT) on a bounded sample: one coupled box solve
-    of the same 256^3 workload, scaled by the box solves per step of the GPU run."""
+def cpu_baseline(iface, grid, co, p, dt, V0, q0):
+    """The oracle as it stands (FP64 NumPy/SciPy, FFTs on every host core) on a bounded sample of the
+    same workload: one bidomain step from the initial state (GMRES from zero, tolerance 1e-8) and
+    one matrix-vector product, timed after the oracle's setup (setup excluded, stated)."""
     import numpy as np
 
-    from oracle import boxsolve
-    f = np.random.default_rng(0).normal(size=(co.ncomp, grid.n ** grid.dim))
+    from oracle import bidomain as obd
+    from oracle import boxsolve as obs
+    from oracle import kfbi as ok
     t0 = time.perf_counter()
-    boxsolve.box_solve(f, grid, co)
-    dt_box = time.perf_counter() - t0
-    s_per_step = dt_box * box_solves_per_step
-    return {"value": 1.0 / s_per_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one coupled {grid.cells}^3 box solve by the oracle ({dt_box:.2f} s), scaled by "
-                      f"{box_solves_per_step:.1f} box solves per step (matvecs + volume + final solve); "
-                      f"interface work (<2% of a matvec) not included",
+    o = ok.Problem(iface, grid, co)
+    setup_s = time.perf_counter() - t0
+    log(f"cpu baseline: oracle setup {setup_s:.1f} s; timing one oracle step ...")
+    t0 = time.perf_counter()
+    _, _, _, _, info = obd.step(o, p, V0, q0, dt, tol=1e-8)
+    step_s = time.perf_counter() - t0
+    psi = np.random.default_rng(0).uniform(-1, 1, size=(2, o.M))
+    t0 = time.perf_counter()
+    o.apply(psi)
+    apply_s = time.perf_counter() - t0
+    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": obs.WORKERS, "kind": "oracle step, timed",
+            "sample": f"one oracle bidomain step of this workload from its initial state ({step_s:.1f} s, "
+                      f"{info['iters']} GMRES iterations from zero at tolerance 1e-8) and one coupled "
+                      f"matrix-vector product ({apply_s:.2f} s); oracle setup ({setup_s:.0f} s) excluded; "
+                      f"scipy.fft with {obs.WORKERS} workers",
+            "apply_s": round(apply_s, 3), "step_s": round(step_s, 2), "setup_s": round(setup_s, 1),
             "host_cpu": platform.processor() or platform.machine(),
             "host_cores_available": len(os.sched_getaffinity(0))}
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of a dense DST pass from the committed rocprofv3 counter summary
+    """HBM bytes per launch of a DST pass from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size); None if the kernel
     source has changed since the counters were taken."""
     import hashlib
@@ -102,9 +127,9 @@ def measured_traffic(kernel):
     return None, "no counter summary"
 
 
-def batch_bench(a, torch):
+def batch_run(torch, warmup=1, reps=5, singles=True):
     """64 seeded 2D Neumann problems (manufactured u = e^x sin(pi y)), FP32 inner GMRES with
-    FP64 refinement to 1e-10 per problem: one batch vs the problems one at a time."""
+    FP64 refinement to 1e-10 per problem: one batch, and (singles) the problems one at a time."""
     import numpy as np
 
     from paper_2104_05024_amd import kfbi as K
@@ -113,52 +138,51 @@ def batch_bench(a, torch):
     t0 = time.perf_counter()
     b = K.Batch(probs)
     setup_s = time.perf_counter() - t0
-    singles = [K.Problem(*p) for p in probs]
     dev = torch.device("cuda:0")
     fs, gs = [], []
-    for (iface, grid, co), p in zip(probs, singles):
+    for (iface, grid, co) in probs:
         pts = W.grid_points(grid)
         fs.append((np.pi ** 2 - 1 + co.kappa) * np.exp(pts[:, 0]) * np.sin(np.pi * pts[:, 1]))
-        X, n = p.table("nodes_X").reshape(-1, 2), p.table("nodes_n").reshape(-1, 2)
+    for pr in probs:
+        h = K.Problem(*pr, host_only=True)     # node positions and normals (host tables only)
+        X, n = h.table("nodes_X").reshape(-1, 2), h.table("nodes_n").reshape(-1, 2)
+        h.close()
         gs.append(n[:, 0] * np.exp(X[:, 0]) * np.sin(np.pi * X[:, 1])
                   + n[:, 1] * np.pi * np.exp(X[:, 0]) * np.cos(np.pi * X[:, 1]))
     f = torch.tensor(np.concatenate(fs), device=dev)
     g = torch.tensor(np.concatenate(gs), device=dev)
     opts = dict(tol=1e-10, precision=1, inner_tol=1e-4)
-    for _ in range(max(a.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         b.solve_neumann(g, f, **opts)
     torch.cuda.synchronize()
-    reps = max(1, min(a.steps, 10))
     t0 = time.perf_counter()
     for _ in range(reps):
         u, psi, infos = b.solve_neumann(g, f, **opts)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
-    worst = max(i["rel_resid"] for i in infos)
-    # the same problems one at a time through the single-problem entry point
-    segs = [(f[b.goff[i]:b.goff[i] + b.N[i] ** 2].reshape(1, -1).contiguous(),
-             g[b.ioff[i]:b.ioff[i] + b.M[i]].reshape(1, -1).contiguous()) for i in range(b.n)]
-    for p, (fi, gi) in zip(singles, segs):
-        p.solve_neumann(gi, fi, **opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for p, (fi, gi) in zip(singles, segs):
+    out = {"problems_per_s": round(b.n / t_batch, 1), "n_problems": b.n, "ms_per_batch": round(1000 * t_batch, 2),
+           "max_final_rel_resid": max(i["rel_resid"] for i in infos),
+           "mean_inner_iters": float(np.mean([i["iters"] for i in infos])), "setup_s": round(setup_s, 2),
+           "cells": sorted(set(gr.cells for _, gr, _ in probs))}
+    if singles:
+        ps = [K.Problem(*pr) for pr in probs]
+        segs = [(f[b.goff[i]:b.goff[i] + b.N[i] ** 2].reshape(1, -1).contiguous(),
+                 g[b.ioff[i]:b.ioff[i] + b.M[i]].reshape(1, -1).contiguous()) for i in range(b.n)]
+        for p, (fi, gi) in zip(ps, segs):
             p.solve_neumann(gi, fi, **opts)
-    torch.cuda.synchronize()
-    t_single = (time.perf_counter() - t0) / reps
-    for p in singles:
-        p.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for p, (fi, gi) in zip(ps, segs):
+                p.solve_neumann(gi, fi, **opts)
+        torch.cuda.synchronize()
+        t_single = (time.perf_counter() - t0) / reps
+        out["one_at_a_time_problems_per_s"] = round(b.n / t_single, 1)
+        out["speedup_vs_one_at_a_time"] = round(t_single / t_batch, 2)
+        for p in ps:
+            p.close()
     b.close()
-    print(json.dumps({
-        "metric": "batched 2D Neumann solves, problems/s (FP32 inner + FP64 refinement to 1e-10)",
-        "value": round(b.n / t_batch, 2), "unit": "problems/s", "n_problems": b.n,
-        "one_at_a_time_problems_per_s": round(b.n / t_single, 2), "speedup_vs_one_at_a_time": round(t_single / t_batch, 2),
-        "ms_per_batch": round(1000 * t_batch, 2), "reps": reps, "max_final_rel_resid": worst,
-        "mean_inner_iters": float(np.mean([i["iters"] for i in infos])),
-        "setup_s": round(setup_s, 2), "data": "synthetic (seeded stars, manufactured solution)",
-        "config": {"workload": "64 star-shaped 2D Neumann problems, cells in {64,...,1024}, 3-8 lobes, "
-                               "amplitude 0.05-0.2, kappa 50-2000, M = 2 cells"}}))
+    return out
 
 
 def copy_calibration(a, torch):
@@ -182,6 +206,24 @@ def copy_calibration(a, torch):
     print(json.dumps(out))
 
 
+# variant -> Bidomain keyword arguments
+def variant_kwargs(name, a):
+    mixed = dict(precision=2, inner_tol=a.switch)
+    return {
+        "plain": dict(precision=0, warm_start=0),
+        "mixed": dict(warm_start=0, **mixed),
+        "learned": dict(warm_start=4, **mixed),
+        "projected": dict(precision=0, warm_start=3),
+        "projected_mixed": dict(warm_start=3, **mixed),
+        "mixed_ir": dict(precision=1, warm_start=0, inner_tol=a.inner_tol),
+        "richardson": dict(precision=0, warm_start=0, method=1, gamma=0.8, max_iters=400),
+    }[name]
+
+
+KERNELS = ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse", "dst_last_sparse", "dst_last_out",
+           "dst_x_fhn", "jumps", "correct", "gather")
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -194,7 +236,12 @@ def main():
         copy_calibration(a, torch)
         return
     if a.batch:
-        batch_bench(a, torch)
+        out = batch_run(torch, warmup=max(a.warmup, 1), reps=max(1, min(a.steps, 10)))
+        print(json.dumps({"metric": "batched 2D Neumann solves, problems/s (FP32 inner + FP64 refinement to 1e-10)",
+                          "value": out["problems_per_s"], "unit": "problems/s", **out,
+                          "data": "synthetic (seeded stars, manufactured solution)",
+                          "config": {"workload": "64 star-shaped 2D Neumann problems, cells in {64,...,1024}, "
+                                                 "3-8 lobes, amplitude 0.05-0.2, kappa 50-2000, M = 2 cells"}}))
         return
     from paper_2104_05024_amd import kfbi as K
     from paper_2104_05024_amd import workloads as W
@@ -210,90 +257,109 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"setup {setup_s:.1f} s: M={prob.M} crossings={prob.n_crossings} irregular={prob.n_irregular}")
     V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.25)
+    ball = torch.tensor(V0 > 0.5, device=dev)
+    tissue = torch.tensor(prob.table("inside").astype(bool), device=dev)
+    n_tissue = float(tissue.sum())
 
     variants = [v for v in a.variants.split(",") if v]
     if a.profile_run:
         variants = variants[:1]
-    results = {}
-    kt = {}
+    t_win0 = PREFIX + a.warmup
+    results, kt = {}, {}
     for name in variants:
+        bd = K.Bidomain(prob, p, tol=1e-8, **variant_kwargs(name, a))
         if name == "learned":
-            try:
-                bd = K.Bidomain(prob, p, tol=1e-8, precision=1, warm_start=1, inner_tol=a.inner_tol)
-                bd.mlp_init(capacity=max(a.train_steps, 1), seed=3)
-            except K.KfbiError as e:
-                log(f"learned variant unavailable: {e}")
-                continue
-        elif name in ("projected", "projected_mixed"):
-            bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "projected_mixed" else 0, warm_start=3,
-                            inner_tol=a.inner_tol)
-        else:
-            bd = K.Bidomain(prob, p, tol=1e-8, precision=1 if name == "mixed" else 0, warm_start=0,
-                            inner_tol=a.inner_tol)
+            bd.mlp_init(capacity=PREFIX, seed=3)
         V = torch.tensor(V0, device=dev)
         q = torch.tensor(q0, device=dev)
         hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=dev)
-        # every variant times the same window of the simulation: steps n_warm .. n_warm + steps
-        n_warm = max(a.warmup, a.train_steps) if "learned" in variants else a.warmup
-        for i in range(n_warm):
-            bd.step(V, q, hist, dt)
+        step_no = 0
+
+        def step(v=name):
+            nonlocal step_no
+            if step_no == PACE_AT:
+                V[ball] = 1.0
+            step_no += 1
+            return bd.step(V, q, hist, dt)
+
+        for _ in range(PREFIX):
+            step()
         if name == "learned":
             loss = bd.train(epochs=a.epochs, lr=1e-3)
-            log(f"learned: trained on {a.train_steps} steps, loss {loss:.3e}")
+            log(f"learned: network trained on steps 1-{PREFIX}, loss {loss:.3e}")
+        for _ in range(a.warmup):
+            step()
+        exc0 = float(((V > 0.5) & tissue).sum()) / n_tissue
         infos = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(a.steps):
-            infos.append(bd.step(V, q, hist, dt))
+        for _ in range(a.steps):
+            infos.append(step())
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        exc1 = float(((V > 0.5) & tissue).sum()) / n_tissue
         # per-kernel HIP-event timing over the next steps (event timing launches every kernel
         # directly, so it stays out of the timed window, where GMRES replays captured steps)
         prob.profile(True)
-        for i in range(a.kernel_steps):
-            bd.step(V, q, hist, dt)
+        for _ in range(a.kernel_steps):
+            step()
         torch.cuda.synchronize()
-        kt[name] = {k: prob.kernel_time(k) for k in ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse",
-                                                     "dst_last_sparse", "dst_last_out", "dst_x_fhn",
-                                                     "jumps", "correct", "gather")}
+        kt[name] = {k: prob.kernel_time(k) for k in KERNELS}
         prob.profile(False)
-        worst = max(i["rel_resid"] for i in infos)
+        # the FP64 residual of the following solves by explicit products
+        bd.true_resid(True)
+        checks = [step() for _ in range(a.check_steps)]
+        bd.true_resid(False)
         results[name] = {
             "steps_per_s": a.steps / el, "ms_per_step": 1000 * el / a.steps,
             "mean_iters": float(np.mean([i["iters"] for i in infos])),
             "mean_matvecs_fp64": float(np.mean([i["matvecs_fp64"] for i in infos])),
             "mean_matvecs_fp32": float(np.mean([i["matvecs_fp32"] for i in infos])),
-            "max_final_rel_resid": worst,
+            "max_final_rel_resid": max(i["rel_resid"] for i in infos),
+            "max_true_rel_resid": max(i["true_resid"] for i in checks) if checks else None,
             "mean_start_resid": float(np.mean([i["start_resid"] for i in infos])),
-            "warm_start_used": int(sum(i["warm_start_used"] for i in infos)),
+            "start_used": int(sum(i["warm_start_used"] & 1 for i in infos)),
+            "learned_direction_used": int(sum((i["warm_start_used"] >> 1) & 1 for i in infos)),
+            "fp64_checks": int(sum(i["outer"] for i in infos)) if name in ("mixed", "learned", "projected_mixed") else 0,
+            "excited_fraction_window_start_end": [round(exc0, 3), round(exc1, 3)],
             "V_max": float(V.max().item()),
         }
         log(f"{name}: {results[name]}")
         bd.close()
 
-    head = "learned" if "learned" in results else ("mixed" if "mixed" in results else "plain")
+    head = "learned" if "learned" in results else ("mixed" if "mixed" in results else variants[0])
     r = results[head]
-    # roofline of the dominant FP64 pencil kernel (plain variant: every launch is FP64).  The
-    # dense passes (dst_x, dst_y, dst_last) each read and write the whole coupled field.  The
-    # z pass of the matrix-vector product (dst_last_sparse) reads only the z planes that hold
-    # irregular nodes (the others are zero) and writes only those that hold extrapolation
-    # stencil nodes; the z pass of the BIE right-hand side's volume solve (dst_last_out) reads
-    # every plane and writes only the stencil planes.  The row-masked x and y passes
-    # (dst_x_rows, dst_y_sparse) are not priced.  The three x passes of a step that carry the
-    # reaction (dst_x_fhn) are priced per launch as the mean of: forward Euler + source (V, q
-    # read, the transformed pair written), source + correction (V, q and the correction rows
-    # read, the pair written) and inverse + backward Euler (the pair, V and q read, V, q written).
+    for name in results:
+        m64, m32 = results[name]["mean_matvecs_fp64"], results[name]["mean_matvecs_fp32"]
+        results[name]["products_per_step"] = round(m64 + m32, 3)
+
+    # roofline of the dominant FP64 pencil kernel (plain variant: every launch is FP64).  Dense
+    # passes (dst_x, dst_y, dst_last) read and write the whole coupled field.  The matvec's z pass
+    # (dst_last_sparse) reads only the z planes holding irregular nodes and writes only those holding
+    # extrapolation-stencil nodes; the volume solve's z pass (dst_last_out) reads every plane and
+    # writes the stencil planes.  The row-list x pass (dst_x_rows) reads and writes the rows holding
+    # irregular nodes (forward) or stencil nodes (inverse); the masked y pass (dst_y_sparse) reads the
+    # irregular rows and writes whole planes that hold any (forward), or reads whole stencil planes
+    # and writes the stencil rows (inverse); each is priced per launch as the mean of its two forms.
+    # The x passes of a step's box solves that carry the reaction (dst_x_fhn) are priced as the mean
+    # of: forward Euler + source (V, q read, the pair written), source + correction (V, q and the
+    # correction rows read, the pair written) and inverse + backward Euler (the pair, V and q read,
+    # V, q written).
     ref = "plain" if "plain" in kt else head
     N = grid.n
-    field_bytes = co.ncomp * N ** 3 * 8
-    planes_in = len(np.unique(prob.table("irregular") // (N * N)))
-    planes_out = len(np.unique(prob.table("st_lin") // (N * N)))
-    rows_in = len(np.unique(prob.table("irregular") // N))
+    nc = co.ncomp
+    field_bytes = nc * N ** 3 * 8
+    irr = prob.table("irregular")
+    stl = prob.table("st_lin")
+    planes_in, planes_out = len(np.unique(irr // (N * N))), len(np.unique(stl // (N * N)))
+    rows_in, rows_out = nc * len(np.unique(irr // N)), nc * len(np.unique(stl // N))
     algo_of = {"dst_x": 2.0 * field_bytes, "dst_y": 2.0 * field_bytes, "dst_last": 2.0 * field_bytes,
-               "dst_last_sparse": float(co.ncomp * N * N * 8 * (planes_in + planes_out)),
-               "dst_last_out": float(field_bytes + co.ncomp * N * N * 8 * planes_out),
-               "dst_x_fhn": (2.0 * field_bytes + (2.0 * field_bytes + co.ncomp * rows_in * N * 8)
-                             + 3.0 * field_bytes) / 3.0}
+               "dst_last_sparse": float(nc * N * N * 8 * (planes_in + planes_out)),
+               "dst_last_out": float(field_bytes + nc * N * N * 8 * planes_out),
+               "dst_x_rows": float((rows_in + rows_out) * N * 8),
+               "dst_y_sparse": float(((rows_in * N + planes_in * nc * N * N) + (planes_out * nc * N * N + rows_out * N))
+                                     * 8 / 2),
+               "dst_x_fhn": (2.0 * field_bytes + (2.0 * field_bytes + rows_in * N * 8) + 3.0 * field_bytes) / 3.0}
     tot = {k: us * n for k, (us, n) in kt[ref].items()}
     priced = [k for k in algo_of if kt[ref][k][1] > 0]
     dom = max(priced, key=tot.get)
@@ -304,40 +370,43 @@ def main():
     roof = {"bound": "hbm", "kernel": f"k_{dom} (FP64, {ref} variant)", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_source": traffic_src, "algorithmic_bytes_per_launch": algo, "avg_launch_us": round(avg_us, 2),
+            "launches": launches,
             "z_planes_read_written_by_dst_last_sparse": [planes_in, planes_out],
+            "rows_in_out": [rows_in, rows_out],
             "hbm_frac_by_class": {k: round(algo_of[k] / (kt[ref][k][0] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                   for k in priced},
-            "note": ("dst_last_sparse transforms every z pencil like the dense pass but moves only the "
-                     "planes that hold irregular or stencil nodes, so its time is set by the transform "
-                     "work in LDS and registers rather than by HBM") if dom == "dst_last_sparse" else None,
             "algorithmic_bytes_per_launch_by_class": algo_of,
-            "launches": launches,
             "kernel_timing": f"HIP events on the solve stream over the {a.kernel_steps} steps after the timed window",
             "kernel_avg_us": {k: round(v[0], 2) for k, v in kt[ref].items()},
             "kernel_share_of_timed_kernels": {k: round(v / sum(tot.values()), 3) for k, v in tot.items()}}
+    if "mixed" in kt:
+        roof["kernel_avg_us_mixed_variant"] = {k: round(v[0], 2) for k, v in kt["mixed"].items()}
     out = {
         "metric": METRIC, "value": round(r["steps_per_s"], 3), "unit": "steps/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": n_warm, "ms_per_step": round(r["ms_per_step"], 3),
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(r["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if head == "plain" else "f32+f64",
-        "data": "synthetic (seeded thick-shell geometry and stimulus ball)",
+        "dtype": "f64" if head in ("plain", "projected", "richardson") else "f32+f64",
+        "data": "synthetic (seeded thick-shell geometry, stimulus ball at steps 0 and 300)",
         "config": {"workload": f"FHN bidomain on a thick shell, {a.cells}^3 grid, {prob.M} interface nodes, "
-                               f"dt=0.01, GMRES(50) tol 1e-8, timed steps {n_warm}-{n_warm + a.steps}",
+                               f"dt=0.01, GMRES(50) tol 1e-8, {PREFIX} untimed steps (the learned variant's "
+                               f"training data) + {a.warmup} warm-up, timed steps {t_win0 + 1}-{t_win0 + a.steps}",
                    "variant": head, "cells": a.cells,
                    "interface_nodes": prob.M, "crossings": prob.n_crossings, "parallelism": "single GPU"},
+        "prefix_steps": PREFIX,
         "variants": {k: {kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},
-        "untimed_steps_before_window": n_warm,
-        "speedup_vs_plain": round(r["steps_per_s"] / results["plain"]["steps_per_s"], 3) if "plain" in results else None,
+        "speedup_vs_plain": {k: round(v["steps_per_s"] / results["plain"]["steps_per_s"], 3) for k, v in results.items()}
+        if "plain" in results else None,
         "roofline": roof,
         "setup_s": round(setup_s, 2),
         "autotuned_tile_widths": {"f64": list(prob.tiles(K.KFBI_F64)), "f32": list(prob.tiles(K.KFBI_F32))},
     }
-    if not a.no_cpu_baseline and not a.profile_run:
-        per_step = results[ref]["mean_matvecs_fp64"] + results[ref]["mean_matvecs_fp32"] + 2
-        log("cpu baseline: timing the oracle's coupled box solve ...")
-        out["cpu_baseline"] = cpu_baseline(grid, co, per_step)
     prob.close()
+    if not a.no_batch and not a.profile_run:
+        log("batched 2D workload ...")
+        out["batch"] = batch_run(torch, singles=False)
+    if not a.no_cpu_baseline and not a.profile_run:
+        out["cpu_baseline"] = cpu_baseline(iface, grid, co, p, dt, V0, q0)
     print(json.dumps(out))
 
 

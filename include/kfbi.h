@@ -169,9 +169,14 @@ typedef struct {
   double tol;           /* stop when ||g' - A psi||_2 <= tol ||g'||_2 (FP64 residual) */
   int32_t restart;      /* GMRES(m) restart length, 1..64 */
   int32_t max_iters;    /* total inner iterations */
-  int32_t precision;    /* 0: FP64 throughout; 1: FP32 inner GMRES + FP64 refinement */
+  int32_t precision;    /* 0: FP64 throughout; 1: FP32 inner GMRES + FP64 refinement;
+                           2: one FP64-Arnoldi GMRES whose products run in FP32 (as kfbi_apply's
+                           KFBI_F32) once its residual is below inner_tol ||g'|| and in FP64 before,
+                           then an FP64 product of the result checks the residual (the solve goes
+                           on from that residual if it misses the tolerance) */
   int32_t x0;           /* 0: start from psi = 0 (Algorithm 1); 1: from psi_inout */
-  double inner_tol;     /* precision = 1: relative tolerance of each FP32 inner solve */
+  double inner_tol;     /* precision = 1: relative tolerance of each FP32 inner solve;
+                           precision = 2: relative residual below which the products are FP32 */
   int32_t max_outer;    /* precision = 1: maximum FP64 refinement steps */
   int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4) */
   double gamma;         /* Richardson parameter, gamma in (0,1) */
@@ -182,12 +187,13 @@ typedef struct {
 
 typedef struct {
   int32_t iters;            /* inner iterations (FP64 or FP32) */
-  int32_t outer;            /* FP64 refinement steps (precision = 1) */
+  int32_t outer;            /* FP64 refinement steps (precision = 1); FP64 residual checks (2) */
   int32_t matvecs_fp64;
   int32_t matvecs_fp32;
   double rel_resid;         /* final ||g' - A64 psi|| / ||g'|| */
   double gp_norm;           /* ||g'||_2 */
-  int32_t warm_start_used;  /* bidomain_step: 1 if the learned start was taken */
+  int32_t warm_start_used;  /* bidomain_step: bit 0: the learned (1) or projection (3, 4) start was
+                               taken; bit 1: the learned search direction (4) was used */
   int32_t pad_;
   double start_resid;       /* ||g' - A64 psi0|| / ||g'|| of the start density (1 for a zero start) */
   double true_resid;        /* opts.true_resid = 1: ||g' - A64 psi|| / ||g'|| by an explicit product,
@@ -230,7 +236,11 @@ typedef struct {
   int32_t newton_maxit;
   int32_t warm_start;               /* 0: psi^{n-1}; 1: learned (MLP) start with fallback; 2: zero;
                                        3: least-residual combination of the last 8 solutions
-                                       (their images are known without a product) */
+                                       (their images are known without a product);
+                                       4: that combination, and the learned prediction's difference
+                                       from it as the first search direction of the GMRES (no
+                                       product of its own), with the cost check of the learned
+                                       start switching it off */
   kfbi_solve_opts solve;            /* diffusion solve options (tol, precision, ...) */
 } bidomain_params;
 
@@ -268,6 +278,10 @@ int bidomain_step(bidomain_ctx b, bidomain_state *state, double dt, kfbi_solve_i
  * solutions recorded for the projection start (warm_start = 3) and the step count that the
  * learned start waits on (its network is kept). */
 int bidomain_reset(bidomain_ctx b);
+/* bidomain_true_resid: from the next step on (enable != 0), every solve also forms g' - A64 psi
+ * with an explicit FP64 product and reports its relative norm in info.true_resid (a check of the
+ * residual the solve reports, at the cost of one product; the same as solve.true_resid = 1). */
+int bidomain_true_resid(bidomain_ctx b, int32_t enable);
 
 /* Learned warm start (not in the paper, which starts GMRES from zero).  The change of the
  * density between steps solves A (psi^n - psi^{n-1}) = g'^n - g'^{n-1}; the start is

@@ -222,6 +222,12 @@ int bidomain_use_graph(bidomain_ctx b, int32_t enable) {
   return KFBI_OK;
 }
 
+int bidomain_true_resid(bidomain_ctx b, int32_t enable) {
+  if (!b || !b->solver) return fail(KFBI_EINVAL, "argument");
+  b->params.solve.true_resid = enable != 0;
+  return KFBI_OK;
+}
+
 int bidomain_reset(bidomain_ctx b) {
   if (!b || !b->solver) return fail(KFBI_EINVAL, "argument");
   b->reset();
@@ -293,6 +299,7 @@ int kfbi_batch_solve_neumann(kfbi_batch b, const double *g, const double *f, dou
   return guard([&]() -> int {
     if (!b || !f || !u || !psi || !opts) return fail(KFBI_EINVAL, "argument");
     if (opts->method != 0) return fail(KFBI_EINVAL, "batched solves use GMRES");
+    if (opts->precision != 0 && opts->precision != 1) return fail(KFBI_EINVAL, "batched solves use precision 0 or 1");
     if (opts->restart < 1 || opts->restart > Batch::kMaxRestart || opts->max_iters < 1 || !(opts->tol > 0))
       return fail(KFBI_EINVAL, "solve options");
     const int rc = b->b.solve(g, f, u, psi, *opts, info, (hipStream_t)stream);
@@ -351,6 +358,8 @@ int bidomain_create(kfbi_problem p, const bidomain_params *params, bidomain_ctx 
     if (!p || !params || !out) return fail(KFBI_EINVAL, "null argument");
     if (!p->p.on_device) return fail(KFBI_ENODEV, "problem set up host-only");
     if (p->p.ncomp != 2) return fail(KFBI_EINVAL, "bidomain needs the coupled two-component problem");
+    if (params->warm_start < 0 || params->warm_start > 4) return fail(KFBI_EINVAL, "warm_start is 0..4");
+    if (params->solve.precision < 0 || params->solve.precision > 2) return fail(KFBI_EINVAL, "precision is 0, 1 or 2");
     *out = nullptr;
     std::unique_ptr<bidomain_s> b(new bidomain_s());
     b->prob = &p->p;

@@ -24,6 +24,7 @@ struct Solver {
   // captured Arnoldi step (per precision of the product), replayed every GMRES iteration
   bool use_graph = true;
   double *vin = nullptr, *wv = nullptr;
+  double *zbuf = nullptr;      // normalised first search direction of a flexible GMRES cycle
   int *jdev = nullptr, *jhost = nullptr;
   // step counter: each replayed step ends by storing its number in pinned host memory, which
   // the host polls instead of sleeping in a stream synchronisation between steps
@@ -53,10 +54,25 @@ struct Solver {
 
   double dot(const double *a, const double *b, hipStream_t st);
   double residual_norm(const double *b, const double *Ax, hipStream_t st);   // ||b - Ax||_2 (uses d)
-  // r0 (optional): b - A x already known (no product for the first residual)
-  int gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
-            int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
-            double *beta0 = nullptr, const double *r0 = nullptr);
+  // GMRES(m) with FP64 Arnoldi (CGS2) and Givens rotations on A x = b (stops at ||b - A x|| <= tol_abs).
+  // Products in precision a.prec, or with a.relax FP32 once the current residual is <= a.sw_abs and
+  // FP64 before: the computed residual of such a solve is then checked by an FP64 product of the
+  // result (counted in certs), and the iteration continues from that residual if it misses.
+  // a.r0: b - A x already known (no first product).  a.z0: first search direction of the first
+  // cycle (flexible GMRES: x += y_0 z0/|z0| + sum_{j>=1} y_j V_j).  On return r = b - A x (exact
+  // to rounding: from the Arnoldi relation when every product was FP64, else the FP64 product).
+  struct GmresArgs {
+    int prec = 0;
+    bool relax = false;
+    double sw_abs = 0;
+    const double *r0 = nullptr, *z0 = nullptr;
+  };
+  struct GmresStats {
+    int its = 0, mv64 = 0, mv32 = 0, certs = 0;
+    double resid = 0, beta0 = 0;
+  };
+  int gmres(DevProblem &p, const double *b, double bnorm, double *x, bool x_zero, double tol_abs, int restart,
+            int maxit, const GmresArgs &a, GmresStats &s, hipStream_t st);
   int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
                  int &its, int &matvecs, double &resid, hipStream_t st, double *r0 = nullptr);
   // g' = g - n.D grad (S f)+, with f already in fpad (padded). g may be null.
@@ -66,8 +82,11 @@ struct Solver {
   // its residual gp - A psi if already known, unless *r0_bad (pinned host memory, valid after the
   // first wait of the solve) is set, when the residual is computed with an FP64 product.
   // Afterwards last_resid holds gp - A64 psi.
+  // z0 (optional): first search direction of the GMRES (precision 0 and 2) or of the first FP32 inner
+  // solve (precision 1), e.g. a predicted correction of the start.
   int solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                    hipStream_t st, const double *r0 = nullptr, const int *r0_bad = nullptr);
+                    hipStream_t st, const double *r0 = nullptr, const int *r0_bad = nullptr,
+                    const double *z0 = nullptr);
   const double *last_resid = nullptr;
   // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added)
   // fa: bidomain step (source from V); fuse_be: the inverse x pass also finishes the step
@@ -96,6 +115,7 @@ struct bidomain_s {
   // residual with an FP64 product instead
   double *psi_last = nullptr;
   const double *hist_last = nullptr;
+  double *zdir = nullptr;      // warm_start 4: predicted correction of the start (first search direction)
   int *r0_bad_dev = nullptr, *r0_bad_host = nullptr;
   bool have_prev = false;
   void reset();                // forget the recycled residual, the projection history and the counts

@@ -274,6 +274,7 @@ void Solver::init(DevProblem &p) {
   KFBI_HIP(hipHostMalloc(&ypin, 2 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
   vin = dalloc<double>(L);
   wv = dalloc<double>(L);
+  zbuf = dalloc<double>(L);
   jdev = dalloc<int>(1);
   KFBI_HIP(hipHostMalloc(&jhost, sizeof(int), hipHostMallocDefault));
   seqdev = dalloc<int>(1);
@@ -304,7 +305,7 @@ void Solver::release() {
   if (seqhost) (void)hipHostFree(seqhost);
   seqdev = nullptr;
   seqhost = nullptr;
-  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &npart, &hdev, &ydev, &vin, &wv};
+  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &npart, &hdev, &ydev, &vin, &wv, &zbuf};
   for (double **q : dp) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -420,54 +421,73 @@ void Solver::run_step(DevProblem &p, int prec, int m, hipStream_t st) {
   KFBI_HIP(hipGraphLaunch(graph[prec], st));
 }
 
-int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double *x, bool x_zero, double tol_abs,
-                  int restart, int maxit, int &its, int &matvecs, double &resid, hipStream_t st,
-                  double *beta0, const double *r0) {
+int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool x_zero, double tol_abs, int restart,
+                  int maxit, const GmresArgs &a, GmresStats &s, hipStream_t st) {
   const int m = std::max(1, std::min(restart, kMaxRestart));
-  its = 0;
+  s = GmresStats{};
   if (bnorm == 0.0) {
     // b = 0: the solution is 0 and so is its residual, which callers read from r
     k_axpby<<<nblk(L), kB, 0, st>>>(x, 0.0, b, 0.0, nullptr, L);
     k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, 0.0, nullptr, L);
     KFBI_HIP(hipGetLastError());
-    resid = 0;
-    if (beta0) *beta0 = 0;
     return KFBI_OK;
   }
+  auto count = [&](int prec) {
+    if (prec) ++s.mv32;
+    else ++s.mv64;
+  };
+  // the product of a restart residual: FP64 in a relaxed solve, else the solve's own precision
+  const int prec_res = a.relax ? 0 : a.prec;
   // r = b - A x
   if (x_zero) {
     KFBI_HIP(hipMemcpyAsync(r, b, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-  } else if (r0) {
-    KFBI_HIP(hipMemcpyAsync(r, r0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else if (a.r0) {
+    KFBI_HIP(hipMemcpyAsync(r, a.r0, L * sizeof(double), hipMemcpyDeviceToDevice, st));
   } else {
-    apply_vec(p, prec, x, t, st);
-    ++matvecs;
+    apply_vec(p, prec_res, x, t, st);
+    count(prec_res);
     k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
   }
   double beta = std::sqrt(dot(r, r, st));
-  if (beta0) *beta0 = beta;
+  s.beta0 = beta;
   std::vector<double> H((size_t)(m + 1) * m), Hc((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), z(m + 1);
-  while (beta > tol_abs && its < maxit) {
+  bool first_cycle = true;
+  while (beta > tol_abs && s.its < maxit) {
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(Hc.begin(), Hc.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     const double beta_cycle = beta;
     k_axpby<<<nblk(L), kB, 0, st>>>(V, 1.0 / beta, r, 0.0, nullptr, L);
+    // flexible first step: search along z0 (normalised into zbuf) instead of V_0
+    bool flex = false;
+    if (first_cycle && a.z0) {
+      const double zn = std::sqrt(dot(a.z0, a.z0, st));
+      if (zn > 0) {
+        k_axpby<<<nblk(L), kB, 0, st>>>(zbuf, 1.0 / zn, a.z0, 0.0, nullptr, L);
+        flex = true;
+      }
+    }
+    const double *first_in = flex ? zbuf : V;
     int jend = 0;
-    bool breakdown = false;
+    bool breakdown = false, any32 = false;
     const bool graphed = use_graph && !p.profile;
     if (graphed) {
       *jhost = 0;
       KFBI_HIP(hipMemcpyAsync(jdev, jhost, sizeof(int), hipMemcpyHostToDevice, st));
-      k_axpby<<<nblk(L), kB, 0, st>>>(vin, 1.0 / beta, r, 0.0, nullptr, L);   // the first step's input V_0
+      KFBI_HIP(hipMemcpyAsync(vin, first_in, L * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
+    double target = tol_abs;
     for (int j = 0; j < m; ++j) {
+      // relaxed: FP32 products once the current (Givens) residual is below sw_abs
+      const int pj = a.relax ? (std::fabs(g[j]) <= a.sw_abs ? 1 : 0) : a.prec;
+      any32 = any32 || pj == 1;
       if (graphed) {
-        run_step(p, prec, m, st);
+        run_step(p, pj, m, st);
       } else {
-        double *vj = V + (int64_t)j * L, *vn = V + (int64_t)(j + 1) * L;
-        apply_vec(p, prec, vj, vn, st);
+        const double *vj = j == 0 ? first_in : V + (int64_t)j * L;
+        double *vn = V + (int64_t)(j + 1) * L;
+        apply_vec(p, pj, vj, vn, st);
         // classical Gram-Schmidt, twice; then the norm
         for (int pass = 0; pass < 2; ++pass) {
           k_multidot<<<dim3(nb, j + 1), kB, 0, st>>>(V, L, vn, L, partials);
@@ -479,8 +499,8 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
         KFBI_HIP(hipGetLastError());
         KFBI_HIP(hipMemcpyAsync(hhost, hdev, 3 * (kMaxRestart + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
       }
-      ++matvecs;
-      ++its;
+      count(pj);
+      ++s.its;
       if (graphed) wait_step(st);
       else KFBI_HIP(hipStreamSynchronize(st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + hhost[(kMaxRestart + 2) + i];
@@ -488,20 +508,24 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       H[(size_t)(j + 1) * m + j] = hn;
       for (int i = 0; i <= j + 1; ++i) Hc[(size_t)i * m + j] = H[(size_t)i * m + j];   // before rotations
       for (int i = 0; i < j; ++i) {
-        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+        const double av = H[(size_t)i * m + j], cv = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * av + sn[i] * cv;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * av + cs[i] * cv;
       }
-      const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-      const double den = std::hypot(a, c);
-      cs[j] = den > 0 ? a / den : 1.0;
-      sn[j] = den > 0 ? c / den : 0.0;
+      const double av = H[(size_t)j * m + j], cv = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(av, cv);
+      cs[j] = den > 0 ? av / den : 1.0;
+      sn[j] = den > 0 ? cv / den : 0.0;
       H[(size_t)j * m + j] = den;
       H[(size_t)(j + 1) * m + j] = 0.0;
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
       jend = j + 1;
-      if (std::fabs(g[j + 1]) <= tol_abs || its >= maxit) break;
+      // after FP32 products the computed residual differs from the true one by the products'
+      // errors weighted with the solution's coefficients; converging it to a quarter of the
+      // tolerance leaves that gap room before the FP64 check
+      target = any32 ? 0.25 * tol_abs : tol_abs;
+      if (std::fabs(g[j + 1]) <= target || s.its >= maxit) break;
       if (hn == 0.0) {
         breakdown = true;
         break;
@@ -512,12 +536,17 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
       y[i] = acc / H[(size_t)i * m + i];
     }
+    // x += Z y with Z = [first search direction, V_1, ..., V_{jend-1}]
     std::copy(y.begin(), y.begin() + jend, ypin);
+    if (flex) ypin[0] = 0.0;
     KFBI_HIP(hipMemcpyAsync(ydev, ypin, jend * sizeof(double), hipMemcpyHostToDevice, st));
     k_combine<<<nblk(L), kB, 0, st>>>(x, V, L, ydev, jend, 1.0, L);
+    if (flex) k_axpby<<<nblk(L), kB, 0, st>>>(x, 1.0, x, y[0], zbuf, L);
     KFBI_HIP(hipGetLastError());
-    if (std::fabs(g[jend]) <= tol_abs && !breakdown) {
-      // converged: the residual vector follows from the Arnoldi relation without a product,
+    first_cycle = false;
+    const bool converged = std::fabs(g[jend]) <= target && !breakdown;
+    if (converged && !any32) {
+      // exact products: the residual vector follows from the Arnoldi relation without a product,
       //   b - A x = V_{j+1} (beta e_1 - Hbar y)
       for (int i = 0; i <= jend; ++i) {
         double acc = i == 0 ? beta_cycle : 0.0;
@@ -534,12 +563,15 @@ int Solver::gmres(DevProblem &p, int prec, const double *b, double bnorm, double
       host_wait(st);
       break;
     }
-    apply_vec(p, prec, x, t, st);
-    ++matvecs;
+    // the true residual: the FP64 certificate of a relaxed solve, else a restart
+    const int pr = any32 && a.relax ? 0 : prec_res;
+    apply_vec(p, pr, x, t, st);
+    count(pr);
+    if (a.relax && any32) ++s.certs;
     k_axpby<<<nblk(L), kB, 0, st>>>(r, 1.0, b, -1.0, t, L);
     beta = std::sqrt(dot(r, r, st));
   }
-  resid = beta;
+  s.resid = beta;
   return beta <= tol_abs ? KFBI_OK : KFBI_ENOCONV;
 }
 
@@ -573,23 +605,36 @@ void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnAr
 }
 
 int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                          hipStream_t st, const double *r0, const int *r0_bad) {
+                          hipStream_t st, const double *r0, const int *r0_bad, const double *z0) {
   const double gn = std::sqrt(dot(gp, gp, st));
   if (r0 && r0_bad && *r0_bad) r0 = nullptr;   // read after the wait above: r0 does not belong to psi
   info.gp_norm = gn;
   const double tol_abs = o.tol * gn;
-  int its = 0, mv = 0, rc = KFBI_OK;
+  int rc = KFBI_OK;
   double res = 0, res0 = gn;
   if (!x0) KFBI_HIP(hipMemsetAsync(psi, 0, L * sizeof(double), st));
   if (o.method == 1) {
+    int its = 0, mv = 0;
     rc = richardson(p, gp, gn, psi, o.gamma, tol_abs, o.max_iters, its, mv, res, st, &res0);
     info.iters = its;
     info.matvecs_fp64 = mv;
     last_resid = r;
-  } else if (o.precision == 0) {
-    rc = gmres(p, 0, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, its, mv, res, st, &res0, r0);
-    info.iters = its;
-    info.matvecs_fp64 = mv;
+  } else if (o.precision == 0 || o.precision == 2) {
+    // precision 2: one GMRES whose products turn FP32 once the residual is below inner_tol ||g'||,
+    // with an FP64 product of the result as its certificate
+    GmresArgs a;
+    a.relax = o.precision == 2;
+    a.sw_abs = o.inner_tol * gn;
+    a.r0 = r0;
+    a.z0 = z0;
+    GmresStats gs;
+    rc = gmres(p, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, a, gs, st);
+    info.iters = gs.its;
+    info.outer = gs.certs;
+    info.matvecs_fp64 = gs.mv64;
+    info.matvecs_fp32 = gs.mv32;
+    res = gs.resid;
+    res0 = gs.beta0;
     last_resid = r;
   } else {
     // iterative refinement: FP64 residual, FP32-operator GMRES on the correction
@@ -608,13 +653,15 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
       res = std::sqrt(dot(d, d, st));
       if (outer == 0) res0 = res;
       if (res <= tol_abs || outer >= o.max_outer || total >= o.max_iters) break;
-      int it = 0, mvi = 0;
-      double r_in = 0;
       KFBI_HIP(hipMemsetAsync(w, 0, L * sizeof(double), st));
       const double tin = std::max(o.inner_tol * res, 0.5 * tol_abs);
-      gmres(p, 1, d, res, w, true, tin, o.restart, o.max_iters - total, it, mvi, r_in, st);
-      total += it;
-      mv32 += mvi;
+      GmresArgs a;
+      a.prec = 1;
+      a.z0 = outer == 0 ? z0 : nullptr;
+      GmresStats gs;
+      gmres(p, d, res, w, true, tin, o.restart, o.max_iters - total, a, gs, st);
+      total += gs.its;
+      mv32 += gs.mv32;
       k_axpby<<<nblk(L), kB, 0, st>>>(psi, 1.0, psi, 1.0, w, L);
       have_x = true;
       ++outer;
@@ -702,11 +749,12 @@ void bidomain_s::init() {
   KFBI_HIP(hipMemset(d_prev, 0, L * sizeof(double)));
   KFBI_HIP(hipMalloc(&psi_last, L * sizeof(double)));
   KFBI_HIP(hipMemset(psi_last, 0, L * sizeof(double)));
+  KFBI_HIP(hipMalloc(&zdir, L * sizeof(double)));
   KFBI_HIP(hipMalloc(&r0_bad_dev, sizeof(int)));
   KFBI_HIP(hipMemset(r0_bad_dev, 0, sizeof(int)));
   KFBI_HIP(hipHostMalloc(&r0_bad_host, sizeof(int), hipHostMallocDefault));
   *r0_bad_host = 0;
-  if (params.warm_start == 3) {
+  if (params.warm_start == 3 || params.warm_start == 4) {
     KFBI_HIP(hipMalloc(&proj_psi, (size_t)kProj * L * sizeof(double)));
     KFBI_HIP(hipMalloc(&proj_b, (size_t)kProj * L * sizeof(double)));
   }
@@ -785,10 +833,10 @@ void bidomain_s::reset() {
 }
 
 void bidomain_s::release() {
-  double *ps[] = {psi0, r0v, gp_prev, d_prev, psi_last, proj_psi, proj_b};
+  double *ps[] = {psi0, r0v, gp_prev, d_prev, psi_last, zdir, proj_psi, proj_b};
   for (double *q : ps)
     if (q) (void)hipFree(q);
-  psi0 = r0v = gp_prev = d_prev = psi_last = proj_psi = proj_b = nullptr;
+  psi0 = r0v = gp_prev = d_prev = psi_last = zdir = proj_psi = proj_b = nullptr;
   if (r0_bad_dev) (void)hipFree(r0_bad_dev);
   if (r0_bad_host) (void)hipHostFree(r0_bad_host);
   r0_bad_dev = nullptr;
@@ -841,7 +889,7 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
       have_r0 = true;
       r0_flag = r0_bad_host;
     }
-    if (params.warm_start == 3 && proj_n >= 2) {
+    if ((params.warm_start == 3 || params.warm_start == 4) && proj_n >= 2) {
       // least-residual start over the recorded solutions (its residual is exact whatever the
       // caller's history holds); kept only if that residual is below psi^{n-1}'s, or taken
       // when psi^{n-1}'s residual is unknown or invalid
@@ -863,7 +911,7 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
         // precision of the inner solves: FP32 rounding noise in the starting residual would
         // slow an FP64 GMRES that must resolve it, while iterative refinement absorbs it.
         k_axpby<<<nblk(L), kB, 0, st>>>(sv.w, 1.0, sv.w, -1.0, hist1, L);
-        const int pd = o.precision == 1 && o.method == 0 ? 1 : 0;
+        const int pd = o.precision != 0 && o.method == 0 ? 1 : 0;
         sv.apply_vec(p, pd, sv.w, sv.t, st);
         if (pd) extra32 = 1;
         else extra64 = 1;
@@ -898,11 +946,25 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
       }
     }
   }
-  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr, r0_flag);
+  // warm_start 4: the network's prediction enters as the first search direction of the GMRES
+  // started from the projection: z0 = prediction - start.  Its product is the one the first
+  // iteration computes anyway, so the prediction costs no product; the cost check below switches
+  // it off when the solves it starts are not cheaper than those without it.
+  const double *z0 = nullptr;
+  bool learned_dir = false;
+  if (params.warm_start == 4 && mlp && steps_done >= 2 && o.method == 0 &&
+      mlp_warm_start(this, hist1, hist2, zdir, st)) {
+    k_axpby<<<nblk(L), kB, 0, st>>>(zdir, 1.0, zdir, -1.0, psi0, L);
+    KFBI_HIP(hipGetLastError());
+    z0 = zdir;
+    learned_dir = true;
+    info.warm_start_used |= 2;
+  }
+  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr, r0_flag, z0);
   info.matvecs_fp32 += extra32;
   info.matvecs_fp64 += extra64;
   KFBI_HIP(hipMemcpyAsync(d_prev, sv.last_resid, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (params.warm_start == 3) proj_record(psi0, st);
+  if (params.warm_start == 3 || params.warm_start == 4) proj_record(psi0, st);
   // u = S(f + C psi); the midpoint update and step 3 (reaction over dt/2, backward Euler) ride
   // in its inverse x pass unless the potentials are returned as well
   sv.reconstruct(p, psi0, st, &fa, s.phi == nullptr);
@@ -917,6 +979,7 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   if (mlp && steps_done >= 2) {
     mlp_record(this, hist1, hist2, psi0, st);
     if (params.warm_start == 1) mlp_note_cost(this, info.matvecs_fp64 + 0.5 * info.matvecs_fp32, info.warm_start_used);
+    if (params.warm_start == 4) mlp_note_cost(this, info.matvecs_fp64 + 0.5 * info.matvecs_fp32, learned_dir);
   }
   ++steps_done;
   k_end_step<<<nblk(L), kB, 0, st>>>(gp_prev, sv.gp, hist2, hist1, psi_last, psi0, r0_bad_dev, L);

@@ -25,7 +25,7 @@ EXPORTED = [
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
     "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
     "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles", "kfbi_use_graph", "bidomain_use_graph",
-    "kfbi_profile", "bidomain_reset", "kfbi_box_solve_noalloc",
+    "kfbi_profile", "bidomain_reset", "kfbi_box_solve_noalloc", "bidomain_true_resid",
 ]
 
 
@@ -119,6 +119,7 @@ def lib():
     L.kfbi_use_graph.argtypes = [vp, i32]
     L.bidomain_use_graph.argtypes = [vp, i32]
     L.bidomain_reset.argtypes = [vp]
+    L.bidomain_true_resid.argtypes = [vp, i32]
     L.kfbi_box_solve_noalloc.argtypes = [C.POINTER(GridDesc), C.POINTER(CoeffsDesc), vp, vp, i32, vp]
     L.kfbi_set_tiles.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.kfbi_batch_setup.argtypes = [i32, C.POINTER(Interface), C.POINTER(GridDesc), C.POINTER(CoeffsDesc),
@@ -441,6 +442,10 @@ class Bidomain:
 
     def reset(self):
         _check(lib().bidomain_reset(self._h))
+
+    def true_resid(self, enable=True):
+        """Report the FP64 residual of every following solve from an explicit product."""
+        _check(lib().bidomain_true_resid(self._h, 1 if enable else 0))
 
     def mlp_init(self, capacity=256, seed=3):
         _check(lib().bidomain_mlp_init(self._h, capacity, seed))

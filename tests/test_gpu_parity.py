@@ -195,6 +195,45 @@ def test_solve_neumann_mixed_precision_reaches_fp64_residual():
     assert e < 1e-9, e
 
 
+@pytest.mark.parametrize("switch", [1e-2, 1.0])
+def test_solve_neumann_relaxed_precision_matches_oracle(switch):
+    """precision 2: one GMRES with FP64 Arnoldi whose products turn FP32 once the residual is below
+    switch ||g'|| (1.0: from the first product on), its result checked by an FP64 product: the
+    checked residual meets the tolerance, an explicit product agrees, and u equals the oracle's."""
+    g, o, iface, grid, co = problems("star2d_128")
+    f, gn, _ = _mms2d(o, grid)
+    say(f"[solve relaxed, switch {switch}] star2d_128")
+    u, psi, info = g.solve_neumann(T(gn), T(f), tol=1e-10, precision=2, inner_tol=switch, true_resid=1)
+    uo, _, _ = o.solve_neumann(gn, f, tol=1e-13)
+    ins = o.inside
+    e = err(u.cpu().numpy()[0][ins], uo[0][ins])
+    say(f"    fp64 {info['matvecs_fp64']} fp32 {info['matvecs_fp32']} checks {info['outer']}; residual "
+        f"{info['rel_resid']:.2e}, by explicit product {info['true_resid']:.2e}; u err {e:.2e}")
+    assert info["matvecs_fp32"] > 0 and info["outer"] >= 1
+    assert info["rel_resid"] <= 1e-10 and info["true_resid"] <= 1e-10
+    assert abs(info["true_resid"] - info["rel_resid"]) <= 1e-3 * info["rel_resid"] + 1e-16
+    assert e < 1e-9
+
+
+def test_bidomain_relaxed_precision_steps_match_oracle():
+    """Bidomain steps with precision 2 (FP32 products once the residual is below 1e-2 ||g'||, an
+    FP64 check of every solve) against the oracle's steps."""
+    g, o, iface, grid, co = problems("ellipsoid_bido_32")
+    V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
+    bd = K.Bidomain(g, P_BIDO, tol=1e-11, precision=2, inner_tol=1e-2)
+    V, q = T(V0), T(q0)
+    hist = torch.zeros(2, 2, g.M, dtype=torch.float64, device=DEV)
+    Vo, qo, psi = V0.copy(), q0.copy(), None
+    for s_ in range(4):
+        info = bd.step(V, q, hist, 0.01)
+        Vo, qo, _, psi, infoo = obd.step(o, P_BIDO, Vo, qo, 0.01, psi0=psi, tol=1e-12)
+        eV = err(V.cpu().numpy(), Vo)
+        say(f"[bidomain relaxed] step {s_}: V err {eV:.2e}, fp64 {info['matvecs_fp64']} fp32 {info['matvecs_fp32']}")
+        assert info["rel_resid"] <= 1e-11
+        assert eV < 1e-9
+    bd.close()
+
+
 def test_solve_neumann_coupled_gauge_and_V():
     g, o, iface, grid, co = problems("shell_64")
     pts = ogeo.grid_points(grid)
