@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="leave the batched 2D workload out of the line")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3 (first listed variant only, no CPU baseline, no batch)")
+    ap.add_argument("--prefix", type=int, default=PREFIX,
+                    help="untimed steps before the warm-up (the workload's first 200; fewer only for profiling "
+                         "runs, which then no longer time the workload's window)")
     ap.add_argument("--batch", action="store_true",
                     help="only the batched 2D workload: 64 seeded Neumann problems of sizes 64..1024, "
                          "solved as one batch and one by one (problems/s)")
@@ -264,12 +267,12 @@ def main():
     variants = [v for v in a.variants.split(",") if v]
     if a.profile_run:
         variants = variants[:1]
-    t_win0 = PREFIX + a.warmup
+    t_win0 = a.prefix + a.warmup
     results, kt = {}, {}
     for name in variants:
         bd = K.Bidomain(prob, p, tol=1e-8, **variant_kwargs(name, a))
         if name == "learned":
-            bd.mlp_init(capacity=PREFIX, seed=3)
+            bd.mlp_init(capacity=max(a.prefix, 1), seed=3)
         V = torch.tensor(V0, device=dev)
         q = torch.tensor(q0, device=dev)
         hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=dev)
@@ -282,11 +285,11 @@ def main():
             step_no += 1
             return bd.step(V, q, hist, dt)
 
-        for _ in range(PREFIX):
+        for _ in range(a.prefix):
             step()
         if name == "learned":
             loss = bd.train(epochs=a.epochs, lr=1e-3)
-            log(f"learned: network trained on steps 1-{PREFIX}, loss {loss:.3e}")
+            log(f"learned: network trained on steps 1-{a.prefix}, loss {loss:.3e}")
         for _ in range(a.warmup):
             step()
         exc0 = float(((V > 0.5) & tissue).sum()) / n_tissue
@@ -388,11 +391,11 @@ def main():
         "dtype": "f64" if head in ("plain", "projected", "richardson") else "f32+f64",
         "data": "synthetic (seeded thick-shell geometry, stimulus ball at steps 0 and 300)",
         "config": {"workload": f"FHN bidomain on a thick shell, {a.cells}^3 grid, {prob.M} interface nodes, "
-                               f"dt=0.01, GMRES(50) tol 1e-8, {PREFIX} untimed steps (the learned variant's "
+                               f"dt=0.01, GMRES(50) tol 1e-8, {a.prefix} untimed steps (the learned variant's "
                                f"training data) + {a.warmup} warm-up, timed steps {t_win0 + 1}-{t_win0 + a.steps}",
                    "variant": head, "cells": a.cells,
                    "interface_nodes": prob.M, "crossings": prob.n_crossings, "parallelism": "single GPU"},
-        "prefix_steps": PREFIX,
+        "prefix_steps": a.prefix,
         "variants": {k: {kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},
         "speedup_vs_plain": {k: round(v["steps_per_s"] / results["plain"]["steps_per_s"], 3) for k, v in results.items()}
