@@ -24,6 +24,9 @@ learned variant without the network, in FP64 and mixed precision); mixed_ir (FP3
 with FP64 iterative refinement); richardson (the simple iteration, gamma = 0.8, FP64).  Every
 solve ends at the same FP64 relative residual bound.
 
+Also reported: the batched 2D workload (problems/s) and the paper's own examples in its parameter
+regime (GMRES iterations per step, steps/s, the simple iteration's residual).
+
 Prints one JSON line (see the "metric" key).  --batch and --copy-calibration run the batched
 2D workload and the counter calibration alone.
 """
@@ -66,6 +69,7 @@ def parse():
                     help="steps after those whose FP64 residual is checked by an explicit product")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="leave the batched 2D workload out of the line")
+    ap.add_argument("--no-examples", action="store_true", help="leave the paper's examples out of the line")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3 (first listed variant only, no CPU baseline, no batch)")
     ap.add_argument("--prefix", type=int, default=PREFIX,
@@ -185,6 +189,51 @@ def batch_run(torch, warmup=1, reps=5, singles=True):
         for p in ps:
             p.close()
     b.close()
+    return out
+
+
+def paper_examples(torch):
+    """The paper's own regime (anisotropic D_i = diag(30, 5[, 5]), D_e = diag(20, 10[, 10]), beta = 1000,
+    dt = h, virtual electrode): GMRES iterations per step and steps/s for Example 1 (circle, 256^2,
+    128 steps) and Example 3 (sphere, 128^3, 32 steps), and for the sphere the residual the simple
+    iteration (gamma = 0.8) reaches in 25 and 100 iterations."""
+    import numpy as np
+
+    from paper_2104_05024_amd import kfbi as K
+    from paper_2104_05024_amd import workloads as W
+    dev = torch.device("cuda:0")
+    out = {}
+    for key, fn, cells, steps in (("example1_circle_256", W.paper_circle_example, 256, 128),
+                                  ("example3_sphere_128", W.paper_sphere_example, 128, 32)):
+        iface, grid, co, p, dt, stim = fn(cells)
+        prob = K.Problem(iface, grid, co)
+        n = grid.n ** grid.dim
+        Is = torch.tensor(stim, device=dev)
+        res = {"cells": cells, "interface_nodes": prob.M, "steps": steps, "dt": dt}
+        runs = [("gmres", dict(), steps, False)]
+        if grid.dim == 3:
+            runs += [(f"simple_iteration_{mi}", dict(method=1, gamma=0.8, max_iters=mi), 3, True) for mi in (25, 100)]
+        for tag, kw, ns, noconv in runs:
+            bd = K.Bidomain(prob, p, tol=1e-8, **kw)
+            V = torch.zeros(n, dtype=torch.float64, device=dev)
+            q = torch.zeros_like(V)
+            hist = torch.zeros(2, 2, prob.M, dtype=torch.float64, device=dev)
+            bd.step(V, q, hist, dt, I_stim=Is, allow_noconv=noconv)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = [bd.step(V, q, hist, dt, I_stim=Is, allow_noconv=noconv) for _ in range(ns - 1)]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            if tag == "gmres":
+                res.update(gmres_iters_per_step=round(float(np.mean([i["iters"] for i in infos])), 2),
+                           steps_per_s=round((ns - 1) / el, 1), max_rel_resid=max(i["rel_resid"] for i in infos),
+                           V_max=round(float(V.max().item()), 4))
+            else:
+                res[f"{tag}_rel_resid"] = float(f"{max(i['rel_resid'] for i in infos):.3e}")
+            bd.close()
+        prob.close()
+        out[key] = res
+        log(f"{key}: {res}")
     return out
 
 
@@ -408,6 +457,9 @@ def main():
     if not a.no_batch and not a.profile_run:
         log("batched 2D workload ...")
         out["batch"] = batch_run(torch, singles=False)
+    if not a.no_examples and not a.profile_run:
+        log("the paper's examples ...")
+        out["paper_examples"] = paper_examples(torch)
     if not a.no_cpu_baseline and not a.profile_run:
         out["cpu_baseline"] = cpu_baseline(iface, grid, co, p, dt, V0, q0)
     print(json.dumps(out))

@@ -307,6 +307,44 @@ def bidomain_coeffs(dim, params: BidomainParams, dt: float) -> Coeffs:
     return Coeffs(2, [[params.sigma_i] * dim, [params.sigma_e] * dim], kappa)
 
 
+# ----------------------------------------------------------------------------- the paper's examples
+
+def paper_params() -> BidomainParams:
+    """The parameters of the paper's numerical section: C_m = 1, beta = 1000, FitzHugh-Nagumo with
+    H = 100, theta = 0.25, alpha = 5/20, zeta = 1, Newton tolerance 1e-10."""
+    return BidomainParams(Cm=1.0, beta=1000.0, H=100.0, theta=0.25, alpha=0.25, zeta=1.0)
+
+
+def paper_circle_example(cells, R=0.8):
+    """Example 1 (2D circle) with dt = h.  Box [-1, 1]^2 (the paper's trajectory points
+    (0.5625..0.71875, 0) are grid nodes of that box) and a circle of radius R = 0.8 (not stated; it
+    must hold those points), given by `cells` quasi-uniform nodes through a periodic cubic spline;
+    D_i = diag(30, 5), D_e = diag(20, 10) (fibers along x); kappa = 2 C_m beta / dt; the virtual
+    electrode: anode (-0.3, 0), cathode (0.3, 0), radius 0.25, V_stim = 10.
+    Returns (interface, grid, coeffs, params, dt, I_stim on the box nodes)."""
+    grid = box(2, cells, -1.0, 1.0)
+    p = paper_params()
+    dt = grid.h
+    co = Coeffs(2, [[30.0, 5.0], [20.0, 10.0]], 2.0 * p.Cm * p.beta / dt)
+    stim = virtual_electrode(grid, (-0.3, 0.0), (0.3, 0.0), radius=0.25, amplitude=10.0)
+    return spline_circle(R, n_nodes=cells), grid, co, p, dt, stim
+
+
+def paper_sphere_example(cells, R=0.9, n_nodes=None):
+    """Example 3 (3D sphere) with dt = h.  Box [-1, 1]^3 (the trajectory points (0.5625..0.875, 0, 0)
+    are grid nodes of that box), a sphere of radius R = 0.9 (not stated; it must hold them) with
+    (cells/8)^2 + 2 nodes (the paper's 66 at 64^3, 258 at 128^3) unless n_nodes is given; D_i = diag(30, 5, 5),
+    D_e = diag(20, 10, 10); kappa = 2 C_m beta / dt; virtual electrode at (-0.3, 0, 0) / (0.3, 0, 0),
+    radius 0.25, V_stim = 10.  Returns (interface, grid, coeffs, params, dt, I_stim)."""
+    grid = box(3, cells, -1.0, 1.0)
+    p = paper_params()
+    dt = grid.h
+    co = Coeffs(2, [[30.0, 5.0, 5.0], [20.0, 10.0, 10.0]], 2.0 * p.Cm * p.beta / dt)
+    stim = virtual_electrode(grid, (-0.3, 0.0, 0.0), (0.3, 0.0, 0.0), radius=0.25, amplitude=10.0)
+    m = n_nodes if n_nodes is not None else (cells // 8) ** 2 + 2
+    return sphere(R, n_nodes=m), grid, co, p, dt, stim
+
+
 # ----------------------------------------------------------------------------- named configs
 
 def config(name: str):
