@@ -136,7 +136,9 @@ def measured_traffic(kernel):
 
 def batch_run(torch, warmup=1, reps=5, singles=True):
     """64 seeded 2D Neumann problems (manufactured u = e^x sin(pi y)), FP32 inner GMRES with
-    FP64 refinement to 1e-10 per problem: one batch, and (singles) the problems one at a time."""
+    FP64 refinement to 1e-10 per problem: one batch (each DST pass one launch over all size
+    groups; also timed with one launch per group and pass), and (singles) the problems one at a
+    time."""
     import numpy as np
 
     from paper_2104_05024_amd import kfbi as K
@@ -167,7 +169,18 @@ def batch_run(torch, warmup=1, reps=5, singles=True):
         u, psi, infos = b.solve_neumann(g, f, **opts)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
+    # the same solves with one DST launch per size group and pass
+    b.merge(False)
+    b.solve_neumann(g, f, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.solve_neumann(g, f, **opts)
+    torch.cuda.synchronize()
+    t_grouped = (time.perf_counter() - t0) / reps
+    b.merge(True)
     out = {"problems_per_s": round(b.n / t_batch, 1), "n_problems": b.n, "ms_per_batch": round(1000 * t_batch, 2),
+           "grouped_launches_problems_per_s": round(b.n / t_grouped, 1),
            "max_final_rel_resid": max(i["rel_resid"] for i in infos),
            "mean_inner_iters": float(np.mean([i["iters"] for i in infos])), "setup_s": round(setup_s, 2),
            "cells": sorted(set(gr.cells for _, gr, _ in probs))}

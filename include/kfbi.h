@@ -316,7 +316,7 @@ int bidomain_mlp_eval(bidomain_ctx b, const float *X, int64_t R, float *Y, const
 
 /* A batch of independent two-dimensional one-component Neumann problems (the scalar form
  * of the interface problem, Sec. 2 and 4) with uneven grid sizes (cells = 2^k in [16, 1024])
- * and shapes, solved together: problems of one grid size share each DST pass launch; the
+ * and shapes, solved together: the problems share each DST pass launch (kfbi_batch_merge); the
  * jump, correction and gather kernels of all problems run as one launch each over a work
  * list; GMRES runs in lockstep for all problems with one Arnoldi step captured once as a
  * hipGraph and replayed.  Concatenated layouts: interface arrays [problem][M_p] (offsets from
@@ -341,6 +341,12 @@ int kfbi_batch_solve_neumann(kfbi_batch b, const double *g, const double *f, dou
                              const kfbi_solve_opts *opts, kfbi_solve_info *info, void *stream);
 /* enable != 0 (default): replay the captured Arnoldi step; 0: launch its kernels directly. */
 int kfbi_batch_graph(kfbi_batch b, int32_t enable);
+/* enable != 0 (default): when every grid size of the batch is 64..1024 cells, each DST pass of
+ * the box solves is one launch over all size groups together (the tiles of small grids run
+ * beside those of large ones); 0: one launch per size group and pass, at the tile widths timed
+ * for that group.  Results are identical.  Waits for the batch's capture stream; the captured
+ * Arnoldi steps are captured again at their next use. */
+int kfbi_batch_merge(kfbi_batch b, int32_t enable);
 
 /* ----------------------------------------------------------------- utilities */
 

@@ -314,6 +314,16 @@ int kfbi_batch_graph(kfbi_batch b, int32_t enable) {
   return KFBI_OK;
 }
 
+int kfbi_batch_merge(kfbi_batch b, int32_t enable) {
+  if (!b) return fail(KFBI_EINVAL, "argument");
+  return guard([&]() -> int {
+    KFBI_HIP(hipStreamSynchronize(b->b.cap));
+    b->b.merged = enable != 0;
+    b->b.drop_graphs();
+    return KFBI_OK;
+  });
+}
+
 int kfbi_profile(kfbi_problem p, int32_t enable) {
   if (!p) return fail(KFBI_EINVAL, "null problem");
   return guard([&]() -> int {

@@ -58,6 +58,13 @@ struct Batch {
   int seq_next = 0;
   void host_wait(hipStream_t st);
   bool use_graph = true;
+  // box solves of all size groups as one launch per pass (box_solve_multi) when every group's
+  // size is 64..1024; otherwise, or when switched off, one launch per group and pass
+  bool merged = true;
+  bool mergeable() const;
+  template <typename T>
+  void box_all(bool from_fpad, hipStream_t st);   // every group: src (rhs, or fpad if from_fpad) -> work
+  void drop_graphs();                              // the captured steps are captured again when next used
   hipStream_t cap = nullptr;           // capture stream (the caller's stream may be the null stream)
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graph_m[2] = {0, 0};

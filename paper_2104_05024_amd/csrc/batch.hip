@@ -361,16 +361,50 @@ void Batch::release() {
   probs.clear();
 }
 
+bool Batch::mergeable() const {
+  if (groups.empty() || (int)groups.size() > kMaxMultiGroups) return false;
+  for (const Group &g : groups)
+    if (g.Mfft < 64 || g.Mfft > 1024) return false;
+  return true;
+}
+
+void Batch::drop_graphs() {
+  for (int k = 0; k < 2; ++k)
+    if (graph[k]) {
+      (void)hipGraphExecDestroy(graph[k]);
+      graph[k] = nullptr;
+      graph_m[k] = 0;
+    }
+}
+
+template <typename T>
+void Batch::box_all(bool from_fpad, hipStream_t st) {
+  auto src_of = [&](const Group &g) -> const T * {
+    if constexpr (sizeof(T) == 8) return from_fpad ? g.fpad64 : g.rhs64;
+    else return from_fpad ? g.fpad32 : g.rhs32;
+  };
+  if (merged && mergeable()) {
+    MultiGroupDesc d[kMaxMultiGroups];
+    int k = 0;
+    for (const Group &g : groups) {
+      const PrecTables<T> &tb = const_cast<DevProblem &>(*probs[g.members[0]]).tab<T>();
+      d[k++] = MultiGroupDesc{g.Mfft, (int)g.members.size(), g.cs, src_of(g), g.work<T>(), g.msv, tb.tw, tb.sp};
+    }
+    box_solve_multi<T>(d, k, st);
+    return;
+  }
+  for (const Group &g : groups) {
+    const PrecTables<T> &tb = const_cast<DevProblem &>(*probs[g.members[0]]).tab<T>();
+    box_solve_group<T>(g.Mfft, (int)g.members.size(), src_of(g), g.work<T>(), g.cs, g.msv, tb.tw, tb.sp,
+                       g.tile_w[sizeof(T) == 8 ? 0 : 1], st);
+  }
+}
+
 template <typename T>
 void Batch::matvec(const double *in, double *out, hipStream_t st) {
   launch_batch_jumps<T>(items<T>(), counts, in, st);
   launch_batch_correct<T>(items<T>(), counts, 0, st);
-  for (const Group &g : groups) {
-    const DevProblem &p0 = *probs[g.members[0]];
-    const PrecTables<T> &tb = const_cast<DevProblem &>(p0).tab<T>();
-    box_solve_group<T>(g.Mfft, (int)g.members.size(), g.rhs<T>(), g.work<T>(), g.cs, g.msv, tb.tw, tb.sp,
-                       g.tile_w[sizeof(T) == 8 ? 0 : 1], st);
-  }
+  box_all<T>(false, st);
   launch_batch_gather<T>(items<T>(), counts, true, out, st);
 }
 template void Batch::matvec<double>(const double *, double *, hipStream_t);
@@ -561,11 +595,7 @@ int Batch::solve(const double *g, const double *f, double *u, double *psi, const
                  kfbi_solve_info *info, hipStream_t st) {
   // volume part: u_V = S f, g' = g - n.D grad u_V+
   pack(f, 0, true, st);
-  for (const Group &gr : groups) {
-    const DevProblem &p0 = *probs[gr.members[0]];
-    box_solve_group<double>(gr.Mfft, (int)gr.members.size(), gr.fpad64, gr.work64, gr.cs, gr.msv, p0.f64.tw,
-                            p0.f64.sp, gr.tile_w[0], st);
-  }
+  box_all<double>(true, st);
   launch_batch_gather<double>(items64, counts, false, t, st);
   if (g) k_axpby<<<nb(L), kB, 0, st>>>(gp, 1.0, g, -1.0, t, L);
   else k_axpby<<<nb(L), kB, 0, st>>>(gp, -1.0, t, 0.0, nullptr, L);
@@ -627,11 +657,7 @@ int Batch::solve(const double *g, const double *f, double *u, double *psi, const
   // u = S(f + C psi)
   launch_batch_jumps<double>(items64, counts, psi, st);
   launch_batch_correct<double>(items64, counts, 1, st);
-  for (const Group &gr : groups) {
-    const DevProblem &p0 = *probs[gr.members[0]];
-    box_solve_group<double>(gr.Mfft, (int)gr.members.size(), gr.fpad64, gr.work64, gr.cs, gr.msv, p0.f64.tw,
-                            p0.f64.sp, gr.tile_w[0], st);
-  }
+  box_all<double>(true, st);
   pack(u, 1, false, st);
   KFBI_HIP(hipStreamSynchronize(st));
   bool ok = true;

@@ -298,6 +298,22 @@ void launch_batch_gather(const BatchItem<T> *items, const BatchCounts &c, bool w
 template <typename T>
 void box_solve_group(int Mfft, int G, const T *src, T *dst, int64_t cs, const ModeParams *msv, const T *tw,
                      const T *sp, const int *w, hipStream_t st);
+// Merged 2D box solve of several such groups (each with its own size): one launch per pass for
+// all groups together, so the tiles of small grids run beside those of large ones instead of in
+// launches of their own that cannot fill the GPU.  Sizes 64..1024, tile width 1; the groups are
+// those of one precision, src -> dst per group as in box_solve_group.  Results are identical to
+// box_solve_group's.
+struct MultiGroupDesc {
+  int Mfft = 0, G = 0;
+  int64_t cs = 0;
+  const void *src = nullptr;
+  void *dst = nullptr;
+  const ModeParams *msv = nullptr;
+  const void *tw = nullptr, *sp = nullptr;
+};
+constexpr int kMaxMultiGroups = 8;
+template <typename T>
+void box_solve_multi(const MultiGroupDesc *groups, int ngroups, hipStream_t st);
 // Autotuner: time each dense pass at both tile widths and keep the faster (cached per process
 // by dimension, grid size, components and precision); clears the work buffers afterwards.
 void autotune_tiles(DevProblem &p, hipStream_t st);

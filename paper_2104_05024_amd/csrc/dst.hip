@@ -306,16 +306,16 @@ struct alignas(16) V16 {
 
 // DST along contiguous rows: pairs of consecutive rows of the flattened [comp][..][x] list.
 // PIN / POUT: input / output in the padded layout (row pitch M) instead of pitch N.
+// One tile (2 NP rows, tile index blk) in the LDS buffer sbuf of NP * PADM values.
 template <typename T, int M, bool PIN, bool POUT, int W = 1>
-__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restrict__ in, T *__restrict__ out,
-                                                             int64_t nrows, const C2<T> *__restrict__ tw,
-                                                             const T *__restrict__ sp) {
+__device__ __forceinline__ void dst_x_tile(const T *__restrict__ in, T *__restrict__ out, int64_t nrows,
+                                           const C2<T> *__restrict__ tw, const T *__restrict__ sp, C2<T> *sbuf,
+                                           int64_t blk) {
   using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM, VW = 16 / sizeof(T);
   constexpr int ROWS = 2 * NP;
-  __shared__ C2<T> sbuf[NP * PADM];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  const int64_t r0 = blk * ROWS;
   const Sines<T, M> sn(sp, tid % Sh::TPP);
   if constexpr (M >= 64) {
     // one pencil pair per wave at a time; a lane moves whole complex values (two 8-byte row
@@ -446,6 +446,15 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restr
       }
     }
   }
+}
+
+template <typename T, int M, bool PIN, bool POUT, int W = 1>
+__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_x(const T *__restrict__ in, T *__restrict__ out,
+                                                             int64_t nrows, const C2<T> *__restrict__ tw,
+                                                             const T *__restrict__ sp) {
+  using Sh = Shape<T, M, W>;
+  __shared__ C2<T> sbuf[Sh::NP * Sh::PADM];
+  dst_x_tile<T, M, PIN, POUT, W>(in, out, nrows, tw, sp, sbuf, blockIdx.x);
 }
 
 // Row predicates of the strided tile mover: every row; rows in a bit set read once from memory
@@ -728,30 +737,26 @@ struct ModeHook {
 // the bit sets zin / zout name the planes that may be nonzero on input (the others are not
 // read) and the planes needed on output (the others are not written); ZM = 2: every plane is
 // read, only the planes in zout are written.
+// One tile of the pass: tile number id of total (gx tiles per row of the grid of tiles), LDS
+// buffers sbuf (NP * PADM values), slam (M) and ssin (M / 2 + 1).
 template <typename T, int M, int NC, int DIM, int W = 1, int ZM = 0>
-__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__restrict__ ain, T *__restrict__ a,
-                                                                     int64_t P, int64_t comp_stride,
-                                                                  ModeScale ms0, const C2<T> *__restrict__ tw,
-                                                                  const T *__restrict__ sp,
-                                                                  const ModeScale *__restrict__ msv = nullptr,
-                                                                  int64_t pstride = 0, PlaneBits zin = {},
-                                                                  PlaneBits zout = {}) {
+__device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__restrict__ a, int64_t P,
+                                              int64_t comp_stride, const ModeScale &ms0,
+                                              const C2<T> *__restrict__ tw, const T *__restrict__ sp,
+                                              const ModeScale *__restrict__ msv, int64_t pstride,
+                                              const PlaneBits &zin, const PlaneBits &zout, C2<T> *sbuf, T *slam,
+                                              T *ssin, int64_t id, int64_t total, int gx) {
   using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
   constexpr int64_t LS = DIM == 3 ? (int64_t)N : 1;  // rows of the last axis step by LS * P
   using Tl = StridedTile<T, M, TX, NC, W>;
-  __shared__ C2<T> sbuf[NP * PADM];
-  __shared__ T slam[M];
-  __shared__ T ssin[M / 2 + 1];
   const int tid = threadIdx.x;
   // At W = 1 a tile row of TX columns is half of a 128-byte line; the tile sharing the line is
   // given to the workgroup dispatched 8 later, i.e. on the same XCD (round-robin dispatch), so
   // the second half of the line comes from that XCD's L2 instead of a second HBM fetch.
-  int64_t id = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
-  const int64_t total = (int64_t)gridDim.x * gridDim.y;
   if (id < (total & ~int64_t(15))) id = (id & ~int64_t(15)) + 2 * (id & 7) + ((id >> 3) & 1);
-  const int bx = (int)(id % gridDim.x), by = (int)(id / gridDim.x);
+  const int bx = (int)(id % gx), by = (int)(id / gx);
   const int x0 = bx * TX, y = DIM == 3 ? by : 0;
   const int64_t boff = DIM == 3 ? (int64_t)y * P : (int64_t)by * pstride;
   T *base = a + boff;
@@ -792,6 +797,23 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
   dst_pair<T, M>(mine, lane, tw, Sines<T, M>(ssin, lane), mh);
   if constexpr (ZM != 0) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
   else Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
+}
+
+template <typename T, int M, int NC, int DIM, int W = 1, int ZM = 0>
+__global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__restrict__ ain, T *__restrict__ a,
+                                                                     int64_t P, int64_t comp_stride,
+                                                                  ModeScale ms0, const C2<T> *__restrict__ tw,
+                                                                  const T *__restrict__ sp,
+                                                                  const ModeScale *__restrict__ msv = nullptr,
+                                                                  int64_t pstride = 0, PlaneBits zin = {},
+                                                                  PlaneBits zout = {}) {
+  using Sh = Shape<T, M, W>;
+  __shared__ C2<T> sbuf[Sh::NP * Sh::PADM];
+  __shared__ T slam[M];
+  __shared__ T ssin[M / 2 + 1];
+  dst_last_tile<T, M, NC, DIM, W, ZM>(ain, a, P, comp_stride, ms0, tw, sp, msv, pstride, zin, zout, sbuf, slam, ssin,
+                                      blockIdx.x + (int64_t)gridDim.x * blockIdx.y,
+                                      (int64_t)gridDim.x * gridDim.y, (int)gridDim.x);
 }
 
 // DST along contiguous rows listed in `rows` (indices into the flattened [comp][..] row list),
@@ -1333,6 +1355,102 @@ void run_box_group(int G, const T *src, T *dst, int64_t cs, const ModeParams *ms
   pass_x<T, M>(w[0], dst, false, dst, false, rows, tw, sp, st);
 }
 
+// ---------------------------------------------------------------- merged 2D group passes
+//
+// One launch per pass over several size groups: the workgroups of group k are the block range
+// [begin_k, begin_{k+1}) and run that group's tile at its own size M (a switch on the uniform
+// size).  The workgroup size BASE / 16 is the same at every M, and so is the LDS tile buffer
+// up to a few hundred bytes, so one shape serves all sizes.
+
+template <typename T>
+struct MultiX {
+  struct G {
+    const T *in;
+    T *out;
+    int64_t rows;
+    const C2<T> *tw;
+    const T *sp;
+    int M, begin;
+  } g[kMaxMultiGroups];
+  int ng;
+};
+
+template <typename T>
+struct MultiLast {
+  struct G {
+    T *a;
+    int64_t cs;
+    const ModeScale *msv;
+    const C2<T> *tw;
+    const T *sp;
+    int M, begin, gx, nprob;
+  } g[kMaxMultiGroups];
+  int ng;
+};
+
+// largest tile buffer over the sizes 64..1024 at width 1 (NP * PADM, in complex values)
+template <typename T>
+constexpr int multi_sbuf() {
+  return std::max({Shape<T, 64>::NP * Shape<T, 64>::PADM, Shape<T, 128>::NP * Shape<T, 128>::PADM,
+                   Shape<T, 256>::NP * Shape<T, 256>::PADM, Shape<T, 512>::NP * Shape<T, 512>::PADM,
+                   Shape<T, 1024>::NP * Shape<T, 1024>::PADM});
+}
+
+template <typename T, typename Mp>
+__device__ __forceinline__ int multi_group(const Mp &mp) {
+  int k = 0;
+#pragma unroll
+  for (int j = 1; j < kMaxMultiGroups; ++j)
+    if (j < mp.ng && (int)blockIdx.x >= mp.g[j].begin) k = j;
+  return k;
+}
+
+template <typename T>
+__global__ __launch_bounds__((Shape<T, 64>::NT)) void k_dst_x_multi(MultiX<T> mp) {
+  static_assert(Shape<T, 64>::NT == Shape<T, 1024>::NT, "one workgroup size for every M");
+  __shared__ C2<T> sbuf[multi_sbuf<T>()];
+  const int k = multi_group<T>(mp);
+  const auto &g = mp.g[k];
+  const int64_t b = (int64_t)blockIdx.x - g.begin;
+  switch (g.M) {
+    case 64: dst_x_tile<T, 64, true, true>(g.in, g.out, g.rows, g.tw, g.sp, sbuf, b); break;
+    case 128: dst_x_tile<T, 128, true, true>(g.in, g.out, g.rows, g.tw, g.sp, sbuf, b); break;
+    case 256: dst_x_tile<T, 256, true, true>(g.in, g.out, g.rows, g.tw, g.sp, sbuf, b); break;
+    case 512: dst_x_tile<T, 512, true, true>(g.in, g.out, g.rows, g.tw, g.sp, sbuf, b); break;
+    default: dst_x_tile<T, 1024, true, true>(g.in, g.out, g.rows, g.tw, g.sp, sbuf, b); break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__((Shape<T, 64>::NT)) void k_dst_last_multi(MultiLast<T> mp) {
+  __shared__ C2<T> sbuf[multi_sbuf<T>()];
+  __shared__ T slam[1024];
+  __shared__ T ssin[1024 / 2 + 1];
+  const int k = multi_group<T>(mp);
+  const auto &g = mp.g[k];
+  const int64_t b = (int64_t)blockIdx.x - g.begin, total = (int64_t)g.gx * g.nprob;
+  const ModeScale none{};
+  const PlaneBits nob{};
+  switch (g.M) {
+#define KFBI_MULTI_LAST(MM)                                                                                    \
+    case MM:                                                                                                   \
+      dst_last_tile<T, MM, 1, 2>(g.a, g.a, MM, g.cs, none, g.tw, g.sp, g.msv, g.cs, nob, nob, sbuf, slam, ssin, b, \
+                                 total, g.gx);                                                                 \
+      break;
+    KFBI_MULTI_LAST(64) KFBI_MULTI_LAST(128) KFBI_MULTI_LAST(256) KFBI_MULTI_LAST(512)
+    default:
+      dst_last_tile<T, 1024, 1, 2>(g.a, g.a, 1024, g.cs, none, g.tw, g.sp, g.msv, g.cs, nob, nob, sbuf, slam, ssin,
+                                   b, total, g.gx);
+      break;
+#undef KFBI_MULTI_LAST
+  }
+}
+
+template <typename T>
+int tile_rows(int M) {   // rows per x-pass tile at width 1
+  return 2 * ((sizeof(T) == 8 ? 2048 : 4096) / M);
+}
+
 // Timing data: a fixed pseudo-random pattern in [-0.5, 0.5) (all-zero data runs at a higher
 // clock than real data under the power limit, which would bias the choice).
 template <typename T>
@@ -1469,6 +1587,45 @@ void box_solve_group(int Mfft, int G, const T *src, T *dst, int64_t cs, const Mo
     default: throw std::invalid_argument("unsupported grid size");
   }
 }
+template <typename T>
+void box_solve_multi(const MultiGroupDesc *gd, int ng, hipStream_t st) {
+  if (ng < 1 || ng > kMaxMultiGroups) throw std::invalid_argument("merged passes take 1 to 8 groups");
+  // largest grids first: their long-running tiles start first, the small ones fill in after
+  int order[kMaxMultiGroups];
+  for (int k = 0; k < ng; ++k) order[k] = k;
+  std::sort(order, order + ng, [&](int a, int b) { return gd[a].Mfft > gd[b].Mfft; });
+  MultiX<T> x1{}, x2{};
+  MultiLast<T> la{};
+  int bx = 0, bl = 0;
+  for (int j = 0; j < ng; ++j) {
+    const MultiGroupDesc &d = gd[order[j]];
+    const int M = d.Mfft, N = M - 1;
+    if (M < 64 || M > 1024 || (M & (M - 1)) || d.G < 1 || d.cs != (int64_t)N * M)
+      throw std::invalid_argument("merged passes: sizes 64..1024, padded groups");
+    const int64_t rows = (int64_t)d.G * N;
+    const int tr = tile_rows<T>(M), np = tr / 2;
+    const C2<T> *tw = reinterpret_cast<const C2<T> *>(d.tw);
+    const T *sp = static_cast<const T *>(d.sp);
+    T *dst = static_cast<T *>(d.dst);
+    x1.g[j] = {static_cast<const T *>(d.src), dst, rows, tw, sp, M, bx};
+    x2.g[j] = {dst, dst, rows, tw, sp, M, bx};
+    bx += (int)((rows + tr - 1) / tr);
+    const int gx = (N + 2 * np - 1) / (2 * np);
+    la.g[j] = {dst, d.cs, d.msv, tw, sp, M, bl, gx, d.G};
+    bl += gx * d.G;
+  }
+  x1.ng = x2.ng = la.ng = ng;
+  constexpr int NT = Shape<T, 64>::NT;
+  k_dst_x_multi<T><<<bx, NT, 0, st>>>(x1);
+  KFBI_HIP(hipGetLastError());
+  k_dst_last_multi<T><<<bl, NT, 0, st>>>(la);
+  KFBI_HIP(hipGetLastError());
+  k_dst_x_multi<T><<<bx, NT, 0, st>>>(x2);
+  KFBI_HIP(hipGetLastError());
+}
+template void box_solve_multi<double>(const MultiGroupDesc *, int, hipStream_t);
+template void box_solve_multi<float>(const MultiGroupDesc *, int, hipStream_t);
+
 template void box_solve_group<double>(int, int, const double *, double *, int64_t, const ModeParams *,
                                       const double *, const double *, const int *, hipStream_t);
 template void box_solve_group<float>(int, int, const float *, float *, int64_t, const ModeParams *, const float *,

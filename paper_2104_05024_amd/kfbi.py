@@ -25,7 +25,7 @@ EXPORTED = [
     "bidomain_mlp_params", "bidomain_mlp_eval", "kfbi_strerror", "kfbi_last_error", "kfbi_kernel_time",
     "kfbi_batch_setup", "kfbi_batch_destroy", "kfbi_batch_query", "kfbi_batch_apply", "kfbi_batch_solve_neumann",
     "kfbi_batch_graph", "kfbi_get_tiles", "kfbi_set_tiles", "kfbi_use_graph", "bidomain_use_graph",
-    "kfbi_profile", "bidomain_reset", "kfbi_box_solve_noalloc", "bidomain_true_resid",
+    "kfbi_profile", "bidomain_reset", "kfbi_box_solve_noalloc", "bidomain_true_resid", "kfbi_batch_merge",
 ]
 
 
@@ -130,6 +130,7 @@ def lib():
     L.kfbi_batch_apply.argtypes = [vp, vp, vp, i32, vp]
     L.kfbi_batch_solve_neumann.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     L.kfbi_batch_graph.argtypes = [vp, i32]
+    L.kfbi_batch_merge.argtypes = [vp, i32]
     _lib = L
     return L
 
@@ -363,6 +364,10 @@ class Batch:
 
     def graph(self, enable=True):
         _check(lib().kfbi_batch_graph(self._h, 1 if enable else 0))
+
+    def merge(self, enable=True):
+        """One DST launch per pass over all size groups (default) or one per group and pass."""
+        _check(lib().kfbi_batch_merge(self._h, 1 if enable else 0))
 
     def apply(self, psi, out=None):
         """A psi for every problem; psi is a concatenated (L,) torch tensor (float64 / float32)."""

@@ -1,8 +1,9 @@
 """Batched 2D Neumann problems on the GPU: 64 seeded problems of grid sizes 64..1024 and
 star shapes with 3-8 lobes, one batch.  Parity against the FP64 oracle (element by element) on
 small problems and on a 512^2 and a 1024^2 member, against the single-problem GPU path on all,
-manufactured-solution accuracy on all, the mixed-precision batch against the FP64 batch, and the
-captured Arnoldi step against direct launches."""
+manufactured-solution accuracy on all, the mixed-precision batch against the FP64 batch, the
+captured Arnoldi step against direct launches, and the merged DST launches against one launch per
+size group."""
 import sys
 import time
 
@@ -159,13 +160,21 @@ def test_batch_solve_f64_parity_and_accuracy(batch):
         e = err(gseg(u, b, i)[o.inside], uo[0][o.inside])
         ep = err(seg(psi, b, i), psio[0])
         # both densities solve A psi = g' to their tolerances, so A maps their difference to at most
-        # the sum of the two residual bounds; element by element they can differ more at the finest
-        # grids, where a node-to-node oscillation of psi (node spacing about h) is nearly invisible to A
+        # the sum of the two residual bounds plus the difference of the two right-hand sides.  g' =
+        # g - dn u_V is formed with cancellation (|g - g'| / |g'| = cg, up to 8e4 at 1024^2 here) from
+        # a one-sided derivative (weights of order 1/h) of the box solution, so the two FP64 box
+        # solves' rounding reaches g' amplified by both: bounded here by 4 times the derivative
+        # that the extrapolation takes of the measured difference of the two solutions.  Element
+        # by element the densities can differ more at the finest grids, where a node-to-node
+        # oscillation of psi (node spacing about h) is nearly invisible to A.
         ea = np.linalg.norm(o.apply(seg(psi, b, i)[None] - psio)) / np.linalg.norm(gp)
+        cg = np.linalg.norm(gi[None] - gp) / np.linalg.norm(gp)
+        du = np.linalg.norm(o.extrapolate_smooth(gseg(u, b, i) - uo[0], co.D[0])) / np.linalg.norm(gp)
         say(f"    problem {i} (cells {grid.cells}): u err vs oracle {e:.2e}, psi err {ep:.2e}, "
-            f"|A (psi - psi_oracle)| / |g'| {ea:.2e}, iters {infos[i]['iters']} / {infoo['iters']}")
+            f"|A (psi - psi_oracle)| / |g'| {ea:.2e} (cancellation in g' {cg:.0f}, derivative of the u "
+            f"difference {du:.1e}), iters {infos[i]['iters']} / {infoo['iters']}")
         assert e < 1e-10
-        assert ea <= 1.2e-12
+        assert ea <= 1.2e-12 + 4.0 * du
         if grid.cells <= 512:
             assert ep < 1e-9
 
@@ -197,6 +206,30 @@ def test_batch_graph_replay_matches_direct_launches(batch):
     assert [x["iters"] for x in i1] == [x["iters"] for x in i2] == [x["iters"] for x in i3]
     assert torch.equal(u1, u2) and torch.equal(p1, p2)
     assert torch.equal(u1, u3) and torch.equal(p1, p3)
+
+
+def test_batch_merged_launches_match_grouped_launches(batch):
+    """Each DST pass as one launch over all size groups (the default) against one launch per
+    group and pass: the same arithmetic for every pencil, so identical products (FP64 and FP32)
+    and identical FP64 and mixed-precision solves."""
+    b, probs, f, g, _ = batch
+    rng = np.random.default_rng(17)
+    psi = rng.uniform(-1, 1, size=b.L)
+    out = {}
+    for merged in (True, False):
+        b.merge(merged)
+        a64 = b.apply(T(psi))
+        a32 = b.apply(torch.tensor(psi, dtype=torch.float32, device=DEV))
+        s64 = b.solve_neumann(T(g), T(f), tol=1e-10)
+        smx = b.solve_neumann(T(g), T(f), tol=1e-10, precision=1, inner_tol=1e-4)
+        out[merged] = (a64, a32, s64, smx)
+    b.merge(True)
+    (a64, a32, s64, smx), (b64, b32, t64, tmx) = out[True], out[False]
+    assert torch.equal(a64, b64) and torch.equal(a32, b32)
+    for x, y in ((s64, t64), (smx, tmx)):
+        assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1])
+        assert [i["iters"] for i in x[2]] == [i["iters"] for i in y[2]]
+    say(f"    merged == grouped: products and solves identical ({b.n} problems)")
 
 
 def test_batch_with_spline_boundaries_matches_single_problems():
