@@ -440,6 +440,7 @@ def main():
             "rows_in_out": [rows_in, rows_out],
             "hbm_frac_by_class": {k: round(algo_of[k] / (kt[ref][k][0] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                   for k in priced},
+            "traffic_by_class": {k: measured_traffic(k)[0] for k in priced},
             "algorithmic_bytes_per_launch_by_class": algo_of,
             "kernel_timing": f"HIP events on the solve stream over the {a.kernel_steps} steps after the timed window",
             "kernel_avg_us": {k: round(v[0], 2) for k, v in kt[ref].items()},
