@@ -59,8 +59,9 @@ struct Solver {
   // FP64 before: the computed residual of such a solve is then checked by an FP64 product of the
   // result (counted in certs), and the iteration continues from that residual if it misses.
   // a.r0: b - A x already known (no first product).  a.z0: first search direction of the first
-  // cycle (flexible GMRES: x += y_0 z0/|z0| + sum_{j>=1} y_j V_j).  On return r = b - A x (exact
-  // to rounding: from the Arnoldi relation when every product was FP64, else the FP64 product).
+  // cycle (flexible GMRES: x += y_0 z0/|z0| + sum_{j>=1} y_j V_j).  On return r = b - A x: from
+  // the Arnoldi relation (exact to rounding when every product was FP64; the FP32 operator's
+  // residual for a.prec = 1), or the FP64 certificate product of a relaxed solve.
   struct GmresArgs {
     int prec = 0;
     bool relax = false;

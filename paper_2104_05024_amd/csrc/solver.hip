@@ -521,10 +521,10 @@ int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool 
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
       jend = j + 1;
-      // after FP32 products the computed residual differs from the true one by the products'
-      // errors weighted with the solution's coefficients; converging it to a quarter of the
-      // tolerance leaves that gap room before the FP64 check
-      target = any32 ? 0.25 * tol_abs : tol_abs;
+      // relaxed solve: after FP32 products the computed residual differs from the true one by
+      // the products' errors weighted with the solution's coefficients; converging it to a
+      // quarter of the tolerance leaves that gap room before the FP64 certificate
+      target = any32 && a.relax ? 0.25 * tol_abs : tol_abs;
       if (std::fabs(g[j + 1]) <= target || s.its >= maxit) break;
       if (hn == 0.0) {
         breakdown = true;
@@ -545,9 +545,14 @@ int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool 
     KFBI_HIP(hipGetLastError());
     first_cycle = false;
     const bool converged = std::fabs(g[jend]) <= target && !breakdown;
-    if (converged && !any32) {
-      // exact products: the residual vector follows from the Arnoldi relation without a product,
-      //   b - A x = V_{j+1} (beta e_1 - Hbar y)
+    if (converged && !(any32 && a.relax)) {
+      // the residual vector follows from the Arnoldi relation without a product,
+      //   b - A x = V_{j+1} (beta e_1 - Hbar y):
+      // exact to rounding when every product was FP64; for an FP32-operator solve (the inner
+      // solve of iterative refinement) it is the residual of that operator, which the caller
+      // does not use: it takes the FP64 residual itself.  Checking it with an FP32 product
+      // instead would restart without end once the solution's norm makes the product's
+      // rounding exceed the tolerance (a large near-null component of the coupled pair).
       for (int i = 0; i <= jend; ++i) {
         double acc = i == 0 ? beta_cycle : 0.0;
         for (int k = 0; k < jend; ++k) acc -= Hc[(size_t)i * m + k] * y[k];
