@@ -18,7 +18,8 @@ Module map (each function cites the passage of the paper it restates):
 * ``kfbi``      -- density transfer, jump relations, right-hand-side
   correction (Sec. 5.3, eq. correct), quadratic extrapolation of limit values
   (Sec. 5.4, eqs. taylor-*, ji, je), the BIE operator and right-hand side
-  (Sec. 4, eq. bie; Algorithm 1), the Neumann solve.
+  (Sec. 4, eq. bie; Algorithm 1), the Neumann solve, the coupled pair's null
+  density (its removal before the potentials are reconstructed is a reading).
 * ``gmres``     -- restarted GMRES with Givens rotations and the simple
   (Richardson) iteration (Sec. 4, eq. simple iteration).
 * ``bidomain``  -- FitzHugh-Nagumo reaction steps, Strang splitting and the

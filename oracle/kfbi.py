@@ -34,6 +34,15 @@ The pieces, in the order of Algorithm 1:
 * BIE operator A psi = n.D grad u+ and right-hand side
   g' = g^N - n.D grad u_V+ with u_V the uncorrected box solve of the
   smoothly extended source (Sec. 4, eq. bie; Sec. 5.1, eq. volume).
+* the coupled pair's null density (reading, not in the paper): the insulated
+  tissue (Sec. 2, eq. bdry cond) fixes both potentials only up to one common
+  constant, so the BIE operator of the coupled pair is singular, its null space
+  spanned by the density whose single-layer potential is a constant pair in
+  Omega.  The potentials are reconstructed from the density with that component
+  removed: in Omega this changes them by a constant pair, which the gauge takes
+  away, while outside Omega, where the transmembrane potential is also evolved
+  (Sec. 5.1), it removes a field that the discrete operator's near-zero
+  eigenvalue would otherwise make large and step-dependent.
 """
 from __future__ import annotations
 
@@ -387,8 +396,39 @@ class Problem:
                        for c in range(self.coeffs.ncomp)])
         return gp, uV
 
+    def null_density(self, tol=1e-12, max_iter=6):
+        """Coupled pair only: the unit density spanning the (discrete) null space of A, the
+        eigenvector of smallest |eigenvalue|, by inverse iteration from the constant density
+        (each step one GMRES solve to tol); stops when successive iterates agree to 1e-10 up to
+        sign.  Cached."""
+        if self.coeffs.ncomp != 2:
+            raise ValueError("the null density belongs to the coupled pair")
+        if getattr(self, "_null", None) is None:
+            x = np.ones(2 * self.M) / math.sqrt(2 * self.M)
+            for _ in range(max_iter):
+                y, _ = gmres(lambda v: self.apply(v).ravel(), x, np.zeros_like(x), tol, 50, 500)
+                y = y / np.linalg.norm(y)
+                if np.dot(y, x) < 0:
+                    y = -y
+                done = np.linalg.norm(y - x) < 1e-10
+                x = y
+                if done:
+                    break
+            self._null = x.reshape(2, self.M)
+        return self._null
+
+    def remove_null(self, psi):
+        """psi minus its component along the null density (coupled pair; unchanged otherwise)."""
+        psi = np.asarray(psi, dtype=np.float64).reshape(self.coeffs.ncomp, self.M)
+        if self.coeffs.ncomp != 2:
+            return psi
+        z = self.null_density()
+        return psi - np.sum(z * psi) * z
+
     def reconstruct(self, f, psi):
-        """u = box solve of (f + C psi); the coupled pair is gauged to mean_Omega(Phi_e) = 0."""
+        """u = box solve of (f + C psi); the coupled pair's density without its null component,
+        and the pair gauged to mean_Omega(Phi_e) = 0."""
+        psi = self.remove_null(psi)
         rhs = np.asarray(f, dtype=np.float64).reshape(self.coeffs.ncomp, -1) + self.correction_from_density(psi)
         u = boxsolve.box_solve(rhs, self.grid, self.coeffs)
         if self.coeffs.ncomp == 2:

@@ -54,7 +54,8 @@ struct Solver {
 
   double dot(const double *a, const double *b, hipStream_t st);
   double residual_norm(const double *b, const double *Ax, hipStream_t st);   // ||b - Ax||_2 (uses d)
-  // GMRES(m) with FP64 Arnoldi (CGS2) and Givens rotations on A x = b (stops at ||b - A x|| <= tol_abs).
+  // GMRES(m) with FP64 Arnoldi (CGS2) and Givens rotations on A x = b (stops at ||b - A x|| <= tol_abs);
+  // the update is added to x, so x_zero (r = b without a product) requires x to hold zeros.
   // Products in precision a.prec, or with a.relax FP32 once the current residual is <= a.sw_abs and
   // FP64 before: the computed residual of such a solve is then checked by an FP64 product of the
   // result (counted in certs), and the iteration continues from that residual if it misses.
@@ -89,7 +90,19 @@ struct Solver {
                     hipStream_t st, const double *r0 = nullptr, const int *r0_bad = nullptr,
                     const double *z0 = nullptr);
   const double *last_resid = nullptr;
-  // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added)
+  // The coupled pair's null density (insulated tissue: both potentials fixed up to one common
+  // constant, so the BIE operator of the pair is singular): the unit eigenvector of A of smallest
+  // |eigenvalue|, found once by inverse iteration (null_init, FP64 GMRES solves; it uses the
+  // Krylov workspace, so it runs before a solve forms any of its vectors).  The potentials are
+  // reconstructed from the density without its component along it: in Omega that changes them
+  // by a constant pair (which the gauge removes); outside Omega, where V is evolved too, it
+  // removes the field of a component that the near-zero eigenvalue makes large and
+  // step-dependent, and that would otherwise feed back through the extended source.
+  double *nullz = nullptr, *nully = nullptr, *nullp = nullptr, *nullc = nullptr;
+  bool null_ready = false;
+  void null_init(DevProblem &p, hipStream_t st);
+  // u = S(fpad + C psi) into the padded work buffer (fpad gets the correction added); for the
+  // coupled pair psi without its null component (null_init must have run)
   // fa: bidomain step (source from V); fuse_be: the inverse x pass also finishes the step
   // (midpoint update and backward Euler half step), leaving no potentials in work
   void reconstruct(DevProblem &p, const double *psi, hipStream_t st, const FhnArgs *fa = nullptr,

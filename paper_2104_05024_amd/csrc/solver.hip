@@ -161,6 +161,19 @@ __global__ __launch_bounds__(kB) void k_axpby(double *__restrict__ z, double a, 
   z[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }
 
+__global__ __launch_bounds__(kB) void k_fill(double *__restrict__ z, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) z[i] = v;
+}
+
+// out = psi - c z with the coefficient c = <z, psi> read from device memory
+__global__ __launch_bounds__(kB) void k_remove_along(double *__restrict__ out, const double *__restrict__ psi,
+                                                     const double *__restrict__ z, const double *__restrict__ c,
+                                                     int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) out[i] = psi[i] - c[0] * z[i];
+}
+
 // Starting residual of psi^{n-1} without a product: (g'^n - g'^{n-1}) + (g'^{n-1} - A psi^{n-1}).
 // It holds only if the caller's psi^{n-1} (hist1) is still the density the previous solve
 // returned (psi_last, the context's own copy): any node that differs sets *bad.
@@ -275,6 +288,13 @@ void Solver::init(DevProblem &p) {
   vin = dalloc<double>(L);
   wv = dalloc<double>(L);
   zbuf = dalloc<double>(L);
+  if (p.ncomp == 2) {
+    nullz = dalloc<double>(L);
+    nully = dalloc<double>(L);
+    nullp = dalloc<double>(L);
+    nullc = dalloc<double>(1);
+  }
+  null_ready = false;
   jdev = dalloc<int>(1);
   KFBI_HIP(hipHostMalloc(&jhost, sizeof(int), hipHostMallocDefault));
   seqdev = dalloc<int>(1);
@@ -305,7 +325,8 @@ void Solver::release() {
   if (seqhost) (void)hipHostFree(seqhost);
   seqdev = nullptr;
   seqhost = nullptr;
-  double **dp[] = {&V, &r, &w, &t, &gp, &d, &fpad, &partials, &npart, &hdev, &ydev, &vin, &wv, &zbuf};
+  double **dp[] = {&V,    &r,    &w,  &t,   &gp,    &d,     &fpad,  &partials, &npart,
+                   &hdev, &ydev, &vin, &wv, &zbuf, &nullz, &nully, &nullp, &nullc};
   for (double **q : dp) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -691,7 +712,39 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
   return rc;
 }
 
+void Solver::null_init(DevProblem &p, hipStream_t st) {
+  if (p.ncomp != 2 || null_ready) return;
+  // inverse iteration from the constant density: z <- A^{-1} z / |A^{-1} z|, each step one FP64
+  // GMRES solve to 1e-12, until successive unit iterates agree to 1e-10 up to sign
+  k_fill<<<nblk(L), kB, 0, st>>>(nullz, 1.0 / std::sqrt((double)L), L);
+  KFBI_HIP(hipGetLastError());
+  GmresArgs a;
+  for (int it = 0; it < 6; ++it) {
+    GmresStats gs;
+    k_fill<<<nblk(L), kB, 0, st>>>(nully, 0.0, L);   // gmres adds its update to x
+    (void)gmres(p, nullz, 1.0, nully, true, 1e-12, 50, 500, a, gs, st);
+    const double ny = std::sqrt(dot(nully, nully, st));
+    if (!(ny > 0)) break;
+    const double sc = dot(nully, nullz, st) < 0 ? -1.0 / ny : 1.0 / ny;
+    k_axpby<<<nblk(L), kB, 0, st>>>(nullp, sc, nully, -1.0, nullz, L);
+    const double dn = std::sqrt(dot(nullp, nullp, st));
+    k_axpby<<<nblk(L), kB, 0, st>>>(nullz, sc, nully, 0.0, nullptr, L);
+    KFBI_HIP(hipGetLastError());
+    if (dn < 1e-10) break;
+  }
+  null_ready = true;
+}
+
 void Solver::reconstruct(DevProblem &p, const double *psi, hipStream_t st, const FhnArgs *fa, bool fuse_be) {
+  if (p.ncomp == 2) {
+    // the coupled pair: the density without its component along the null density
+    if (!null_ready) throw std::logic_error("reconstruct: null density not initialised");
+    k_multidot<<<dim3(nb, 1), kB, 0, st>>>(nullz, L, psi, L, partials);
+    k_finish<<<1, kB, 0, st>>>(partials, nb, nullc);
+    k_remove_along<<<nblk(L), kB, 0, st>>>(nullp, psi, nullz, nullc, L);
+    KFBI_HIP(hipGetLastError());
+    psi = nullp;
+  }
   launch_jumps<double>(p, psi, st);
   if (fa) {
     launch_correct<double>(p, st);
@@ -726,6 +779,7 @@ __global__ __launch_bounds__(kB) void k_from_padded(const double *__restrict__ f
 int Solver::solve_neumann(DevProblem &p, const double *g, const double *f, double *u, double *psi,
                           const kfbi_solve_opts &o, kfbi_solve_info &info, hipStream_t st) {
   if (o.restart < 1 || o.max_iters < 0 || !(o.tol > 0)) throw std::invalid_argument("solve options");
+  null_init(p, st);
   const int64_t nplain = (int64_t)p.ht.inside.size();
   k_to_padded<<<nblk(nplain * p.ncomp), kB, 0, st>>>(f, fpad, nplain, p.N, p.P, p.comp_stride, p.ncomp);
   KFBI_HIP(hipGetLastError());
@@ -872,6 +926,7 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
   // on the device, only if its newest density is still the one that step returned)
   const bool prev_ok = have_prev && s.psi_hist == hist_last;
   have_prev = false;   // set again when this step completes
+  sv.null_init(p, st);   // once: before any of the step's vectors are formed
   sv.bie_rhs(p, nullptr, st, &fa);
   double *hist1 = s.psi_hist, *hist2 = s.psi_hist + L;
   kfbi_solve_opts o = params.solve;

@@ -3,7 +3,7 @@ D_i = diag(30, 5[, 5]), D_e = diag(20, 10[, 10]), C_m = 1, beta = 1000, dt = h, 
 electrode, FitzHugh-Nagumo with theta = 0.25.
 
 * Example 1 (2D circle given by spline nodes): oracle parity of the first steps, second-order
-  convergence of V in space and time together (dt = h) over 64^2 .. 512^2, and the
+  convergence of V in space and time together (dt = h) over 64^2 .. 1024^2, and the
   GMRES iterations per step (the paper reports 7-10 at relative tolerance 1e-8).
 * Example 3 (3D sphere): GMRES iterations per step beside the simple (Richardson) iteration with
   gamma = 0.8 (the paper: 18-21 iterations), with the virtual electrode and with a stimulus ball.
@@ -95,33 +95,38 @@ def test_example1_circle_matches_oracle():
 
 
 def test_example1_circle_second_order_and_gmres_iterations():
-    """V at t = 0.5, 1 and 2 on 64^2 .. 512^2: the differences of consecutive grids at the coarser
-    grid's tissue nodes (scaled l2 and max norm, the norms of the paper's tables) fall at second order
-    (dt = h, so space and time together); GMRES iterations per step at tolerance 1e-8 stay near the
-    paper's 7-10 and do not grow with refinement.  (On 1024^2 this set-up is unstable in the oracle
-    and on the GPU alike: the density grows about 1.7-fold per step from rest.)"""
+    """V at t = 0.5, 1 and 2 on 64^2 .. 1024^2 (the sizes of the paper's Tables 1-4): the
+    differences of consecutive grids at the coarser grid's tissue nodes (scaled l2 and max norm,
+    the norms of the paper's tables) fall at second order (dt = h, so space and time together);
+    V stays bounded at every size; GMRES iterations per step at tolerance 1e-8 stay near the
+    paper's 7-10 and do not grow with refinement.  (Before the coupled pair's null density was
+    removed from the reconstruction, 1024^2 blew up within 16 steps in the oracle and on the GPU
+    alike: the null component's exterior field fed back through the extended source.)"""
     times = (0.5, 1.0, 2.0)
+    sizes = (64, 128, 256, 512, 1024)
     runs = {}
-    for cells in (64, 128, 256, 512):
+    for cells in sizes:
         snaps, infos, wall, grid, inside = run(W.paper_circle_example, cells, 2.0, times=times)
         assert all(i["rel_resid"] <= 1e-8 for i in infos)
         its = float(np.mean([i["iters"] for i in infos]))
         runs[cells] = (snaps, inside, its)
+        vmax = max(float(np.max(np.abs(v))) for v in snaps.values())
         say(f"[example 1] {cells}^2: {len(infos)} steps in {wall:.2f} s, GMRES {its:.2f} per step, "
-            f"max V at t=2 {snaps[2.0].max():.3f}")
+            f"max V at t=2 {snaps[2.0].max():.3f}, max |V| {vmax:.3f}")
+        assert vmax < 1.2
     for t in times:
         d = []
-        for c in (64, 128, 256):
+        for c in sizes[:-1]:
             idx = np.arange(1, c) * 2 - 1
             e = (runs[c][0][t].reshape(c - 1, c - 1) - runs[2 * c][0][t].reshape(2 * c - 1, 2 * c - 1)[np.ix_(idx, idx)]).ravel()
             e = e[runs[c][1]]
             d.append((float(np.sqrt(np.mean(e * e))), float(np.max(np.abs(e)))))
-        o2 = [np.log2(d[i][0] / d[i + 1][0]) for i in range(2)]
-        oi = [np.log2(d[i][1] / d[i + 1][1]) for i in range(2)]
+        o2 = [np.log2(d[i][0] / d[i + 1][0]) for i in range(len(d) - 1)]
+        oi = [np.log2(d[i][1] / d[i + 1][1]) for i in range(len(d) - 1)]
         say(f"[example 1] t={t}: differences l2 {[f'{x[0]:.3e}' for x in d]} (orders {[f'{o:.2f}' for o in o2]}), "
             f"max {[f'{x[1]:.3e}' for x in d]} (orders {[f'{o:.2f}' for o in oi]})")
-        assert o2[-1] > 1.7 and np.mean(o2) > 1.7
-    its = [runs[c][2] for c in (64, 128, 256, 512)]
+        assert min(o2[-2:]) > 1.7 and np.mean(o2) > 1.7
+    its = [runs[c][2] for c in sizes]
     assert max(its) <= 16 and its[-1] <= its[0] + 3
 
 

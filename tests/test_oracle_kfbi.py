@@ -439,3 +439,43 @@ def test_neumann_mms_anisotropic_3d():
         e = np.abs(u[0] - ue(pts))[P.inside]
         errs.append(np.sqrt(np.mean(e * e)))
     assert math.log2(errs[0] / errs[1]) > 1.8, errs
+
+
+def test_null_density_is_the_common_constant_mode():
+    """The coupled pair's null density (reading: the insulated tissue fixes both potentials up to
+    one common constant, Sec. 2; the BIE operator of the pair is therefore singular, Sec. 4).
+    Pinned against its definition: its single-layer potential is one and the same constant in
+    both components on the tissue (to the discretisation), A maps it to almost nothing while a
+    random density's Rayleigh quotient sits in the bulk of the second-kind spectrum near 1/2,
+    the near-zero eigenvalue shrinks under refinement, and adding any multiple of it to a density
+    leaves the reconstructed potentials unchanged everywhere."""
+    lams = []
+    for cells in (64, 128):
+        iface, grid, co = W.paper_circle_example(cells)[:3]
+        o = kfbi.Problem(iface, grid, co)
+        z = o.null_density()
+        assert abs(np.linalg.norm(z) - 1.0) < 1e-12
+        lam = float(np.sum(z * o.apply(z)))
+        lams.append(abs(lam))
+        rng = np.random.default_rng(cells)
+        r = rng.normal(size=(2, o.M))
+        r /= np.linalg.norm(r)
+        assert np.sum(r * o.apply(r)) > 0.1
+        u = boxsolve.box_solve(o.correction_from_density(z), grid, co)
+        m = u[:, o.inside].mean(axis=1)
+        assert np.min(np.abs(m)) > 0
+        assert abs(m[0] - m[1]) <= 1e-5 * np.max(np.abs(m))
+        assert np.max(np.abs(u[:, o.inside] - m[:, None])) <= 2e-2 * np.max(np.abs(m))
+        psi = rng.normal(size=(2, o.M))
+        f = rng.normal(size=(2, grid.n ** 2))
+        u1, u2 = o.reconstruct(f, psi), o.reconstruct(f, psi + 37.0 * z)
+        assert np.max(np.abs(u1 - u2)) <= 1e-12 * np.max(np.abs(u1))
+        assert np.max(np.abs(o.remove_null(z))) < 1e-14
+    assert lams[0] < 1e-3 and lams[1] < lams[0] / 2
+
+
+def test_remove_null_leaves_one_component_problems_alone():
+    iface, grid, co = W.config("star2d_128")
+    o = kfbi.Problem(iface, W.box(2, 32), co)
+    psi = np.random.default_rng(3).normal(size=(1, o.M))
+    assert np.array_equal(o.remove_null(psi), psi)
