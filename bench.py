@@ -210,8 +210,8 @@ def batch_run(torch, warmup=1, reps=5, singles=True):
 def paper_examples(torch):
     """The paper's own regime (anisotropic D_i = diag(30, 5[, 5]), D_e = diag(20, 10[, 10]), beta = 1000,
     dt = h, virtual electrode): GMRES iterations per step and steps/s for Example 1 (circle, 256^2,
-    128 steps) and Example 3 (sphere, 128^3, 32 steps), and for the sphere the residual the simple
-    iteration (gamma = 0.8) reaches in 25 and 100 iterations."""
+    128 steps) and Example 3 (sphere, 128^3, 32 steps), for the sphere also the simple iteration
+    (gamma = 0.8; the coupled pair's residual measured without its null-density component)."""
     import numpy as np
 
     from paper_2104_05024_amd import kfbi as K
@@ -227,7 +227,7 @@ def paper_examples(torch):
         res = {"cells": cells, "interface_nodes": prob.M, "steps": steps, "dt": dt}
         runs = [("gmres", dict(), steps, False)]
         if grid.dim == 3:
-            runs += [(f"simple_iteration_{mi}", dict(method=1, gamma=0.8, max_iters=mi), 3, True) for mi in (25, 100)]
+            runs += [("simple_iteration", dict(method=1, gamma=0.8, max_iters=500), steps, False)]
         for tag, kw, ns, noconv in runs:
             bd = K.Bidomain(prob, p, tol=1e-8, **kw)
             V = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -244,7 +244,9 @@ def paper_examples(torch):
                            steps_per_s=round((ns - 1) / el, 1), max_rel_resid=max(i["rel_resid"] for i in infos),
                            V_max=round(float(V.max().item()), 4))
             else:
-                res[f"{tag}_rel_resid"] = float(f"{max(i['rel_resid'] for i in infos):.3e}")
+                res.update(simple_iteration_iters_per_step=round(float(np.mean([i["iters"] for i in infos])), 2),
+                           simple_iteration_steps_per_s=round((ns - 1) / el, 1),
+                           simple_iteration_max_rel_resid=max(i["rel_resid"] for i in infos))
             bd.close()
         prob.close()
         out[key] = res

@@ -178,7 +178,10 @@ typedef struct {
   double inner_tol;     /* precision = 1: relative tolerance of each FP32 inner solve;
                            precision = 2: relative residual below which the products are FP32 */
   int32_t max_outer;    /* precision = 1: maximum FP64 refinement steps */
-  int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4) */
+  int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4); for the coupled
+                           pair its residual and ||g'|| are measured without their component
+                           along the null density (the part of g' no density can match; the
+                           iterates are the paper's) */
   double gamma;         /* Richardson parameter, gamma in (0,1) */
   int32_t true_resid;   /* 1: after the solve form g' - A64 psi with an explicit FP64 product and
                            report its relative norm in info.true_resid (a check: one product more) */
@@ -196,14 +199,18 @@ typedef struct {
                                taken; bit 1: the learned search direction (4) was used */
   int32_t pad_;
   double start_resid;       /* ||g' - A64 psi0|| / ||g'|| of the start density (1 for a zero start) */
-  double true_resid;        /* opts.true_resid = 1: ||g' - A64 psi|| / ||g'|| by an explicit product,
-                               else -1 */
+  double true_resid;        /* opts.true_resid = 1: ||g' - A64 psi|| / ||g'|| by an explicit product
+                               (measured as the solve measures it), else -1 */
 } kfbi_solve_info;
 
 /* kfbi_solve_neumann: solve the Neumann problem above (Algorithm 1 with GMRES):
  *   u_V = box solve of f (f extended over the whole box; Sec. 5.1), g' = g - n.D grad u_V+,
  *   A psi = g' by GMRES (FP64, or FP32-inner with FP64 refinement), u = box solve of f + C psi.
- * For ncomp = 2 the pair is returned in the gauge mean_{Omega nodes}(u_2) = 0.
+ * For ncomp = 2 the pair is returned in the gauge mean_{Omega nodes}(u_2) = 0, reconstructed
+ * from the density without its component along the null density: the insulated tissue fixes
+ * both potentials only up to one common constant, so A is singular for the pair; its discrete
+ * null vector (the eigenvector of smallest |eigenvalue|) is found once, by inverse iteration, at
+ * the first coupled solve or bidomain step.  psi is returned as the solver found it.
  * g: device f64 [ncomp][M] (NULL = homogeneous); f, u: device f64 [ncomp][N^d];
  * psi_inout: device f64 [ncomp][M], initial guess if opts->x0 = 1, solution on return.
  * info may be NULL. Returns KFBI_ENOCONV (outputs filled) if max_iters is hit. */

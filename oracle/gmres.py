@@ -5,7 +5,8 @@
   of Sec. 4).  Convergence is ||g - A psi||_2 <= tol ||g||_2, judged by the
   Givens residual inside a cycle and by the true residual at each restart.
 * ``richardson``: the simple iteration psi <- psi + 2 gamma (g - A psi)
-  (Sec. 4, eq. simple iteration; Algorithm 1).
+  (Sec. 4, eq. simple iteration; Algorithm 1); for a singular operator (the coupled
+  pair) its residual may be measured without the null direction (a reading).
 """
 from __future__ import annotations
 
@@ -69,17 +70,27 @@ def gmres(matvec, b, x0, tol=1e-10, restart=50, maxit=500):
     return x, info
 
 
-def richardson(matvec, b, x0, gamma=0.8, tol=1e-8, maxit=500):
+def richardson(matvec, b, x0, gamma=0.8, tol=1e-8, maxit=500, null=None):
+    """The simple iteration.  null (unit vector, optional): the operator's null direction; the
+    residual and the right-hand side are then measured without their component along it (the
+    part of b no x can match when the operator is singular up to the discretisation), while the
+    iterates are unchanged."""
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
-    bnorm = np.linalg.norm(b)
+
+    def norm(v):
+        if null is None:
+            return np.linalg.norm(v)
+        return np.linalg.norm(v - np.dot(null, v) * null)
+
+    bnorm = norm(b)
     info = {"iters": 0, "matvecs": 0, "rel_resid": 0.0}
     if bnorm == 0.0:
         return np.zeros_like(b), info
     for it in range(maxit + 1):
         r = b - matvec(x)
         info["matvecs"] += 1
-        rel = np.linalg.norm(r) / bnorm
+        rel = norm(r) / bnorm
         info["rel_resid"] = rel
         if rel <= tol or it == maxit:
             break

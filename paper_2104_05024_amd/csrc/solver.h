@@ -75,8 +75,11 @@ struct Solver {
   };
   int gmres(DevProblem &p, const double *b, double bnorm, double *x, bool x_zero, double tol_abs, int restart,
             int maxit, const GmresArgs &a, GmresStats &s, hipStream_t st);
+  // the simple iteration; nz (unit, optional): residuals measured without their component along it
   int richardson(DevProblem &p, const double *b, double bnorm, double *x, double gamma, double tol_abs, int maxit,
-                 int &its, int &matvecs, double &resid, hipStream_t st, double *r0 = nullptr);
+                 int &its, int &matvecs, double &resid, hipStream_t st, double *r0 = nullptr,
+                 const double *nz = nullptr);
+  double norm_without(const double *v, const double *nz, hipStream_t st);
   // g' = g - n.D grad (S f)+, with f already in fpad (padded). g may be null.
   // fa: bidomain step (source from V after the forward Euler half step it performs; fpad unused)
   void bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnArgs *fa = nullptr);

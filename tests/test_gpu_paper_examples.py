@@ -5,8 +5,8 @@ electrode, FitzHugh-Nagumo with theta = 0.25.
 * Example 1 (2D circle given by spline nodes): oracle parity of the first steps, second-order
   convergence of V in space and time together (dt = h) over 64^2 .. 1024^2, and the
   GMRES iterations per step (the paper reports 7-10 at relative tolerance 1e-8).
-* Example 3 (3D sphere): GMRES iterations per step beside the simple (Richardson) iteration with
-  gamma = 0.8 (the paper: 18-21 iterations), with the virtual electrode and with a stimulus ball.
+* Example 3 (3D sphere): GMRES beside the simple (Richardson) iteration with gamma = 0.8 (the
+  paper: 18-21 iterations), with the virtual electrode and with a stimulus ball.
 
 The radius of the circle and sphere and the box are not stated in the paper; the readings are
 those of workloads.paper_circle_example / paper_sphere_example, so the paper's error values are
@@ -131,29 +131,27 @@ def test_example1_circle_second_order_and_gmres_iterations():
 
 
 def test_example3_sphere_gmres_and_the_simple_iteration():
-    """Example 3 on the sphere at 64^3 and 128^3 (dt = h), tolerance 1e-8, from the virtual electrode
-    and from a stimulus ball (no stimulus current).  GMRES converges every step in about 20
-    iterations (the paper's simple iteration: 19 at 64^3, 21 at 128^3).  The simple iteration with
-    gamma = 0.8 does not converge on this discretisation: the coupled pure-Neumann operator is
-    singular (both potentials shifted by one constant), its discrete counterpart has an eigenvalue
-    just below zero on that mode (|1 - 2 gamma lambda| > 1), and the iteration stops at the residual
-    the right-hand side leaves on it, reached within 25 iterations and growing slowly after that.
-    That floor is set by the discretisation: it falls under refinement."""
-    floors = {}
+    """Example 3 on the sphere at 64^3 and 128^3 (dt = h) to t = 0.25, tolerance 1e-8, from the
+    virtual electrode and from a stimulus ball (no stimulus current).  GMRES and the simple
+    iteration (gamma = 0.8) both converge every step and give the same V; iterations per step are
+    reported beside the paper's (the simple iteration: 19 at 64^3, 21 at 128^3).  The coupled
+    pair's operator is singular up to the discretisation (one eigenvalue near zero, along the null
+    density), so the simple iteration's residual is measured without its component along the null
+    density: measured in full it stalls at the part of g' that no density can match (8e-3 at 64^3,
+    5e-4 at 128^3 from the electrode), reached within 25 iterations."""
     for cells in (64, 128):
         for ball in (False, True):
             tag = "ball" if ball else "electrode"
-            _, ig, wg, _, _ = run(W.paper_sphere_example, cells, 0.25, ball=ball)
-            its = float(np.mean([i["iters"] for i in ig]))
-            assert all(i["rel_resid"] <= 1e-8 for i in ig) and its <= 40
-            f = []
-            for mi in (25, 100):
-                _, ir, wr, _, _ = run(W.paper_sphere_example, cells, 3 * (2.0 / cells), ball=ball, method=1,
-                                      gamma=0.8, max_iters=mi, allow_noconv=True)
-                f.append(max(i["rel_resid"] for i in ir))
-            floors[cells, ball] = f[0]
-            say(f"[example 3, {tag}] {cells}^3: GMRES {its:.2f} iterations per step ({len(ig) / wg:.1f} steps/s); "
-                f"simple iteration residual {f[0]:.2e} after 25 iterations, {f[1]:.2e} after 100")
-            assert 0.5 * f[0] <= f[1] <= 2.0 * f[0] and f[0] < 0.05
-    for ball in (False, True):
-        assert floors[128, ball] < floors[64, ball] / 3
+            sg, ig, wg, _, inside = run(W.paper_sphere_example, cells, 0.25, times=(0.25,), ball=ball)
+            sr, ir, wr, _, _ = run(W.paper_sphere_example, cells, 0.25, times=(0.25,), ball=ball, method=1,
+                                   gamma=0.8, max_iters=500)
+            assert all(i["rel_resid"] <= 1e-8 for i in ig + ir)
+            its_g = float(np.mean([i["iters"] for i in ig]))
+            its_r = float(np.mean([i["iters"] for i in ir]))
+            d = np.max(np.abs(sr[0.25] - sg[0.25])) / np.max(np.abs(sg[0.25]))
+            di = np.max(np.abs(sr[0.25] - sg[0.25])[inside]) / np.max(np.abs(sg[0.25]))
+            say(f"[example 3, {tag}] {cells}^3, {len(ig)} steps: GMRES {its_g:.2f} iterations per step "
+                f"({len(ig) / wg:.1f} steps/s), simple iteration {its_r:.2f} ({len(ir) / wr:.1f} steps/s); "
+                f"V difference {d:.1e} (tissue {di:.1e})")
+            assert its_g <= 40 and its_r <= 120
+            assert d < 1e-5

@@ -261,3 +261,28 @@ def test_change_fields_and_prediction_roundtrip():
     np.testing.assert_allclose(mlp.predict_density(y, psi1, sd), 2 * psi1 - psi2, atol=1e-13)
     t = mlp.target(psi, psi1, sd)
     np.testing.assert_allclose(mlp.predict_density(t, psi1, sd), psi, atol=1e-13)
+
+
+def test_richardson_measured_without_the_null_direction():
+    """A symmetric operator with one eigenvalue just below zero and the rest in [0.3, 0.9], and a
+    right-hand side with a component along that eigenvector: the simple iteration's residual
+    stalls at that component (its iterates cannot remove it), while the residual measured
+    without the null direction converges at the rate of the remaining spectrum; the iterates
+    are the same in both."""
+    rng = np.random.default_rng(11)
+    n = 60
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    lam = np.concatenate([[-1e-6], rng.uniform(0.3, 0.9, n - 1)])
+    A = (Q * lam) @ Q.T
+    b = rng.normal(size=n)
+    z = Q[:, 0]
+    x1, i1 = gmres.richardson(lambda v: A @ v, b, np.zeros(n), 0.8, 1e-10, 200)
+    x2, i2 = gmres.richardson(lambda v: A @ v, b, np.zeros(n), 0.8, 1e-10, 200, null=z)
+    assert i1["iters"] == 200 and i1["rel_resid"] > 0.05
+    assert i2["rel_resid"] <= 1e-10 and i2["iters"] < 60
+    # the same iterates: the null-measured run is the plain run stopped earlier
+    x3, _ = gmres.richardson(lambda v: A @ v, b, np.zeros(n), 0.8, 0.0, i2["iters"])
+    np.testing.assert_array_equal(x2, x3)
+    # what it converged to solves the system without the null component, up to that component
+    r = b - A @ x2
+    assert np.linalg.norm(r - np.dot(z, r) * z) <= 1e-10 * np.linalg.norm(b - np.dot(z, b) * z)
