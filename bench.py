@@ -18,8 +18,8 @@ Neumann solve, reaction) with all inputs resident in HBM.
 
 Variants: plain (FP64, GMRES from psi^{n-1}); mixed (one GMRES whose products turn FP32 once
 the residual allows, with an FP64 product certifying the result); learned (the value: start
-from the least-residual combination of the last 8 solutions, the trained network's prediction
-as the first search direction, mixed precision as in mixed); projected and projected_mixed (the
+from the least-residual combination of the last 8 solutions, one minimal-residual step along the
+trained network's predicted correction, mixed precision as in mixed); projected and projected_mixed (the
 learned variant without the network, in FP64 and mixed precision); mixed_ir (FP32 inner GMRES
 with FP64 iterative refinement); richardson (the simple iteration, gamma = 0.8, FP64).  Every
 solve ends at the same FP64 relative residual bound.
@@ -388,7 +388,8 @@ def main():
             "max_true_rel_resid": max(i["true_resid"] for i in checks) if checks else None,
             "mean_start_resid": float(np.mean([i["start_resid"] for i in infos])),
             "start_used": int(sum(i["warm_start_used"] & 1 for i in infos)),
-            "learned_direction_used": int(sum((i["warm_start_used"] >> 1) & 1 for i in infos)),
+            "learned_step_tried": int(sum((i["warm_start_used"] >> 2) & 1 for i in infos)),
+            "learned_step_taken": int(sum((i["warm_start_used"] >> 1) & 1 for i in infos)),
             "fp64_checks": int(sum(i["outer"] for i in infos)) if name in ("mixed", "learned", "projected_mixed") else 0,
             "excited_fraction_window_start_end": [round(exc0, 3), round(exc1, 3)],
             "V_max": float(V.max().item()),

@@ -171,12 +171,14 @@ typedef struct {
   int32_t max_iters;    /* total inner iterations */
   int32_t precision;    /* 0: FP64 throughout; 1: FP32 inner GMRES + FP64 refinement;
                            2: one FP64-Arnoldi GMRES whose products run in FP32 (as kfbi_apply's
-                           KFBI_F32) once its residual is below inner_tol ||g'|| and in FP64 before,
-                           then an FP64 product of the result checks the residual (the solve goes
-                           on from that residual if it misses the tolerance) */
+                           KFBI_F32) once its residual is below min(inner_tol, tol / 1e-6) ||g'||
+                           (an FP32 product's relative error, about 1e-6, is then within the
+                           inexact-Krylov bound tol ||g'|| / ||r||) and in FP64 before, then an
+                           FP64 product of the result checks the residual (the solve goes on from
+                           that residual if it misses the tolerance) */
   int32_t x0;           /* 0: start from psi = 0 (Algorithm 1); 1: from psi_inout */
   double inner_tol;     /* precision = 1: relative tolerance of each FP32 inner solve;
-                           precision = 2: relative residual below which the products are FP32 */
+                           precision = 2: relative residual below which the products may be FP32 */
   int32_t max_outer;    /* precision = 1: maximum FP64 refinement steps */
   int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4); for the coupled
                            pair its residual and ||g'|| are measured without their component
@@ -196,7 +198,8 @@ typedef struct {
   double rel_resid;         /* final ||g' - A64 psi|| / ||g'|| */
   double gp_norm;           /* ||g'||_2 */
   int32_t warm_start_used;  /* bidomain_step: bit 0: the learned (1) or projection (3, 4) start was
-                               taken; bit 1: the learned search direction (4) was used */
+                               taken; bit 1: the learned step (4) was taken; bit 2: it was tried
+                               (its product spent, taken or not) */
   int32_t pad_;
   double start_resid;       /* ||g' - A64 psi0|| / ||g'|| of the start density (1 for a zero start) */
   double true_resid;        /* opts.true_resid = 1: ||g' - A64 psi|| / ||g'|| by an explicit product
@@ -244,10 +247,10 @@ typedef struct {
   int32_t warm_start;               /* 0: psi^{n-1}; 1: learned (MLP) start with fallback; 2: zero;
                                        3: least-residual combination of the last 8 solutions
                                        (their images are known without a product);
-                                       4: that combination, and the learned prediction's difference
-                                       from it as the first search direction of the GMRES (no
-                                       product of its own), with the cost check of the learned
-                                       start switching it off */
+                                       4: that combination, then one minimal-residual step along
+                                       the learned prediction's difference from it (one FP64
+                                       product; never increases the residual), with the cost
+                                       check of the learned start switching it off */
   kfbi_solve_opts solve;            /* diffusion solve options (tol, precision, ...) */
 } bidomain_params;
 

@@ -24,7 +24,6 @@ struct Solver {
   // captured Arnoldi step (per precision of the product), replayed every GMRES iteration
   bool use_graph = true;
   double *vin = nullptr, *wv = nullptr;
-  double *zbuf = nullptr;      // normalised first search direction of a flexible GMRES cycle
   int *jdev = nullptr, *jhost = nullptr;
   // step counter: each replayed step ends by storing its number in pinned host memory, which
   // the host polls instead of sleeping in a stream synchronisation between steps
@@ -59,15 +58,14 @@ struct Solver {
   // Products in precision a.prec, or with a.relax FP32 once the current residual is <= a.sw_abs and
   // FP64 before: the computed residual of such a solve is then checked by an FP64 product of the
   // result (counted in certs), and the iteration continues from that residual if it misses.
-  // a.r0: b - A x already known (no first product).  a.z0: first search direction of the first
-  // cycle (flexible GMRES: x += y_0 z0/|z0| + sum_{j>=1} y_j V_j).  On return r = b - A x: from
-  // the Arnoldi relation (exact to rounding when every product was FP64; the FP32 operator's
-  // residual for a.prec = 1), or the FP64 certificate product of a relaxed solve.
+  // a.r0: b - A x already known (no first product).  On return r = b - A x: from the Arnoldi
+  // relation (exact to rounding when every product was FP64; the FP32 operator's residual for
+  // a.prec = 1), or the FP64 certificate product of a relaxed solve.
   struct GmresArgs {
     int prec = 0;
     bool relax = false;
     double sw_abs = 0;
-    const double *r0 = nullptr, *z0 = nullptr;
+    const double *r0 = nullptr;
   };
   struct GmresStats {
     int its = 0, mv64 = 0, mv32 = 0, certs = 0;
@@ -87,11 +85,8 @@ struct Solver {
   // its residual gp - A psi if already known, unless *r0_bad (pinned host memory, valid after the
   // first wait of the solve) is set, when the residual is computed with an FP64 product.
   // Afterwards last_resid holds gp - A64 psi.
-  // z0 (optional): first search direction of the GMRES (precision 0 and 2) or of the first FP32 inner
-  // solve (precision 1), e.g. a predicted correction of the start.
   int solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                    hipStream_t st, const double *r0 = nullptr, const int *r0_bad = nullptr,
-                    const double *z0 = nullptr);
+                    hipStream_t st, const double *r0 = nullptr, const int *r0_bad = nullptr);
   const double *last_resid = nullptr;
   // The coupled pair's null density (insulated tissue: both potentials fixed up to one common
   // constant, so the BIE operator of the pair is singular): the unit eigenvector of A of smallest
@@ -132,7 +127,7 @@ struct bidomain_s {
   // residual with an FP64 product instead
   double *psi_last = nullptr;
   const double *hist_last = nullptr;
-  double *zdir = nullptr;      // warm_start 4: predicted correction of the start (first search direction)
+  double *zdir = nullptr;      // warm_start 4: predicted correction of the start (minimal-residual step)
   int *r0_bad_dev = nullptr, *r0_bad_host = nullptr;
   bool have_prev = false;
   void reset();                // forget the recycled residual, the projection history and the counts

@@ -166,8 +166,8 @@ __global__ __launch_bounds__(kB) void k_fill(double *__restrict__ z, double v, i
   if (i < n) z[i] = v;
 }
 
-// out = psi - c z with the coefficient c = <z, psi> read from device memory
-__global__ __launch_bounds__(kB) void k_remove_along(double *__restrict__ out, const double *__restrict__ psi,
+// out = psi - c z with the coefficient c = <z, psi> read from device memory (out may be psi)
+__global__ __launch_bounds__(kB) void k_remove_along(double *out, const double *psi,
                                                      const double *__restrict__ z, const double *__restrict__ c,
                                                      int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -287,7 +287,6 @@ void Solver::init(DevProblem &p) {
   KFBI_HIP(hipHostMalloc(&ypin, 2 * (kMaxRestart + 2) * sizeof(double), hipHostMallocDefault));
   vin = dalloc<double>(L);
   wv = dalloc<double>(L);
-  zbuf = dalloc<double>(L);
   if (p.ncomp == 2) {
     nullz = dalloc<double>(L);
     nully = dalloc<double>(L);
@@ -326,7 +325,7 @@ void Solver::release() {
   seqdev = nullptr;
   seqhost = nullptr;
   double **dp[] = {&V,    &r,    &w,  &t,   &gp,    &d,     &fpad,  &partials, &npart,
-                   &hdev, &ydev, &vin, &wv, &zbuf, &nullz, &nully, &nullp, &nullc};
+                   &hdev, &ydev, &vin, &wv, &nullz, &nully, &nullp, &nullc};
   for (double **q : dp) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -472,7 +471,6 @@ int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool 
   double beta = std::sqrt(dot(r, r, st));
   s.beta0 = beta;
   std::vector<double> H((size_t)(m + 1) * m), Hc((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), z(m + 1);
-  bool first_cycle = true;
   while (beta > tol_abs && s.its < maxit) {
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(Hc.begin(), Hc.end(), 0.0);
@@ -480,23 +478,13 @@ int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool 
     g[0] = beta;
     const double beta_cycle = beta;
     k_axpby<<<nblk(L), kB, 0, st>>>(V, 1.0 / beta, r, 0.0, nullptr, L);
-    // flexible first step: search along z0 (normalised into zbuf) instead of V_0
-    bool flex = false;
-    if (first_cycle && a.z0) {
-      const double zn = std::sqrt(dot(a.z0, a.z0, st));
-      if (zn > 0) {
-        k_axpby<<<nblk(L), kB, 0, st>>>(zbuf, 1.0 / zn, a.z0, 0.0, nullptr, L);
-        flex = true;
-      }
-    }
-    const double *first_in = flex ? zbuf : V;
     int jend = 0;
     bool breakdown = false, any32 = false;
     const bool graphed = use_graph && !p.profile;
     if (graphed) {
       *jhost = 0;
       KFBI_HIP(hipMemcpyAsync(jdev, jhost, sizeof(int), hipMemcpyHostToDevice, st));
-      KFBI_HIP(hipMemcpyAsync(vin, first_in, L * sizeof(double), hipMemcpyDeviceToDevice, st));
+      KFBI_HIP(hipMemcpyAsync(vin, V, L * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
     double target = tol_abs;
     for (int j = 0; j < m; ++j) {
@@ -506,7 +494,7 @@ int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool 
       if (graphed) {
         run_step(p, pj, m, st);
       } else {
-        const double *vj = j == 0 ? first_in : V + (int64_t)j * L;
+        const double *vj = V + (int64_t)j * L;
         double *vn = V + (int64_t)(j + 1) * L;
         apply_vec(p, pj, vj, vn, st);
         // classical Gram-Schmidt, twice; then the norm
@@ -557,14 +545,11 @@ int Solver::gmres(DevProblem &p, const double *b, double bnorm, double *x, bool 
       for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
       y[i] = acc / H[(size_t)i * m + i];
     }
-    // x += Z y with Z = [first search direction, V_1, ..., V_{jend-1}]
+    // x += V y
     std::copy(y.begin(), y.begin() + jend, ypin);
-    if (flex) ypin[0] = 0.0;
     KFBI_HIP(hipMemcpyAsync(ydev, ypin, jend * sizeof(double), hipMemcpyHostToDevice, st));
     k_combine<<<nblk(L), kB, 0, st>>>(x, V, L, ydev, jend, 1.0, L);
-    if (flex) k_axpby<<<nblk(L), kB, 0, st>>>(x, 1.0, x, y[0], zbuf, L);
     KFBI_HIP(hipGetLastError());
-    first_cycle = false;
     const bool converged = std::fabs(g[jend]) <= target && !breakdown;
     if (converged && !(any32 && a.relax)) {
       // the residual vector follows from the Arnoldi relation without a product,
@@ -640,8 +625,11 @@ void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnAr
   KFBI_HIP(hipGetLastError());
 }
 
+// relative error of an FP32 matrix-vector product (observed 1e-7 .. 4e-6)
+constexpr double kFp32ProductError = 1e-6;
+
 int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
-                          hipStream_t st, const double *r0, const int *r0_bad, const double *z0) {
+                          hipStream_t st, const double *r0, const int *r0_bad) {
   const double gn = std::sqrt(dot(gp, gp, st));
   if (r0 && r0_bad && *r0_bad) r0 = nullptr;   // read after the wait above: r0 does not belong to psi
   info.gp_norm = gn;
@@ -669,9 +657,11 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
     // with an FP64 product of the result as its certificate
     GmresArgs a;
     a.relax = o.precision == 2;
-    a.sw_abs = o.inner_tol * gn;
+    // inexact Krylov: a product made when the residual is r may err by about tol ||g'|| / ||r||
+    // (relative), so FP32 products (relative error about 1e-6) only once ||r|| <= tol ||g'|| / 1e-6,
+    // and not before inner_tol ||g'||
+    a.sw_abs = std::min(o.inner_tol, o.tol / kFp32ProductError) * gn;
     a.r0 = r0;
-    a.z0 = z0;
     GmresStats gs;
     rc = gmres(p, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, a, gs, st);
     info.iters = gs.its;
@@ -702,7 +692,6 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
       const double tin = std::max(o.inner_tol * res, 0.5 * tol_abs);
       GmresArgs a;
       a.prec = 1;
-      a.z0 = outer == 0 ? z0 : nullptr;
       GmresStats gs;
       gmres(p, d, res, w, true, tin, o.restart, o.max_iters - total, a, gs, st);
       total += gs.its;
@@ -1028,21 +1017,41 @@ int bidomain_s::step(bidomain_state &s, double dt, kfbi_solve_info &info, hipStr
       }
     }
   }
-  // warm_start 4: the network's prediction enters as the first search direction of the GMRES
-  // started from the projection: z0 = prediction - start.  Its product is the one the first
-  // iteration computes anyway, so the prediction costs no product; the cost check below switches
-  // it off when the solves it starts are not cheaper than those without it.
-  const double *z0 = nullptr;
+  // warm_start 4: one minimal-residual step from the projection start along the network's
+  // predicted correction d = prediction - start: psi0 += a d, r0 -= a A d with
+  // a = <A d, r0> / |A d|^2.  It costs one FP64 product and cannot increase the residual; the cost
+  // check below switches it off when the solves it starts are not cheaper than those without it.
+  // (Taking d as GMRES's first search direction instead saves that product, but drops the
+  // residual itself from the search space: a poor prediction then slows GMRES down.)
   bool learned_dir = false;
-  if (params.warm_start == 4 && mlp && steps_done >= 2 && o.method == 0 &&
+  if (params.warm_start == 4 && mlp && steps_done >= 2 && o.method == 0 && have_r0 && !r0_flag &&
       mlp_warm_start(this, hist1, hist2, zdir, st)) {
     k_axpby<<<nblk(L), kB, 0, st>>>(zdir, 1.0, zdir, -1.0, psi0, L);
+    if (p.ncomp == 2 && sv.null_ready) {
+      // without its component along the null density: the network also predicts the density's
+      // step-dependent null component, which A hardly sees, and the step would scale it freely
+      k_multidot<<<dim3(sv.nb, 1), kB, 0, st>>>(sv.nullz, L, zdir, L, sv.partials);
+      k_finish<<<1, kB, 0, st>>>(sv.partials, sv.nb, sv.nullc);
+      k_remove_along<<<nblk(L), kB, 0, st>>>(zdir, zdir, sv.nullz, sv.nullc, L);
+    }
     KFBI_HIP(hipGetLastError());
-    z0 = zdir;
-    learned_dir = true;
-    info.warm_start_used |= 2;
+    sv.apply_vec(p, 0, zdir, sv.t, st);
+    ++extra64;
+    learned_dir = true;   // its product is charged to the learned steps either way
+    info.warm_start_used |= 4;
+    const double tt = sv.dot(sv.t, sv.t, st), tr = sv.dot(sv.t, r0v, st), rr = sv.dot(r0v, r0v, st);
+    // taken only if it cuts the residual at least tenfold (|r0 - a A d|^2 = |r0|^2 - tr^2 / tt):
+    // less is worth less than the GMRES iteration its product costs, and a rough correction can
+    // make the residual harder for GMRES even where it makes it smaller
+    if (tt > 0 && rr - tr * tr / tt <= 0.01 * rr) {
+      const double a = tr / tt;
+      k_axpby<<<nblk(L), kB, 0, st>>>(psi0, 1.0, psi0, a, zdir, L);
+      k_axpby<<<nblk(L), kB, 0, st>>>(r0v, 1.0, r0v, -a, sv.t, L);
+      KFBI_HIP(hipGetLastError());
+      info.warm_start_used |= 2;
+    }
   }
-  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr, r0_flag, z0);
+  const int rc = sv.solve_density(p, psi0, o, x0, info, st, have_r0 ? r0v : nullptr, r0_flag);
   info.matvecs_fp32 += extra32;
   info.matvecs_fp64 += extra64;
   KFBI_HIP(hipMemcpyAsync(d_prev, sv.last_resid, L * sizeof(double), hipMemcpyDeviceToDevice, st));
