@@ -171,14 +171,12 @@ typedef struct {
   int32_t max_iters;    /* total inner iterations */
   int32_t precision;    /* 0: FP64 throughout; 1: FP32 inner GMRES + FP64 refinement;
                            2: one FP64-Arnoldi GMRES whose products run in FP32 (as kfbi_apply's
-                           KFBI_F32) once its residual is below min(inner_tol, tol / 1e-6) ||g'||
-                           (an FP32 product's relative error, about 1e-6, is then within the
-                           inexact-Krylov bound tol ||g'|| / ||r||) and in FP64 before, then an
-                           FP64 product of the result checks the residual (the solve goes on from
-                           that residual if it misses the tolerance) */
+                           KFBI_F32) once its residual is below inner_tol ||g'|| and in FP64 before,
+                           then an FP64 product of the result checks the residual (the solve goes
+                           on from that residual if it misses the tolerance) */
   int32_t x0;           /* 0: start from psi = 0 (Algorithm 1); 1: from psi_inout */
   double inner_tol;     /* precision = 1: relative tolerance of each FP32 inner solve;
-                           precision = 2: relative residual below which the products may be FP32 */
+                           precision = 2: relative residual below which the products are FP32 */
   int32_t max_outer;    /* precision = 1: maximum FP64 refinement steps */
   int32_t method;       /* 0: GMRES; 1: simple (Richardson) iteration (Sec. 4); for the coupled
                            pair its residual and ||g'|| are measured without their component

@@ -625,9 +625,6 @@ void Solver::bie_rhs(DevProblem &p, const double *g, hipStream_t st, const FhnAr
   KFBI_HIP(hipGetLastError());
 }
 
-// relative error of an FP32 matrix-vector product (observed 1e-7 .. 4e-6)
-constexpr double kFp32ProductError = 1e-6;
-
 int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, bool x0, kfbi_solve_info &info,
                           hipStream_t st, const double *r0, const int *r0_bad) {
   const double gn = std::sqrt(dot(gp, gp, st));
@@ -657,10 +654,7 @@ int Solver::solve_density(DevProblem &p, double *psi, const kfbi_solve_opts &o, 
     // with an FP64 product of the result as its certificate
     GmresArgs a;
     a.relax = o.precision == 2;
-    // inexact Krylov: a product made when the residual is r may err by about tol ||g'|| / ||r||
-    // (relative), so FP32 products (relative error about 1e-6) only once ||r|| <= tol ||g'|| / 1e-6,
-    // and not before inner_tol ||g'||
-    a.sw_abs = std::min(o.inner_tol, o.tol / kFp32ProductError) * gn;
+    a.sw_abs = o.inner_tol * gn;
     a.r0 = r0;
     GmresStats gs;
     rc = gmres(p, gp, gn, psi, !x0, tol_abs, o.restart, o.max_iters, a, gs, st);
