@@ -138,12 +138,24 @@ __device__ __forceinline__ void dft(C2<T> *v) {
 #endif
 __device__ __forceinline__ int pad(int i) { return i + (i >> KFBI_LDS_PAD_SHIFT); }
 
+// Barrier for the LDS exchanges inside one pencil pair.  The M / 16 threads of a pair are
+// consecutive and M <= 1024, so a pair never straddles two wavefronts, and one wavefront's LDS
+// operations are carried out in program order: a wavefront-scope fence, which only stops the
+// compiler from moving LDS accesses across it, is enough.  Exchanges between pairs (the tile
+// loads and stores) still need __syncthreads.
+__device__ __forceinline__ void pair_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 // W: tile-width multiplier picked by the autotuner (1 or 2 times the base pairs per workgroup)
 template <typename T, int M, int W = 1>
 struct Shape {
   static constexpr int N = M - 1;
   static constexpr int TPP = M / 16;                          // threads per pencil pair
+  static_assert(TPP <= 64 && 64 % TPP == 0, "a pencil pair must lie inside one wavefront");
   static constexpr int NP = W * (sizeof(T) == 8 ? 2048 : 4096) / M;  // pencil pairs per workgroup
   static constexpr int NT = NP * TPP;                         // threads per workgroup (W x 128 / 256)
   static constexpr int PADM = M + (M >> KFBI_LDS_PAD_SHIFT) + KFBI_LDS_PAIR_SKEW;                  // padded LDS length of one pair (odd:
@@ -167,7 +179,7 @@ __device__ __forceinline__ void stage(C2<T> *buf, int lane, const C2<T> *__restr
     }
     dft<T, R>(&v[b * R]);
   }
-  __syncthreads();
+  pair_sync();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = lane + TPP * b;
@@ -176,7 +188,7 @@ __device__ __forceinline__ void stage(C2<T> *buf, int lane, const C2<T> *__restr
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[pad(base + r * Ns)] = v[b * R + r];
   }
-  __syncthreads();
+  pair_sync();
 }
 
 template <typename T, int M, int Ns>
@@ -235,13 +247,12 @@ __device__ __forceinline__ void dst_pre(C2<T> *buf, int lane, const Sines<T, M> 
   if (lane == 0) buf[pad(0)] = {0, 0};
 }
 
-// The FFT of the pre-processed pencil pair and the post-processing (prefix scan over the odd
-// outputs); result at positions 1..N.  All threads of the workgroup must call it.
+// Post-processing of the FFT of a pre-processed pencil pair held in buf (prefix scan over the odd
+// outputs): lane owns k in [8 lane, 8 lane + 8), so its outputs are the DST values at positions
+// 16 lane + q, q < 16, returned in y[q] (y[0] of lane 0, position 0, is not an output: zero).
 template <typename T, int M>
-__device__ __forceinline__ void dst_rest(C2<T> *buf, int lane, const C2<T> *__restrict__ tw) {
+__device__ __forceinline__ void dst_post(const C2<T> *buf, int lane, C2<T> (&y)[16]) {
   constexpr int TPP = M / 16;
-  fft_stages<T, M, 1>(buf, lane, tw);
-  // post-processing: lane owns k in [8 lane, 8 lane + 8)
   C2<T> ev[8], od[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -257,22 +268,33 @@ __device__ __forceinline__ void dst_rest(C2<T> *buf, int lane, const C2<T> *__re
   C2<T> inc = tot;
 #pragma unroll
   for (int off = 1; off < TPP; off <<= 1) {
-    const C2<T> y = {shfl_up_w(inc.x, off, TPP), shfl_up_w(inc.y, off, TPP)};
-    if (lane >= off) inc = inc + y;
+    const C2<T> u = {shfl_up_w(inc.x, off, TPP), shfl_up_w(inc.y, off, TPP)};
+    if (lane >= off) inc = inc + u;
   }
   const C2<T> excl = inc - tot;
   const C2<T> E0 = {shfl_w(e0.x, 0, TPP), shfl_w(e0.y, 0, TPP)};
   const C2<T> half0 = (T)0.5 * E0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) od[i] = (excl + od[i]) - half0;
-  __syncthreads();
-#pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int k = 8 * lane + i;
-    if (k > 0) buf[pad(2 * k)] = ev[i];
-    buf[pad(2 * k + 1)] = od[i];
+    y[2 * i] = (i > 0 || lane > 0) ? ev[i] : C2<T>{T(0), T(0)};
+    y[2 * i + 1] = (excl + od[i]) - half0;
   }
-  __syncthreads();
+}
+
+// The FFT of the pre-processed pencil pair and the post-processing; result at positions 1..N.
+// All threads of the workgroup must call it.  BLOCK: end with a workgroup barrier (the caller
+// reads other pairs' results next) rather than a pair one.
+template <typename T, int M, bool BLOCK = true>
+__device__ __forceinline__ void dst_rest(C2<T> *buf, int lane, const C2<T> *__restrict__ tw) {
+  fft_stages<T, M, 1>(buf, lane, tw);
+  C2<T> y[16];
+  dst_post<T, M>(buf, lane, y);
+  pair_sync();
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (q > 0 || lane > 0) buf[pad(16 * lane + q)] = y[q];
+  if constexpr (BLOCK) __syncthreads();
+  else pair_sync();
 }
 
 // DST-I (unnormalised: y_k = sum_n x_n sin(pi n k / M)) of one pencil pair held in LDS as
@@ -282,7 +304,7 @@ template <typename T, int M, typename Hook = NoHook<T>>
 __device__ __forceinline__ void dst_pair(C2<T> *buf, int lane, const C2<T> *__restrict__ tw,
                                          const Sines<T, M> &sn, const Hook &hook = Hook()) {
   dst_pre<T, M>(buf, lane, sn, hook);
-  __syncthreads();
+  pair_sync();
   dst_rest<T, M>(buf, lane, tw);
 }
 
@@ -769,7 +791,7 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
   C2<T> *mine = sbuf + pr * PADM;
-  dst_rest<T, M>(mine, lane, tw);
+  dst_rest<T, M, false>(mine, lane, tw);
   // inverse transform with the mode solve applied as it reads the spectrum
   ModeHook<T, NC> mh;
   mh.slam = slam;
