@@ -1,21 +1,25 @@
 // Interface-side kernels of the KFBI matrix-vector product and the table upload.
 //
-//  k_jumps       : density -> jumps [u_a], [u_aa] at every grid-line intersection
-//                  (single-layer interface problem, Sec. 5.1 eq. single; jump relations
-//                  from [u] = 0 and [n.D grad u] = psi for diagonal D_c), and
-//                  [grad u], [Hess u] at every interface node, in one launch.
-//  k_correct     : right-hand-side correction at irregular grid nodes (Sec. 5.3, eq.
-//                  correct): rhs_p = sum_arms s_p D_{c,a}/h^2 ([u_a] d + [u_aa] d^2 / 2).
-//                  One thread owns one irregular node, so no atomics are needed.
-//  k_gather      : n.D grad u+ at every interface node from its 6/10-node quadratic fit,
-//                  adding the Taylor-expanded jump to values on the "-" side
-//                  (Sec. 5.4, eqs. taylor-i-po, taylor-i-co, ji).
+//  k_jumps_nc     : density -> jumps [u_a], [u_aa] at every grid-line intersection
+//                   (single-layer interface problem, Sec. 5.1 eq. single; jump relations
+//                   from [u] = 0 and [n.D grad u] = psi for diagonal D_c), and
+//                   [grad u], [Hess u] at every interface node, in one launch.
+//  k_correct_nc   : right-hand-side correction at irregular grid nodes (Sec. 5.3, eq.
+//                   correct): rhs_p = sum_arms s_p D_{c,a}/h^2 ([u_a] d + [u_aa] d^2 / 2).
+//                   One thread owns one irregular node, so no atomics are needed.
+//  k_gather_coop  : n.D grad u+ at every interface node from its 6/10-node quadratic fit,
+//                   adding the Taylor-expanded jump to values on the "-" side
+//                   (Sec. 5.4, eqs. taylor-i-po, taylor-i-co, ji).
+// The single-problem gather is wavefront-cooperative (a group of lanes per node, one stencil
+// point per lane, a DPP butterfly for the sums); the jumps and the correction keep one thread
+// per item, as do the batched kernels (each choice measured).
 //
 // Precision: the density, the transfer and jump weights, the node jumps and the extrapolation
 // fits are FP64 in every product.  Only the grid side follows the product's precision T: the
 // crossing jumps are stored in T for the correction, which writes the T right-hand side that
 // the T box solve transforms, and the gather reads the T grid values into its FP64 fit.
 #include <cmath>
+#include <type_traits>
 #include <stdexcept>
 
 #include "device.h"
@@ -26,7 +30,7 @@ namespace {
 constexpr int kBlock = 256;
 
 // All stencil sizes are compile-time constants so that every index load of a thread is
-// issued before the dependent gathers (the kernels are latency-bound, not bandwidth-bound).
+// issued before the dependent gathers (the per-item forms are latency-bound).
 // The jump relations enter through per-point weights built at setup (linear in the density
 // values of the transfer stencil), so these kernels hold no geometry and serve any diagonal D.
 
@@ -55,7 +59,7 @@ __device__ __forceinline__ void jumps_cross_at(int64_t c, const double *__restri
   }
 }
 
-// One thread per irregular node; at most 2D arms, loaded predicated and all at once.
+// One irregular node per thread (batched kernels); at most 2D arms, loaded predicated and all at once.
 // arm_s[comp][arm] = s_p D_{c,a} / h^2 for the arm's axis a.
 template <typename T, int D>
 __device__ __forceinline__ void correct_at(int64_t r, const int32_t *__restrict__ irr_pos,
@@ -92,19 +96,6 @@ __device__ __forceinline__ void correct_at(int64_t r, const int32_t *__restrict_
     else
       *o = acc;
   }
-}
-
-template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_correct(int64_t nirr, const int32_t *__restrict__ irr_pos,
-                                                    const int32_t *__restrict__ irr_ptr,
-                                                    const int32_t *__restrict__ arm_cross,
-                                                    const T *__restrict__ arm_d, const T *__restrict__ arm_s,
-                                                    int64_t narm, const T *__restrict__ jz, int64_t nc, int ncomp,
-                                                    T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nirr)
-    correct_at<T, D>(r, irr_pos, irr_ptr, arm_cross, arm_d, arm_s, narm, jz, nc, ncomp, rhs, comp_stride,
-                     accumulate);
 }
 
 template <int D>
@@ -159,24 +150,6 @@ __device__ __forceinline__ void jumps_nodes_at(int64_t q, const double *__restri
   }
 }
 
-// Both jump sets in one launch (they are independent): blocks [0, nbc) take the crossings,
-// the others the interface nodes.
-template <typename TZ, int D, int K, int KN>
-__global__ __launch_bounds__(kBlock) void k_jumps(const double *__restrict__ psi, int64_t M, int64_t nc,
-                                                  int64_t nbc, const int32_t *__restrict__ z_idx,
-                                                  const double *__restrict__ zA, const double *__restrict__ zB,
-                                                  const int32_t *__restrict__ q_idx, const double *__restrict__ q_wg,
-                                                  const double *__restrict__ q_c, const double *__restrict__ q_G,
-                                                  int ncomp, TZ *__restrict__ jz, double *__restrict__ jq) {
-  if ((int64_t)blockIdx.x < nbc) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nc) jumps_cross_at<TZ, K>(c, psi, M, nc, z_idx, zA, zB, ncomp, jz);
-  } else {
-    const int64_t q = ((int64_t)blockIdx.x - nbc) * blockDim.x + threadIdx.x;
-    if (q < M) jumps_nodes_at<D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, ncomp, jq);
-  }
-}
-
 // n.D_c grad u+ at one node: st_nw[comp][j] = sum_a n_a D_{c,a} (gradient weight of node j)_a.
 template <typename TU, int D, int S>
 __device__ __forceinline__ void gather_at(int64_t q, const TU *__restrict__ u, int64_t comp_stride, int64_t M,
@@ -228,17 +201,178 @@ __device__ __forceinline__ void gather_at(int64_t q, const TU *__restrict__ u, i
   }
 }
 
-template <typename TU, int D, int S>
-__global__ __launch_bounds__(kBlock) void k_gather(const TU *__restrict__ u, int64_t comp_stride, int64_t M,
-                                                   const int32_t *__restrict__ st_pos,
-                                                   const double *__restrict__ st_nw, const double *__restrict__ st_r,
-                                                   const double *__restrict__ jq, int ncomp, int with_jumps,
-                                                   double *__restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < M) gather_at<TU, D, S>(q, u, comp_stride, M, st_pos, st_nw, st_r, jq, ncomp, with_jumps, out);
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------- wavefront-cooperative gather
+//
+// One thread per node leaves the single-problem gather short of parallelism: 40,960 nodes of a
+// 3D problem are 640 wavefronts for 1024 SIMDs, each a chain of dependent loads (stencil index
+// -> grid value -> weighted sum).  Here a group of G consecutive lanes (4, 8 or 16, the next
+// power of two at or above the stencil size) shares one node: lane k takes stencil point k, and
+// the weighted sum is finished by a butterfly across the group.  Tables keep their
+// [point][node] layout.  The summation order differs from the one-thread form (a fixed tree
+// instead of a left-to-right sum), deterministically.
+
+constexpr int coop_group(int S) { return S <= 4 ? 4 : (S <= 8 ? 8 : 16); }
+
+// Sum over the G lanes of a group (G = 4, 8 or 16, aligned); every lane receives the total.
+// A butterfly of DPP moves within a row of 16 lanes: swap neighbours, swap pairs (quad
+// permutes 1,0,3,2 and 2,3,0,1), then mirror within half rows and within the row, each step
+// pairing every lane with one of the other half of its current block.  VALU moves only, so the
+// LDS pipe, which a lane shuffle would use, stays free.  Additions are commutative, so every
+// lane holds bitwise the same total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int2 w = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(0, w.x, CTRL, 0xF, 0xF, false),
+                                              __builtin_amdgcn_update_dpp(0, w.y, CTRL, 0xF, 0xF, false)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+  auto mv = [](T x, auto ctrl) {
+    if constexpr (sizeof(T) == 8) return dpp_f64<decltype(ctrl)::value>(x);
+    else return dpp_f32<decltype(ctrl)::value>(x);
+  };
+  v += mv(v, std::integral_constant<int, 0xB1>{});   // quad_perm 1,0,3,2
+  v += mv(v, std::integral_constant<int, 0x4E>{});   // quad_perm 2,3,0,1
+  if constexpr (G >= 8) v += mv(v, std::integral_constant<int, 0x141>{});   // row_half_mirror
+  if constexpr (G >= 16) v += mv(v, std::integral_constant<int, 0x140>{});  // row_mirror
+  return v;
 }
 
-inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+// [u_a], [u_aa] at crossing c for NC components, one thread per crossing: at 154,210 crossings
+// of a 3D problem that is 2.4 wavefronts per SIMD already, and a lane group per crossing was
+// measured slower (its butterflies cost more than the latency they hide).
+template <typename TZ, int K, int NC>
+__device__ __forceinline__ void jumps_cross_nc(int64_t c, const double *__restrict__ psi, int64_t M, int64_t nc,
+                                               const int32_t *__restrict__ z_idx, const double *__restrict__ zA,
+                                               const double *__restrict__ zB, TZ *__restrict__ jz) {
+  int32_t j[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) j[k] = z_idx[k * nc + c];
+#pragma unroll
+  for (int comp = 0; comp < NC; ++comp) {
+    const double *ps = psi + comp * M;
+    const double *A = zA + (int64_t)comp * K * nc, *B = zB + (int64_t)comp * K * nc;
+    double ju = 0, juu = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double v = ps[j[k]];
+      ju += A[k * nc + c] * v;
+      juu += B[k * nc + c] * v;
+    }
+    jz[(2 * comp) * nc + c] = (TZ)ju;
+    jz[(2 * comp + 1) * nc + c] = (TZ)juu;
+  }
+}
+
+// Both jump sets in one launch (they are independent): blocks [0, nbc) take the crossings,
+// the others the interface nodes, one thread per item with the components unrolled.  A lane
+// group per node (one transfer point per lane, then butterflies over the group) was measured
+// slower: with the tables in [point][node] order each load of a group touches a separate line
+// per point, where a thread per node reads whole lines.
+template <typename TZ, int D, int K, int KN, int NC>
+__global__ __launch_bounds__(kBlock) void k_jumps_nc(const double *__restrict__ psi, int64_t M, int64_t nc,
+                                                     int64_t nbc, const int32_t *__restrict__ z_idx,
+                                                     const double *__restrict__ zA, const double *__restrict__ zB,
+                                                     const int32_t *__restrict__ q_idx, const double *__restrict__ q_wg,
+                                                     const double *__restrict__ q_c, const double *__restrict__ q_G,
+                                                     TZ *__restrict__ jz, double *__restrict__ jq) {
+  if ((int64_t)blockIdx.x < nbc) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c < nc) jumps_cross_nc<TZ, K, NC>(c, psi, M, nc, z_idx, zA, zB, jz);
+  } else {
+    const int64_t q = ((int64_t)blockIdx.x - nbc) * kBlock + threadIdx.x;
+    if (q < M) jumps_nodes_at<D, KN>(q, psi, M, q_idx, q_wg, q_c, q_G, NC, jq);
+  }
+}
+
+// n.D_c grad u+ at node q, lane k < S taking stencil point k (its value, its jump term on the
+// "-" side, its flux weight).
+template <typename TU, int D, int S, int NC, int G>
+__device__ __forceinline__ void gather_coop(int64_t q, int k, const TU *__restrict__ u, int64_t comp_stride,
+                                            int64_t M, const int32_t *__restrict__ st_pos,
+                                            const double *__restrict__ st_nw, const double *__restrict__ st_r,
+                                            const double *__restrict__ jq, int with_jumps,
+                                            double *__restrict__ out) {
+  constexpr int NHv = NH<D>::v, STR = D + NHv;
+  const bool act = k < S;
+  const int32_t pe = act ? st_pos[k * M + q] : 0;
+  const int64_t pu = pe < 0 ? -(int64_t)pe - 1 : pe;
+  const bool minus = act && pe < 0 && with_jumps;
+  double val[NC], nw[NC], r[D];
+#pragma unroll
+  for (int comp = 0; comp < NC; ++comp) {
+    val[comp] = act ? (double)u[comp * comp_stride + pu] : 0.0;
+    nw[comp] = act ? st_nw[((int64_t)comp * S + k) * M + q] : 0.0;
+  }
+  if (minus) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = st_r[(k * D + a) * M + q];
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) {
+      const double *o = jq + (int64_t)comp * STR * M;
+      double du[D], H[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) du[a] = o[a * M + q];
+#pragma unroll
+      for (int e = 0; e < NHv; ++e) {
+        int a, b;
+        sym_index<D>(e, a, b);
+        H[a][b] = H[b][a] = o[(D + e) * M + q];
+      }
+      double Jv = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double hr = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) hr += H[a][b] * r[b];
+        Jv += r[a] * (du[a] + 0.5 * hr);
+      }
+      val[comp] += Jv;
+    }
+  }
+#pragma unroll
+  for (int comp = 0; comp < NC; ++comp) {
+    const double acc = group_sum<G>(nw[comp] * val[comp]);
+    if (k == comp) out[comp * M + q] = acc;
+  }
+}
+
+template <typename TU, int D, int S, int NC>
+__global__ __launch_bounds__(kBlock) void k_gather_coop(const TU *__restrict__ u, int64_t comp_stride, int64_t M,
+                                                        const int32_t *__restrict__ st_pos,
+                                                        const double *__restrict__ st_nw,
+                                                        const double *__restrict__ st_r,
+                                                        const double *__restrict__ jq, int with_jumps,
+                                                        double *__restrict__ out) {
+  constexpr int G = coop_group(S);
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t q = t / G;
+  if (q < M) gather_coop<TU, D, S, NC, G>(q, (int)(t % G), u, comp_stride, M, st_pos, st_nw, st_r, jq, with_jumps,
+                                          out);
+}
+
+// Correction at irregular node r, one thread per node with the components unrolled (a lane
+// per arm was measured slower: at most six arms give little to share).
+template <typename T, int D, int NC>
+__global__ __launch_bounds__(kBlock) void k_correct_nc(int64_t nirr, const int32_t *__restrict__ irr_pos,
+                                                       const int32_t *__restrict__ irr_ptr,
+                                                       const int32_t *__restrict__ arm_cross,
+                                                       const T *__restrict__ arm_d, const T *__restrict__ arm_s,
+                                                       int64_t narm, const T *__restrict__ jz, int64_t nc,
+                                                       T *__restrict__ rhs, int64_t comp_stride, int accumulate) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nirr)
+    correct_at<T, D>(r, irr_pos, irr_ptr, arm_cross, arm_d, arm_s, narm, jz, nc, NC, rhs, comp_stride, accumulate);
+}
+
+inline unsigned nblk_g(int64_t n, int G) { return (unsigned)((n * G + kBlock - 1) / kBlock); }
 
 // Problem of a flattened batch item: the largest p with cum[p] <= i (cum[0] = 0 <= i < cum[n]).
 __device__ __forceinline__ int batch_problem(const int64_t *__restrict__ cum, int n, int64_t i) {
@@ -361,32 +495,45 @@ void free_prec(PrecTables<T> &tb) {
 
 }  // namespace
 
-template <typename T>
-void launch_jumps(DevProblem &p, const double *psi, hipStream_t st) {
+template <typename T, int D, int K, int KN, int NC>
+static void jumps_nc(DevProblem &p, const double *psi, hipStream_t st) {
   const PrecTables<double> &tb = p.f64;
-  T *jz = p.tab<T>().jz;
   const int64_t nbc = p.nc > 0 ? nblk(p.nc) : 0;
   const unsigned g = (unsigned)(nbc + nblk(p.M));
-  if (p.dim == 2)
-    k_jumps<T, 2, 4, 5><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B, p.q_idx, tb.q_wg,
-                                              tb.q_c, tb.q_G, p.ncomp, jz, tb.jq);
-  else
-    k_jumps<T, 3, kLsqNodes, kLsqNodes><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B,
-                                                              p.q_idx, tb.q_wg, tb.q_c, tb.q_G, p.ncomp, jz,
-                                                              tb.jq);
+  k_jumps_nc<T, D, K, KN, NC><<<g, kBlock, 0, st>>>(psi, p.M, p.nc, nbc, p.z_idx, tb.z_A, tb.z_B, p.q_idx, tb.q_wg,
+                                                    tb.q_c, tb.q_G, p.tab<T>().jz, tb.jq);
+}
+
+template <typename T>
+void launch_jumps(DevProblem &p, const double *psi, hipStream_t st) {
+  if (p.dim == 2) {
+    if (p.ncomp == 2) jumps_nc<T, 2, 4, 5, 2>(p, psi, st);
+    else jumps_nc<T, 2, 4, 5, 1>(p, psi, st);
+  } else {
+    if (p.ncomp == 2) jumps_nc<T, 3, kLsqNodes, kLsqNodes, 2>(p, psi, st);
+    else jumps_nc<T, 3, kLsqNodes, kLsqNodes, 1>(p, psi, st);
+  }
   KFBI_HIP(hipGetLastError());
+}
+
+template <typename T, int D, int NC>
+static void correct_nc(DevProblem &p, T *field, int accumulate, hipStream_t st) {
+  PrecTables<T> &tb = p.tab<T>();
+  k_correct_nc<T, D, NC><<<nblk(p.nirr), kBlock, 0, st>>>(
+      p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s, p.narm, tb.jz, p.nc, field, p.comp_stride,
+      accumulate);
 }
 
 template <typename T>
 static void correct_into(DevProblem &p, T *field, int accumulate, hipStream_t st) {
-  PrecTables<T> &tb = p.tab<T>();
   if (p.nirr == 0) return;
-  if (p.dim == 2)
-    k_correct<T, 2><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s,
-                                                    p.narm, tb.jz, p.nc, p.ncomp, field, p.comp_stride, accumulate);
-  else
-    k_correct<T, 3><<<nblk(p.nirr), kBlock, 0, st>>>(p.nirr, p.irr_pos, p.irr_ptr, p.arm_cross, tb.arm_d, tb.arm_s,
-                                                    p.narm, tb.jz, p.nc, p.ncomp, field, p.comp_stride, accumulate);
+  if (p.dim == 2) {
+    if (p.ncomp == 2) correct_nc<T, 2, 2>(p, field, accumulate, st);
+    else correct_nc<T, 2, 1>(p, field, accumulate, st);
+  } else {
+    if (p.ncomp == 2) correct_nc<T, 3, 2>(p, field, accumulate, st);
+    else correct_nc<T, 3, 1>(p, field, accumulate, st);
+  }
   KFBI_HIP(hipGetLastError());
 }
 
@@ -400,15 +547,22 @@ void launch_add_correction(DevProblem &p, T *field_padded, hipStream_t st) {
   correct_into<T>(p, field_padded, 1, st);
 }
 
+template <typename T, int D, int S, int NC>
+static void gather_coop_launch(DevProblem &p, const T *u, bool with_jumps, double *out, hipStream_t st) {
+  const PrecTables<double> &tb = p.f64;
+  k_gather_coop<T, D, S, NC><<<nblk_g(p.M, coop_group(S)), kBlock, 0, st>>>(
+      u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq, with_jumps ? 1 : 0, out);
+}
+
 template <typename T>
 void launch_gather(DevProblem &p, const T *u, bool with_jumps, double *out, hipStream_t st) {
-  const PrecTables<double> &tb = p.f64;
-  if (p.dim == 2)
-    k_gather<T, 2, 6><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
-                                                   p.ncomp, with_jumps ? 1 : 0, out);
-  else
-    k_gather<T, 3, 10><<<nblk(p.M), kBlock, 0, st>>>(u, p.comp_stride, p.M, p.st_pos, tb.st_nw, tb.st_r, tb.jq,
-                                                    p.ncomp, with_jumps ? 1 : 0, out);
+  if (p.dim == 2) {
+    if (p.ncomp == 2) gather_coop_launch<T, 2, 6, 2>(p, u, with_jumps, out, st);
+    else gather_coop_launch<T, 2, 6, 1>(p, u, with_jumps, out, st);
+  } else {
+    if (p.ncomp == 2) gather_coop_launch<T, 3, 10, 2>(p, u, with_jumps, out, st);
+    else gather_coop_launch<T, 3, 10, 1>(p, u, with_jumps, out, st);
+  }
   KFBI_HIP(hipGetLastError());
 }
 
