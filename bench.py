@@ -290,7 +290,7 @@ def variant_kwargs(name, a):
 
 
 KERNELS = ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse", "dst_last_sparse", "dst_last_out",
-           "dst_x_fhn", "jumps", "correct", "gather")
+           "dst_x_fhn", "dst_x_fe1", "dst_y1", "dst_last_anti", "jumps", "correct", "gather")
 
 
 def main():
@@ -414,7 +414,10 @@ def main():
     # The x passes of a step's box solves that carry the reaction (dst_x_fhn) are priced as the mean
     # of: forward Euler + source (V, q read, the pair written), source + correction (V, q and the
     # correction rows read, the pair written) and inverse + backward Euler (the pair, V and q read,
-    # V, q written).
+    # V, q written).  Without a stimulus current the volume solve's source is antisymmetric and its
+    # forward passes run over one field: dst_x_fe1 (V, q read, one field written), dst_y1 (one field
+    # read and written) and dst_last_anti (one field read, the stencil planes of both components
+    # written); dst_x_fhn then holds only the other two forms.
     ref = "plain" if "plain" in kt else head
     N = grid.n
     nc = co.ncomp
@@ -429,7 +432,11 @@ def main():
                "dst_x_rows": float((rows_in + rows_out) * N * 8),
                "dst_y_sparse": float(((rows_in * N + planes_in * nc * N * N) + (planes_out * nc * N * N + rows_out * N))
                                      * 8 / 2),
-               "dst_x_fhn": (2.0 * field_bytes + (2.0 * field_bytes + rows_in * N * 8) + 3.0 * field_bytes) / 3.0}
+               "dst_x_fe1": 1.5 * field_bytes, "dst_y1": float(field_bytes),
+               "dst_last_anti": float(field_bytes / 2 + nc * N * N * 8 * planes_out),
+               "dst_x_fhn": ((2.0 * field_bytes + (2.0 * field_bytes + rows_in * N * 8) + 3.0 * field_bytes) / 3.0
+                             if kt[ref]["dst_x_fe1"][1] == 0 else
+                             ((2.0 * field_bytes + rows_in * N * 8) + 3.0 * field_bytes) / 2.0)}
     tot = {k: us * n for k, (us, n) in kt[ref].items()}
     priced = [k for k in algo_of if kt[ref][k][1] > 0]
     dom = max(priced, key=tot.get)

@@ -367,7 +367,10 @@ const char *kfbi_last_error(void);
  * "dst_last_sparse" (row- and plane-masked passes of the matrix-vector product), "dst_last_out"
  * (the z pass of the volume solve whose result is read only at the interface stencils: every
  * plane read, stencil planes written), "dst_x_fhn" (the x passes of a bidomain step's box solves
- * that also carry its reaction half steps), "correct", "gather", "jumps").
+ * that also carry its reaction half steps), "dst_x_fe1", "dst_y1", "dst_last_anti" (the volume
+ * solve of a step without stimulus current, whose source is antisymmetric: the forward x and y
+ * passes over the one field kappa V1, and the z pass that reads it as the pair (g, -g)),
+ * "correct", "gather", "jumps").
  * Returns KFBI_EINVAL if the name is unknown. */
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
 /* DST tile widths (1 or 2: multiples of the base pencil pairs per workgroup) of the x, y and

@@ -584,9 +584,11 @@ struct StridedTile {
   // two fused: a thread loads rows r and N-1-r (positions n and M-n) of its columns and writes
   // t_n and t_{M-n} straight into LDS, which saves one LDS round trip of the tile.  The same
   // arithmetic as load(), barrier, dst_pre.  A barrier must follow before the transform.
-  template <typename R = AllRows>
+  // ANTI (NC = 2): only component 0 is read; component 1 is taken as its negative.
+  template <bool ANTI = false, typename R = AllRows>
   __device__ static void load_pre(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
                                   const T *__restrict__ sp, const R &rows = R()) {
+    static_assert(!ANTI || (NC == 2 && VEC), "an antisymmetric pair is read as two components");
     if constexpr (!VEC) {
       load(base, RS, CS, x0, sbuf, tid, rows);
       __syncthreads();
@@ -600,7 +602,7 @@ struct StridedTile {
         const int s = e % VPR, p = e / VPR, r0 = p, r1 = N - 1 - p;
         const bool ok0 = e < NU && rows(r0), ok1 = e < NU && rows(r1);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < (ANTI ? 1 : NC); ++c) {
           const T *q = base + c * CS + x0 + s * VW;
           if (ok0) ra[i][c] = *reinterpret_cast<const V16<T> *>(q + (int64_t)r0 * RS);
           else
@@ -622,7 +624,10 @@ struct StridedTile {
 #pragma unroll
           for (int j = 0; j < NW; ++j) {
             C2<T> a, b;
-            if constexpr (NC == 2) {
+            if constexpr (ANTI) {
+              a = {ra[i][0].v[j], -ra[i][0].v[j]};
+              b = {rb[i][0].v[j], -rb[i][0].v[j]};
+            } else if constexpr (NC == 2) {
               a = {ra[i][0].v[j], ra[i][1].v[j]};
               b = {rb[i][0].v[j], rb[i][1].v[j]};
             } else {
@@ -758,7 +763,9 @@ struct ModeHook {
 // ZM (3D): plane-masked forms, kernels of their own so that traces tell them apart.  ZM = 1:
 // the bit sets zin / zout name the planes that may be nonzero on input (the others are not
 // read) and the planes needed on output (the others are not written); ZM = 2: every plane is
-// read, only the planes in zout are written.
+// read, only the planes in zout are written; ZM = 3 (coupled pair): as ZM = 2 for an
+// antisymmetric source, component 1 of the input being minus component 0, so that only
+// component 0 is read (the input may then hold one component).
 // One tile of the pass: tile number id of total (gx tiles per row of the grid of tiles), LDS
 // buffers sbuf (NP * PADM values), slam (M) and ssin (M / 2 + 1).
 template <typename T, int M, int NC, int DIM, int W = 1, int ZM = 0>
@@ -786,7 +793,9 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   for (int i = tid; i <= M / 2; i += NT) ssin[i] = sp[i];
   constexpr int NW = (N + 63) / 64;
+  static_assert(ZM != 3 || (NC == 2 && DIM == 3), "the antisymmetric z pass is for the coupled 3D pair");
   if constexpr (ZM == 1) Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp, BitRows<NW>{zin});
+  else if constexpr (ZM == 3) Tl::template load_pre<true>(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
   else Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
@@ -1121,6 +1130,73 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fhn(FhnArgs a,
   }
 }
 
+// The forward x pass of the volume solve when the source is antisymmetric (no stimulus current:
+// f = (kappa V1, -kappa V1), V1 the forward Euler half step of V): only g = kappa V1 is
+// transformed, as one field in component 0 of work (rows of that field paired as in k_dst_x),
+// and the z pass takes component 1 as -g.  Half the pencils and half the writes of FHN_FE.
+// One pencil pair per wave at a time: a lane forms the values of both rows at one position and
+// writes them as one 16-byte LDS word.  M >= 64.
+template <int M>
+__global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fe1(FhnArgs a, double *__restrict__ work,
+                                                                    int64_t rows, const C2<double> *__restrict__ tw,
+                                                                    const double *__restrict__ sp) {
+  static_assert(M >= 64, "one pencil pair per wave needs M >= 64");
+  using Sh = Shape<double, M>;
+  using C = C2<double>;
+  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
+  constexpr int NWV = NT / 64, PPW = NP / NWV, KS = M / 64;
+  __shared__ C sbuf[NP * PADM];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 2 * NP;
+  const Sines<double, M> sn(sp, tid % Sh::TPP);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+  const double *__restrict__ V = a.V;
+  const double *__restrict__ q = a.q;
+  double va[PPW][KS][2], qa[PPW][KS][2];
+#pragma unroll
+  for (int pp = 0; pp < PPW; ++pp) {
+    const int64_t rowa = r0 + 2 * (wv + NWV * pp);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool ok = rowa + h < rows;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        va[pp][k][h] = ok && n < N ? V[(rowa + h) * N + n] : 0.0;
+        qa[pp][k][h] = ok && n < N ? q[(rowa + h) * N + n] : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < PPW; ++pp)
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int n = lane + 64 * k;
+      if (n < N) {
+        double v0 = va[pp][k][0], g0 = qa[pp][k][0], v1 = va[pp][k][1], g1 = qa[pp][k][1];
+        fhn_fe(v0, g0, a.dth, a.m);
+        fhn_fe(v1, g1, a.dth, a.m);
+        sbuf[(wv + NWV * pp) * PADM + pad(n + 1)] = C{a.kappa * v0, a.kappa * v1};
+      }
+    }
+  __syncthreads();
+  dst_pair<double, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
+#pragma unroll
+  for (int pp = 0; pp < PPW; ++pp) {
+    const int rr = wv + NWV * pp;
+    const int64_t rowa = r0 + 2 * rr;
+    const bool oka = rowa < rows, okb = rowa + 1 < rows;
+    double *oa = work + rowa * M, *ob = oa + M;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int n = lane + 64 * k;   // n = N: the pad column, written as zero
+      const C c = n < N ? sbuf[rr * PADM + pad(n + 1)] : C{0.0, 0.0};
+      if (oka) oa[n] = c.x;
+      if (okb) ob[n] = c.y;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 //
 // Every dense pass exists at two tile widths (W = 1, 2: pencil pairs per workgroup); the
@@ -1154,12 +1230,19 @@ void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint6
 template <typename T, int M, int W>
 void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms,
                  const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr) {
+                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr, bool anti = false) {
   using Sh = Shape<T, M, W>;
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
+  if (anti && (dim != 3 || ncomp != 2 || zin || !zout))
+    throw std::invalid_argument("the antisymmetric z pass takes the coupled 3D pair and an output plane mask");
   if (dim == 3) {
-    if (zin && zout) {
+    if (anti) {
+      if constexpr (StridedTile<T, M, Sh::NP, 2, W>::VEC)
+        k_dst_last<T, M, 2, 3, W, 3><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, {}, *zout);
+      else
+        throw std::invalid_argument("the antisymmetric z pass needs tiles of whole 16-byte vectors (M >= 64)");
+    } else if (zin && zout) {
       if (ncomp == 2) k_dst_last<T, M, 2, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
       else k_dst_last<T, M, 1, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
     } else if (zout) {
@@ -1192,10 +1275,11 @@ void pass_y(int w, const T *in, T *out, int64_t P, int64_t cs, int ncomp, const 
 template <typename T, int M>
 void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
                const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-               const T *in = nullptr, const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr) {
+               const T *in = nullptr, const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr,
+               bool anti = false) {
   if (!in) in = a;
-  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout);
-  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout);
+  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, anti);
+  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, anti);
 }
 
 template <typename T>
@@ -1257,7 +1341,7 @@ void run_box(DevProblem &p, const T *src, bool src_plain, T *dst, bool dst_plain
 // values at every stencil node are identical to the full solve.
 // skip_x: work already holds the forward x pass of the source (src unused).
 template <typename T, int M>
-void run_box_stencils(DevProblem &p, const T *src, hipStream_t st, bool skip_x = false) {
+void run_box_stencils(DevProblem &p, const T *src, hipStream_t st, bool skip_x = false, bool anti = false) {
   constexpr int N = M - 1;
   using Sh = Shape<T, M>;
   PrecTables<T> &tb = p.tab<T>();
@@ -1275,12 +1359,24 @@ void run_box_stencils(DevProblem &p, const T *src, hipStream_t st, bool skip_x =
     pass_x<T, M>(w[0], src, false, A, false, rows, tw, sp, st);
     toc(p.t_dst_x);
   }
-  tic(p.t_dst_y);
-  pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
-  toc(p.t_dst_y);
-  tic(p.t_dst_last_out);
-  pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, nullptr, nullptr, &p.planes_out_bits);
-  toc(p.t_dst_last_out);
+  if (anti) {
+    // antisymmetric source (component 1 = -component 0): y forward over component 0 only, and
+    // the z pass reads it as the pair (g, -g) and writes both components
+    tic(p.t_dst_y1);
+    pass_y<T, M>(w[1], A, A, P, cs, 1, nullptr, nullptr, tw, sp, st);
+    toc(p.t_dst_y1);
+    tic(p.t_dst_last_anti);
+    pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, nullptr, nullptr, &p.planes_out_bits,
+                    true);
+    toc(p.t_dst_last_anti);
+  } else {
+    tic(p.t_dst_y);
+    pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, nullptr, tw, sp, st);
+    toc(p.t_dst_y);
+    tic(p.t_dst_last_out);
+    pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, nullptr, nullptr, &p.planes_out_bits);
+    toc(p.t_dst_last_out);
+  }
   tic(p.t_dst_y_sparse);
   pass_y<T, M>(w[1], A, A, P, cs, p.ncomp, nullptr, p.mask_out, tw, sp, st, p.planes_out);
   toc(p.t_dst_y_sparse);
@@ -1306,8 +1402,31 @@ void launch_x_fhn(DevProblem &p, const FhnArgs &a, hipStream_t st) {
   p.t_dst_x_fhn.toc(p.profile, st);
 }
 
+// Without a stimulus current the source (kappa V1, -kappa V1) is antisymmetric: the 3D volume
+// solve then transforms the one field kappa V1 forward along x and y, and its z pass takes the
+// second component as the negative of the first (k_dst_x_fe1, dst_last_tile with ZM = 3).
+template <int M>
+void launch_x_fe1(DevProblem &p, const FhnArgs &a, hipStream_t st) {
+  using Sh = Shape<double, M>;
+  if (p.ncomp != 2 || p.P != M || p.dim != 3) throw std::invalid_argument("antisymmetric x pass: coupled 3D pair");
+  const int64_t rows = p.N * p.N;
+  const unsigned g = (unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP));
+  p.t_dst_x_fe1.tic(p.profile, st);
+  k_dst_x_fe1<M><<<g, Sh::NT, 0, st>>>(a, p.f64.work, rows, reinterpret_cast<const C2<double> *>(p.f64.tw),
+                                       p.f64.sp);
+  KFBI_HIP(hipGetLastError());
+  p.t_dst_x_fe1.toc(p.profile, st);
+}
+
 template <int M>
 void run_bidomain_volume(DevProblem &p, const FhnArgs &a, hipStream_t st) {
+  if constexpr (M >= 64) {
+    if (p.dim == 3 && p.sparse && !a.stim) {
+      launch_x_fe1<M>(p, a, st);
+      run_box_stencils<double, M>(p, nullptr, st, true, true);
+      return;
+    }
+  }
   launch_x_fhn<M, FHN_FE>(p, a, st);
   if (p.dim == 3 && p.sparse) run_box_stencils<double, M>(p, nullptr, st, true);
   else run_box<double, M>(p, nullptr, false, p.f64.work, false, st, 1);

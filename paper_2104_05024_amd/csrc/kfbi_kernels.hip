@@ -832,7 +832,8 @@ void upload_tables(DevProblem &p) {
   p.red = dalloc<double>(4096);
   KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
-                 &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn};
+                 &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn, &p.t_dst_x_fe1,
+                 &p.t_dst_y1, &p.t_dst_last_anti};
   for (Timer *tm : ts) tm->create();
 }
 
@@ -864,7 +865,8 @@ void free_tables(DevProblem &p) {
   free_prec(p.f64);
   free_prec(p.f32);
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
-                 &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn};
+                 &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn, &p.t_dst_x_fe1,
+                 &p.t_dst_y1, &p.t_dst_last_anti};
   for (Timer *tm : ts) tm->destroy();
 }
 
