@@ -736,6 +736,29 @@ def test_bidomain_zero_state_then_stimulus():
     bd.close()
 
 
+def test_antisymmetric_volume_solve_matches_the_coupled_one():
+    """Without a stimulus current the volume solve's source (kappa V1, -kappa V1) is
+    antisymmetric, and its forward passes run over the one field kappa V1 (the second component
+    taken as its negative).  Three steps on the 64^3 shell with I_stim = None (that path) against
+    the same steps with an all-zero stimulus current (the coupled path): V, q and the densities
+    agree to rounding."""
+    g, o, iface, grid, co = problems("shell_64")
+    n = grid.n ** 3
+    V0, q0 = W.ball_state(grid, W.stimulus_center(iface), radius=0.3)
+    out = []
+    for stim in (None, T(np.zeros(n))):
+        bd = K.Bidomain(g, P_BIDO, tol=1e-12)
+        V, q, hist = T(V0), T(q0), _zeros_hist(g)
+        for _ in range(3):
+            info = bd.step(V, q, hist, 0.01, I_stim=stim)
+            assert info["rel_resid"] <= 1e-12
+        out.append((V.cpu().numpy(), q.cpu().numpy(), hist.cpu().numpy()))
+        bd.close()
+    eV, eq, ep = err(out[0][0], out[1][0]), err(out[0][1], out[1][1]), err(out[0][2], out[1][2])
+    say(f"[antisymmetric volume solve] V {eV:.2e} q {eq:.2e} psi {ep:.2e}")
+    assert eV < 1e-10 and eq < 1e-10 and ep < 1e-9
+
+
 def test_recycled_residual_does_not_drift_over_100_steps():
     """Plain FP64 steps take their starting residual from the previous step and their final one
     from the Arnoldi relation, never from a product.  Over 100 steps of the 64^3 shell the true
