@@ -290,7 +290,8 @@ def variant_kwargs(name, a):
 
 
 KERNELS = ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse", "dst_last_sparse", "dst_last_out",
-           "dst_x_fhn", "dst_x_fe1", "dst_y1", "dst_last_anti", "jumps", "correct", "gather")
+           "dst_x_fhn", "dst_x_fe1", "dst_y1", "dst_last_anti", "dst_last_diff", "dst_x_be1", "jumps", "correct",
+           "gather")
 
 
 def main():
@@ -417,7 +418,10 @@ def main():
     # V, q written).  Without a stimulus current the volume solve's source is antisymmetric and its
     # forward passes run over one field: dst_x_fe1 (V, q read, one field written), dst_y1 (one field
     # read and written) and dst_last_anti (one field read, the stencil planes of both components
-    # written); dst_x_fhn then holds only the other two forms.
+    # written).  When the potentials are not returned, the final solve needs only Phi_i - Phi_e:
+    # dst_last_diff (the pair read, one field written), dst_y1 again for its inverse y pass, and
+    # dst_x_be1 (one field, V and q read, V and q written).  dst_x_fhn is priced as the mean of the
+    # forms it still holds.
     ref = "plain" if "plain" in kt else head
     N = grid.n
     nc = co.ncomp
@@ -434,9 +438,10 @@ def main():
                                      * 8 / 2),
                "dst_x_fe1": 1.5 * field_bytes, "dst_y1": float(field_bytes),
                "dst_last_anti": float(field_bytes / 2 + nc * N * N * 8 * planes_out),
-               "dst_x_fhn": ((2.0 * field_bytes + (2.0 * field_bytes + rows_in * N * 8) + 3.0 * field_bytes) / 3.0
-                             if kt[ref]["dst_x_fe1"][1] == 0 else
-                             ((2.0 * field_bytes + rows_in * N * 8) + 3.0 * field_bytes) / 2.0)}
+               "dst_last_diff": 1.5 * field_bytes, "dst_x_be1": 2.5 * field_bytes,
+               "dst_x_fhn": float(np.mean([2.0 * field_bytes + rows_in * N * 8]
+                                          + ([2.0 * field_bytes] if kt[ref]["dst_x_fe1"][1] == 0 else [])
+                                          + ([3.0 * field_bytes] if kt[ref]["dst_x_be1"][1] == 0 else [])))}
     tot = {k: us * n for k, (us, n) in kt[ref].items()}
     priced = [k for k in algo_of if kt[ref][k][1] > 0]
     dom = max(priced, key=tot.get)

@@ -370,7 +370,10 @@ const char *kfbi_last_error(void);
  * that also carry its reaction half steps), "dst_x_fe1", "dst_y1", "dst_last_anti" (the volume
  * solve of a step without stimulus current, whose source is antisymmetric: the forward x and y
  * passes over the one field kappa V1, and the z pass that reads it as the pair (g, -g)),
- * "correct", "gather", "jumps").
+ * "dst_last_diff", "dst_x_be1" (the final solve of a step whose potentials are not returned:
+ * the z pass that stores only Phi_i - Phi_e, and the inverse x pass with the backward Euler
+ * update over that one field; its inverse y pass counts under "dst_y1"), "correct", "gather",
+ * "jumps").
  * Returns KFBI_EINVAL if the name is unknown. */
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
 /* DST tile widths (1 or 2: multiples of the base pencil pairs per workgroup) of the x, y and

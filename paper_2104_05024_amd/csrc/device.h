@@ -131,7 +131,7 @@ struct DevProblem {
 
   bool profile = false;
   Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse, t_dst_last_sparse,
-      t_dst_last_out, t_dst_x_fhn, t_dst_x_fe1, t_dst_y1, t_dst_last_anti;
+      t_dst_last_out, t_dst_x_fhn, t_dst_x_fe1, t_dst_y1, t_dst_last_anti, t_dst_last_diff, t_dst_x_be1;
   hipStream_t stream = nullptr;
 
   template <typename T>

@@ -645,10 +645,12 @@ struct StridedTile {
     }
   }
 
-  // rows: only rows r with rows(r) true are written
-  template <typename R = AllRows>
+  // rows: only rows r with rows(r) true are written.  DIFF (NC = 2): only the difference
+  // component 0 - component 1 is written, into component 0.
+  template <bool DIFF = false, typename R = AllRows>
   __device__ static void store(T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
                                const R &rows = R()) {
+    static_assert(!DIFF || (NC == 2 && VEC), "a difference is stored from a pair of components");
     if constexpr (VEC) {
       constexpr int VPR = TX / VW, NU = N * VPR, PU = (NU + NT - 1) / NT;
       V16<T> reg[PU][NC];
@@ -657,7 +659,13 @@ struct StridedTile {
         const int e = tid + i * NT;
         const int s = e % VPR, r = e / VPR;
         if (e < NU) {
-          if constexpr (NC == 2) {
+          if constexpr (DIFF) {
+#pragma unroll
+            for (int j = 0; j < VW; ++j) {
+              const C2<T> v = sbuf[(s * VW + j) * PADM + pad(r + 1)];
+              reg[i][0].v[j] = x0 + s * VW + j < N ? v.x - v.y : T(0);
+            }
+          } else if constexpr (NC == 2) {
 #pragma unroll
             for (int j = 0; j < VW; ++j) {
               const C2<T> v = sbuf[(s * VW + j) * PADM + pad(r + 1)];
@@ -681,7 +689,7 @@ struct StridedTile {
         const int s = e % VPR, r = e / VPR;
         if (e < NU && rows(r))
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
+          for (int c = 0; c < (DIFF ? 1 : NC); ++c)
             *reinterpret_cast<V16<T> *>(base + c * CS + (int64_t)r * RS + x0 + s * VW) = reg[i][c];
       }
     } else {
@@ -765,7 +773,9 @@ struct ModeHook {
 // read) and the planes needed on output (the others are not written); ZM = 2: every plane is
 // read, only the planes in zout are written; ZM = 3 (coupled pair): as ZM = 2 for an
 // antisymmetric source, component 1 of the input being minus component 0, so that only
-// component 0 is read (the input may then hold one component).
+// component 0 is read (the input may then hold one component); ZM = 4 (coupled pair): every
+// plane read, and only the difference component 0 - component 1 written, into component 0 (the
+// final solve of a step whose potentials are not returned needs only Phi_i - Phi_e).
 // One tile of the pass: tile number id of total (gx tiles per row of the grid of tiles), LDS
 // buffers sbuf (NP * PADM values), slam (M) and ssin (M / 2 + 1).
 template <typename T, int M, int NC, int DIM, int W = 1, int ZM = 0>
@@ -793,7 +803,7 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   for (int i = tid; i <= M / 2; i += NT) ssin[i] = sp[i];
   constexpr int NW = (N + 63) / 64;
-  static_assert(ZM != 3 || (NC == 2 && DIM == 3), "the antisymmetric z pass is for the coupled 3D pair");
+  static_assert((ZM != 3 && ZM != 4) || (NC == 2 && DIM == 3), "the ZM = 3, 4 z passes are for the coupled 3D pair");
   if constexpr (ZM == 1) Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp, BitRows<NW>{zin});
   else if constexpr (ZM == 3) Tl::template load_pre<true>(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
   else Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
@@ -826,7 +836,8 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
   dst_pair<T, M>(mine, lane, tw, Sines<T, M>(ssin, lane), mh);
-  if constexpr (ZM != 0) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
+  if constexpr (ZM == 4) Tl::template store<true>(base, LS * P, comp_stride, x0, sbuf, tid);
+  else if constexpr (ZM != 0) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
   else Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
 
@@ -1197,6 +1208,83 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fe1(FhnArgs a,
   }
 }
 
+// The inverse x pass of the final solve when its potentials are not returned: only
+// d = Phi_i - Phi_e enters the step (V <- 2 d - V1, then backward Euler), and the inverse
+// transforms are linear, so the z pass stores d (ZM = 4), the inverse y pass runs over that one
+// field, and this pass transforms its rows in pairs (as k_dst_x) before the pointwise update of
+// FHN_BE.  Half the pencils and a third less traffic than FHN_BE.  M >= 64.
+template <int M>
+__global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_be1(FhnArgs a, const double *__restrict__ work,
+                                                                    int64_t rows, const C2<double> *__restrict__ tw,
+                                                                    const double *__restrict__ sp) {
+  static_assert(M >= 64, "one pencil pair per wave needs M >= 64");
+  using Sh = Shape<double, M>;
+  using C = C2<double>;
+  constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
+  constexpr int NWV = NT / 64, PPW = NP / NWV, KS = M / 64;
+  __shared__ C sbuf[NP * PADM];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 2 * NP;
+  const Sines<double, M> sn(sp, tid % Sh::TPP);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+  double *__restrict__ V = a.V;
+  double *__restrict__ q = a.q;
+  {
+    C d[PPW][KS];
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp) {
+      const int64_t rowa = r0 + 2 * (wv + NWV * pp);
+      const bool oka = rowa < rows, okb = rowa + 1 < rows;
+      const double *ra = work + rowa * M, *rb = ra + M;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        d[pp][k] = {oka && n < N ? ra[n] : 0.0, okb && n < N ? rb[n] : 0.0};
+      }
+    }
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp)
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int n = lane + 64 * k;
+        if (n < N) sbuf[(wv + NWV * pp) * PADM + pad(n + 1)] = d[pp][k];
+      }
+  }
+  __syncthreads();
+  dst_pair<double, M>(sbuf + (tid / Sh::TPP) * PADM, tid % Sh::TPP, tw, sn);
+  // V and q after the transform (fetched ahead of it they would be held across it), a thread's
+  // elements in two chunks whose loads are all issued before the chunk's first store (V and q
+  // are read and written through the same pointers, so loads are not moved across stores)
+  constexpr int NE = 2 * NP * N, PER = (NE + NT - 1) / NT, CH = PER > 16 ? 16 : PER;
+#pragma unroll
+  for (int c0 = 0; c0 < PER; c0 += CH) {
+    double va[CH], qa[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int e = tid + (c0 + i) * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      const bool ok = c0 + i < PER && e < NE && row < rows;
+      va[i] = ok ? V[row * N + n] : 0.0;
+      qa[i] = ok ? q[row * N + n] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int e = tid + (c0 + i) * NT;
+      const int rr = e / N, n = e - rr * N;
+      const int64_t row = r0 + rr;
+      if (c0 + i < PER && e < NE && row < rows) {
+        const C u = sbuf[(rr >> 1) * PADM + pad(n + 1)];
+        double v1 = va[i], q1 = qa[i], vn, qn;
+        fhn_fe(v1, q1, a.dth, a.m);
+        fhn_be(2.0 * ((rr & 1) ? u.y : u.x) - v1, q1, a.dth, a.m, vn, qn);
+        V[row * N + n] = vn;
+        q[row * N + n] = qn;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 //
 // Every dense pass exists at two tile widths (W = 1, 2: pencil pairs per workgroup); the
@@ -1230,18 +1318,23 @@ void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint6
 template <typename T, int M, int W>
 void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms,
                  const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr, bool anti = false) {
+                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr, int form = 0) {
   using Sh = Shape<T, M, W>;
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
-  if (anti && (dim != 3 || ncomp != 2 || zin || !zout))
+  // form 3: antisymmetric source (needs zout); form 4: the difference of the pair (no masks)
+  if (form == 3 && (dim != 3 || ncomp != 2 || zin || !zout))
     throw std::invalid_argument("the antisymmetric z pass takes the coupled 3D pair and an output plane mask");
+  if (form == 4 && (dim != 3 || ncomp != 2 || zin || zout))
+    throw std::invalid_argument("the difference z pass takes the coupled 3D pair and no plane masks");
   if (dim == 3) {
-    if (anti) {
-      if constexpr (StridedTile<T, M, Sh::NP, 2, W>::VEC)
-        k_dst_last<T, M, 2, 3, W, 3><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, {}, *zout);
-      else
-        throw std::invalid_argument("the antisymmetric z pass needs tiles of whole 16-byte vectors (M >= 64)");
+    if (form == 3 || form == 4) {
+      if constexpr (StridedTile<T, M, Sh::NP, 2, W>::VEC) {
+        if (form == 3) k_dst_last<T, M, 2, 3, W, 3><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, {}, *zout);
+        else k_dst_last<T, M, 2, 3, W, 4><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+      } else {
+        throw std::invalid_argument("the z passes of forms 3 and 4 need tiles of whole 16-byte vectors (M >= 64)");
+      }
     } else if (zin && zout) {
       if (ncomp == 2) k_dst_last<T, M, 2, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
       else k_dst_last<T, M, 1, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
@@ -1276,10 +1369,10 @@ template <typename T, int M>
 void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
                const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
                const T *in = nullptr, const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr,
-               bool anti = false) {
+               int form = 0) {
   if (!in) in = a;
-  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, anti);
-  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, anti);
+  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, form);
+  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, form);
 }
 
 template <typename T>
@@ -1367,7 +1460,7 @@ void run_box_stencils(DevProblem &p, const T *src, hipStream_t st, bool skip_x =
     toc(p.t_dst_y1);
     tic(p.t_dst_last_anti);
     pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, nullptr, nullptr, &p.planes_out_bits,
-                    true);
+                    3);
     toc(p.t_dst_last_anti);
   } else {
     tic(p.t_dst_y);
@@ -1434,6 +1527,35 @@ void run_bidomain_volume(DevProblem &p, const FhnArgs &a, hipStream_t st) {
 
 template <int M>
 void run_bidomain_final(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st) {
+  if constexpr (M >= 64) {
+    if (p.dim == 3 && fuse_be) {
+      // only Phi_i - Phi_e is needed: the z pass stores it, and the inverse y and x passes (the
+      // latter with the backward Euler update) run over that one field
+      launch_x_fhn<M, FHN_SRC>(p, a, st);
+      using Sh = Shape<double, M>;
+      PrecTables<double> &tb = p.f64;
+      double *A = tb.work;
+      const C2<double> *tw = reinterpret_cast<const C2<double> *>(tb.tw);
+      const int64_t P = p.P, cs = p.comp_stride;
+      const int *w = p.tile_w[0];
+      p.t_dst_y.tic(p.profile, st);
+      pass_y<double, M>(w[1], A, A, P, cs, 2, nullptr, nullptr, tw, tb.sp, st);
+      p.t_dst_y.toc(p.profile, st);
+      p.t_dst_last_diff.tic(p.profile, st);
+      pass_last<double, M>(w[2], A, 3, 2, P, cs, mode_of<double>(p), tw, tb.sp, nullptr, 1, 0, st, nullptr, nullptr,
+                           nullptr, 4);
+      p.t_dst_last_diff.toc(p.profile, st);
+      p.t_dst_y1.tic(p.profile, st);
+      pass_y<double, M>(w[1], A, A, P, cs, 1, nullptr, nullptr, tw, tb.sp, st);
+      p.t_dst_y1.toc(p.profile, st);
+      const int64_t rows = p.N * p.N;
+      p.t_dst_x_be1.tic(p.profile, st);
+      k_dst_x_be1<M><<<(unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP)), Sh::NT, 0, st>>>(a, A, rows, tw, tb.sp);
+      KFBI_HIP(hipGetLastError());
+      p.t_dst_x_be1.toc(p.profile, st);
+      return;
+    }
+  }
   launch_x_fhn<M, FHN_SRC>(p, a, st);
   run_box<double, M>(p, nullptr, false, p.f64.work, false, st, fuse_be ? 3 : 1);
   if (fuse_be) launch_x_fhn<M, FHN_BE>(p, a, st);

@@ -833,7 +833,7 @@ void upload_tables(DevProblem &p) {
   KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
                  &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn, &p.t_dst_x_fe1,
-                 &p.t_dst_y1, &p.t_dst_last_anti};
+                 &p.t_dst_y1, &p.t_dst_last_anti, &p.t_dst_last_diff, &p.t_dst_x_be1};
   for (Timer *tm : ts) tm->create();
 }
 
@@ -866,7 +866,7 @@ void free_tables(DevProblem &p) {
   free_prec(p.f32);
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
                  &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn, &p.t_dst_x_fe1,
-                 &p.t_dst_y1, &p.t_dst_last_anti};
+                 &p.t_dst_y1, &p.t_dst_last_anti, &p.t_dst_last_diff, &p.t_dst_x_be1};
   for (Timer *tm : ts) tm->destroy();
 }
 

@@ -323,11 +323,13 @@ def test_bidomain_mixed_precision_step():
     bd.close()
 
 
-def test_bidomain_state_does_not_depend_on_returning_potentials():
+@pytest.mark.parametrize("name", ["ellipsoid_bido_32", "shell_64"])
+def test_bidomain_state_does_not_depend_on_returning_potentials(name):
     """Without phi the midpoint update and the backward Euler half step ride in the inverse x
-    pass of the final box solve; with phi they run as a separate sweep after the gauge.  Both
-    give the same V and q."""
-    g, o, iface, grid, co = problems("ellipsoid_bido_32")
+    pass of the final box solve (from 64^3 on, over the one field Phi_i - Phi_e, which the z
+    pass stores); with phi they run as a separate sweep after the gauge.  Both give the same V
+    and q."""
+    g, o, iface, grid, co = problems(name)
     V0, q0 = obd.initial_state(grid, W.stimulus_center(iface), radius=0.3)
     out = []
     for with_phi in (False, True):
