@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_fe1(FhnArgs a,
 // d = Phi_i - Phi_e enters the step (V <- 2 d - V1, then backward Euler), and the inverse
 // transforms are linear, so the z pass stores d (ZM = 4), the inverse y pass runs over that one
 // field, and this pass transforms its rows in pairs (as k_dst_x) before the pointwise update of
-// FHN_BE.  Half the pencils and a third less traffic than FHN_BE.  M >= 64.
+// FHN_BE.  Half the pencils and a sixth less traffic than FHN_BE.  M >= 64.
 template <int M>
 __global__ __launch_bounds__((Shape<double, M>::NT)) void k_dst_x_be1(FhnArgs a, const double *__restrict__ work,
                                                                     int64_t rows, const C2<double> *__restrict__ tw,
