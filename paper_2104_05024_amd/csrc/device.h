@@ -264,11 +264,13 @@ struct FhnArgs {
 // value and the pointwise work of the splitting rides in those passes:
 //   bidomain_volume_solve: S f for f = (kappa V1, -kappa V1 + beta I), (V1, q1) the forward
 //     Euler half step of (V, q), into work (extrapolation-stencil values, as
-//     box_solve_stencils); V and q are left unchanged;
+//     box_solve_stencils); V and q are left unchanged.  Without I (3D, M >= 64) the source is
+//     antisymmetric and the forward x and y passes run over the one field kappa V1;
 //   bidomain_final_solve: S(f + C psi) with C psi taken from rhs (launch_correct), into work;
 //     with fuse_be the inverse x pass instead finishes the step: V <- 2 (u_i - u_e) - V1 and the
 //     backward Euler half step from q1 into V and q, and work is left holding the y-inverse
-//     output.  Each pass recomputes (V1, q1) from the unchanged (V, q).
+//     output (3D, M >= 64: of u_i - u_e alone, in component 0, the only field the update
+//     needs).  Each pass recomputes (V1, q1) from the unchanged (V, q).
 void bidomain_volume_solve(DevProblem &p, const FhnArgs &a, hipStream_t st);
 void bidomain_final_solve(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream_t st);
 
