@@ -290,8 +290,8 @@ def variant_kwargs(name, a):
 
 
 KERNELS = ("dst_x", "dst_y", "dst_last", "dst_x_rows", "dst_y_sparse", "dst_last_sparse", "dst_last_out",
-           "dst_x_fhn", "dst_x_fe1", "dst_y1", "dst_last_anti", "dst_last_diff", "dst_x_be1", "jumps", "correct",
-           "gather")
+           "dst_x_fhn", "dst_x_fe1", "dst_y1", "dst_last_anti", "dst_last_diff", "dst_last_comb", "dst_x_be1", "jumps",
+           "correct", "gather")
 
 
 def main():
@@ -420,8 +420,10 @@ def main():
     # read and written) and dst_last_anti (one field read, the stencil planes of both components
     # written).  When the potentials are not returned, the final solve needs only Phi_i - Phi_e:
     # dst_last_diff (the pair read, one field written), dst_y1 again for its inverse y pass, and
-    # dst_x_be1 (one field, V and q read, V and q written).  dst_x_fhn is priced as the mean of the
-    # forms it still holds.
+    # dst_x_be1 (one field, V and q read, V and q written).  Without a stimulus current as well, that
+    # z pass (dst_last_comb) adds C psi's transform, taken through the masked row and plane passes,
+    # to the volume solve's transform of kappa V1 as it loads: one field and the irregular planes of
+    # the pair read, one field written.  dst_x_fhn is priced as the mean of the forms it still holds.
     ref = "plain" if "plain" in kt else head
     N = grid.n
     nc = co.ncomp
@@ -439,9 +441,12 @@ def main():
                "dst_x_fe1": 1.5 * field_bytes, "dst_y1": float(field_bytes),
                "dst_last_anti": float(field_bytes / 2 + nc * N * N * 8 * planes_out),
                "dst_last_diff": 1.5 * field_bytes, "dst_x_be1": 2.5 * field_bytes,
-               "dst_x_fhn": float(np.mean([2.0 * field_bytes + rows_in * N * 8]
+               "dst_last_comb": float(field_bytes + nc * N * N * 8 * planes_in),
+               "dst_x_fhn": float(np.mean(([2.0 * field_bytes + rows_in * N * 8]
+                                           if kt[ref]["dst_last_comb"][1] == 0 else [])
                                           + ([2.0 * field_bytes] if kt[ref]["dst_x_fe1"][1] == 0 else [])
-                                          + ([3.0 * field_bytes] if kt[ref]["dst_x_be1"][1] == 0 else [])))}
+                                          + ([3.0 * field_bytes] if kt[ref]["dst_x_be1"][1] == 0 else [])
+                                          or [0.0]))}
     tot = {k: us * n for k, (us, n) in kt[ref].items()}
     priced = [k for k in algo_of if kt[ref][k][1] > 0]
     dom = max(priced, key=tot.get)

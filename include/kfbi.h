@@ -372,8 +372,10 @@ const char *kfbi_last_error(void);
  * passes over the one field kappa V1, and the z pass that reads it as the pair (g, -g)),
  * "dst_last_diff", "dst_x_be1" (the final solve of a step whose potentials are not returned:
  * the z pass that stores only Phi_i - Phi_e, and the inverse x pass with the backward Euler
- * update over that one field; its inverse y pass counts under "dst_y1"), "correct", "gather",
- * "jumps").
+ * update over that one field; its inverse y pass counts under "dst_y1"), "dst_last_comb" (that
+ * z pass when the step also has no stimulus current: it adds the transform of C psi, taken
+ * through the masked row and plane passes, to the volume solve's transform of kappa V1 as it
+ * loads), "correct", "gather", "jumps").
  * Returns KFBI_EINVAL if the name is unknown. */
 int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t *launches);
 /* DST tile widths (1 or 2: multiples of the base pencil pairs per workgroup) of the x, y and

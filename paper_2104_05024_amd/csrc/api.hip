@@ -332,7 +332,7 @@ int kfbi_profile(kfbi_problem p, int32_t enable) {
     Timer *ts[] = {&p->p.t_dst_x, &p->p.t_dst_y, &p->p.t_dst_last, &p->p.t_correct, &p->p.t_gather,
                    &p->p.t_jumps, &p->p.t_dst_x_rows, &p->p.t_dst_y_sparse, &p->p.t_dst_last_sparse,
                    &p->p.t_dst_last_out, &p->p.t_dst_x_fhn, &p->p.t_dst_x_fe1, &p->p.t_dst_y1,
-                   &p->p.t_dst_last_anti, &p->p.t_dst_last_diff, &p->p.t_dst_x_be1};
+                   &p->p.t_dst_last_anti, &p->p.t_dst_last_diff, &p->p.t_dst_x_be1, &p->p.t_dst_last_comb};
     for (Timer *t : ts) t->reset();
     return KFBI_OK;
   });
@@ -358,6 +358,7 @@ int kfbi_kernel_time(kfbi_problem p, const char *kernel, double *avg_us, int64_t
   else if (s == "dst_last_anti") t = &p->p.t_dst_last_anti;
   else if (s == "dst_last_diff") t = &p->p.t_dst_last_diff;
   else if (s == "dst_x_be1") t = &p->p.t_dst_x_be1;
+  else if (s == "dst_last_comb") t = &p->p.t_dst_last_comb;
   else return fail(KFBI_EINVAL, "unknown kernel class");
   return guard([&]() -> int {
     if (p->p.on_device) t->harvest();

@@ -39,6 +39,8 @@ struct PrecTables {          // per-precision device copies of the numeric table
   T *rhs = nullptr, *work = nullptr;     // matvec right-hand side (zero off irregular nodes), work field
   T *xbuf = nullptr;                     // sparse matvec: x-forward output, zero outside the rhs rows
   T *ybuf = nullptr;                     // sparse matvec: y-forward output, zero in planes without rhs rows
+  T *gbuf = nullptr;                     // coupled 3D FP64: x-y transform of kappa V1 (one component),
+                                         // kept from a step's volume solve for its final solve
   T *jz = nullptr;                       // jumps at crossings [comp][2][nc] (written in this precision)
   T *jq = nullptr;                       // jumps at nodes [comp][d+nh][M] (FP64 set only)
 };
@@ -131,7 +133,8 @@ struct DevProblem {
 
   bool profile = false;
   Timer t_dst_x, t_dst_y, t_dst_last, t_correct, t_gather, t_jumps, t_dst_x_rows, t_dst_y_sparse, t_dst_last_sparse,
-      t_dst_last_out, t_dst_x_fhn, t_dst_x_fe1, t_dst_y1, t_dst_last_anti, t_dst_last_diff, t_dst_x_be1;
+      t_dst_last_out, t_dst_x_fhn, t_dst_x_fe1, t_dst_y1, t_dst_last_anti, t_dst_last_diff, t_dst_x_be1,
+      t_dst_last_comb;
   hipStream_t stream = nullptr;
 
   template <typename T>

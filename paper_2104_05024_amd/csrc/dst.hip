@@ -584,11 +584,14 @@ struct StridedTile {
   // two fused: a thread loads rows r and N-1-r (positions n and M-n) of its columns and writes
   // t_n and t_{M-n} straight into LDS, which saves one LDS round trip of the tile.  The same
   // arithmetic as load(), barrier, dst_pre.  A barrier must follow before the transform.
-  // ANTI (NC = 2): only component 0 is read; component 1 is taken as its negative.
-  template <bool ANTI = false, typename R = AllRows>
+  // ANTI (NC = 2): only component 0 is read; component 1 is taken as its negative.  ADD2 (with
+  // ANTI): the pair read from base2 (both components, on the rows flagged by rows2) is added.
+  template <bool ANTI = false, bool ADD2 = false, typename R = AllRows, typename R2 = AllRows>
   __device__ static void load_pre(const T *__restrict__ base, int64_t RS, int64_t CS, int x0, C2<T> *sbuf, int tid,
-                                  const T *__restrict__ sp, const R &rows = R()) {
+                                  const T *__restrict__ sp, const R &rows = R(),
+                                  const T *__restrict__ base2 = nullptr, const R2 &rows2 = R2()) {
     static_assert(!ANTI || (NC == 2 && VEC), "an antisymmetric pair is read as two components");
+    static_assert(!ADD2 || ANTI, "the second input is added to an antisymmetric pair");
     if constexpr (!VEC) {
       load(base, RS, CS, x0, sbuf, tid, rows);
       __syncthreads();
@@ -596,11 +599,27 @@ struct StridedTile {
     } else {
       constexpr int VPR = TX / VW, NPR = M / 2, NU = NPR * VPR, PU = (NU + NT - 1) / NT;
       V16<T> ra[PU][NC], rb[PU][NC];
+      V16<T> sa[ADD2 ? PU : 1][2], sb[ADD2 ? PU : 1][2];
 #pragma unroll
       for (int i = 0; i < PU; ++i) {
         const int e = tid + i * NT;
         const int s = e % VPR, p = e / VPR, r0 = p, r1 = N - 1 - p;
         const bool ok0 = e < NU && rows(r0), ok1 = e < NU && rows(r1);
+        if constexpr (ADD2) {
+          const bool o20 = e < NU && rows2(r0), o21 = e < NU && rows2(r1);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const T *q2 = base2 + c * CS + x0 + s * VW;
+            if (o20) sa[i][c] = *reinterpret_cast<const V16<T> *>(q2 + (int64_t)r0 * RS);
+            else
+#pragma unroll
+              for (int j = 0; j < VW; ++j) sa[i][c].v[j] = T(0);
+            if (o21) sb[i][c] = *reinterpret_cast<const V16<T> *>(q2 + (int64_t)r1 * RS);
+            else
+#pragma unroll
+              for (int j = 0; j < VW; ++j) sb[i][c].v[j] = T(0);
+          }
+        }
 #pragma unroll
         for (int c = 0; c < (ANTI ? 1 : NC); ++c) {
           const T *q = base + c * CS + x0 + s * VW;
@@ -624,7 +643,10 @@ struct StridedTile {
 #pragma unroll
           for (int j = 0; j < NW; ++j) {
             C2<T> a, b;
-            if constexpr (ANTI) {
+            if constexpr (ADD2) {
+              a = {ra[i][0].v[j] + sa[i][0].v[j], -ra[i][0].v[j] + sa[i][1].v[j]};
+              b = {rb[i][0].v[j] + sb[i][0].v[j], -rb[i][0].v[j] + sb[i][1].v[j]};
+            } else if constexpr (ANTI) {
               a = {ra[i][0].v[j], -ra[i][0].v[j]};
               b = {rb[i][0].v[j], -rb[i][0].v[j]};
             } else if constexpr (NC == 2) {
@@ -775,7 +797,9 @@ struct ModeHook {
 // antisymmetric source, component 1 of the input being minus component 0, so that only
 // component 0 is read (the input may then hold one component); ZM = 4 (coupled pair): every
 // plane read, and only the difference component 0 - component 1 written, into component 0 (the
-// final solve of a step whose potentials are not returned needs only Phi_i - Phi_e).
+// final solve of a step whose potentials are not returned needs only Phi_i - Phi_e); ZM = 5
+// (coupled pair): as ZM = 4 for an input that is the antisymmetric pair (g, -g) of ain's
+// component 0 plus the pair read from ain2 on the planes in zin.
 // One tile of the pass: tile number id of total (gx tiles per row of the grid of tiles), LDS
 // buffers sbuf (NP * PADM values), slam (M) and ssin (M / 2 + 1).
 template <typename T, int M, int NC, int DIM, int W = 1, int ZM = 0>
@@ -784,7 +808,8 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
                                               const C2<T> *__restrict__ tw, const T *__restrict__ sp,
                                               const ModeScale *__restrict__ msv, int64_t pstride,
                                               const PlaneBits &zin, const PlaneBits &zout, C2<T> *sbuf, T *slam,
-                                              T *ssin, int64_t id, int64_t total, int gx) {
+                                              T *ssin, int64_t id, int64_t total, int gx,
+                                              const T *__restrict__ ain2 = nullptr) {
   using Sh = Shape<T, M, W>;
   constexpr int N = Sh::N, NP = Sh::NP, NT = Sh::NT, PADM = Sh::PADM;
   constexpr int TX = NC == 2 ? NP : 2 * NP;          // columns per tile
@@ -803,9 +828,12 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
   for (int i = tid; i < N; i += NT) slam[i] = (T)ms.lam[i];
   for (int i = tid; i <= M / 2; i += NT) ssin[i] = sp[i];
   constexpr int NW = (N + 63) / 64;
-  static_assert((ZM != 3 && ZM != 4) || (NC == 2 && DIM == 3), "the ZM = 3, 4 z passes are for the coupled 3D pair");
+  static_assert(ZM < 3 || (NC == 2 && DIM == 3), "the ZM = 3, 4, 5 z passes are for the coupled 3D pair");
   if constexpr (ZM == 1) Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp, BitRows<NW>{zin});
   else if constexpr (ZM == 3) Tl::template load_pre<true>(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
+  else if constexpr (ZM == 5)
+    Tl::template load_pre<true, true>(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp, AllRows{}, ain2 + boff,
+                                      BitRows<NW>{zin});
   else Tl::load_pre(ain + boff, LS * P, comp_stride, x0, sbuf, tid, sp);
   __syncthreads();
   const int pr = tid / Sh::TPP, lane = tid % Sh::TPP;
@@ -836,7 +864,7 @@ __device__ __forceinline__ void dst_last_tile(const T *__restrict__ ain, T *__re
   mh.kap = (T)ms.kappa;
   mh.nrm = (T)ms.norm;
   dst_pair<T, M>(mine, lane, tw, Sines<T, M>(ssin, lane), mh);
-  if constexpr (ZM == 4) Tl::template store<true>(base, LS * P, comp_stride, x0, sbuf, tid);
+  if constexpr (ZM == 4 || ZM == 5) Tl::template store<true>(base, LS * P, comp_stride, x0, sbuf, tid);
   else if constexpr (ZM != 0) Tl::store(base, LS * P, comp_stride, x0, sbuf, tid, BitRows<NW>{zout});
   else Tl::store(base, LS * P, comp_stride, x0, sbuf, tid);
 }
@@ -848,14 +876,15 @@ __global__ __launch_bounds__((Shape<T, M, W>::NT)) void k_dst_last(const T *__re
                                                                   const T *__restrict__ sp,
                                                                   const ModeScale *__restrict__ msv = nullptr,
                                                                   int64_t pstride = 0, PlaneBits zin = {},
-                                                                  PlaneBits zout = {}) {
+                                                                  PlaneBits zout = {},
+                                                                  const T *__restrict__ ain2 = nullptr) {
   using Sh = Shape<T, M, W>;
   __shared__ C2<T> sbuf[Sh::NP * Sh::PADM];
   __shared__ T slam[M];
   __shared__ T ssin[M / 2 + 1];
   dst_last_tile<T, M, NC, DIM, W, ZM>(ain, a, P, comp_stride, ms0, tw, sp, msv, pstride, zin, zout, sbuf, slam, ssin,
                                       blockIdx.x + (int64_t)gridDim.x * blockIdx.y,
-                                      (int64_t)gridDim.x * gridDim.y, (int)gridDim.x);
+                                      (int64_t)gridDim.x * gridDim.y, (int)gridDim.x, ain2);
 }
 
 // DST along contiguous rows listed in `rows` (indices into the flattened [comp][..] row list),
@@ -1318,22 +1347,27 @@ void launch_y(const T *in, T *out, int64_t P, int64_t cs, int ncomp, const uint6
 template <typename T, int M, int W>
 void launch_last(const T *in, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms,
                  const C2<T> *tw, const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
-                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr, int form = 0) {
+                 const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr, int form = 0,
+                 const T *in2 = nullptr) {
   using Sh = Shape<T, M, W>;
   const int tx = ncomp == 2 ? Sh::NP : 2 * Sh::NP;
   const dim3 g((Sh::N + tx - 1) / tx, dim == 3 ? Sh::N : nprob, 1);
-  // form 3: antisymmetric source (needs zout); form 4: the difference of the pair (no masks)
+  // form 3: antisymmetric source (needs zout); form 4: the difference of the pair (no masks);
+  // form 5: form 4 for the antisymmetric pair of in plus the pair of in2 on the planes in zin
   if (form == 3 && (dim != 3 || ncomp != 2 || zin || !zout))
     throw std::invalid_argument("the antisymmetric z pass takes the coupled 3D pair and an output plane mask");
   if (form == 4 && (dim != 3 || ncomp != 2 || zin || zout))
     throw std::invalid_argument("the difference z pass takes the coupled 3D pair and no plane masks");
+  if (form == 5 && (dim != 3 || ncomp != 2 || !zin || zout || !in2))
+    throw std::invalid_argument("the combined z pass takes the coupled 3D pair, a second input and its plane mask");
   if (dim == 3) {
-    if (form == 3 || form == 4) {
+    if (form >= 3) {
       if constexpr (StridedTile<T, M, Sh::NP, 2, W>::VEC) {
         if (form == 3) k_dst_last<T, M, 2, 3, W, 3><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, {}, *zout);
-        else k_dst_last<T, M, 2, 3, W, 4><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+        else if (form == 4) k_dst_last<T, M, 2, 3, W, 4><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp);
+        else k_dst_last<T, M, 2, 3, W, 5><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, {}, in2);
       } else {
-        throw std::invalid_argument("the z passes of forms 3 and 4 need tiles of whole 16-byte vectors (M >= 64)");
+        throw std::invalid_argument("the z passes of forms 3 to 5 need tiles of whole 16-byte vectors (M >= 64)");
       }
     } else if (zin && zout) {
       if (ncomp == 2) k_dst_last<T, M, 2, 3, W, 1><<<g, Sh::NT, 0, st>>>(in, a, P, cs, ms, tw, sp, nullptr, 0, *zin, *zout);
@@ -1369,10 +1403,10 @@ template <typename T, int M>
 void pass_last(int w, T *a, int dim, int ncomp, int64_t P, int64_t cs, const ModeScale &ms, const C2<T> *tw,
                const T *sp, const ModeScale *msv, int nprob, int64_t pstride, hipStream_t st,
                const T *in = nullptr, const PlaneBits *zin = nullptr, const PlaneBits *zout = nullptr,
-               int form = 0) {
+               int form = 0, const T *in2 = nullptr) {
   if (!in) in = a;
-  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, form);
-  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, form);
+  if (w == 2) launch_last<T, M, 2>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, form, in2);
+  else launch_last<T, M, 1>(in, a, dim, ncomp, P, cs, ms, tw, sp, msv, nprob, pstride, st, zin, zout, form, in2);
 }
 
 template <typename T>
@@ -1453,14 +1487,16 @@ void run_box_stencils(DevProblem &p, const T *src, hipStream_t st, bool skip_x =
     toc(p.t_dst_x);
   }
   if (anti) {
-    // antisymmetric source (component 1 = -component 0): y forward over component 0 only, and
-    // the z pass reads it as the pair (g, -g) and writes both components
+    // antisymmetric source (component 1 = -component 0), its one field in gbuf after the x
+    // pass: y forward over it (kept there for the step's final solve), and the z pass reads it
+    // as the pair (g, -g) and writes both components' stencil planes into work
+    T *G = tb.gbuf;
+    if (!G) throw std::logic_error("antisymmetric volume solve without its buffer");
     tic(p.t_dst_y1);
-    pass_y<T, M>(w[1], A, A, P, cs, 1, nullptr, nullptr, tw, sp, st);
+    pass_y<T, M>(w[1], G, G, P, cs, 1, nullptr, nullptr, tw, sp, st);
     toc(p.t_dst_y1);
     tic(p.t_dst_last_anti);
-    pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, nullptr, nullptr, &p.planes_out_bits,
-                    3);
+    pass_last<T, M>(w[2], A, 3, p.ncomp, P, cs, ms, tw, sp, nullptr, 1, 0, st, G, nullptr, &p.planes_out_bits, 3);
     toc(p.t_dst_last_anti);
   } else {
     tic(p.t_dst_y);
@@ -1496,16 +1532,18 @@ void launch_x_fhn(DevProblem &p, const FhnArgs &a, hipStream_t st) {
 }
 
 // Without a stimulus current the source (kappa V1, -kappa V1) is antisymmetric: the 3D volume
-// solve then transforms the one field kappa V1 forward along x and y, and its z pass takes the
-// second component as the negative of the first (k_dst_x_fe1, dst_last_tile with ZM = 3).
+// solve then transforms the one field kappa V1 forward along x and y (into gbuf, where the
+// step's final solve finds it again), and its z pass takes the second component as the
+// negative of the first (k_dst_x_fe1, dst_last_tile with ZM = 3).
 template <int M>
 void launch_x_fe1(DevProblem &p, const FhnArgs &a, hipStream_t st) {
   using Sh = Shape<double, M>;
   if (p.ncomp != 2 || p.P != M || p.dim != 3) throw std::invalid_argument("antisymmetric x pass: coupled 3D pair");
   const int64_t rows = p.N * p.N;
   const unsigned g = (unsigned)((rows + 2 * Sh::NP - 1) / (2 * Sh::NP));
+  if (!p.f64.gbuf) throw std::logic_error("antisymmetric x pass without its buffer");
   p.t_dst_x_fe1.tic(p.profile, st);
-  k_dst_x_fe1<M><<<g, Sh::NT, 0, st>>>(a, p.f64.work, rows, reinterpret_cast<const C2<double> *>(p.f64.tw),
+  k_dst_x_fe1<M><<<g, Sh::NT, 0, st>>>(a, p.f64.gbuf, rows, reinterpret_cast<const C2<double> *>(p.f64.tw),
                                        p.f64.sp);
   KFBI_HIP(hipGetLastError());
   p.t_dst_x_fe1.toc(p.profile, st);
@@ -1531,20 +1569,39 @@ void run_bidomain_final(DevProblem &p, const FhnArgs &a, bool fuse_be, hipStream
     if (p.dim == 3 && fuse_be) {
       // only Phi_i - Phi_e is needed: the z pass stores it, and the inverse y and x passes (the
       // latter with the backward Euler update) run over that one field
-      launch_x_fhn<M, FHN_SRC>(p, a, st);
       using Sh = Shape<double, M>;
       PrecTables<double> &tb = p.f64;
       double *A = tb.work;
       const C2<double> *tw = reinterpret_cast<const C2<double> *>(tb.tw);
       const int64_t P = p.P, cs = p.comp_stride;
       const int *w = p.tile_w[0];
-      p.t_dst_y.tic(p.profile, st);
-      pass_y<double, M>(w[1], A, A, P, cs, 2, nullptr, nullptr, tw, tb.sp, st);
-      p.t_dst_y.toc(p.profile, st);
-      p.t_dst_last_diff.tic(p.profile, st);
-      pass_last<double, M>(w[2], A, 3, 2, P, cs, mode_of<double>(p), tw, tb.sp, nullptr, 1, 0, st, nullptr, nullptr,
-                           nullptr, 4);
-      p.t_dst_last_diff.toc(p.profile, st);
+      if (p.sparse && !a.stim && tb.gbuf) {
+        // f + C psi with f = (g, -g) antisymmetric: the volume solve left g's x-y transform in
+        // gbuf, so only C psi is transformed, on the rows and planes holding irregular nodes as
+        // in the product, and the z pass adds the two as it loads
+        double *X = tb.xbuf, *Y = tb.ybuf;
+        const unsigned gin = (unsigned)((p.n_rows_in + 2 * Sh::NP - 1) / (2 * Sh::NP));
+        p.t_dst_x_rows.tic(p.profile, st);
+        if (gin) k_dst_x_rows<double, M><<<gin, Sh::NT, 0, st>>>(tb.rhs, X, p.rows_in, p.n_rows_in, tw, tb.sp);
+        KFBI_HIP(hipGetLastError());
+        p.t_dst_x_rows.toc(p.profile, st);
+        p.t_dst_y_sparse.tic(p.profile, st);
+        pass_y<double, M>(w[1], X, Y, P, cs, 2, p.mask_in, nullptr, tw, tb.sp, st, p.planes_in);
+        p.t_dst_y_sparse.toc(p.profile, st);
+        p.t_dst_last_comb.tic(p.profile, st);
+        pass_last<double, M>(w[2], A, 3, 2, P, cs, mode_of<double>(p), tw, tb.sp, nullptr, 1, 0, st, tb.gbuf,
+                             &p.planes_in_bits, nullptr, 5, Y);
+        p.t_dst_last_comb.toc(p.profile, st);
+      } else {
+        launch_x_fhn<M, FHN_SRC>(p, a, st);
+        p.t_dst_y.tic(p.profile, st);
+        pass_y<double, M>(w[1], A, A, P, cs, 2, nullptr, nullptr, tw, tb.sp, st);
+        p.t_dst_y.toc(p.profile, st);
+        p.t_dst_last_diff.tic(p.profile, st);
+        pass_last<double, M>(w[2], A, 3, 2, P, cs, mode_of<double>(p), tw, tb.sp, nullptr, 1, 0, st, nullptr, nullptr,
+                             nullptr, 4);
+        p.t_dst_last_diff.toc(p.profile, st);
+      }
       p.t_dst_y1.tic(p.profile, st);
       pass_y<double, M>(w[1], A, A, P, cs, 1, nullptr, nullptr, tw, tb.sp, st);
       p.t_dst_y1.toc(p.profile, st);

@@ -477,6 +477,10 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const NumTables &h) {
     KFBI_HIP(hipMemset(tb.xbuf, 0, field * sizeof(T)));
     tb.ybuf = dalloc<T>(field);
     KFBI_HIP(hipMemset(tb.ybuf, 0, field * sizeof(T)));
+    if (fits && p.ncomp == 2) {
+      tb.gbuf = dalloc<T>((size_t)p.comp_stride);
+      KFBI_HIP(hipMemset(tb.gbuf, 0, (size_t)p.comp_stride * sizeof(T)));
+    }
   }
   const int nh = p.dim == 2 ? 3 : 6;
   tb.jz = dalloc<T>((size_t)p.ncomp * 2 * std::max<int64_t>(p.nc, 1));
@@ -486,7 +490,7 @@ void upload_prec(DevProblem &p, PrecTables<T> &tb, const NumTables &h) {
 template <typename T>
 void free_prec(PrecTables<T> &tb) {
   T **all[] = {&tb.z_A, &tb.z_B, &tb.q_wg, &tb.q_c, &tb.q_G, &tb.arm_d, &tb.arm_s, &tb.st_nw, &tb.st_r,
-               &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.ybuf, &tb.jz, &tb.jq};
+               &tb.tw, &tb.sp, &tb.rhs, &tb.work, &tb.xbuf, &tb.ybuf, &tb.gbuf, &tb.jz, &tb.jq};
   for (T **q : all) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -833,7 +837,7 @@ void upload_tables(DevProblem &p) {
   KFBI_HIP(hipHostMalloc(&p.host_red, 4096 * sizeof(double), hipHostMallocDefault));
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
                  &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn, &p.t_dst_x_fe1,
-                 &p.t_dst_y1, &p.t_dst_last_anti, &p.t_dst_last_diff, &p.t_dst_x_be1};
+                 &p.t_dst_y1, &p.t_dst_last_anti, &p.t_dst_last_diff, &p.t_dst_x_be1, &p.t_dst_last_comb};
   for (Timer *tm : ts) tm->create();
 }
 
@@ -866,7 +870,7 @@ void free_tables(DevProblem &p) {
   free_prec(p.f32);
   Timer *ts[] = {&p.t_dst_x, &p.t_dst_y, &p.t_dst_last, &p.t_correct, &p.t_gather, &p.t_jumps, &p.t_dst_x_rows,
                  &p.t_dst_y_sparse, &p.t_dst_last_sparse, &p.t_dst_last_out, &p.t_dst_x_fhn, &p.t_dst_x_fe1,
-                 &p.t_dst_y1, &p.t_dst_last_anti, &p.t_dst_last_diff, &p.t_dst_x_be1};
+                 &p.t_dst_y1, &p.t_dst_last_anti, &p.t_dst_last_diff, &p.t_dst_x_be1, &p.t_dst_last_comb};
   for (Timer *tm : ts) tm->destroy();
 }
 
